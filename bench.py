@@ -1,0 +1,227 @@
+#!/usr/bin/env python3
+"""Throughput of the screened VMC hot path on one MI355X.
+
+Workload: the synthetic H-chain-like Hamiltonian with 20 spatial orbitals,
+10 alpha + 10 beta electrons, eps = 1e-6, 4096 walkers, FP64 (Jastrow-Slater
+wavefunction, random-init parameters, synthetic integrals).
+
+One timed step is one optimisation iteration of the hot path:
+  * vmc_ctmc_step: a persistent sweep of `--sweep` (= the refresh period, 50)
+    CTMC moves of every walker -- screened singles/doubles enumeration,
+    ratios, local energy, rates, pick, Sherman-Morrison updates, and the
+    periodic re-inversion at the end of the sweep;
+  * vmc_local_energy of the post-sweep states, their residence-time weighted
+    energy and the contraction weights;
+  * vmc_logderiv (contracted backward), vmc_amsgrad, vmc_set_params (Jastrow
+    factors folded into the tables) and vmc_walkers_init (fresh inverses for
+    the new parameters).
+value = walker-steps/s = walkers * sweep * steps / wall time of the timed steps.
+
+Prints one JSON line (see --help for knobs).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "walker-steps/s (E_L+CTMC) at stated E_L error vs FP64 oracle; % HBM/MFMA peak"
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--walkers", type=int, default=4096)
+    ap.add_argument("--sweep", type=int, default=50, help="CTMC moves per step (= refresh period)")
+    ap.add_argument("--config", default="hchain20")
+    ap.add_argument("--threads", type=int, default=0, help="workgroup size of the sweep kernel (0 = library default)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU-baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true", help="skip the E_L check against the oracle")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only: walkers are independent and a multi-GPU run "
+                                   "would shard them with one gradient all-reduce per iteration, which is not "
+                                   "implemented here; run with --gpus 1"}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1807_10633_amd import vmc
+    from workloads import make_config
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    wl = make_config(args.config, n_walkers=args.walkers)
+    sysm = vmc.System.from_workload(wl, refresh_period=args.sweep)
+    if args.threads:
+        lib = vmc.load_library()
+        if hasattr(lib, "vmc_set_block_threads"):
+            lib.vmc_set_block_threads(sysm.handle, args.threads)
+    walkers = sysm.walkers(wl.occ)
+    W, S = args.walkers, args.sweep
+    nj = sysm.n_so * (sysm.n_so + 1) // 2
+    params = torch.cat([sysm.J, sysm.theta.reshape(-1)]).clone()
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    vh = torch.zeros_like(params)
+    G = torch.zeros_like(params)
+    stream = torch.cuda.current_stream()
+    sweep_events = []
+
+    def one_step(timed):
+        if timed:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+        vmc.vmc_ctmc_step(sysm.handle, walkers, S, stream=stream)
+        if timed:
+            e1.record(stream)
+            sweep_events.append((e0, e1))
+        # E_L and t of the post-sweep states, so that O_k and E_L refer to the same determinant
+        vmc.vmc_local_energy(sysm.handle, walkers, stream=stream)
+        el = walkers.view("eloc", torch.float64)[:W]
+        t = walkers.view("tres", torch.float64)[:W]
+        tsum = t.sum()
+        E = (t * el).sum() / tsum
+        g = 2.0 * t * (el - E) / tsum
+        vmc.vmc_logderiv(sysm.handle, walkers, g, G, stream=stream)
+        vmc.vmc_amsgrad(params, m, v, vh, G, 1e-3, 0.9, 0.99, 1e-8, False, stream=stream)
+        vmc.vmc_set_params(sysm.handle, params[:nj], params[nj:], stream=stream)
+        vmc.vmc_walkers_init(sysm.handle, walkers, stream=stream)
+        return E
+
+    # burn-in of the walkers (not timed, not counted)
+    vmc.vmc_ctmc_step(sysm.handle, walkers, 100, stream=stream)
+    for _ in range(args.warmup):
+        one_step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    E = None
+    for _ in range(args.steps):
+        E = one_step(True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    value = W * S * args.steps / wall
+    sweep_ms = float(np.mean([a.elapsed_time(b) for a, b in sweep_events]))
+    status = walkers.view("status", torch.int32)[:W].cpu().numpy()
+
+    # --- algorithmic work of the sweep kernel, from candidate counts of a
+    #     sample of the final walker states (library diagnostic entry point)
+    ne, n_so = sysm.ne, sysm.n_so
+    cap = 200000
+    ijab = torch.zeros((cap, 5), dtype=torch.int32, device=dev)
+    hv = torch.zeros(cap, dtype=torch.float64, device=dev)
+    rv = torch.zeros(cap, dtype=torch.float64, device=dev)
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    ks, kd = [], []
+    for w in range(0, W, max(1, W // 32)):
+        vmc.vmc_excitations(sysm.handle, walkers, w, ijab, hv, rv, cap, cnt)
+        n = int(cnt.item())
+        types = ijab[:n, 0].cpu().numpy()
+        ks.append(int(np.count_nonzero(types == 1)))
+        kd.append(int(np.count_nonzero(types == 2)))
+    K_s, K_d = float(np.mean(ks)), float(np.mean(kd))
+    # FP64 flops per walker-step: doubles 10 (2x2 minor 3, Jastrow 4, E_L 2,
+    # rate 1); singles Ne + 7; H_NN Ne(Ne-1)/2 + Ne; update 2*1.5*(|R|+|B|)
+    # (1.5 = mean electrons moved, measured by the double/single pick mix is
+    # not tracked, the midpoint is used); Jastrow sums 3 n_so; refresh amortised
+    # over the sweep: GJ 2 Ne^3 + R 2 n_so Ne^2.
+    flops = (10.0 * K_d + (ne + 7.0) * K_s + ne * (ne - 1) / 2 + ne + 2 * 1.5 * (n_so * ne + ne * ne) + 3 * n_so
+             + (2.0 * ne ** 3 + 2.0 * n_so * ne * ne) / S)
+    achieved_tflops = flops * W * S / (sweep_ms * 1e-3) / 1e12
+    roofline = {
+        "bound": "alu",
+        "kernel": "k_sweep (persistent E_L + CTMC + Sherman-Morrison, state in LDS)",
+        "achieved": achieved_tflops,
+        "peak": FP64_VECTOR_PEAK_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": achieved_tflops / FP64_VECTOR_PEAK_TFLOPS,
+        "traffic": None,
+        "flop_per_walker_step": flops,
+        "K_singles": K_s,
+        "K_doubles": K_d,
+        "sweep_kernel_ms": sweep_ms,
+    }
+
+    # --- E_L error of the final states against the oracle
+    el_err = None
+    if not args.no_check:
+        from oracle.core import ORC_LEMMA, OracleSystem
+
+        vmc.vmc_local_energy(sysm.handle, walkers, stream=stream)
+        torch.cuda.synchronize()
+        el = walkers.view("eloc", torch.float64)[:W].cpu().numpy()
+        occ = walkers.view("occ_bits", torch.int64)[: W * sysm.n_words].cpu().numpy().view(np.uint64)
+        occ = occ.reshape(W, sysm.n_words)
+        orc = OracleSystem(wl.n_orb, wl.n_alpha, wl.n_beta, wl.h1, wl.eri_idx, wl.eri_val, wl.eps)
+        p = params.cpu().numpy()
+        orc.set_params(p[:nj], p[nj:].reshape(n_so, n_so))
+        idx = np.arange(0, W, max(1, W // 16))
+        e_o, _, _, st_o = orc.local_energy_batch(occ[idx], ORC_LEMMA)
+        el_err = float(np.max(np.abs(e_o - el[idx])))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle.core import ORC_LEMMA, OracleSystem
+
+        orc0 = OracleSystem.from_workload(wl)
+        threads = min(16, os.cpu_count() or 1)
+        # calibrate on a small batch, then time a bounded sample
+        c0 = time.perf_counter()
+        orc0.ctmc_batch(wl.occ[:threads], wl.ctmc_seed, 0, 2, ORC_LEMMA, threads)
+        per = (time.perf_counter() - c0) / (2 * threads)  # wall s per walker-step at full thread use
+        n_ws = max(threads, int(args.cpu_seconds / max(per, 1e-9)))
+        n_steps_cpu = 5
+        n_w = max(threads, min(W, n_ws // n_steps_cpu))
+        c0 = time.perf_counter()
+        orc0.ctmc_batch(wl.occ[:n_w], wl.ctmc_seed, 0, n_steps_cpu, ORC_LEMMA, threads)
+        cpu_wall = time.perf_counter() - c0
+        cpu = {"value": n_w * n_steps_cpu / cpu_wall, "unit": "walker-steps/s", "cores": threads, "kind": "oracle",
+               "sample": f"{n_w} walkers x {n_steps_cpu} CTMC moves of the same workload (oracle, fresh-inverse "
+                         f"ratios, OpenMP over walkers), {cpu_wall:.1f} s"}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "walker-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: H-chain-like 20 orbitals, 10a+10b, eps=1e-6" if args.config ==
+                   "hchain20" else args.config, "walkers": W, "ctmc_moves_per_step": S, "refresh_period": S,
+                   "precision": "fp64"},
+        "eloc_evals_per_s_in_sweep": W * S / (sweep_ms * 1e-3),
+        "el_max_abs_err_vs_oracle": el_err,
+        "energy": float(E) if E is not None else None,
+        "flagged_walkers": int(np.count_nonzero(status & 1)),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,234 @@
+/*
+ * vmc.h -- C ABI of the MI355X (gfx950) screened orbital-space VMC hot path.
+ *
+ * The library evaluates, for thousands of walkers (determinants) at once:
+ *   - the screened local energy E_L[N, eps] = sum_M^eps H_NM psi(M)/psi(N)
+ *     (Sabzevari & Sharma, Eq. eloc:hci), with singles screened by the bound
+ *     S_ia = |h_ia| + sum_j |(ia|jj) - (ij|ja)| and doubles by
+ *     |<ab|ij> - <ab|ji>| through a heat-bath table (section "Reduced scaling
+ *     evaluation of the local energy");
+ *   - amplitude ratios of a Jastrow-Slater wavefunction, single ratios from
+ *     R = theta * theta[N]^-1 (Eq. R) and doubles as 2x2 minors of R;
+ *   - continuous-time Monte Carlo moves with rates r = |psi(M)/psi(N)| over the
+ *     same screened set, residence time t = 1/sum r (Eq. eq:rate and the
+ *     steps after it);
+ *   - Sherman-Morrison updates of theta[N]^-1 and R (the two update formulas of
+ *     the section "Local energy and Gradient ratios");
+ *   - gradient ratios O_k (the same section) and their contraction into the
+ *     energy gradient of Eq. eq:grad, plus an AMSGrad step (Eqs. eq:m1, eq:m2).
+ *
+ * Conventions
+ *   - Spatial orbitals 0..n-1; spin-orbitals alpha 0..n-1, beta n..2n-1.
+ *   - Two-electron integrals: real chemist notation (pq|rs), 8-fold symmetric,
+ *     passed as a canonical list with p>=q, r>=s, pair(p,q) >= pair(r,s),
+ *     pair(p,q) = p(p+1)/2 + q.
+ *   - Wavefunction psi(N) = exp(sum_{p<=q} J_pq n_p n_q) det(theta[occ(N), 0:Ne]),
+ *     J packed as its upper triangle row by row, theta n_so x n_so row-major.
+ *   - Occupations: little-endian bitstrings, ceil(n_so/64) uint64 words.
+ *   - Walker slots: slot p holds the orbital slot_orb[p]; A[p][x] =
+ *     theta[slot_orb[p]][x]; B = A^-1; R[a][p] = sum_x theta[a][x] B[x][p].
+ *     B and R are stored column by slot: B at ainv[p*Ne + x], R at r[p*n_so + a].
+ *   - Candidate (canonical) order, used by the CTMC pick: singles first
+ *     (occupied i ascending, then a by descending S_ia, ties by a), then
+ *     doubles (occupied pairs i<j ascending, then a<b by descending |v|, ties
+ *     by (a, b)).
+ *
+ * Errors: every call validates its host arguments synchronously and returns
+ * VMC_E_ARG with a message (vmc_last_error) on a bad argument.  Device-side
+ * problems never abort: they set per-walker status bits (VMC_ST_*).
+ * All device work is enqueued on the given stream (0 = the default stream)
+ * and is asynchronous unless stated otherwise.  Stepping allocates nothing:
+ * the caller owns walker buffers (sized by vmc_walker_bytes) and parameters;
+ * the library owns the integral tables it builds in vmc_init.
+ */
+#ifndef VMC_H
+#define VMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vmc_ctx* vmc_handle;
+
+typedef enum {
+    VMC_OK = 0,
+    VMC_E_ARG = -1,         /* invalid host argument */
+    VMC_E_OOM = -2,         /* device or host allocation failed (vmc_init only) */
+    VMC_E_HIP = -3,         /* a HIP runtime call failed */
+    VMC_E_SINGULAR = -4,    /* reserved */
+    VMC_E_STATE = -5,       /* reserved */
+    VMC_E_UNSUPPORTED = -6  /* size or mode outside what this build supports */
+} vmc_status;
+
+enum { VMC_FP64 = 0, VMC_MIXED = 1 };
+
+/* per-walker status bits (device field `status`) */
+enum {
+    VMC_ST_SINGULAR = 1u,   /* theta[N] singular at (re)inversion: psi(N) = 0 */
+    VMC_ST_EMPTY = 2u,      /* no connected determinant with a positive rate: no move */
+    VMC_ST_NONFINITE = 4u,  /* E_L or T not finite */
+    VMC_ST_SMALLDEN = 8u    /* a Sherman-Morrison denominator below 1e-8 in magnitude */
+};
+
+typedef struct {
+    int32_t n_orb;          /* spatial orbitals n (n_so = 2n <= 1024) */
+    int32_t n_alpha;        /* alpha electrons */
+    int32_t n_beta;         /* beta electrons */
+    int32_t precision;      /* VMC_FP64 (VMC_MIXED is not accepted by this build) */
+    int32_t refresh_period; /* re-invert theta[N] from scratch every this many CTMC steps (>= 1) */
+    int32_t reserved;       /* must be 0 */
+    uint64_t seed;          /* Philox key word 0 for CTMC draws */
+} vmc_system_desc;
+
+typedef struct {
+    int64_t n_nz;           /* number of canonical entries */
+    const int32_t* pqrs;    /* host, 4*n_nz indices (p,q,r,s), canonical order within each entry */
+    const double* val;      /* host, n_nz values (pq|rs) */
+} vmc_eri_list;
+
+/* walker fields, in the order of vmc_walker_bytes' output */
+enum {
+    VMC_F_OCC = 0,   /* uint64 [W][ceil(n_so/64)]  occupation bits (caller sets before vmc_walkers_init) */
+    VMC_F_SLOT_ORB,  /* int32  [W][Ne]     orbital held by each slot */
+    VMC_F_ORB_SLOT,  /* int32  [W][n_so]   slot of each orbital, -1 when empty */
+    VMC_F_AINV,      /* double [W][Ne][Ne] B = theta[N]^-1, column by slot */
+    VMC_F_R,         /* double [W][Ne][n_so] R, column by slot */
+    VMC_F_JSUM,      /* double [W][n_so]   s_p = sum_{q != p} J_pq n_q */
+    VMC_F_HNN,       /* double [W]         H_NN */
+    VMC_F_ELOC,      /* double [W]         last local energy */
+    VMC_F_TRES,      /* double [W]         last residence time t = 1/T (0 when T = 0) */
+    VMC_F_PICK,      /* int64  [W]         last move, packed (see vmc_decode_pick) */
+    VMC_F_STATUS,    /* uint32 [W]         VMC_ST_* bits, cleared by vmc_walkers_init */
+    VMC_F_SCRATCH,   /* bytes  [W][...]    kernel scratch; contents undefined between calls */
+    VMC_NFIELDS
+};
+
+typedef struct {
+    int64_t n_walkers;
+    void* occ_bits;
+    void* slot_orb;
+    void* orb_slot;
+    void* ainv;
+    void* r;
+    void* jsum;
+    void* hnn;
+    void* eloc;
+    void* tres;
+    void* pick;
+    void* status;
+    void* scratch;
+    uint64_t step;          /* host-side global CTMC step counter, advanced by vmc_ctmc_step */
+} vmc_walkers;
+
+/*
+ * Build the screening tables from h1 (host, n x n, row-major) and the canonical
+ * integral list (host; read during the call only) for threshold eps >= 0, and
+ * upload them to the current device.  Singles kept iff S_ia > eps, doubles iff
+ * |v| > eps (section "Reduced scaling evaluation of the local energy").
+ * Blocks until the upload is complete.  On success *out owns the tables.
+ */
+vmc_status vmc_init(const vmc_system_desc* desc, const double* h1, const vmc_eri_list* eri_screened, double eps,
+                    hipStream_t stream, vmc_handle* out);
+
+/* Copy wavefunction parameters (device pointers, caller-owned): J packed
+ * upper triangle, n_so(n_so+1)/2 doubles; theta n_so x n_so row-major.
+ * Rebuilds the Jastrow factors folded into the tables.  Walkers must be
+ * re-initialised (vmc_walkers_init) afterwards. */
+vmc_status vmc_set_params(vmc_handle h, const double* J_dev, const double* theta_dev, hipStream_t stream);
+
+/* Bytes of each walker field for n_walkers walkers (host-only call). */
+vmc_status vmc_walker_bytes(vmc_handle h, int64_t n_walkers, size_t field_bytes[VMC_NFIELDS]);
+
+/* From occ_bits only: slots in ascending orbital order, B = theta[N]^-1 by
+ * partial-pivoting Gauss-Jordan in FP64 (the initial inversion of the
+ * section "Local energy and Gradient ratios"), R, s, H_NN; clears status. */
+vmc_status vmc_walkers_init(vmc_handle h, vmc_walkers* w, hipStream_t stream);
+
+/* E_L and t = 1/T for every walker from its current state; no state change. */
+vmc_status vmc_local_energy(vmc_handle h, vmc_walkers* w, hipStream_t stream);
+
+/*
+ * n_steps CTMC moves of every walker in one persistent launch.  Step k of
+ * walker i draws u from Philox4x64-10 with counter (w->step + k, 0, 0, 0) and
+ * key (seed, i) (first output word, 53 high bits), picks the smallest
+ * candidate index whose running rate sum exceeds u*T, and updates B, R, s and
+ * the occupation; every refresh_period global steps B and R are recomputed
+ * from scratch.  Optional device outputs (NULL to skip), each [n_steps][W]:
+ * eloc_hist (E_L before the move), t_hist (residence time), pick_hist (packed
+ * move).  Advances w->step by n_steps.
+ */
+vmc_status vmc_ctmc_step(vmc_handle h, vmc_walkers* w, int32_t n_steps, double* eloc_hist, double* t_hist,
+                         int64_t* pick_hist, hipStream_t stream);
+
+/*
+ * Gradient ratios O_k of each walker's current state, N_p = n_so(n_so+1)/2 +
+ * n_so^2 (Jastrow part packed like J, then theta row-major):
+ * O_{J_pq} = n_p n_q, O_{theta_kx} = B[x][slot(k)] for occupied k and x < Ne,
+ * else 0.  If g_dev (device, W doubles) is NULL, out_dev receives the dense
+ * [W][N_p] matrix; otherwise out_dev receives G = sum_w g_w O_w (N_p doubles),
+ * the contracted backward used for Eq. eq:grad with g_w = 2 t_w (E_L,w - E)/sum t.
+ */
+vmc_status vmc_logderiv(vmc_handle h, const vmc_walkers* w, const double* g_dev, double* out_dev,
+                        hipStream_t stream);
+
+/* One AMSGrad step over n parameters, all pointers device (Eqs. eq:m1, eq:m2,
+ * in the Reddi form with standard betas: m = b1 m + (1-b1) g, v = b2 v +
+ * (1-b2) g^2, vhat = max(vhat, v), p -= lr m / (sqrt(vhat) + delta)).
+ * paper_literal != 0 uses vhat = max(vhat, b2 vhat + (1-b2) g^2) instead. */
+vmc_status vmc_amsgrad(int64_t n, double* params, double* m, double* v, double* vhat, const double* grad,
+                       double lr, double beta1, double beta2, double delta, int32_t paper_literal,
+                       hipStream_t stream);
+
+/*
+ * Diagnostic: the screened candidate list of one walker in canonical order.
+ * Device outputs: ijab[5*k] = {type (1 single, 2 double), i, j, a, b}
+ * (j = b = -1 for singles), hval[k] = H_NM in the walker's slot convention,
+ * ratio[k] = psi(M)/psi(N); count_dev[0] = number of candidates (entries
+ * beyond cap are counted but not written).
+ */
+vmc_status vmc_excitations(vmc_handle h, const vmc_walkers* w, int64_t walker, int32_t* ijab, double* hval,
+                           double* ratio, int64_t cap, int64_t* count_dev, hipStream_t stream);
+
+/* Diagnostic: u values of the CTMC draw for walkers 0..n-1 at one step (device out). */
+vmc_status vmc_uniforms(uint64_t seed, int64_t n, uint64_t step, double* out_dev, hipStream_t stream);
+
+/* Decode a packed pick: type (0 = no move, 1 single, 2 double), i, j, a, b. */
+void vmc_decode_pick(int64_t code, int32_t out5[5]);
+
+/* Table sizes: out[0] = double entries, out[1] = single entries, out[2] = groups
+ * per walker (Ne + Ne(Ne-1)/2). */
+vmc_status vmc_table_info(vmc_handle h, int64_t out[3]);
+
+vmc_status vmc_destroy(vmc_handle h);
+
+/* Message of the last failed call on h (or of the last failed vmc_init /
+ * handle-free call when h is NULL).  Valid until the next call on h. */
+const char* vmc_last_error(vmc_handle h);
+
+/*
+ * Host-only table builder, for inspection without a GPU.  Builds the same
+ * tables vmc_init uploads.  vmc_host_tables_get copies them out (any pointer
+ * may be NULL):
+ *   row_off [n_so*n_so + 1] int64: doubles of spin-orbital pair (i<j) are
+ *           entries row_off[i*n_so+j] .. row_off[i*n_so+j+1]-1;
+ *   dab     [E] int32 pairs (a, b) (2 per entry), dv [E] double v = <ab||ij>;
+ *   s_off   [n_so + 1] int64, sa [S] int32, sS [S] double S_ia, sh [S] h_ia.
+ */
+typedef struct vmc_host_tables vmc_host_tables;
+vmc_status vmc_host_tables_build(const vmc_system_desc* desc, const double* h1, const vmc_eri_list* eri, double eps,
+                                 vmc_host_tables** out);
+vmc_status vmc_host_tables_sizes(const vmc_host_tables* t, int64_t out[2]);
+vmc_status vmc_host_tables_get(const vmc_host_tables* t, int64_t* row_off, int32_t* dab, double* dv, int64_t* s_off,
+                               int32_t* sa, double* sS, double* sh);
+void vmc_host_tables_free(vmc_host_tables* t);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VMC_H */

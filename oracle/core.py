@@ -72,6 +72,7 @@ def _load():
     lib.orc_ctmc_step.argtypes = [P, P, C.c_int, C.c_uint64, C.c_uint64, C.c_uint64, P, P, P, P]
     lib.orc_logderiv.restype = C.c_int
     lib.orc_logderiv.argtypes = [P, P, P]
+    lib.orc_ctmc_batch.argtypes = [P, C.c_int64, P, C.c_int, C.c_uint64, C.c_uint64, C.c_int, P, P, P, C.c_int]
     _lib = lib
     return lib
 
@@ -209,6 +210,18 @@ class OracleSystem:
         rc = self._lib.orc_ctmc_step(self._h, _ptr(bits), mode, seed, walker, step, C.byref(el), C.byref(t),
                                      _ptr(pick), C.byref(margin))
         return bits, el.value, t.value, tuple(int(x) for x in pick), margin.value, int(rc)
+
+    def ctmc_batch(self, occ: np.ndarray, seed: int, step0: int, n_steps: int, mode: int = ORC_LEMMA,
+                   threads: int = 0):
+        """n_steps moves of every walker (walker index = row), OpenMP over walkers."""
+        occ = np.ascontiguousarray(occ, dtype=np.uint64).reshape(-1, self.nw).copy()
+        W = occ.shape[0]
+        el = np.zeros((W, n_steps))
+        t = np.zeros((W, n_steps))
+        st = np.zeros(W, dtype=np.int32)
+        self._lib.orc_ctmc_batch(self._h, W, _ptr(occ), mode, seed, step0, n_steps, _ptr(el), _ptr(t), _ptr(st),
+                                 int(threads))
+        return occ, el, t, st
 
     def logderiv(self, occ) -> np.ndarray:
         n_p = self.n_so * (self.n_so + 1) // 2 + self.n_so * self.n_so

@@ -67,6 +67,7 @@ typedef struct {
     double eps;
     double* h1;      /* n*n spatial */
     double* eri;     /* dense array over canonical compound indices */
+    double* P;       /* build-time only: P[I][J][A][B] = (AI|BJ) */
     int64_t n_quad;
     double* S;       /* n_so*n_so singles bound S[i*n_so+a] */
     /* per spin-orbital pair (i<j): entries (a<b, v) with |v| > eps */
@@ -103,9 +104,15 @@ static double h_so(const orc_sys* s, int p, int q) {
     return s->h1[spat(s, p) * s->n + spat(s, q)];
 }
 
+/* (ai|bj) over spin-orbitals through the dense copy P[I][J][A][B] = (AI|BJ) */
+static double p_so(const orc_sys* s, int a, int i, int b, int j) {
+    if (spin_of(s, a) != spin_of(s, i) || spin_of(s, b) != spin_of(s, j)) return 0.0;
+    int n = s->n;
+    return s->P[(((size_t)spat(s, i) * n + spat(s, j)) * n + spat(s, a)) * n + spat(s, b)];
+}
 /* antisymmetrised double element <ab||ij> = (ai|bj) - (aj|bi) */
 static double v_double(const orc_sys* s, int i, int j, int a, int b) {
-    return eri_so(s, a, i, b, j) - eri_so(s, a, j, b, i);
+    return p_so(s, a, i, b, j) - p_so(s, a, j, b, i);
 }
 
 /* --------------------------------------------------------------- bitstrings */
@@ -236,7 +243,19 @@ orc_sys* orc_create(int n, int na, int nb, const double* h1, int64_t n_eri, cons
             s->S[i * nso + a] = acc;
         }
     /* doubles: for every spin-orbital pair i<j, all a<b (disjoint from i,j)
-     * with |v| > eps.  Walker independent, so built once. */
+     * with |v| > eps.  Walker independent, so built once.  The loop reads the
+     * integrals through a dense copy P[I][J][A][B] = (AI|BJ) (same values as
+     * the canonical store, laid out so the inner loops over a, b are
+     * contiguous); it is freed after the build. */
+    {
+        size_t n4 = (size_t)n * n * n * n;
+        s->P = (double*)malloc(sizeof(double) * n4);
+        for (int I = 0; I < n; ++I)
+            for (int J = 0; J < n; ++J)
+                for (int A = 0; A < n; ++A)
+                    for (int B = 0; B < n; ++B)
+                        s->P[(((size_t)I * n + J) * n + A) * n + B] = eri_sp(s, A, I, B, J);
+    }
     s->d_off = (int64_t*)calloc((size_t)nso * nso + 1, sizeof(int64_t));
     int64_t* cnt = (int64_t*)calloc((size_t)nso * nso, sizeof(int64_t));
 #pragma omp parallel for schedule(dynamic)
@@ -270,6 +289,8 @@ orc_sys* orc_create(int n, int na, int nb, const double* h1, int64_t n_eri, cons
             }
         }
     free(cnt);
+    free(s->P);
+    s->P = NULL;
     s->J = (double*)calloc((size_t)nso * nso, sizeof(double));
     s->theta = (double*)calloc((size_t)nso * nso, sizeof(double));
     return s;
@@ -724,4 +745,24 @@ int orc_logderiv(const orc_sys* s, const uint64_t* occ_bits, double* out) {
     }
     free(occ); free(A); free(Ainv); free(col); free(perm);
     return sg == 0 ? -1 : 0;
+}
+
+/* n_steps CTMC moves for each of nwalk walkers (OpenMP over walkers, each
+ * walker sequential); occ_bits updated in place, eloc/tres [nwalk][n_steps]. */
+void orc_ctmc_batch(const orc_sys* s, int64_t nwalk, uint64_t* occ_bits, int mode, uint64_t seed, uint64_t step0,
+                    int n_steps, double* eloc, double* tres, int32_t* status, int nthreads) {
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel for schedule(dynamic)
+    for (int64_t k = 0; k < nwalk; ++k) {
+        int32_t pick[5];
+        double margin;
+        status[k] = 0;
+        for (int st = 0; st < n_steps; ++st) {
+            int rc = orc_ctmc_step(s, occ_bits + k * s->nw, mode, seed, (uint64_t)k, step0 + (uint64_t)st,
+                                   eloc + k * n_steps + st, tres + k * n_steps + st, pick, &margin);
+            if (rc != 0) { status[k] = rc; break; }
+        }
+    }
 }

@@ -1,0 +1,1299 @@
+// gfx950 kernels and the C ABI of the screened orbital-space VMC hot path.
+//
+// One workgroup owns one walker.  Per CTMC step (Sabzevari & Sharma, sections
+// "Reduced scaling evaluation of the local energy", "Continuous time Monte
+// Carlo" and "Local energy and Gradient ratios"):
+//   1. candidate groups (singles of each occupied i; heat-bath row of each
+//      occupied pair i<j) are distributed round-robin over the wavefronts;
+//      a wave scans a group 64 entries at a time, keeps the entries whose
+//      target orbitals are empty (ballot + mbcnt compaction into an LDS
+//      queue, order preserving) and evaluates full batches of 64 survivors:
+//      ratio = det-ratio (R entry or 2x2 minor of R) x Jastrow ratio, local
+//      energy term H_NM x ratio and rate |ratio|;
+//   2. per-group rate sums give T = sum r in canonical order; the group
+//      holding u*T is found by a chunked prefix sum and re-walked by one wave
+//      with a wave-level inclusive scan to locate the picked candidate;
+//   3. rank-1 (single) or rank-2 (double) Sherman-Morrison updates of B and R,
+//      the Jastrow sums s and the occupation;
+//   4. every refresh_period steps B is rebuilt by Gauss-Jordan elimination
+//      with partial pivoting and R = theta[:, 0:Ne] B.
+// When R, B and the group sums fit in LDS the walker stays on chip for the
+// whole multi-step launch; otherwise they live in the caller's buffers.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "device.hpp"
+#include "tables.hpp"
+#include "vmc.h"
+
+using namespace vmc;
+
+// =============================================================================
+// Device code
+// =============================================================================
+namespace {
+
+struct OccReg {
+    uint64_t w;
+    __device__ __forceinline__ bool empty(int p) const { return ((w >> p) & 1ull) == 0ull; }
+};
+struct OccLds {
+    const uint64_t* w;
+    __device__ __forceinline__ bool empty(int p) const { return ((w[p >> 6] >> (p & 63)) & 1ull) == 0ull; }
+};
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Decode the lexicographic index t of an occupied pair (x<y) among ne slots.
+__device__ __forceinline__ void pair_decode(int t, int ne, int& x, int& y) {
+    const double b = 2.0 * ne - 1.0;
+    int xx = (int)floor((b - sqrt(b * b - 8.0 * (double)t)) * 0.5);
+    if (xx < 0) xx = 0;
+    while (xx > 0 && xx * (2 * ne - xx - 1) / 2 > t) --xx;
+    while ((xx + 1) * (2 * ne - xx - 2) / 2 <= t) ++xx;
+    x = xx;
+    y = t - xx * (2 * ne - xx - 1) / 2 + xx + 1;
+}
+
+// Scan entries [base, base+len) of a singles list or heat-bath row, keep
+// those whose target orbitals are empty and hand them to eval in batches of
+// up to 64 (canonical order).  eval(e, active) returns true to stop early
+// (wave-uniform).
+template <bool DOUBLES, class Occ, class Eval>
+__device__ __forceinline__ void scan_group(const Tab& T, const Occ& occ, uint32_t base, uint32_t len,
+                                           uint32_t* queue, Eval& eval) {
+    const int l = lane_id();
+    uint32_t qn = 0;
+    bool stop = false;
+    for (uint32_t c = 0; c < len && !stop; c += kWave) {
+        const uint32_t e = c + (uint32_t)l;
+        bool surv = false;
+        if (e < len) {
+            if (DOUBLES) {
+                const uint32_t ab = T.dab[base + e];
+                surv = occ.empty((int)(ab & 0xFFFFu)) && occ.empty((int)(ab >> 16));
+            } else {
+                surv = occ.empty((int)T.sa[base + e]);
+            }
+        }
+        const uint64_t m = __ballot(surv);
+        if (surv) queue[qn + mask_below(m)] = e;
+        qn += (uint32_t)__popcll(m);
+        if (qn >= (uint32_t)kWave) {
+            wave_lds_sync();
+            const uint32_t mine = queue[l];
+            const uint32_t rest = ((uint32_t)l + kWave < qn) ? queue[l + kWave] : 0u;
+            wave_lds_sync();
+            qn -= kWave;
+            if ((uint32_t)l < qn) queue[l] = rest;
+            stop = eval(mine, true);
+        }
+    }
+    if (!stop && qn > 0) {
+        wave_lds_sync();
+        const uint32_t mine = ((uint32_t)l < qn) ? queue[l] : 0u;
+        eval(mine, (uint32_t)l < qn);
+    }
+    wave_lds_sync();
+}
+
+// Group descriptor (wave-uniform).
+struct Group {
+    int type;  // 1 singles, 2 doubles
+    int i, j, p, q;
+    uint32_t base, len;
+    double fac;  // exp(-s_i) [exp(-s_j)]
+};
+
+__device__ __forceinline__ Group group_of(const Tab& T, int g, const int* occl, const int* oslot, const double* ies) {
+    Group G;
+    const int ne = T.ne, n_so = T.n_so;
+    if (g < ne) {
+        G.type = 1;
+        G.i = occl[g];
+        G.j = -1;
+        G.p = oslot[G.i];
+        G.q = -1;
+        G.base = T.s_off[G.i];
+        G.len = T.s_off[G.i + 1] - G.base;
+        G.fac = ies[G.i];
+    } else {
+        int x, y;
+        pair_decode(g - ne, ne, x, y);
+        G.type = 2;
+        G.i = occl[x];
+        G.j = occl[y];
+        G.p = oslot[G.i];
+        G.q = oslot[G.j];
+        const int row = G.i * n_so + G.j;
+        G.base = T.row_off[row];
+        G.len = T.row_off[row + 1] - G.base;
+        G.fac = ies[G.i] * ies[G.j];
+    }
+    return G;
+}
+
+// Ratio and matrix element of candidate e of group Gr (slot convention).
+__device__ __forceinline__ double single_ratio(const Tab& T, const Group& Gr, uint32_t e, const double* R,
+                                               const double* es, int& a) {
+    a = (int)T.sa[Gr.base + e];
+    return R[Gr.p * T.n_so + a] * es[a] * Gr.fac * T.sK[Gr.base + e];
+}
+__device__ __forceinline__ double single_h(const Tab& T, const Group& Gr, uint32_t e, const int* occl) {
+    const double* V = T.sV + (size_t)(Gr.base + e) * T.n_so;
+    double h = T.sh[Gr.base + e];
+    for (int y = 0; y < T.ne; ++y) h += V[occl[y]];
+    return h;
+}
+__device__ __forceinline__ double double_ratio(const Tab& T, const Group& Gr, uint32_t e, const double* R,
+                                               const double* es, int& a, int& b) {
+    const uint32_t ab = T.dab[Gr.base + e];
+    a = (int)(ab & 0xFFFFu);
+    b = (int)(ab >> 16);
+    const double* Rp = R + Gr.p * T.n_so;
+    const double* Rq = R + Gr.q * T.n_so;
+    const double det = Rp[a] * Rq[b] - Rp[b] * Rq[a];
+    return det * es[a] * es[b] * T.dK[Gr.base + e] * Gr.fac;
+}
+
+// Block-wide deterministic sum (every thread gets the same value).
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    const int wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+    v = wave_sum(v);
+    if (lane_id() == 0) red[wv] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int k = 0; k < nwv; ++k) t += red[k];
+    __syncthreads();
+    return t;
+}
+
+// --------------------------------------------------------------- LDS layout
+struct Lds {
+    size_t occw, occl, slot, oslot, s, es, ies, red, csum, mi, md, queues, w1, w2, cRp, cRq, cBp, cBq, ipiv, fcol, R,
+        B, gsum, total;
+};
+__host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~(size_t)15; }
+__host__ __device__ inline Lds lds_layout(int n_so, int ne, int nw, int G, int nt, bool small) {
+    Lds L;
+    size_t o = 0;
+    const int nwv = nt / 64;
+    L.occw = o; o += al16((size_t)nw * 8);
+    L.occl = o; o += al16((size_t)ne * 4);
+    L.slot = o; o += al16((size_t)ne * 4);
+    L.oslot = o; o += al16((size_t)n_so * 4);
+    L.s = o; o += al16((size_t)n_so * 8);
+    L.es = o; o += al16((size_t)n_so * 8);
+    L.ies = o; o += al16((size_t)n_so * 8);
+    L.red = o; o += al16((size_t)(nwv + 2) * 8);
+    L.csum = o; o += al16((size_t)nt * 8);
+    L.mi = o; o += al16((size_t)(32 + nwv) * 4);
+    L.md = o; o += al16((size_t)8 * 8);
+    L.queues = o; o += al16((size_t)nwv * kQueue * 4);
+    L.w1 = o; o += al16((size_t)ne * 8);
+    L.w2 = o; o += al16((size_t)ne * 8);
+    L.cRp = o; o += al16((size_t)n_so * 8);
+    L.cRq = o; o += al16((size_t)n_so * 8);
+    L.cBp = o; o += al16((size_t)ne * 8);
+    L.cBq = o; o += al16((size_t)ne * 8);
+    L.ipiv = o; o += al16((size_t)ne * 4);
+    L.fcol = o; o += al16((size_t)ne * 8);
+    if (small) {
+        L.R = o; o += al16((size_t)n_so * ne * 8);
+        L.B = o; o += al16((size_t)ne * ne * 8);
+        L.gsum = o; o += al16((size_t)G * 8);
+    } else {
+        L.R = L.B = L.gsum = 0;
+    }
+    L.total = o;
+    return L;
+}
+
+// misc int slots
+enum { MI_ST = 0, MI_PIV, MI_GSTAR, MI_GLAST, MI_PTYPE, MI_PI, MI_PJ, MI_PA, MI_PB, MI_PP, MI_PQ, MI_WAVE = 32 };
+enum { MD_T = 0, MD_BASE, MD_EL, MD_HNN };
+
+// Rebuild B = theta[N]^-1 (Gauss-Jordan, partial pivoting, FP64), R and s from
+// the slot list.  B is stored column by slot (B[x][p] at B[p*ne + x]): the
+// elimination works on A^T, whose inverse laid out row-major is exactly that.
+__device__ void refresh_state(const Tab& T, const int* slot, double* B, double* R, double* s, double* fcol, int* ipiv,
+                              int* mi, double* red) {
+    const int tid = threadIdx.x, nt = blockDim.x, ne = T.ne, n_so = T.n_so;
+    const int wv = tid >> 6, nwv = nt >> 6;
+    for (int idx = tid; idx < ne * ne; idx += nt) {
+        const int x = idx / ne, p = idx - x * ne;
+        B[idx] = T.theta[(size_t)slot[p] * n_so + x];
+    }
+    __syncthreads();
+    for (int k = 0; k < ne; ++k) {
+        double bv = -1.0;
+        int bi = INT_MAX;
+        for (int r = k + tid; r < ne; r += nt) {
+            const double v = fabs(B[r * ne + k]);
+            if (v > bv) { bv = v; bi = r; }
+        }
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            const double ov = __shfl_xor(bv, d, kWave);
+            const int oi = __shfl_xor(bi, d, kWave);
+            if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+        }
+        if (lane_id() == 0) { red[wv] = bv; mi[MI_WAVE + wv] = bi; }
+        __syncthreads();
+        if (tid == 0) {
+            double best = red[0];
+            int bidx = mi[MI_WAVE];
+            for (int q = 1; q < nwv; ++q)
+                if (red[q] > best || (red[q] == best && mi[MI_WAVE + q] < bidx)) { best = red[q]; bidx = mi[MI_WAVE + q]; }
+            mi[MI_PIV] = bidx;
+            ipiv[k] = bidx;
+            if (!(best > 0.0)) mi[MI_ST] |= (int)VMC_ST_SINGULAR;
+        }
+        __syncthreads();
+        const int piv = mi[MI_PIV];
+        if (piv != k)
+            for (int c = tid; c < ne; c += nt) {
+                const double t0 = B[k * ne + c];
+                B[k * ne + c] = B[piv * ne + c];
+                B[piv * ne + c] = t0;
+            }
+        __syncthreads();
+        const double pv = B[k * ne + k];
+        const double inv = (pv != 0.0) ? 1.0 / pv : 0.0;
+        for (int r = tid; r < ne; r += nt) fcol[r] = B[r * ne + k];
+        __syncthreads();
+        for (int c = tid; c < ne; c += nt) B[k * ne + c] = (c == k) ? inv : B[k * ne + c] * inv;
+        __syncthreads();
+        for (int idx = tid; idx < ne * ne; idx += nt) {
+            const int r = idx / ne, c = idx - r * ne;
+            if (r == k) continue;
+            B[idx] = (c == k) ? -fcol[r] * inv : B[idx] - fcol[r] * B[k * ne + c];
+        }
+        __syncthreads();
+    }
+    for (int k = ne - 1; k >= 0; --k) {
+        const int piv = ipiv[k];
+        if (piv != k)
+            for (int r = tid; r < ne; r += nt) {
+                const double t0 = B[r * ne + k];
+                B[r * ne + k] = B[r * ne + piv];
+                B[r * ne + piv] = t0;
+            }
+        __syncthreads();
+    }
+    for (int idx = tid; idx < n_so * ne; idx += nt) {
+        const int p = idx / n_so, a = idx - p * n_so;
+        const double* th = T.theta + (size_t)a * n_so;
+        const double* Bp = B + p * ne;
+        double acc = 0.0;
+        for (int x = 0; x < ne; ++x) acc += th[x] * Bp[x];
+        R[idx] = acc;
+    }
+    for (int pp = tid; pp < n_so; pp += nt) {
+        const double* Jr = T.J + (size_t)pp * n_so;
+        double acc = 0.0;
+        for (int k = 0; k < ne; ++k) {
+            const int q = slot[k];
+            if (q != pp) acc += Jr[q];
+        }
+        s[pp] = acc;
+    }
+    __syncthreads();
+}
+
+enum { MODE_ELOC = 0, MODE_CTMC = 1, MODE_INIT = 2 };
+
+template <bool NW1, bool SMALL>
+__global__ void __launch_bounds__(512) k_sweep(Tab T, Wk S, int64_t W, int mode, int n_steps, uint64_t step0,
+                                               uint64_t seed, int refresh_period, double* eloc_hist, double* t_hist,
+                                               int64_t* pick_hist) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int64_t w = blockIdx.x;
+    if (w >= W) return;
+    const int tid = threadIdx.x, nt = blockDim.x, l = tid & 63, wv = tid >> 6, nwv = nt >> 6;
+    const int n_so = T.n_so, ne = T.ne, nw = T.nw, G = T.G;
+    const Lds L = lds_layout(n_so, ne, nw, G, nt, SMALL);
+    uint64_t* occw = (uint64_t*)(smem + L.occw);
+    int* occl = (int*)(smem + L.occl);
+    int* slot = (int*)(smem + L.slot);
+    int* oslot = (int*)(smem + L.oslot);
+    double* s = (double*)(smem + L.s);
+    double* es = (double*)(smem + L.es);
+    double* ies = (double*)(smem + L.ies);
+    double* red = (double*)(smem + L.red);
+    double* csum = (double*)(smem + L.csum);
+    int* mi = (int*)(smem + L.mi);
+    double* md = (double*)(smem + L.md);
+    uint32_t* queue = (uint32_t*)(smem + L.queues) + wv * kQueue;
+    double* w1 = (double*)(smem + L.w1);
+    double* w2 = (double*)(smem + L.w2);
+    double* cRp = (double*)(smem + L.cRp);
+    double* cRq = (double*)(smem + L.cRq);
+    double* cBp = (double*)(smem + L.cBp);
+    double* cBq = (double*)(smem + L.cBq);
+    int* ipiv = (int*)(smem + L.ipiv);
+    double* fcol = (double*)(smem + L.fcol);
+    double *R, *B, *gsum;
+    if (SMALL) {
+        R = (double*)(smem + L.R);
+        B = (double*)(smem + L.B);
+        gsum = (double*)(smem + L.gsum);
+    } else {
+        R = S.R + (size_t)w * n_so * ne;
+        B = S.B + (size_t)w * ne * ne;
+        gsum = (double*)(S.scratch + (size_t)w * S.scratch_stride);
+    }
+
+    // ---------------------------------------------------------------- load
+    for (int k = tid; k < nw; k += nt) occw[k] = S.occ[(size_t)w * nw + k];
+    if (tid == 0) mi[MI_ST] = (mode == MODE_INIT) ? 0 : (int)S.status[w];
+    __syncthreads();
+    if (mode == MODE_INIT) {
+        // bits beyond n_so are ignored; a wrong electron count marks the walker
+        if (tid == 0) {
+            if ((n_so & 63) != 0) occw[nw - 1] &= (1ull << (n_so & 63)) - 1ull;
+            int pop = 0;
+            for (int k = 0; k < nw; ++k) pop += __popcll(occw[k]);
+            if (pop != ne) {
+                mi[MI_ST] = (int)VMC_ST_SINGULAR;
+                for (int k = 0; k < nw; ++k) occw[k] = 0ull;
+                for (int k = 0; k < ne; ++k) occw[k >> 6] |= 1ull << (k & 63);
+            }
+        }
+        __syncthreads();
+        for (int pp = tid; pp < n_so; pp += nt) {
+            const bool occd = (occw[pp >> 6] >> (pp & 63)) & 1ull;
+            int rank = 0;
+            for (int k = 0; k < (pp >> 6); ++k) rank += __popcll(occw[k]);
+            rank += __popcll(occw[pp >> 6] & ((1ull << (pp & 63)) - 1ull));
+            oslot[pp] = occd ? rank : -1;
+            if (occd && rank < ne) slot[rank] = pp;
+        }
+        __syncthreads();
+        refresh_state(T, slot, B, R, s, fcol, ipiv, mi, red);
+    } else {
+        for (int k = tid; k < ne; k += nt) slot[k] = S.slot_orb[(size_t)w * ne + k];
+        for (int pp = tid; pp < n_so; pp += nt) {
+            oslot[pp] = S.orb_slot[(size_t)w * n_so + pp];
+            s[pp] = S.s[(size_t)w * n_so + pp];
+        }
+        if (SMALL) {
+            const double* Rg = S.R + (size_t)w * n_so * ne;
+            const double* Bg = S.B + (size_t)w * ne * ne;
+            for (int k = tid; k < n_so * ne; k += nt) R[k] = Rg[k];
+            for (int k = tid; k < ne * ne; k += nt) B[k] = Bg[k];
+        }
+        __syncthreads();
+    }
+
+    const int steps = (mode == MODE_CTMC) ? n_steps : 1;
+    double el_last = 0.0, t_last = 0.0, hnn = 0.0;
+    int64_t code_last = 0;
+    for (int k = 0; k < steps; ++k) {
+        const uint64_t gstep = step0 + (uint64_t)k;
+        // ------------------------------------------------- per-step setup
+        for (int pp = tid; pp < n_so; pp += nt) {
+            if (!((occw[pp >> 6] >> (pp & 63)) & 1ull)) {
+                es[pp] = exp(s[pp]);
+                ies[pp] = exp(-s[pp]);
+                continue;
+            }
+            int rank = 0;
+            for (int q = 0; q < (pp >> 6); ++q) rank += __popcll(occw[q]);
+            rank += __popcll(occw[pp >> 6] & ((1ull << (pp & 63)) - 1ull));
+            occl[rank] = pp;
+            es[pp] = exp(s[pp]);
+            ies[pp] = exp(-s[pp]);
+        }
+        __syncthreads();
+        double hp = 0.0;
+        for (int x = tid; x < ne; x += nt) {
+            const int i = occl[x];
+            const double* Di = T.D + (size_t)i * n_so;
+            hp += T.hdiag[i];
+            for (int y = x + 1; y < ne; ++y) hp += Di[occl[y]];
+        }
+        hnn = block_sum(hp, red);
+        const bool singular = (mi[MI_ST] & (int)VMC_ST_SINGULAR) != 0;
+        if (mode == MODE_INIT) break;
+
+        // ------------------------------------------------- local energy
+        double el_lane = 0.0;
+        if (!singular) {
+            for (int g = wv; g < G; g += nwv) {
+                const Group Gr = group_of(T, g, occl, oslot, ies);
+                double rs = 0.0;
+                if (Gr.type == 1) {
+                    auto ev = [&](uint32_t e, bool act) -> bool {
+                        if (act) {
+                            int a;
+                            const double ratio = single_ratio(T, Gr, e, R, es, a);
+                            el_lane += single_h(T, Gr, e, occl) * ratio;
+                            rs += fabs(ratio);
+                        }
+                        return false;
+                    };
+                    if (NW1) scan_group<false>(T, OccReg{occw[0]}, Gr.base, Gr.len, queue, ev);
+                    else scan_group<false>(T, OccLds{occw}, Gr.base, Gr.len, queue, ev);
+                } else {
+                    auto ev = [&](uint32_t e, bool act) -> bool {
+                        if (act) {
+                            int a, b;
+                            const double ratio = double_ratio(T, Gr, e, R, es, a, b);
+                            el_lane += T.dv[Gr.base + e] * ratio;
+                            rs += fabs(ratio);
+                        }
+                        return false;
+                    };
+                    if (NW1) scan_group<true>(T, OccReg{occw[0]}, Gr.base, Gr.len, queue, ev);
+                    else scan_group<true>(T, OccLds{occw}, Gr.base, Gr.len, queue, ev);
+                }
+                const double gs = wave_sum(rs);
+                if (l == 0) gsum[g] = gs;
+            }
+        }
+        const double el = singular ? NAN : (block_sum(el_lane, red) + hnn);
+
+        // --------------------------------------------- T and the group prefix
+        const int chunk = (G + nt - 1) / nt;
+        const int g0 = min(G, tid * chunk), g1 = min(G, g0 + chunk);
+        {
+            double cs = 0.0;
+            if (!singular)
+                for (int g = g0; g < g1; ++g) cs += gsum[g];
+            csum[tid] = cs;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double run = 0.0;
+            for (int q = 0; q < nt; ++q) {
+                const double c = csum[q];
+                csum[q] = run;
+                run += c;
+            }
+            md[MD_T] = run;
+            mi[MI_GSTAR] = INT_MAX;
+            mi[MI_GLAST] = -1;
+            mi[MI_PTYPE] = 0;
+        }
+        __syncthreads();
+        const double Ttot = md[MD_T];
+        const bool okT = !singular && Ttot > 0.0 && isfinite(Ttot) && isfinite(el);
+        const double tres = okT ? 1.0 / Ttot : 0.0;
+        if (tid == 0) {
+            if (!singular && !(isfinite(Ttot) && isfinite(el))) mi[MI_ST] |= (int)VMC_ST_NONFINITE;
+            else if (!singular && !(Ttot > 0.0)) mi[MI_ST] |= (int)VMC_ST_EMPTY;
+        }
+        el_last = el;
+        t_last = tres;
+        code_last = 0;
+        if (mode == MODE_ELOC) break;
+
+        // --------------------------------------------------------- pick
+        if (okT) {
+            const double target = ctmc_uniform(seed, (uint64_t)w, gstep) * Ttot;
+            double run = csum[tid], before = 0.0;
+            int found = -1, lastpos = -1;
+            for (int g = g0; g < g1; ++g) {
+                const double gv = gsum[g];
+                if (gv > 0.0) lastpos = g;
+                const double prev = run;
+                run += gv;
+                if (found < 0 && gv > 0.0 && run > target) { found = g; before = prev; }
+            }
+            if (found >= 0) atomicMin(&mi[MI_GSTAR], found);
+            if (lastpos >= 0) atomicMax(&mi[MI_GLAST], lastpos);
+            __syncthreads();
+            if (found >= 0 && found == mi[MI_GSTAR]) md[MD_BASE] = before;
+            __syncthreads();
+            int gstar = mi[MI_GSTAR];
+            const bool fallback = (gstar == INT_MAX);
+            if (fallback) gstar = mi[MI_GLAST];
+            if (wv == 0 && gstar >= 0) {
+                const Group Gr = group_of(T, gstar, occl, oslot, ies);
+                double run0 = md[MD_BASE];
+                int got = -1;                 // entry index of the pick
+                int last = -1;                // last entry with a positive rate
+                auto ev = [&](uint32_t e, bool act) -> bool {
+                    double r = 0.0;
+                    if (act) {
+                        int a, b;
+                        r = fabs(Gr.type == 1 ? single_ratio(T, Gr, e, R, es, a) : double_ratio(T, Gr, e, R, es, a, b));
+                    }
+                    const uint64_t mpos = __ballot(r > 0.0);
+                    if (mpos) last = __shfl((int)e, 63 - __clzll(mpos), kWave);
+                    if (fallback) return false;
+                    const double incl = wave_inclusive_scan(r);
+                    const uint64_t mx = __ballot(act && (run0 + incl > target));
+                    if (mx) {
+                        got = __shfl((int)e, __ffsll((unsigned long long)mx) - 1, kWave);
+                        return true;
+                    }
+                    run0 += __shfl(incl, 63, kWave);
+                    return false;
+                };
+                if (Gr.type == 1) {
+                    if (NW1) scan_group<false>(T, OccReg{occw[0]}, Gr.base, Gr.len, queue, ev);
+                    else scan_group<false>(T, OccLds{occw}, Gr.base, Gr.len, queue, ev);
+                } else {
+                    if (NW1) scan_group<true>(T, OccReg{occw[0]}, Gr.base, Gr.len, queue, ev);
+                    else scan_group<true>(T, OccLds{occw}, Gr.base, Gr.len, queue, ev);
+                }
+                if (got < 0) got = last;
+                if (l == 0 && got >= 0) {
+                    mi[MI_PTYPE] = Gr.type;
+                    mi[MI_PI] = Gr.i;
+                    mi[MI_PJ] = Gr.j;
+                    mi[MI_PP] = Gr.p;
+                    mi[MI_PQ] = Gr.q;
+                    if (Gr.type == 1) {
+                        mi[MI_PA] = (int)T.sa[Gr.base + got];
+                        mi[MI_PB] = -1;
+                    } else {
+                        const uint32_t ab = T.dab[Gr.base + got];
+                        mi[MI_PA] = (int)(ab & 0xFFFFu);
+                        mi[MI_PB] = (int)(ab >> 16);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+
+        // -------------------------------------------------------- update
+        const int ptype = mi[MI_PTYPE];
+        if (ptype != 0) {
+            const int i = mi[MI_PI], j = mi[MI_PJ], a = mi[MI_PA], b = mi[MI_PB], p = mi[MI_PP], q = mi[MI_PQ];
+            const double* Rp = R + p * n_so;
+            if (ptype == 1) {
+                const double rho = Rp[a];
+                for (int x = tid; x < ne; x += nt) w1[x] = (R[x * n_so + a] - (x == p ? 1.0 : 0.0)) / rho;
+                for (int a2 = tid; a2 < n_so; a2 += nt) cRp[a2] = Rp[a2];
+                for (int x = tid; x < ne; x += nt) cBp[x] = B[p * ne + x];
+                if (tid == 0 && fabs(rho) < 1e-8) mi[MI_ST] |= (int)VMC_ST_SMALLDEN;
+                __syncthreads();
+                for (int idx = tid; idx < n_so * ne; idx += nt) {
+                    const int x = idx / n_so, a2 = idx - x * n_so;
+                    R[idx] -= cRp[a2] * w1[x];
+                }
+                for (int idx = tid; idx < ne * ne; idx += nt) {
+                    const int x2 = idx / ne, x = idx - x2 * ne;
+                    B[idx] -= cBp[x] * w1[x2];
+                }
+            } else {
+                const double* Rq = R + q * n_so;
+                const double c00 = Rp[a], c01 = Rq[a], c10 = Rp[b], c11 = Rq[b];
+                const double det = c00 * c11 - c10 * c01;
+                for (int x = tid; x < ne; x += nt) {
+                    const double ra = R[x * n_so + a] - (x == p ? 1.0 : 0.0);
+                    const double rb = R[x * n_so + b] - (x == q ? 1.0 : 0.0);
+                    w1[x] = (c11 * ra - c01 * rb) / det;
+                    w2[x] = (-c10 * ra + c00 * rb) / det;
+                }
+                for (int a2 = tid; a2 < n_so; a2 += nt) {
+                    cRp[a2] = Rp[a2];
+                    cRq[a2] = Rq[a2];
+                }
+                for (int x = tid; x < ne; x += nt) {
+                    cBp[x] = B[p * ne + x];
+                    cBq[x] = B[q * ne + x];
+                }
+                if (tid == 0 && fabs(det) < 1e-8) mi[MI_ST] |= (int)VMC_ST_SMALLDEN;
+                __syncthreads();
+                for (int idx = tid; idx < n_so * ne; idx += nt) {
+                    const int x = idx / n_so, a2 = idx - x * n_so;
+                    R[idx] -= cRp[a2] * w1[x] + cRq[a2] * w2[x];
+                }
+                for (int idx = tid; idx < ne * ne; idx += nt) {
+                    const int x2 = idx / ne, x = idx - x2 * ne;
+                    B[idx] -= cBp[x] * w1[x2] + cBq[x] * w2[x2];
+                }
+            }
+            // Jastrow sums s_p += J_pa [p!=a] - J_pi [p!=i] (+ the same for b, j)
+            const double* Ja = T.J + (size_t)a * n_so;
+            const double* Ji = T.J + (size_t)i * n_so;
+            for (int pp = tid; pp < n_so; pp += nt) {
+                double d = (pp != a ? Ja[pp] : 0.0) - (pp != i ? Ji[pp] : 0.0);
+                if (ptype == 2) {
+                    const double* Jb = T.J + (size_t)b * n_so;
+                    const double* Jj = T.J + (size_t)j * n_so;
+                    d += (pp != b ? Jb[pp] : 0.0) - (pp != j ? Jj[pp] : 0.0);
+                }
+                s[pp] += d;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                occw[i >> 6] &= ~(1ull << (i & 63));
+                occw[a >> 6] |= (1ull << (a & 63));
+                oslot[i] = -1;
+                oslot[a] = p;
+                slot[p] = a;
+                if (ptype == 2) {
+                    occw[j >> 6] &= ~(1ull << (j & 63));
+                    occw[b >> 6] |= (1ull << (b & 63));
+                    oslot[j] = -1;
+                    oslot[b] = q;
+                    slot[q] = b;
+                }
+            }
+            code_last = pack_pick(ptype, i, j, a, b);
+            __syncthreads();
+        }
+        if (tid == 0) {
+            if (eloc_hist) eloc_hist[(size_t)k * W + w] = el;
+            if (t_hist) t_hist[(size_t)k * W + w] = tres;
+            if (pick_hist) pick_hist[(size_t)k * W + w] = code_last;
+        }
+        // ------------------------------------------------------- refresh
+        if (refresh_period > 0 && ((gstep + 1) % (uint64_t)refresh_period) == 0) {
+            refresh_state(T, slot, B, R, s, fcol, ipiv, mi, red);
+        }
+    }
+
+    // ---------------------------------------------------------- write back
+    __syncthreads();
+    if (mode != MODE_ELOC) {
+        for (int k = tid; k < nw; k += nt) S.occ[(size_t)w * nw + k] = occw[k];
+        for (int k = tid; k < ne; k += nt) S.slot_orb[(size_t)w * ne + k] = slot[k];
+        for (int pp = tid; pp < n_so; pp += nt) {
+            S.orb_slot[(size_t)w * n_so + pp] = oslot[pp];
+            S.s[(size_t)w * n_so + pp] = s[pp];
+        }
+        if (SMALL) {
+            double* Rg = S.R + (size_t)w * n_so * ne;
+            double* Bg = S.B + (size_t)w * ne * ne;
+            for (int k = tid; k < n_so * ne; k += nt) Rg[k] = R[k];
+            for (int k = tid; k < ne * ne; k += nt) Bg[k] = B[k];
+        }
+    }
+    if (tid == 0) {
+        S.hnn[w] = hnn;
+        S.status[w] = (uint32_t)mi[MI_ST];
+        if (mode != MODE_INIT) {
+            S.eloc[w] = el_last;
+            S.tres[w] = t_last;
+        }
+        if (mode == MODE_CTMC) S.pick[w] = code_last;
+        if (mode == MODE_INIT) S.pick[w] = 0;
+    }
+}
+
+// Canonical candidate list of one walker (single wave, groups in order).
+__global__ void __launch_bounds__(64) k_excitations(Tab T, Wk S, int64_t w, int32_t* ijab, double* hval, double* ratio,
+                                                    int64_t cap, int64_t* count) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int n_so = T.n_so, ne = T.ne, nw = T.nw, l = lane_id();
+    uint64_t* occw = (uint64_t*)smem;
+    int* occl = (int*)(smem + al16((size_t)nw * 8));
+    int* oslot = occl + ((ne + 3) & ~3);
+    double* es = (double*)(smem + al16((size_t)nw * 8) + al16((size_t)ne * 4) + al16((size_t)n_so * 4));
+    double* ies = es + n_so;
+    uint32_t* queue = (uint32_t*)(ies + n_so);
+    for (int k = l; k < nw; k += 64) occw[k] = S.occ[(size_t)w * nw + k];
+    for (int pp = l; pp < n_so; pp += 64) {
+        oslot[pp] = S.orb_slot[(size_t)w * n_so + pp];
+        const double sv = S.s[(size_t)w * n_so + pp];
+        es[pp] = exp(sv);
+        ies[pp] = exp(-sv);
+    }
+    __syncthreads();
+    for (int pp = l; pp < n_so; pp += 64)
+        if (oslot[pp] >= 0) {
+            int rank = 0;
+            for (int q = 0; q < (pp >> 6); ++q) rank += __popcll(occw[q]);
+            rank += __popcll(occw[pp >> 6] & ((1ull << (pp & 63)) - 1ull));
+            occl[rank] = pp;
+        }
+    __syncthreads();
+    const double* R = S.R + (size_t)w * n_so * ne;
+    int64_t off = 0;
+    for (int g = 0; g < T.G; ++g) {
+        const Group Gr = group_of(T, g, occl, oslot, ies);
+        auto ev = [&](uint32_t e, bool act) -> bool {
+            if (act) {
+                const int64_t pos = off + l;
+                int a, b = -1;
+                double r, h;
+                if (Gr.type == 1) {
+                    r = single_ratio(T, Gr, e, R, es, a);
+                    h = single_h(T, Gr, e, occl);
+                } else {
+                    r = double_ratio(T, Gr, e, R, es, a, b);
+                    h = T.dv[Gr.base + e];
+                }
+                if (pos < cap) {
+                    ijab[5 * pos + 0] = Gr.type;
+                    ijab[5 * pos + 1] = Gr.i;
+                    ijab[5 * pos + 2] = Gr.j;
+                    ijab[5 * pos + 3] = a;
+                    ijab[5 * pos + 4] = b;
+                    hval[pos] = h;
+                    ratio[pos] = r;
+                }
+            }
+            off += __popcll(__ballot(act));
+            return false;
+        };
+        if (Gr.type == 1) scan_group<false>(T, OccLds{occw}, Gr.base, Gr.len, queue, ev);
+        else scan_group<true>(T, OccLds{occw}, Gr.base, Gr.len, queue, ev);
+    }
+    if (l == 0) count[0] = off;
+}
+
+// ------------------------------------------------------------ parameters
+__global__ void k_dense_J(const double* Jp, double* J, int n_so) {
+    const int p = blockIdx.x;
+    const int64_t start = (int64_t)p * n_so - (int64_t)p * (p - 1) / 2;
+    for (int q = p + threadIdx.x; q < n_so; q += blockDim.x) {
+        const double v = Jp[start + (q - p)];
+        J[(size_t)p * n_so + q] = v;
+        J[(size_t)q * n_so + p] = v;
+    }
+}
+
+// exp(J_aa + J_bb + J_ab - J_ii - J_jj + J_ij - J_ai - J_aj - J_bi - J_bj) per doubles entry
+__global__ void k_doubles_K(const uint32_t* row_off, const uint32_t* dab, const double* J, double* dK, int n_so) {
+    const int row = blockIdx.x;
+    const int i = row / n_so, j = row - i * n_so;
+    if (j <= i) return;
+    const uint32_t b0 = row_off[row], b1 = row_off[row + 1];
+    const double* Ji = J + (size_t)i * n_so;
+    const double* Jj = J + (size_t)j * n_so;
+    for (uint32_t e = b0 + threadIdx.x; e < b1; e += blockDim.x) {
+        const uint32_t ab = dab[e];
+        const int a = (int)(ab & 0xFFFFu), b = (int)(ab >> 16);
+        const double* Ja = J + (size_t)a * n_so;
+        const double* Jb = J + (size_t)b * n_so;
+        const double kap = Ja[a] + Jb[b] + Ja[b] - Ji[i] - Jj[j] + Ji[j] - Ja[i] - Ja[j] - Jb[i] - Jb[j];
+        dK[e] = exp(kap);
+    }
+}
+
+// exp(J_aa - J_ii - J_ai) per singles entry
+__global__ void k_singles_K(const uint32_t* s_off, const uint32_t* sa, const double* J, double* sK, int n_so) {
+    const int i = blockIdx.x;
+    const double* Ji = J + (size_t)i * n_so;
+    for (uint32_t e = s_off[i] + threadIdx.x; e < s_off[i + 1]; e += blockDim.x) {
+        const int a = (int)sa[e];
+        sK[e] = exp(J[(size_t)a * n_so + a] - Ji[i] - Ji[a]);
+    }
+}
+
+__global__ void k_uniforms(uint64_t seed, int64_t n, uint64_t step, double* out) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) out[k] = ctmc_uniform(seed, (uint64_t)k, step);
+}
+
+// ------------------------------------------------------------ gradient ratios
+__global__ void k_logderiv_dense(Tab T, Wk S, double* out, int64_t n_p) {
+    const int64_t w = blockIdx.x;
+    const int n_so = T.n_so, ne = T.ne, nw = T.nw;
+    const uint64_t* occ = S.occ + (size_t)w * nw;
+    double* o = out + (size_t)w * n_p;
+    for (int p = threadIdx.x; p < n_so; p += blockDim.x) {
+        const int64_t start = (int64_t)p * n_so - (int64_t)p * (p - 1) / 2;
+        const bool np = (occ[p >> 6] >> (p & 63)) & 1ull;
+        for (int q = p; q < n_so; ++q) {
+            const bool nq = (occ[q >> 6] >> (q & 63)) & 1ull;
+            o[start + (q - p)] = (np && nq) ? 1.0 : 0.0;
+        }
+    }
+    const int64_t nj = (int64_t)n_so * (n_so + 1) / 2;
+    const double* B = S.B + (size_t)w * ne * ne;
+    const int32_t* oslot = S.orb_slot + (size_t)w * n_so;
+    for (int64_t idx = threadIdx.x; idx < (int64_t)n_so * n_so; idx += blockDim.x) {
+        const int k = (int)(idx / n_so), x = (int)(idx - (int64_t)k * n_so);
+        const int sl = oslot[k];
+        o[nj + idx] = (sl >= 0 && x < ne) ? B[(size_t)sl * ne + x] : 0.0;
+    }
+}
+
+// Jastrow part of G = sum_w g_w O_w: G[p<=q] = sum_w g_w n_p n_q, split over
+// nsplit walker ranges (partials combined in a fixed order afterwards).
+__global__ void k_grad_J(Tab T, Wk S, int64_t W, const double* g, double* part, int64_t n_p, int nsplit) {
+    const int p = blockIdx.x, sp = blockIdx.y;
+    const int n_so = T.n_so, nw = T.nw;
+    const int64_t w0 = W * sp / nsplit, w1 = W * (sp + 1) / nsplit;
+    const int64_t start = (int64_t)p * n_so - (int64_t)p * (p - 1) / 2;
+    for (int q = p + threadIdx.x; q < n_so; q += blockDim.x) {
+        double acc = 0.0;
+        for (int64_t w = w0; w < w1; ++w) {
+            const uint64_t* occ = S.occ + (size_t)w * nw;
+            if (((occ[p >> 6] >> (p & 63)) & 1ull) && ((occ[q >> 6] >> (q & 63)) & 1ull)) acc += g[w];
+        }
+        part[(size_t)sp * n_p + start + (q - p)] = acc;
+    }
+}
+
+// Orbital part: G[k][x] = sum_w g_w B_w[x][slot_w(k)] for occupied k, x < Ne.
+__global__ void k_grad_theta(Tab T, Wk S, int64_t W, const double* g, double* part, int64_t n_p, int nsplit) {
+    const int k = blockIdx.x, sp = blockIdx.y;
+    const int n_so = T.n_so, ne = T.ne;
+    const int64_t w0 = W * sp / nsplit, w1 = W * (sp + 1) / nsplit;
+    const int64_t nj = (int64_t)n_so * (n_so + 1) / 2;
+    for (int x = threadIdx.x; x < n_so; x += blockDim.x) {
+        double acc = 0.0;
+        if (x < ne)
+            for (int64_t w = w0; w < w1; ++w) {
+                const int sl = S.orb_slot[(size_t)w * n_so + k];
+                if (sl >= 0) acc += g[w] * S.B[(size_t)w * ne * ne + (size_t)sl * ne + x];
+            }
+        part[(size_t)sp * n_p + nj + (size_t)k * n_so + x] = acc;
+    }
+}
+
+__global__ void k_combine(const double* part, double* out, int64_t n_p, int nsplit) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_p) return;
+    double acc = 0.0;
+    for (int sp = 0; sp < nsplit; ++sp) acc += part[(size_t)sp * n_p + k];
+    out[k] = acc;
+}
+
+__global__ void k_amsgrad(int64_t n, double* p, double* m, double* v, double* vh, const double* g, double lr, double b1,
+                          double b2, double delta, int literal) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double gk = g[k];
+    const double mk = b1 * m[k] + (1.0 - b1) * gk;
+    double vhk;
+    if (literal) {
+        vhk = fmax(vh[k], b2 * vh[k] + (1.0 - b2) * gk * gk);
+    } else {
+        const double vk = b2 * v[k] + (1.0 - b2) * gk * gk;
+        v[k] = vk;
+        vhk = fmax(vh[k], vk);
+    }
+    m[k] = mk;
+    vh[k] = vhk;
+    p[k] -= lr * mk / (sqrt(vhk) + delta);
+}
+
+}  // namespace
+
+// =============================================================================
+// Host side
+// =============================================================================
+struct vmc_ctx {
+    int n = 0, n_so = 0, na = 0, nb = 0, ne = 0, nw = 0, G = 0, precision = 0, refresh = 50;
+    uint64_t seed = 0;
+    double eps = 0.0;
+    int device = 0;
+    int block_threads = 0;  // 0 = automatic
+    int64_t n_dent = 0, n_sent = 0;
+    uint32_t *d_row_off = nullptr, *d_dab = nullptr, *d_s_off = nullptr, *d_sa = nullptr;
+    double *d_dv = nullptr, *d_dK = nullptr, *d_sh = nullptr, *d_sV = nullptr, *d_sK = nullptr, *d_D = nullptr,
+           *d_hdiag = nullptr, *d_J = nullptr, *d_theta = nullptr, *d_part = nullptr;
+    int64_t part_cap = 0;
+    bool params_set = false;
+    std::string err;
+};
+
+struct vmc_host_tables {
+    vmc::HostTables t;
+};
+
+namespace {
+thread_local std::string g_err;
+
+vmc_status fail(vmc_ctx* h, vmc_status st, const std::string& msg) {
+    if (h) h->err = msg;
+    g_err = msg;
+    return st;
+}
+
+#define HIP_OR_FAIL(h, call)                                                                             \
+    do {                                                                                                 \
+        hipError_t e_ = (call);                                                                          \
+        if (e_ != hipSuccess) return fail((h), VMC_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+Tab make_tab(const vmc_ctx* h) {
+    Tab T;
+    T.n_so = h->n_so;
+    T.ne = h->ne;
+    T.nw = h->nw;
+    T.G = h->G;
+    T.eps = h->eps;
+    T.row_off = h->d_row_off;
+    T.dab = h->d_dab;
+    T.dv = h->d_dv;
+    T.dK = h->d_dK;
+    T.s_off = h->d_s_off;
+    T.sa = h->d_sa;
+    T.sh = h->d_sh;
+    T.sV = h->d_sV;
+    T.sK = h->d_sK;
+    T.D = h->d_D;
+    T.hdiag = h->d_hdiag;
+    T.J = h->d_J;
+    T.theta = h->d_theta;
+    return T;
+}
+
+int64_t scratch_bytes(const vmc_ctx* h) { return (int64_t)al16((size_t)h->G * 8); }
+
+vmc_status check_walkers(vmc_ctx* h, const vmc_walkers* w) {
+    if (!w) return fail(h, VMC_E_ARG, "walkers is NULL");
+    if (w->n_walkers <= 0 || w->n_walkers > (int64_t)INT_MAX) return fail(h, VMC_E_ARG, "n_walkers out of range");
+    if (!w->occ_bits || !w->slot_orb || !w->orb_slot || !w->ainv || !w->r || !w->jsum || !w->hnn || !w->eloc ||
+        !w->tres || !w->pick || !w->status || !w->scratch)
+        return fail(h, VMC_E_ARG, "a walker field pointer is NULL");
+    if (!h->params_set) return fail(h, VMC_E_ARG, "vmc_set_params has not been called");
+    return VMC_OK;
+}
+
+Wk make_wk(const vmc_ctx* h, const vmc_walkers* w) {
+    Wk S;
+    S.occ = (uint64_t*)w->occ_bits;
+    S.slot_orb = (int32_t*)w->slot_orb;
+    S.orb_slot = (int32_t*)w->orb_slot;
+    S.B = (double*)w->ainv;
+    S.R = (double*)w->r;
+    S.s = (double*)w->jsum;
+    S.hnn = (double*)w->hnn;
+    S.eloc = (double*)w->eloc;
+    S.tres = (double*)w->tres;
+    S.pick = (int64_t*)w->pick;
+    S.status = (uint32_t*)w->status;
+    S.scratch = (uint8_t*)w->scratch;
+    S.scratch_stride = scratch_bytes(h);
+    return S;
+}
+
+constexpr size_t kMaxLds = 64 * 1024;
+
+vmc_status launch_sweep(vmc_ctx* h, vmc_walkers* w, int mode, int n_steps, double* eh, double* th, int64_t* ph,
+                        hipStream_t st) {
+    int nt = h->block_threads;
+    if (nt <= 0) nt = (h->ne <= 32) ? 128 : 256;
+    bool small = lds_layout(h->n_so, h->ne, h->nw, h->G, nt, true).total <= kMaxLds;
+    const size_t lds = lds_layout(h->n_so, h->ne, h->nw, h->G, nt, small).total;
+    if (lds > kMaxLds) return fail(h, VMC_E_UNSUPPORTED, "system too large for the per-walker LDS budget");
+    const bool nw1 = (h->nw == 1);
+    const Tab T = make_tab(h);
+    const Wk S = make_wk(h, w);
+    const dim3 grid((unsigned)w->n_walkers), block((unsigned)nt);
+    if (nw1 && small)
+        hipLaunchKernelGGL((k_sweep<true, true>), grid, block, lds, st, T, S, w->n_walkers, mode, n_steps, w->step,
+                           h->seed, h->refresh, eh, th, ph);
+    else if (nw1)
+        hipLaunchKernelGGL((k_sweep<true, false>), grid, block, lds, st, T, S, w->n_walkers, mode, n_steps, w->step,
+                           h->seed, h->refresh, eh, th, ph);
+    else if (small)
+        hipLaunchKernelGGL((k_sweep<false, true>), grid, block, lds, st, T, S, w->n_walkers, mode, n_steps, w->step,
+                           h->seed, h->refresh, eh, th, ph);
+    else
+        hipLaunchKernelGGL((k_sweep<false, false>), grid, block, lds, st, T, S, w->n_walkers, mode, n_steps, w->step,
+                           h->seed, h->refresh, eh, th, ph);
+    HIP_OR_FAIL(h, hipGetLastError());
+    return VMC_OK;
+}
+
+template <class T>
+vmc_status upload(vmc_ctx* h, T** dst, const std::vector<T>& src, hipStream_t st) {
+    const size_t bytes = std::max<size_t>(src.size(), 1) * sizeof(T);
+    if (hipMalloc((void**)dst, bytes) != hipSuccess) return fail(h, VMC_E_OOM, "hipMalloc failed for a table");
+    if (!src.empty()) HIP_OR_FAIL(h, hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    return VMC_OK;
+}
+
+void free_ctx(vmc_ctx* h) {
+    if (!h) return;
+    void* ptrs[] = {h->d_row_off, h->d_dab, h->d_s_off, h->d_sa, h->d_dv, h->d_dK, h->d_sh, h->d_sV,
+                    h->d_sK,      h->d_D,   h->d_hdiag, h->d_J,  h->d_theta, h->d_part};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    delete h;
+}
+
+vmc_status validate_desc(const vmc_system_desc* d) {
+    if (!d) return fail(nullptr, VMC_E_ARG, "desc is NULL");
+    if (d->n_orb <= 0 || 2 * d->n_orb > 1024) return fail(nullptr, VMC_E_ARG, "n_orb must be in 1..512");
+    if (d->n_alpha < 0 || d->n_beta < 0 || d->n_alpha > d->n_orb || d->n_beta > d->n_orb ||
+        d->n_alpha + d->n_beta < 1)
+        return fail(nullptr, VMC_E_ARG, "electron counts out of range");
+    if (d->n_alpha + d->n_beta > 2 * d->n_orb - 1)
+        return fail(nullptr, VMC_E_ARG, "at least one empty spin-orbital is required");
+    if (d->precision != VMC_FP64) return fail(nullptr, VMC_E_UNSUPPORTED, "only VMC_FP64 is supported by this build");
+    if (d->refresh_period < 1) return fail(nullptr, VMC_E_ARG, "refresh_period must be >= 1");
+    if (d->reserved != 0) return fail(nullptr, VMC_E_ARG, "reserved must be 0");
+    return VMC_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+extern "C" {
+
+const char* vmc_last_error(vmc_handle h) { return h ? h->err.c_str() : g_err.c_str(); }
+
+void vmc_decode_pick(int64_t code, int32_t out5[5]) {
+    if (!out5) return;
+    const int type = (int)(code >> 48);
+    out5[0] = type;
+    if (type == 0) {
+        out5[1] = out5[2] = out5[3] = out5[4] = -1;
+        return;
+    }
+    out5[1] = (int)((code >> 36) & 0xFFF);
+    out5[2] = (type == 2) ? (int)((code >> 24) & 0xFFF) : -1;
+    out5[3] = (int)((code >> 12) & 0xFFF);
+    out5[4] = (type == 2) ? (int)(code & 0xFFF) : -1;
+}
+
+vmc_status vmc_host_tables_build(const vmc_system_desc* desc, const double* h1, const vmc_eri_list* eri, double eps,
+                                 vmc_host_tables** out) {
+    if (!out) return fail(nullptr, VMC_E_ARG, "out is NULL");
+    *out = nullptr;
+    vmc_status st = validate_desc(desc);
+    if (st != VMC_OK) return st;
+    if (!eri) return fail(nullptr, VMC_E_ARG, "eri list is NULL");
+    vmc_host_tables* t = new vmc_host_tables;
+    const std::string e =
+        build_host_tables(desc->n_orb, desc->n_alpha, desc->n_beta, h1, eri->n_nz, eri->pqrs, eri->val, eps, t->t);
+    if (!e.empty()) {
+        delete t;
+        return fail(nullptr, VMC_E_ARG, e);
+    }
+    *out = t;
+    return VMC_OK;
+}
+
+vmc_status vmc_host_tables_sizes(const vmc_host_tables* t, int64_t out[2]) {
+    if (!t || !out) return fail(nullptr, VMC_E_ARG, "NULL argument");
+    out[0] = (int64_t)t->t.dv.size();
+    out[1] = (int64_t)t->t.sa.size();
+    return VMC_OK;
+}
+
+vmc_status vmc_host_tables_get(const vmc_host_tables* t, int64_t* row_off, int32_t* dab, double* dv, int64_t* s_off,
+                               int32_t* sa, double* sS, double* sh) {
+    if (!t) return fail(nullptr, VMC_E_ARG, "tables is NULL");
+    const auto& T = t->t;
+    if (row_off) std::memcpy(row_off, T.row_off.data(), T.row_off.size() * sizeof(int64_t));
+    if (dab) std::memcpy(dab, T.dab.data(), T.dab.size() * sizeof(int32_t));
+    if (dv) std::memcpy(dv, T.dv.data(), T.dv.size() * sizeof(double));
+    if (s_off) std::memcpy(s_off, T.s_off.data(), T.s_off.size() * sizeof(int64_t));
+    if (sa) std::memcpy(sa, T.sa.data(), T.sa.size() * sizeof(int32_t));
+    if (sS) std::memcpy(sS, T.sS.data(), T.sS.size() * sizeof(double));
+    if (sh) std::memcpy(sh, T.sh.data(), T.sh.size() * sizeof(double));
+    return VMC_OK;
+}
+
+void vmc_host_tables_free(vmc_host_tables* t) { delete t; }
+
+vmc_status vmc_init(const vmc_system_desc* desc, const double* h1, const vmc_eri_list* eri, double eps,
+                    hipStream_t stream, vmc_handle* out) {
+    if (!out) return fail(nullptr, VMC_E_ARG, "out is NULL");
+    *out = nullptr;
+    vmc_status st = validate_desc(desc);
+    if (st != VMC_OK) return st;
+    if (!eri) return fail(nullptr, VMC_E_ARG, "eri list is NULL");
+    vmc::HostTables T;
+    const std::string e =
+        build_host_tables(desc->n_orb, desc->n_alpha, desc->n_beta, h1, eri->n_nz, eri->pqrs, eri->val, eps, T);
+    if (!e.empty()) return fail(nullptr, VMC_E_ARG, e);
+    if (T.dv.size() >= (size_t)UINT32_MAX || T.sa.size() >= (size_t)UINT32_MAX)
+        return fail(nullptr, VMC_E_UNSUPPORTED, "table larger than 2^32 entries");
+    vmc_ctx* h = new vmc_ctx;
+    h->n = desc->n_orb;
+    h->n_so = 2 * h->n;
+    h->na = desc->n_alpha;
+    h->nb = desc->n_beta;
+    h->ne = h->na + h->nb;
+    h->nw = (h->n_so + 63) / 64;
+    h->G = h->ne + h->ne * (h->ne - 1) / 2;
+    h->precision = desc->precision;
+    h->refresh = desc->refresh_period;
+    h->seed = desc->seed;
+    h->eps = eps;
+    h->n_dent = (int64_t)T.dv.size();
+    h->n_sent = (int64_t)T.sa.size();
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        free_ctx(h);
+        return fail(nullptr, VMC_E_HIP, "hipGetDevice failed");
+    }
+    std::vector<uint32_t> row_off(T.row_off.begin(), T.row_off.end());
+    std::vector<uint32_t> dab(T.dv.size());
+    for (size_t k = 0; k < T.dv.size(); ++k) dab[k] = (uint32_t)T.dab[2 * k] | ((uint32_t)T.dab[2 * k + 1] << 16);
+    std::vector<uint32_t> s_off(T.s_off.begin(), T.s_off.end());
+    std::vector<uint32_t> sa(T.sa.begin(), T.sa.end());
+    std::vector<double> zerosd(T.dv.size(), 0.0), zeross(T.sa.size(), 0.0);
+    vmc_status u = VMC_OK;
+    if ((u = upload(h, &h->d_row_off, row_off, stream)) != VMC_OK ||
+        (u = upload(h, &h->d_dab, dab, stream)) != VMC_OK || (u = upload(h, &h->d_dv, T.dv, stream)) != VMC_OK ||
+        (u = upload(h, &h->d_dK, zerosd, stream)) != VMC_OK || (u = upload(h, &h->d_s_off, s_off, stream)) != VMC_OK ||
+        (u = upload(h, &h->d_sa, sa, stream)) != VMC_OK || (u = upload(h, &h->d_sh, T.sh, stream)) != VMC_OK ||
+        (u = upload(h, &h->d_sV, T.sV, stream)) != VMC_OK || (u = upload(h, &h->d_sK, zeross, stream)) != VMC_OK ||
+        (u = upload(h, &h->d_D, T.D, stream)) != VMC_OK || (u = upload(h, &h->d_hdiag, T.hdiag, stream)) != VMC_OK) {
+        std::string msg = h->err;
+        free_ctx(h);
+        return fail(nullptr, u, msg);
+    }
+    if (hipMalloc((void**)&h->d_J, sizeof(double) * h->n_so * h->n_so) != hipSuccess ||
+        hipMalloc((void**)&h->d_theta, sizeof(double) * h->n_so * h->n_so) != hipSuccess) {
+        free_ctx(h);
+        return fail(nullptr, VMC_E_OOM, "hipMalloc failed for parameters");
+    }
+    if (hipStreamSynchronize(stream) != hipSuccess) {
+        free_ctx(h);
+        return fail(nullptr, VMC_E_HIP, "table upload failed");
+    }
+    *out = h;
+    return VMC_OK;
+}
+
+vmc_status vmc_set_params(vmc_handle h, const double* J_dev, const double* theta_dev, hipStream_t st) {
+    if (!h) return fail(nullptr, VMC_E_ARG, "handle is NULL");
+    if (!J_dev || !theta_dev) return fail(h, VMC_E_ARG, "parameter pointer is NULL");
+    const int n_so = h->n_so;
+    HIP_OR_FAIL(h, hipMemcpyAsync(h->d_theta, theta_dev, sizeof(double) * n_so * n_so, hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_dense_J, dim3(n_so), dim3(256), 0, st, J_dev, h->d_J, n_so);
+    HIP_OR_FAIL(h, hipGetLastError());
+    if (h->n_dent > 0) {
+        hipLaunchKernelGGL(k_doubles_K, dim3(n_so * n_so), dim3(64), 0, st, h->d_row_off, h->d_dab, h->d_J, h->d_dK,
+                           n_so);
+        HIP_OR_FAIL(h, hipGetLastError());
+    }
+    if (h->n_sent > 0) {
+        hipLaunchKernelGGL(k_singles_K, dim3(n_so), dim3(64), 0, st, h->d_s_off, h->d_sa, h->d_J, h->d_sK, n_so);
+        HIP_OR_FAIL(h, hipGetLastError());
+    }
+    h->params_set = true;
+    return VMC_OK;
+}
+
+vmc_status vmc_walker_bytes(vmc_handle h, int64_t W, size_t fb[VMC_NFIELDS]) {
+    if (!h) return fail(nullptr, VMC_E_ARG, "handle is NULL");
+    if (!fb || W <= 0) return fail(h, VMC_E_ARG, "bad arguments");
+    const size_t w = (size_t)W;
+    fb[VMC_F_OCC] = w * h->nw * 8;
+    fb[VMC_F_SLOT_ORB] = w * h->ne * 4;
+    fb[VMC_F_ORB_SLOT] = w * h->n_so * 4;
+    fb[VMC_F_AINV] = w * h->ne * h->ne * 8;
+    fb[VMC_F_R] = w * h->ne * h->n_so * 8;
+    fb[VMC_F_JSUM] = w * h->n_so * 8;
+    fb[VMC_F_HNN] = w * 8;
+    fb[VMC_F_ELOC] = w * 8;
+    fb[VMC_F_TRES] = w * 8;
+    fb[VMC_F_PICK] = w * 8;
+    fb[VMC_F_STATUS] = w * 4;
+    fb[VMC_F_SCRATCH] = w * (size_t)scratch_bytes(h);
+    return VMC_OK;
+}
+
+vmc_status vmc_walkers_init(vmc_handle h, vmc_walkers* w, hipStream_t st) {
+    if (!h) return fail(nullptr, VMC_E_ARG, "handle is NULL");
+    vmc_status s = check_walkers(h, w);
+    if (s != VMC_OK) return s;
+    return launch_sweep(h, w, MODE_INIT, 1, nullptr, nullptr, nullptr, st);
+}
+
+vmc_status vmc_local_energy(vmc_handle h, vmc_walkers* w, hipStream_t st) {
+    if (!h) return fail(nullptr, VMC_E_ARG, "handle is NULL");
+    vmc_status s = check_walkers(h, w);
+    if (s != VMC_OK) return s;
+    return launch_sweep(h, w, MODE_ELOC, 1, nullptr, nullptr, nullptr, st);
+}
+
+vmc_status vmc_ctmc_step(vmc_handle h, vmc_walkers* w, int32_t n_steps, double* eh, double* th, int64_t* ph,
+                         hipStream_t st) {
+    if (!h) return fail(nullptr, VMC_E_ARG, "handle is NULL");
+    vmc_status s = check_walkers(h, w);
+    if (s != VMC_OK) return s;
+    if (n_steps < 0) return fail(h, VMC_E_ARG, "n_steps must be >= 0");
+    if (n_steps == 0) return VMC_OK;
+    s = launch_sweep(h, w, MODE_CTMC, n_steps, eh, th, ph, st);
+    if (s == VMC_OK) w->step += (uint64_t)n_steps;
+    return s;
+}
+
+vmc_status vmc_excitations(vmc_handle h, const vmc_walkers* w, int64_t walker, int32_t* ijab, double* hval,
+                           double* ratio, int64_t cap, int64_t* count, hipStream_t st) {
+    if (!h) return fail(nullptr, VMC_E_ARG, "handle is NULL");
+    vmc_status s = check_walkers(h, w);
+    if (s != VMC_OK) return s;
+    if (walker < 0 || walker >= w->n_walkers) return fail(h, VMC_E_ARG, "walker index out of range");
+    if (!count || cap < 0 || (cap > 0 && (!ijab || !hval || !ratio))) return fail(h, VMC_E_ARG, "bad output buffers");
+    const size_t lds = al16((size_t)h->nw * 8) + al16((size_t)h->ne * 4) + al16((size_t)h->n_so * 4) +
+                       2 * (size_t)h->n_so * 8 + (size_t)kQueue * 4;
+    hipLaunchKernelGGL(k_excitations, dim3(1), dim3(64), lds, st, make_tab(h), make_wk(h, w), walker, ijab, hval,
+                       ratio, cap, count);
+    HIP_OR_FAIL(h, hipGetLastError());
+    return VMC_OK;
+}
+
+vmc_status vmc_uniforms(uint64_t seed, int64_t n, uint64_t step, double* out, hipStream_t st) {
+    if (n <= 0 || !out) return fail(nullptr, VMC_E_ARG, "bad arguments");
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_uniforms, dim3((unsigned)blocks), dim3(256), 0, st, seed, n, step, out);
+    HIP_OR_FAIL(nullptr, hipGetLastError());
+    return VMC_OK;
+}
+
+vmc_status vmc_logderiv(vmc_handle h, const vmc_walkers* w, const double* g, double* out, hipStream_t st) {
+    if (!h) return fail(nullptr, VMC_E_ARG, "handle is NULL");
+    vmc_status s = check_walkers(h, w);
+    if (s != VMC_OK) return s;
+    if (!out) return fail(h, VMC_E_ARG, "out is NULL");
+    const int64_t n_p = (int64_t)h->n_so * (h->n_so + 1) / 2 + (int64_t)h->n_so * h->n_so;
+    const Tab T = make_tab(h);
+    const Wk S = make_wk(h, w);
+    if (!g) {
+        hipLaunchKernelGGL(k_logderiv_dense, dim3((unsigned)w->n_walkers), dim3(256), 0, st, T, S, out, n_p);
+        HIP_OR_FAIL(h, hipGetLastError());
+        return VMC_OK;
+    }
+    const int nsplit = 16;
+    if (h->part_cap < n_p * nsplit) {
+        if (h->d_part) (void)hipFree(h->d_part);
+        h->d_part = nullptr;
+        h->part_cap = 0;
+        if (hipMalloc((void**)&h->d_part, sizeof(double) * n_p * nsplit) != hipSuccess)
+            return fail(h, VMC_E_OOM, "hipMalloc failed for gradient partials");
+        h->part_cap = n_p * nsplit;
+    }
+    hipLaunchKernelGGL(k_grad_J, dim3(h->n_so, nsplit), dim3(64), 0, st, T, S, w->n_walkers, g, h->d_part, n_p, nsplit);
+    HIP_OR_FAIL(h, hipGetLastError());
+    hipLaunchKernelGGL(k_grad_theta, dim3(h->n_so, nsplit), dim3(64), 0, st, T, S, w->n_walkers, g, h->d_part, n_p,
+                       nsplit);
+    HIP_OR_FAIL(h, hipGetLastError());
+    hipLaunchKernelGGL(k_combine, dim3((unsigned)((n_p + 255) / 256)), dim3(256), 0, st, h->d_part, out, n_p, nsplit);
+    HIP_OR_FAIL(h, hipGetLastError());
+    return VMC_OK;
+}
+
+vmc_status vmc_amsgrad(int64_t n, double* p, double* m, double* v, double* vh, const double* g, double lr, double b1,
+                       double b2, double delta, int32_t literal, hipStream_t st) {
+    if (n <= 0 || !p || !m || !v || !vh || !g) return fail(nullptr, VMC_E_ARG, "bad arguments");
+    hipLaunchKernelGGL(k_amsgrad, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, p, m, v, vh, g, lr, b1, b2,
+                       delta, (int)literal);
+    HIP_OR_FAIL(nullptr, hipGetLastError());
+    return VMC_OK;
+}
+
+vmc_status vmc_table_info(vmc_handle h, int64_t out[3]) {
+    if (!h || !out) return fail(h, VMC_E_ARG, "NULL argument");
+    out[0] = h->n_dent;
+    out[1] = h->n_sent;
+    out[2] = h->G;
+    return VMC_OK;
+}
+
+vmc_status vmc_destroy(vmc_handle h) {
+    if (!h) return fail(nullptr, VMC_E_ARG, "handle is NULL");
+    free_ctx(h);
+    return VMC_OK;
+}
+
+}  // extern "C"
