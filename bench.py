@@ -71,9 +71,7 @@ def main():
     wl = make_config(args.config, n_walkers=args.walkers)
     sysm = vmc.System.from_workload(wl, refresh_period=args.sweep)
     if args.threads:
-        lib = vmc.load_library()
-        if hasattr(lib, "vmc_set_block_threads"):
-            lib.vmc_set_block_threads(sysm.handle, args.threads)
+        vmc.vmc_set_launch(sysm.handle, args.threads)
     walkers = sysm.walkers(wl.occ)
     W, S = args.walkers, args.sweep
     nj = sysm.n_so * (sysm.n_so + 1) // 2

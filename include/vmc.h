@@ -200,6 +200,13 @@ vmc_status vmc_uniforms(uint64_t seed, int64_t n, uint64_t step, double* out_dev
 /* Decode a packed pick: type (0 = no move, 1 single, 2 double), i, j, a, b. */
 void vmc_decode_pick(int64_t code, int32_t out5[5]);
 
+/* Launch shape of the sweep kernels: threads per walker workgroup (a multiple
+ * of 64 in 64..512), or 0 for the library's choice.  Host-only; affects
+ * subsequent calls on h.  Results do not depend on it except for the order of
+ * floating-point sums (E_L and T change at rounding level; picks can change
+ * only within that rounding of a cumulative-rate boundary). */
+vmc_status vmc_set_launch(vmc_handle h, int32_t block_threads);
+
 /* Table sizes: out[0] = double entries, out[1] = single entries, out[2] = groups
  * per walker (Ne + Ne(Ne-1)/2). */
 vmc_status vmc_table_info(vmc_handle h, int64_t out[3]);

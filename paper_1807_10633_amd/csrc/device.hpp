@@ -17,8 +17,8 @@ struct Tab {
     double eps;
     const uint32_t* row_off;  // n_so*n_so + 1
     const uint32_t* dab;      // a | b << 16
-    const double* dv;         // <ab||ij>
-    const double* dK;         // exp(Jastrow constant part) per doubles entry
+    const uint64_t* dmask;    // (1 << a) | (1 << b) per doubles entry when n_so <= 64, else null
+    const double* dvK;        // per doubles entry: <ab||ij>, then exp(Jastrow constant part)
     const uint32_t* s_off;    // n_so + 1
     const uint32_t* sa;       // target orbital a
     const double* sh;         // h_ia

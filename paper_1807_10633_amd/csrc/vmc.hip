@@ -163,7 +163,7 @@ __device__ __forceinline__ double double_ratio(const Tab& T, const Group& Gr, ui
     const double* Rp = R + Gr.p * T.n_so;
     const double* Rq = R + Gr.q * T.n_so;
     const double det = Rp[a] * Rq[b] - Rp[b] * Rq[a];
-    return det * es[a] * es[b] * T.dK[Gr.base + e] * Gr.fac;
+    return det * es[a] * es[b] * T.dvK[2 * (size_t)(Gr.base + e) + 1] * Gr.fac;
 }
 
 // Block-wide deterministic sum (every thread gets the same value).
@@ -179,54 +179,87 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 }
 
 // --------------------------------------------------------------- LDS layout
+constexpr int kLogS = 32;   // batch-log entries per wave, singles stream
+constexpr int kLogD = 64;   // batch-log entries per wave, doubles stream
+constexpr int kLogGran = 2; // initial batches per log entry
+constexpr int kUnroll = 4;  // 64-entry chunks whose table loads are issued together
+
 struct Lds {
-    size_t occw, occl, slot, oslot, s, es, ies, red, csum, mi, md, queues, w1, w2, cRp, cRq, cBp, cBq, ipiv, fcol, R,
-        B, gsum, total;
+    uint32_t occw, occl, slot, oslot, s, es, ies, red, stmp, mi, md, wst, wtot, q64, qab, lsum, loff, lg, sgend, sdelta,
+        svend, spq, sfac, dgend, ddelta, dvend, dpq, dfac, w1, w2, cRp, cRq, cBp, cBq, ipiv, fcol, R, B, Rh, total;
 };
 __host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~(size_t)15; }
-__host__ __device__ inline Lds lds_layout(int n_so, int ne, int nw, int G, int nt, bool small) {
+// bytes of the doubles group descriptors (padded stream end, offset delta,
+// valid end, slots, Jastrow factor) for one walker
+__host__ __device__ inline size_t desc_bytes(int ne) {
+    const size_t gd = (size_t)ne * (ne - 1) / 2;
+    return al16(gd * 4) * 4 + al16(gd * 8);
+}
+__host__ __device__ __forceinline__ Lds lds_layout(int n_so, int ne, int nw, int nt, bool small) {
     Lds L;
     size_t o = 0;
     const int nwv = nt / 64;
-    L.occw = o; o += al16((size_t)nw * 8);
-    L.occl = o; o += al16((size_t)ne * 4);
-    L.slot = o; o += al16((size_t)ne * 4);
-    L.oslot = o; o += al16((size_t)n_so * 4);
-    L.s = o; o += al16((size_t)n_so * 8);
-    L.es = o; o += al16((size_t)n_so * 8);
-    L.ies = o; o += al16((size_t)n_so * 8);
-    L.red = o; o += al16((size_t)(nwv + 2) * 8);
-    L.csum = o; o += al16((size_t)nt * 8);
-    L.mi = o; o += al16((size_t)(32 + nwv) * 4);
-    L.md = o; o += al16((size_t)8 * 8);
-    L.queues = o; o += al16((size_t)nwv * kQueue * 4);
-    L.w1 = o; o += al16((size_t)ne * 8);
-    L.w2 = o; o += al16((size_t)ne * 8);
-    L.cRp = o; o += al16((size_t)n_so * 8);
-    L.cRq = o; o += al16((size_t)n_so * 8);
-    L.cBp = o; o += al16((size_t)ne * 8);
-    L.cBq = o; o += al16((size_t)ne * 8);
-    L.ipiv = o; o += al16((size_t)ne * 4);
-    L.fcol = o; o += al16((size_t)ne * 8);
+    const size_t gd = (size_t)ne * (ne - 1) / 2;
+    auto take = [&](size_t bytes) { const size_t r = o; o += al16(bytes); return (uint32_t)r; };
+    L.occw = take((size_t)nw * 8);
+    L.occl = take((size_t)ne * 4);
+    L.slot = take((size_t)ne * 4);
+    L.oslot = take((size_t)n_so * 4);
+    L.s = take((size_t)n_so * 8);
+    L.es = take((size_t)n_so * 8);
+    L.ies = take((size_t)n_so * 8);
+    L.red = take((size_t)(nwv + 2) * 8);
+    L.stmp = take((size_t)(nt + 1) * 4);
+    L.mi = take((size_t)(32 + nwv) * 4);
+    L.md = take((size_t)16 * 8);
+    L.wst = take((size_t)nwv * 8 * 4);
+    L.wtot = take((size_t)nwv * 2 * 8);
+    L.q64 = take((size_t)nwv * kQueue * 8);
+    L.qab = take((size_t)nwv * kQueue * 8);
+    L.lsum = take((size_t)nwv * (kLogS + kLogD) * 8);
+    L.loff = take((size_t)nwv * (kLogS + kLogD) * 4);
+    L.lg = take((size_t)nwv * (kLogS + kLogD) * 4);
+    L.sgend = take((size_t)ne * 4);
+    L.sdelta = take((size_t)ne * 4);
+    L.svend = take((size_t)ne * 4);
+    L.spq = take((size_t)ne * 4);
+    L.sfac = take((size_t)ne * 8);
+    L.w1 = take((size_t)ne * 8);
+    L.w2 = take((size_t)ne * 8);
+    L.cRp = take((size_t)n_so * 8);
+    L.cRq = take((size_t)n_so * 8);
+    L.cBp = take((size_t)ne * 8);
+    L.cBq = take((size_t)ne * 8);
+    L.ipiv = take((size_t)ne * 4);
+    L.fcol = take((size_t)ne * 8);
     if (small) {
-        L.R = o; o += al16((size_t)n_so * ne * 8);
-        L.B = o; o += al16((size_t)ne * ne * 8);
-        L.gsum = o; o += al16((size_t)G * 8);
+        L.dgend = take(gd * 4);
+        L.ddelta = take(gd * 4);
+        L.dvend = take(gd * 4);
+        L.dpq = take(gd * 4);
+        L.dfac = 0;
+        L.R = take((size_t)n_so * ne * 8);
+        L.B = take((size_t)ne * ne * 8);
+        L.Rh = take((size_t)n_so * ne * 8);
     } else {
-        L.R = L.B = L.gsum = 0;
+        L.dgend = L.ddelta = L.dvend = L.dpq = L.dfac = L.R = L.B = L.Rh = 0;
     }
-    L.total = o;
+    L.total = (uint32_t)o;
     return L;
 }
+// per-walker global scratch: the doubles group descriptors when they do not fit in LDS
+__host__ __device__ inline size_t scratch_layout_bytes(int ne) { return desc_bytes(ne) + 16; }
 
 // misc int slots
-enum { MI_ST = 0, MI_PIV, MI_GSTAR, MI_GLAST, MI_PTYPE, MI_PI, MI_PJ, MI_PA, MI_PB, MI_PP, MI_PQ, MI_WAVE = 32 };
-enum { MD_T = 0, MD_BASE, MD_EL, MD_HNN };
+enum { MI_ST = 0, MI_PIV, MI_PTYPE, MI_PP, MI_PQ, MI_PA, MI_PB, MI_FS, MI_FW, MI_FK, MI_FFB, MI_WAVE = 32 };
+enum { MD_T = 0, MD_BASE, MD_EL, MD_HNN, MD_TARGET };
+// per-wave state: entries of the two batch logs and the stream ranges
+enum { WS_NS = 0, WS_R1S = 3, WS_ND = 4, WS_R1D = 7 };
 
 // Rebuild B = theta[N]^-1 (Gauss-Jordan, partial pivoting, FP64), R and s from
 // the slot list.  B is stored column by slot (B[x][p] at B[p*ne + x]): the
 // elimination works on A^T, whose inverse laid out row-major is exactly that.
-__device__ void refresh_state(const Tab& T, const int* slot, double* B, double* R, double* s, double* fcol, int* ipiv,
+__device__ __forceinline__ void refresh_state(const Tab& T, const int* slot, double* B, double* R, double* s, double* fcol, int* ipiv,
                               int* mi, double* red) {
     const int tid = threadIdx.x, nt = blockDim.x, ne = T.ne, n_so = T.n_so;
     const int wv = tid >> 6, nwv = nt >> 6;
@@ -311,18 +344,401 @@ __device__ void refresh_state(const Tab& T, const int* slot, double* B, double* 
     __syncthreads();
 }
 
+
+// In-place inclusive prefix sum of a[0..n) (u32) by the whole block; returns
+// the total.  tmp: blockDim.x + 1 u32 of LDS.
+__device__ __forceinline__ uint32_t block_inclusive_scan(uint32_t* a, int n, uint32_t* tmp) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int chunk = (n + nt - 1) / nt;
+    const int lo = min(n, tid * chunk), hi = min(n, lo + chunk);
+    uint32_t sum = 0;
+    for (int k = lo; k < hi; ++k) sum += a[k];
+    tmp[tid] = sum;
+    __syncthreads();
+    if (tid < kWave) {
+        uint32_t carry = 0;
+        for (int base = 0; base < nt; base += kWave) {
+            const int k = base + tid;
+            const uint32_t v = (k < nt) ? tmp[k] : 0u;
+            uint32_t x = v;
+#pragma unroll
+            for (int d = 1; d < kWave; d <<= 1) {
+                const uint32_t y = __shfl_up(x, d, kWave);
+                if (tid >= d) x += y;
+            }
+            if (k < nt) tmp[k] = carry + x - v;  // exclusive
+            carry += __shfl(x, kWave - 1, kWave);
+        }
+        if (tid == 0) tmp[nt] = carry;
+    }
+    __syncthreads();
+    uint32_t run = tmp[tid];
+    for (int k = lo; k < hi; ++k) {
+        run += a[k];
+        a[k] = run;
+    }
+    const uint32_t total = tmp[nt];
+    __syncthreads();
+    return total;
+}
+
+// first group g with gend[g] > pos (gend inclusive-scanned, pos < gend[ng-1])
+__device__ __forceinline__ uint32_t find_group(const uint32_t* gend, uint32_t ng, uint32_t pos) {
+    uint32_t lo = 0, hi = ng - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (gend[mid] > pos) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// Data-parallel-primitive move of a double (both halves), reading 0 where the
+// row mask disables the destination.
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ double dpp_d(double x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROW_MASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROW_MASK, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+// Sum over the 64 lanes in a fixed order (quads, rows of 16, then row
+// broadcasts), returned as a wave-uniform value.
+__device__ __forceinline__ double wave_total(double x) {
+    x += dpp_d<0xB1>(x);        // quad_perm [1,0,3,2]
+    x += dpp_d<0x4E>(x);        // quad_perm [2,3,0,1]
+    x += dpp_d<0x124>(x);       // row_ror:4
+    x += dpp_d<0x128>(x);       // row_ror:8
+    x += dpp_d<0x142, 0xA>(x);  // row_bcast:15 into rows 1, 3
+    x += dpp_d<0x143, 0xC>(x);  // row_bcast:31 into rows 2, 3
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), 63);
+    return __hiloint2double(hi, lo);
+}
+
+// Block-wide deterministic sum (every thread gets the same value).
+__device__ __forceinline__ double block_total(double v, double* red) {
+    const int wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+    v = wave_total(v);
+    if (lane_id() == 0) red[wv] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int k = 0; k < nwv; ++k) t += red[k];
+    __syncthreads();
+    return t;
+}
+
+// One walker's per-step data.  The candidate stream of each kind is the
+// concatenation of its groups' table rows (singles: one group per occupied
+// orbital; doubles: one per occupied pair), each padded to a multiple of 64
+// positions so that a 64-lane chunk lies within one group.
+struct StepView {
+    const int* occl;
+    const double* es;     // exp(s_p)          (unscaled path)
+    const double* R;      // R (unscaled path) or Rh[p][a] = R[a][p] exp(s_a - s_orb(p)) (scaled path)
+    const uint32_t* sgend;  // singles: padded inclusive stream ends per occupied index
+    const uint32_t* sdelta; //          table offset = stream position + delta
+    const uint32_t* svend;  //          end of the group's valid positions
+    const uint32_t* spq;    //          slot of the occupied orbital
+    const double* sfac;     //          exp(-s_i) (unscaled path)
+    const uint32_t* dgend;  // doubles: the same per occupied pair
+    const uint32_t* ddelta;
+    const uint32_t* dvend;
+    const uint32_t* dpq;    //          slots p | q << 16
+    const double* dfac;     //          exp(-s_i - s_j) (unscaled path)
+};
+
+// Ratio psi(M)/psi(N) (and, when WANT_H, the local-energy term H_NM * ratio)
+// of a queued candidate: table offset `off`, group g, targets in `ab` (a
+// 64-bit occupancy mask when MASK, else a | b << 16 / a).
+template <bool DOUBLES, bool WANT_H, bool MASK, bool SCALED>
+__device__ __forceinline__ double cand_eval(const Tab& T, const StepView& V, uint32_t off, uint32_t g, uint64_t ab,
+                                            double2 vk, double& term, int& cp, int& cq, int& ca, int& cb) {
+    const int n_so = T.n_so;
+    if (DOUBLES) {
+        const uint32_t pq = V.dpq[g];
+        const int p = (int)(pq & 0xFFFFu), q = (int)(pq >> 16);
+        int a, b;
+        if (MASK) {
+            a = __builtin_ctzll(ab);
+            b = 63 - __builtin_clzll(ab);
+        } else {
+            a = (int)(ab & 0xFFFFu);
+            b = (int)((ab >> 16) & 0xFFFFu);
+        }
+        const double* Rp = V.R + p * n_so;
+        const double* Rq = V.R + q * n_so;
+        const double det = Rp[a] * Rq[b] - Rp[b] * Rq[a];
+        const double ratio = SCALED ? det * vk.y : det * V.es[a] * V.es[b] * vk.y * V.dfac[g];
+        if (WANT_H) term = vk.x * ratio;
+        cp = p; cq = q; ca = a; cb = b;
+        return ratio;
+    } else {
+        const int p = (int)V.spq[g];
+        const int a = (int)ab;
+        const double ratio = SCALED ? V.R[p * n_so + a] * T.sK[off] : V.R[p * n_so + a] * V.es[a] * V.sfac[g] * T.sK[off];
+        if (WANT_H) {
+            const double* Vr = T.sV + (size_t)off * n_so;
+            double h = T.sh[off];
+            for (int y = 0; y < T.ne; ++y) h += Vr[V.occl[y]];
+            term = h * ratio;
+        }
+        cp = p; cq = -1; ca = a; cb = -1;
+        return ratio;
+    }
+}
+
+// Batch log of one wave (wave-uniform bookkeeping).  The candidate stream is
+// cut into entries of `gran` consecutive 64-candidate batches; an entry keeps
+// its rate sum and the table offset / group of its first candidate.  Rates of
+// the open entry accumulate per lane and are reduced once when it closes.  A
+// full log merges neighbouring entries pairwise and doubles `gran`.
+struct BatchLog {
+    double* sum;
+    uint32_t* off;
+    uint32_t* grp;
+    int cap, n, gran, cnt;
+    uint32_t cur_off, cur_g;
+    double acc;
+    __device__ __forceinline__ void add_batch(double r, uint32_t o0, uint32_t g0) {
+        if (cnt == 0) { cur_off = o0; cur_g = g0; acc = 0.0; }
+        acc += r;
+        if (++cnt == gran) close();
+    }
+    __device__ __forceinline__ void close() {
+        if (cnt == 0) return;
+        const double s = wave_total(acc);
+        const int l = lane_id();
+        if (n == cap) {
+            wave_lds_sync();
+            double a0 = 0.0, a1 = 0.0;
+            uint32_t oo = 0, gg = 0;
+            const int half = cap >> 1;
+            if (l < half) { a0 = sum[2 * l]; a1 = sum[2 * l + 1]; oo = off[2 * l]; gg = grp[2 * l]; }
+            wave_lds_sync();
+            if (l < half) { sum[l] = a0 + a1; off[l] = oo; grp[l] = gg; }
+            wave_lds_sync();
+            n = half;
+            gran *= 2;
+        }
+        if (l == 0) { sum[n] = s; off[n] = cur_off; grp[n] = cur_g; }
+        ++n;
+        cnt = 0;
+    }
+};
+
+// Pass over the padded stream chunks [c0, c1) of one wave (multiples of 64);
+// g0 = group of c0; positions below `first` are skipped.
+// ELOC: accumulate local-energy terms in `el`, log rate sums.
+// PICK: with running sum `base` at `first`, find the candidate where the
+// running sum first exceeds `target` (or, with `fallback` or after rounding,
+// the last positive-rate candidate); pick = {type, p, q, a, b}; returns true
+// if found.
+// The table loads of kUnroll chunks are issued together before they are consumed.
+template <bool DOUBLES, bool PICK, bool NW1, bool SCALED>
+__device__ __forceinline__ bool stream_pass(const Tab& T, const StepView& V, uint64_t occ0, const uint64_t* occw, uint32_t c0,
+                            uint32_t c1, uint32_t g0, uint32_t first, uint64_t* q64, uint64_t* qab, double2* qvk,
+                            double& el, double* log_sum, uint32_t* log_off, uint32_t* log_grp, int log_cap, int& log_n,
+                            double base, double target, bool fallback, int* pick) {
+    BatchLog lg{log_sum, log_off, log_grp, log_cap, 0, kLogGran, 0, 0u, 0u, 0.0};
+    BatchLog* log = &lg;
+    constexpr bool MASK = DOUBLES && NW1;
+    const int l = lane_id();
+    c0 = uni(c0);
+    c1 = uni(c1);
+    first = uni(first);
+    const uint32_t* gend = DOUBLES ? V.dgend : V.sgend;
+    const uint32_t* delta = DOUBLES ? V.ddelta : V.sdelta;
+    const uint32_t* vend = DOUBLES ? V.dvend : V.svend;
+    uint32_t gc = uni(g0), qn = 0;
+    uint32_t e_end = uni(gend[gc]), e_vend = uni(vend[gc]), e_delta = uni(delta[gc]);
+    double run = base;
+    bool found = false;
+    int last_l = -1;
+    uint32_t last_off = 0, last_g = 0;
+    uint64_t last_ab = 0;
+
+    struct Stage {
+        uint32_t g[kUnroll], off[kUnroll];
+        bool ok[kUnroll];
+        uint64_t ab[kUnroll];
+    };
+    // compute the chunks' groups and offsets (advancing the uniform group
+    // cursor) and issue their table loads
+    auto fetch = [&](uint32_t c, Stage& st) __attribute__((always_inline)) {
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const uint32_t cu = c + (uint32_t)(u * kWave);
+            st.ok[u] = false;
+            st.g[u] = gc;
+            st.off[u] = 0;
+            if (cu < c1) {
+                while (e_end <= cu) {
+                    ++gc;
+                    e_end = uni(gend[gc]);
+                    e_vend = uni(vend[gc]);
+                    e_delta = uni(delta[gc]);
+                }
+                st.g[u] = gc;
+                const uint32_t pos = cu + (uint32_t)l;
+                st.ok[u] = pos < e_vend && pos >= first;
+                st.off[u] = st.ok[u] ? pos + e_delta : 0u;  // entry 0 stands in for lanes without a candidate
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            if (MASK) st.ab[u] = T.dmask[st.off[u]];
+            else if (DOUBLES) st.ab[u] = T.dab[st.off[u]];
+            else st.ab[u] = T.sa[st.off[u]];
+        }
+    };
+    auto batch = [&](int k) __attribute__((always_inline)) -> bool {
+        wave_lds_sync();
+        const bool act = l < k;
+        const uint64_t og = act ? q64[l] : 0ull;
+        const uint64_t ab = act ? qab[l] : 0ull;
+        const uint32_t off = (uint32_t)og, g = (uint32_t)(og >> 32);
+        double2 vk = make_double2(0.0, 0.0);
+        if (DOUBLES && act) vk = *(const double2*)(T.dvK + 2 * (size_t)off);
+        double term = 0.0, r = 0.0;
+        int cp = 0, cq = 0, ca = 0, cb = 0;
+        if (act) r = fabs(cand_eval<DOUBLES, !PICK, MASK, SCALED>(T, V, off, g, ab, vk, term, cp, cq, ca, cb));
+        if (!PICK) {
+            el += term;
+            log->add_batch(r, uni((uint32_t)og), uni((uint32_t)(og >> 32)));
+            return false;
+        }
+        const uint64_t mpos = __ballot(r > 0.0);
+        if (mpos) {
+            last_l = 63 - __clzll((long long)mpos);
+            last_off = __shfl(off, last_l, kWave);
+            last_g = __shfl(g, last_l, kWave);
+            last_ab = ((uint64_t)__shfl((uint32_t)(ab >> 32), last_l, kWave) << 32) |
+                      (uint64_t)__shfl((uint32_t)ab, last_l, kWave);
+        }
+        if (fallback) return false;
+        const double incl = wave_inclusive_scan(r);
+        const uint64_t mx = __ballot(act && r > 0.0 && run + incl > target);
+        if (mx) {
+            const int fl = __ffsll((unsigned long long)mx) - 1;
+            if (l == fl) { pick[0] = DOUBLES ? 2 : 1; pick[1] = cp; pick[2] = cq; pick[3] = ca; pick[4] = cb; }
+            return true;
+        }
+        run += __shfl(incl, kWave - 1, kWave);
+        return false;
+    };
+    auto consume = [&](const Stage& st) __attribute__((always_inline)) {
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            bool surv;
+            if (MASK) {
+                surv = st.ok[u] && (st.ab[u] & occ0) == 0ull;
+            } else if (DOUBLES) {
+                const uint32_t a = (uint32_t)st.ab[u] & 0xFFFFu, b = (uint32_t)st.ab[u] >> 16;
+                surv = st.ok[u] && !((occw[a >> 6] >> (a & 63)) & 1ull) && !((occw[b >> 6] >> (b & 63)) & 1ull);
+            } else {
+                const uint32_t a = (uint32_t)st.ab[u];
+                surv = st.ok[u] && (NW1 ? !((occ0 >> a) & 1ull) : !((occw[a >> 6] >> (a & 63)) & 1ull));
+            }
+            surv = surv && !found;
+            const uint64_t m = __ballot(surv);
+            if (surv) {
+                const uint32_t sq = qn + mask_below(m);
+                q64[sq] = (uint64_t)st.off[u] | ((uint64_t)st.g[u] << 32);
+                qab[sq] = st.ab[u];
+            }
+            qn += (uint32_t)__popcll(m);
+            if (qn >= (uint32_t)kWave) {
+                found = batch(kWave);
+                wave_lds_sync();
+                const bool mv = (uint32_t)l + kWave < qn;
+                const uint64_t r64 = mv ? q64[l + kWave] : 0ull;
+                const uint64_t rab = mv ? qab[l + kWave] : 0ull;
+                wave_lds_sync();
+                qn -= kWave;
+                if ((uint32_t)l < qn) {
+                    q64[l] = r64;
+                    qab[l] = rab;
+                }
+            }
+        }
+    };
+    for (uint32_t c = c0; c < c1 && !found; c += kUnroll * kWave) {
+        Stage st;
+        fetch(c, st);
+        consume(st);
+    }
+    if (!found && qn > 0) found = batch((int)qn);
+    if (!PICK) log->close();
+    log_n = lg.n;
+    wave_lds_sync();
+    if (PICK && !found && last_l >= 0) {
+        // rounding left the target past the last running sum: take the last
+        // candidate with a positive rate
+        if (l == 0) {
+            double term;
+            int cp, cq, ca, cb;
+            const double2 vk = DOUBLES ? *(const double2*)(T.dvK + 2 * (size_t)last_off) : make_double2(0.0, 0.0);
+            cand_eval<DOUBLES, false, MASK, SCALED>(T, V, last_off, last_g, last_ab, vk, term, cp, cq, ca, cb);
+            pick[0] = DOUBLES ? 2 : 1; pick[1] = cp; pick[2] = cq; pick[3] = ca; pick[4] = cb;
+        }
+        found = true;
+    }
+    return found;
+}
+
+// In-place inclusive prefix sum of the first n entries of a wave's log.
+__device__ __forceinline__ double log_prefix(double* a, int n) {
+    const int l = lane_id();
+    double carry = 0.0;
+    for (int base = 0; base < n; base += kWave) {
+        const int k = base + l;
+        const double v = (k < n) ? a[k] : 0.0;
+        const double x = wave_inclusive_scan(v) + carry;
+        if (k < n) a[k] = x;
+        carry = __shfl(x, kWave - 1, kWave);
+    }
+    wave_lds_sync();
+    return carry;
+}
+
 enum { MODE_ELOC = 0, MODE_CTMC = 1, MODE_INIT = 2 };
 
-template <bool NW1, bool SMALL>
-__global__ void __launch_bounds__(512) k_sweep(Tab T, Wk S, int64_t W, int mode, int n_steps, uint64_t step0,
-                                               uint64_t seed, int refresh_period, double* eloc_hist, double* t_hist,
-                                               int64_t* pick_hist) {
+// Occupancy target of the sweep kernel (waves per SIMD); 0 leaves it to the compiler.
+#ifndef VMC_SWEEP_WAVES_PER_EU
+#define VMC_SWEEP_WAVES_PER_EU 0
+#endif
+#if VMC_SWEEP_WAVES_PER_EU > 0
+#define VMC_SWEEP_ATTR __attribute__((amdgpu_waves_per_eu(VMC_SWEEP_WAVES_PER_EU)))
+#else
+#define VMC_SWEEP_ATTR
+#endif
+
+// NSO_T, NE_T, NT_T: compile-time n_so, Ne and workgroup size of a size
+// specialisation (0 = taken from the arguments at run time).  With them the
+// LDS layout and loop bounds fold to constants.
+template <int NSO_T, int NE_T, int NT_T, bool NW1, bool SMALL>
+__global__ void __launch_bounds__(NT_T ? NT_T : 512) VMC_SWEEP_ATTR
+k_sweep(Tab Targ, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, uint64_t seed, int refresh_period,
+        double* eloc_hist, double* t_hist, int64_t* pick_hist) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int64_t w = blockIdx.x;
     if (w >= W) return;
-    const int tid = threadIdx.x, nt = blockDim.x, l = tid & 63, wv = tid >> 6, nwv = nt >> 6;
-    const int n_so = T.n_so, ne = T.ne, nw = T.nw, G = T.G;
-    const Lds L = lds_layout(n_so, ne, nw, G, nt, SMALL);
+    Tab T = Targ;
+    if (NSO_T) {
+        T.n_so = NSO_T;
+        T.ne = NE_T;
+        T.nw = (NSO_T + 63) / 64;
+    }
+    // wave index made explicitly wave-uniform so that everything derived from it
+    // (stream ranges, group cursors, log bookkeeping) lives in scalar registers
+    const int tid = threadIdx.x, nt = NT_T ? NT_T : (int)blockDim.x, l = tid & 63;
+    const int wv = (int)__builtin_amdgcn_readfirstlane((uint32_t)(tid >> 6)), nwv = nt >> 6;
+    const int n_so = T.n_so, ne = T.ne, nw = T.nw;
+    const int gd = ne * (ne - 1) / 2;
+    T.G = ne + gd;
+    const Lds L = lds_layout(n_so, ne, nw, nt, SMALL);
     uint64_t* occw = (uint64_t*)(smem + L.occw);
     int* occl = (int*)(smem + L.occl);
     int* slot = (int*)(smem + L.slot);
@@ -331,10 +747,22 @@ __global__ void __launch_bounds__(512) k_sweep(Tab T, Wk S, int64_t W, int mode,
     double* es = (double*)(smem + L.es);
     double* ies = (double*)(smem + L.ies);
     double* red = (double*)(smem + L.red);
-    double* csum = (double*)(smem + L.csum);
+    uint32_t* stmp = (uint32_t*)(smem + L.stmp);
     int* mi = (int*)(smem + L.mi);
     double* md = (double*)(smem + L.md);
-    uint32_t* queue = (uint32_t*)(smem + L.queues) + wv * kQueue;
+    int* wst = (int*)(smem + L.wst);
+    uint64_t* q64 = (uint64_t*)(smem + L.q64) + wv * kQueue;
+    uint64_t* qab = (uint64_t*)(smem + L.qab) + wv * kQueue;
+    double2* qvk = nullptr;
+    double* wtot = (double*)(smem + L.wtot);
+    double* lsum = (double*)(smem + L.lsum);
+    uint32_t* loff = (uint32_t*)(smem + L.loff);
+    uint32_t* lg = (uint32_t*)(smem + L.lg);
+    uint32_t* sgend = (uint32_t*)(smem + L.sgend);
+    uint32_t* sdelta = (uint32_t*)(smem + L.sdelta);
+    uint32_t* svend = (uint32_t*)(smem + L.svend);
+    uint32_t* spq = (uint32_t*)(smem + L.spq);
+    double* sfac = (double*)(smem + L.sfac);
     double* w1 = (double*)(smem + L.w1);
     double* w2 = (double*)(smem + L.w2);
     double* cRp = (double*)(smem + L.cRp);
@@ -343,16 +771,30 @@ __global__ void __launch_bounds__(512) k_sweep(Tab T, Wk S, int64_t W, int mode,
     double* cBq = (double*)(smem + L.cBq);
     int* ipiv = (int*)(smem + L.ipiv);
     double* fcol = (double*)(smem + L.fcol);
-    double *R, *B, *gsum;
+    double *R, *B, *Rh, *dfac;
+    uint32_t *dgend, *ddelta, *dvend, *dpq;
     if (SMALL) {
         R = (double*)(smem + L.R);
         B = (double*)(smem + L.B);
-        gsum = (double*)(smem + L.gsum);
+        Rh = (double*)(smem + L.Rh);
+        dgend = (uint32_t*)(smem + L.dgend);
+        ddelta = (uint32_t*)(smem + L.ddelta);
+        dvend = (uint32_t*)(smem + L.dvend);
+        dpq = (uint32_t*)(smem + L.dpq);
+        dfac = nullptr;
     } else {
         R = S.R + (size_t)w * n_so * ne;
         B = S.B + (size_t)w * ne * ne;
-        gsum = (double*)(S.scratch + (size_t)w * S.scratch_stride);
+        Rh = R;
+        uint8_t* sc = S.scratch + (size_t)w * S.scratch_stride;
+        const size_t st4 = al16((size_t)gd * 4);
+        dgend = (uint32_t*)sc;
+        ddelta = (uint32_t*)(sc + st4);
+        dvend = (uint32_t*)(sc + 2 * st4);
+        dpq = (uint32_t*)(sc + 3 * st4);
+        dfac = (double*)(sc + 4 * st4);
     }
+    const StepView V{occl, es, SMALL ? Rh : R, sgend, sdelta, svend, spq, sfac, dgend, ddelta, dvend, dpq, dfac};
 
     // ---------------------------------------------------------------- load
     for (int k = tid; k < nw; k += nt) occw[k] = S.occ[(size_t)w * nw + k];
@@ -395,176 +837,203 @@ __global__ void __launch_bounds__(512) k_sweep(Tab T, Wk S, int64_t W, int mode,
         }
         __syncthreads();
     }
+    // H_NN from scratch (at load and after every re-inversion); updated per move
+    auto hnn_full = [&]() __attribute__((always_inline)) {
+        double hp = 0.0;
+        for (int x = tid; x < ne; x += nt) {
+            const int i = slot[x];
+            const double* Di = T.D + (size_t)i * n_so;
+            hp += T.hdiag[i];
+            for (int y = x + 1; y < ne; ++y) hp += Di[slot[y]];
+        }
+        const double h = block_total(hp, red);
+        if (tid == 0) md[MD_HNN] = h;
+        __syncthreads();
+    };
+    hnn_full();
 
     const int steps = (mode == MODE_CTMC) ? n_steps : 1;
-    double el_last = 0.0, t_last = 0.0, hnn = 0.0;
+    double el_last = 0.0, t_last = 0.0;
     int64_t code_last = 0;
-    for (int k = 0; k < steps; ++k) {
+    for (int k = 0; k < steps && mode != MODE_INIT; ++k) {
         const uint64_t gstep = step0 + (uint64_t)k;
+        const bool singular = (mi[MI_ST] & (int)VMC_ST_SINGULAR) != 0;
         // ------------------------------------------------- per-step setup
         for (int pp = tid; pp < n_so; pp += nt) {
-            if (!((occw[pp >> 6] >> (pp & 63)) & 1ull)) {
-                es[pp] = exp(s[pp]);
-                ies[pp] = exp(-s[pp]);
-                continue;
-            }
+            es[pp] = exp(s[pp]);
+            ies[pp] = exp(-s[pp]);
+            if (!((occw[pp >> 6] >> (pp & 63)) & 1ull)) continue;
             int rank = 0;
             for (int q = 0; q < (pp >> 6); ++q) rank += __popcll(occw[q]);
             rank += __popcll(occw[pp >> 6] & ((1ull << (pp & 63)) - 1ull));
             occl[rank] = pp;
-            es[pp] = exp(s[pp]);
-            ies[pp] = exp(-s[pp]);
         }
         __syncthreads();
-        double hp = 0.0;
+        if (SMALL) {
+            // Rh[p][a] = R[a][p] exp(s_a) exp(-s_i), i = slot[p]: the Jastrow
+            // factors of the amplitude ratio folded into the rows and columns
+            // of R (they factor out of every 1x1 and 2x2 minor)
+            for (int idx = tid; idx < n_so * ne; idx += nt) {
+                const int p = idx / n_so, a = idx - p * n_so;
+                Rh[idx] = R[idx] * es[a] * ies[slot[p]];
+            }
+        }
+        // group descriptors: row lengths padded to 64 (scanned into stream
+        // ends), table bases (turned into offset deltas), valid ends, slots
+        // and Jastrow factors
         for (int x = tid; x < ne; x += nt) {
             const int i = occl[x];
-            const double* Di = T.D + (size_t)i * n_so;
-            hp += T.hdiag[i];
-            for (int y = x + 1; y < ne; ++y) hp += Di[occl[y]];
+            const uint32_t b0 = T.s_off[i], len = T.s_off[i + 1] - b0;
+            sdelta[x] = b0;
+            svend[x] = len;
+            sgend[x] = (len + 63u) & ~63u;
+            spq[x] = (uint32_t)oslot[i];
+            sfac[x] = ies[i];
         }
-        hnn = block_sum(hp, red);
-        const bool singular = (mi[MI_ST] & (int)VMC_ST_SINGULAR) != 0;
-        if (mode == MODE_INIT) break;
+        for (int t = tid; t < gd; t += nt) {
+            int x, y;
+            pair_decode(t, ne, x, y);
+            const int i = occl[x], j = occl[y];
+            const int row = i * n_so + j;
+            const uint32_t b0 = T.row_off[row], len = T.row_off[row + 1] - b0;
+            ddelta[t] = b0;
+            dvend[t] = len;
+            dgend[t] = (len + 63u) & ~63u;
+            dpq[t] = (uint32_t)oslot[i] | ((uint32_t)oslot[j] << 16);
+            if (!SMALL) dfac[t] = ies[i] * ies[j];
+        }
+        __syncthreads();
+        const uint32_t LS = uni(block_inclusive_scan(sgend, ne, stmp));
+        const uint32_t LD = (gd > 0) ? uni(block_inclusive_scan(dgend, gd, stmp)) : 0u;
+        for (int x = tid; x < ne; x += nt) {
+            const uint32_t ps = x ? sgend[x - 1] : 0u;
+            sdelta[x] -= ps;
+            svend[x] += ps;
+        }
+        for (int t = tid; t < gd; t += nt) {
+            const uint32_t ps = t ? dgend[t - 1] : 0u;
+            ddelta[t] -= ps;
+            dvend[t] += ps;
+        }
+        __syncthreads();
 
         // ------------------------------------------------- local energy
         double el_lane = 0.0;
         if (!singular) {
-            for (int g = wv; g < G; g += nwv) {
-                const Group Gr = group_of(T, g, occl, oslot, ies);
-                double rs = 0.0;
-                if (Gr.type == 1) {
-                    auto ev = [&](uint32_t e, bool act) -> bool {
-                        if (act) {
-                            int a;
-                            const double ratio = single_ratio(T, Gr, e, R, es, a);
-                            el_lane += single_h(T, Gr, e, occl) * ratio;
-                            rs += fabs(ratio);
-                        }
-                        return false;
-                    };
-                    if (NW1) scan_group<false>(T, OccReg{occw[0]}, Gr.base, Gr.len, queue, ev);
-                    else scan_group<false>(T, OccLds{occw}, Gr.base, Gr.len, queue, ev);
-                } else {
-                    auto ev = [&](uint32_t e, bool act) -> bool {
-                        if (act) {
-                            int a, b;
-                            const double ratio = double_ratio(T, Gr, e, R, es, a, b);
-                            el_lane += T.dv[Gr.base + e] * ratio;
-                            rs += fabs(ratio);
-                        }
-                        return false;
-                    };
-                    if (NW1) scan_group<true>(T, OccReg{occw[0]}, Gr.base, Gr.len, queue, ev);
-                    else scan_group<true>(T, OccLds{occw}, Gr.base, Gr.len, queue, ev);
-                }
-                const double gs = wave_sum(rs);
-                if (l == 0) gsum[g] = gs;
+            // contiguous, chunk-aligned ranges of each padded stream per wave
+            const uint32_t cs = LS >> 6, cd = LD >> 6;
+            const uint32_t r0s = (uint32_t)(((uint64_t)cs * wv / nwv) << 6), r1s = (uint32_t)(((uint64_t)cs * (wv + 1) / nwv) << 6);
+            const uint32_t r0d = (uint32_t)(((uint64_t)cd * wv / nwv) << 6), r1d = (uint32_t)(((uint64_t)cd * (wv + 1) / nwv) << 6);
+            const int lb = wv * (kLogS + kLogD);
+            int ns = 0, nd = 0;
+            const uint64_t occ0 = occw[0];
+            if (r0s < r1s) {
+                const uint32_t g0 = find_group(sgend, (uint32_t)ne, r0s);
+                stream_pass<false, false, NW1, SMALL>(T, V, occ0, occw, r0s, r1s, g0, r0s, q64, qab, qvk, el_lane, lsum + lb, loff + lb, lg + lb, kLogS, ns, 0.0, 0.0, false, nullptr);
             }
+            if (r0d < r1d) {
+                const uint32_t g0 = find_group(dgend, (uint32_t)gd, r0d);
+                stream_pass<true, false, NW1, SMALL>(T, V, occ0, occw, r0d, r1d, g0, r0d, q64, qab, qvk, el_lane, lsum + lb + kLogS, loff + lb + kLogS, lg + lb + kLogS, kLogD, nd, 0.0, 0.0, false, nullptr);
+            }
+            // per-wave inclusive prefix sums of the two logs and their totals
+            const double ts = log_prefix(lsum + lb, ns), td = log_prefix(lsum + lb + kLogS, nd);
+            if (l == 0) {
+                int* ws = wst + wv * 8;
+                ws[WS_NS] = ns; ws[WS_R1S] = (int)r1s;
+                ws[WS_ND] = nd; ws[WS_R1D] = (int)r1d;
+                wtot[2 * wv] = ts;
+                wtot[2 * wv + 1] = td;
+            }
+        } else if (l == 0) {
+            int* ws = wst + wv * 8;
+            ws[WS_NS] = 0; ws[WS_ND] = 0;
+            wtot[2 * wv] = 0.0;
+            wtot[2 * wv + 1] = 0.0;
         }
-        const double el = singular ? NAN : (block_sum(el_lane, red) + hnn);
+        const double el = singular ? NAN : (block_total(el_lane, red) + md[MD_HNN]);
 
-        // --------------------------------------------- T and the group prefix
-        const int chunk = (G + nt - 1) / nt;
-        const int g0 = min(G, tid * chunk), g1 = min(G, g0 + chunk);
-        {
-            double cs = 0.0;
-            if (!singular)
-                for (int g = g0; g < g1; ++g) cs += gsum[g];
-            csum[tid] = cs;
-        }
-        __syncthreads();
+        // ------------------------------------------ T and the pick location
+        // T = sum of the per-wave log totals (singles then doubles, waves in
+        // order); the target u*T is located first among those totals, then by
+        // binary search in that wave's prefix-summed log.
         if (tid == 0) {
-            double run = 0.0;
-            for (int q = 0; q < nt; ++q) {
-                const double c = csum[q];
-                csum[q] = run;
-                run += c;
-            }
-            md[MD_T] = run;
-            mi[MI_GSTAR] = INT_MAX;
-            mi[MI_GLAST] = -1;
+            double Tt = 0.0;
+            if (!singular)
+                for (int st = 0; st < 2; ++st)
+                    for (int q = 0; q < nwv; ++q) Tt += wtot[2 * q + st];
+            md[MD_T] = Tt;
             mi[MI_PTYPE] = 0;
+            mi[MI_FS] = -1;
+            const bool okT0 = !singular && Tt > 0.0 && isfinite(Tt) && isfinite(el);
+            if (!singular && !(isfinite(Tt) && isfinite(el))) mi[MI_ST] |= (int)VMC_ST_NONFINITE;
+            else if (!singular && !(Tt > 0.0)) mi[MI_ST] |= (int)VMC_ST_EMPTY;
+            if (okT0 && mode == MODE_CTMC) {
+                const double target = ctmc_uniform(seed, (uint64_t)w, gstep) * Tt;
+                md[MD_TARGET] = target;
+                double run = 0.0, fbase = 0.0, lbase = 0.0;
+                int fs = -1, fw = -1, ls_ = -1, lw_ = -1;
+                for (int st = 0; st < 2 && fs < 0; ++st)
+                    for (int q = 0; q < nwv && fs < 0; ++q) {
+                        const double v = wtot[2 * q + st];
+                        if (v > 0.0) { ls_ = st; lw_ = q; lbase = run; }
+                        if (v > 0.0 && run + v > target) { fs = st; fw = q; fbase = run; }
+                        else run += v;
+                    }
+                bool fb = false;
+                if (fs < 0 && ls_ >= 0) { fs = ls_; fw = lw_; fbase = lbase; fb = true; }
+                if (fs >= 0) {
+                    const int n_ent = wst[fw * 8 + (fs ? WS_ND : WS_NS)];
+                    const double* pre = lsum + fw * (kLogS + kLogD) + (fs ? kLogS : 0);
+                    int fk;
+                    if (!fb) {
+                        // smallest e with fbase + pre[e] > target
+                        int lo = 0, hi = n_ent - 1;
+                        while (lo < hi) {
+                            const int mid = (lo + hi) >> 1;
+                            if (fbase + pre[mid] > target) hi = mid;
+                            else lo = mid + 1;
+                        }
+                        fk = lo;
+                    } else {
+                        // last entry with a positive sum
+                        fk = n_ent - 1;
+                        while (fk > 0 && !(pre[fk] > pre[fk - 1])) --fk;
+                    }
+                    mi[MI_FS] = fs;
+                    mi[MI_FW] = fw;
+                    mi[MI_FK] = fk;
+                    mi[MI_FFB] = fb ? 1 : 0;
+                    md[MD_BASE] = fbase + (fk ? pre[fk - 1] : 0.0);
+                }
+            }
         }
         __syncthreads();
         const double Ttot = md[MD_T];
         const bool okT = !singular && Ttot > 0.0 && isfinite(Ttot) && isfinite(el);
         const double tres = okT ? 1.0 / Ttot : 0.0;
-        if (tid == 0) {
-            if (!singular && !(isfinite(Ttot) && isfinite(el))) mi[MI_ST] |= (int)VMC_ST_NONFINITE;
-            else if (!singular && !(Ttot > 0.0)) mi[MI_ST] |= (int)VMC_ST_EMPTY;
-        }
         el_last = el;
         t_last = tres;
         code_last = 0;
         if (mode == MODE_ELOC) break;
 
         // --------------------------------------------------------- pick
-        if (okT) {
-            const double target = ctmc_uniform(seed, (uint64_t)w, gstep) * Ttot;
-            double run = csum[tid], before = 0.0;
-            int found = -1, lastpos = -1;
-            for (int g = g0; g < g1; ++g) {
-                const double gv = gsum[g];
-                if (gv > 0.0) lastpos = g;
-                const double prev = run;
-                run += gv;
-                if (found < 0 && gv > 0.0 && run > target) { found = g; before = prev; }
-            }
-            if (found >= 0) atomicMin(&mi[MI_GSTAR], found);
-            if (lastpos >= 0) atomicMax(&mi[MI_GLAST], lastpos);
-            __syncthreads();
-            if (found >= 0 && found == mi[MI_GSTAR]) md[MD_BASE] = before;
-            __syncthreads();
-            int gstar = mi[MI_GSTAR];
-            const bool fallback = (gstar == INT_MAX);
-            if (fallback) gstar = mi[MI_GLAST];
-            if (wv == 0 && gstar >= 0) {
-                const Group Gr = group_of(T, gstar, occl, oslot, ies);
-                double run0 = md[MD_BASE];
-                int got = -1;                 // entry index of the pick
-                int last = -1;                // last entry with a positive rate
-                auto ev = [&](uint32_t e, bool act) -> bool {
-                    double r = 0.0;
-                    if (act) {
-                        int a, b;
-                        r = fabs(Gr.type == 1 ? single_ratio(T, Gr, e, R, es, a) : double_ratio(T, Gr, e, R, es, a, b));
-                    }
-                    const uint64_t mpos = __ballot(r > 0.0);
-                    if (mpos) last = __shfl((int)e, 63 - __clzll(mpos), kWave);
-                    if (fallback) return false;
-                    const double incl = wave_inclusive_scan(r);
-                    const uint64_t mx = __ballot(act && (run0 + incl > target));
-                    if (mx) {
-                        got = __shfl((int)e, __ffsll((unsigned long long)mx) - 1, kWave);
-                        return true;
-                    }
-                    run0 += __shfl(incl, 63, kWave);
-                    return false;
-                };
-                if (Gr.type == 1) {
-                    if (NW1) scan_group<false>(T, OccReg{occw[0]}, Gr.base, Gr.len, queue, ev);
-                    else scan_group<false>(T, OccLds{occw}, Gr.base, Gr.len, queue, ev);
-                } else {
-                    if (NW1) scan_group<true>(T, OccReg{occw[0]}, Gr.base, Gr.len, queue, ev);
-                    else scan_group<true>(T, OccLds{occw}, Gr.base, Gr.len, queue, ev);
-                }
-                if (got < 0) got = last;
-                if (l == 0 && got >= 0) {
-                    mi[MI_PTYPE] = Gr.type;
-                    mi[MI_PI] = Gr.i;
-                    mi[MI_PJ] = Gr.j;
-                    mi[MI_PP] = Gr.p;
-                    mi[MI_PQ] = Gr.q;
-                    if (Gr.type == 1) {
-                        mi[MI_PA] = (int)T.sa[Gr.base + got];
-                        mi[MI_PB] = -1;
-                    } else {
-                        const uint32_t ab = T.dab[Gr.base + got];
-                        mi[MI_PA] = (int)(ab & 0xFFFFu);
-                        mi[MI_PB] = (int)(ab >> 16);
-                    }
-                }
+        if (okT && mi[MI_FS] >= 0) {
+            if (wv == 0) {
+                const int fs = (int)uni((uint32_t)mi[MI_FS]), fw = (int)uni((uint32_t)mi[MI_FW]);
+                const int fk = (int)uni((uint32_t)mi[MI_FK]);
+                const bool fb = uni((uint32_t)mi[MI_FFB]) != 0;
+                const int b = fw * (kLogS + kLogD) + (fs ? kLogS : 0) + fk;
+                const uint32_t o0 = loff[b], g0 = lg[b];
+                const uint32_t p0 = o0 - (fs ? ddelta[g0] : sdelta[g0]);  // stream position of the entry's first candidate
+                const uint32_t c0 = p0 & ~63u;
+                const uint32_t r1 = (uint32_t)wst[fw * 8 + (fs ? WS_R1D : WS_R1S)];
+                const double base = md[MD_BASE], target = md[MD_TARGET];
+                double dummy = 0.0;
+                int dn = 0;
+                if (fs == 0)
+                    stream_pass<false, true, NW1, SMALL>(T, V, occw[0], occw, c0, r1, g0, p0, q64, qab, qvk, dummy, nullptr, nullptr, nullptr, 0, dn, base, target, fb, mi + MI_PTYPE);
+                else
+                    stream_pass<true, true, NW1, SMALL>(T, V, occw[0], occw, c0, r1, g0, p0, q64, qab, qvk, dummy, nullptr, nullptr, nullptr, 0, dn, base, target, fb, mi + MI_PTYPE);
             }
             __syncthreads();
         }
@@ -572,15 +1041,24 @@ __global__ void __launch_bounds__(512) k_sweep(Tab T, Wk S, int64_t W, int mode,
         // -------------------------------------------------------- update
         const int ptype = mi[MI_PTYPE];
         if (ptype != 0) {
-            const int i = mi[MI_PI], j = mi[MI_PJ], a = mi[MI_PA], b = mi[MI_PB], p = mi[MI_PP], q = mi[MI_PQ];
+            const int p = mi[MI_PP], q = mi[MI_PQ], a = mi[MI_PA], b = mi[MI_PB];
+            const int i = slot[p], j = (ptype == 2) ? slot[q] : -1;
             const double* Rp = R + p * n_so;
+            // change of H_NN (sum over the unchanged occupied orbitals)
+            double dh = 0.0;
+            for (int x = tid; x < ne; x += nt) {
+                if (x == p || (ptype == 2 && x == q)) continue;
+                const int kk = slot[x];
+                dh += T.D[(size_t)a * n_so + kk] - T.D[(size_t)i * n_so + kk];
+                if (ptype == 2) dh += T.D[(size_t)b * n_so + kk] - T.D[(size_t)j * n_so + kk];
+            }
             if (ptype == 1) {
                 const double rho = Rp[a];
                 for (int x = tid; x < ne; x += nt) w1[x] = (R[x * n_so + a] - (x == p ? 1.0 : 0.0)) / rho;
                 for (int a2 = tid; a2 < n_so; a2 += nt) cRp[a2] = Rp[a2];
                 for (int x = tid; x < ne; x += nt) cBp[x] = B[p * ne + x];
                 if (tid == 0 && fabs(rho) < 1e-8) mi[MI_ST] |= (int)VMC_ST_SMALLDEN;
-                __syncthreads();
+                dh = block_total(dh, red);  // its barriers also order the w/column writes before use
                 for (int idx = tid; idx < n_so * ne; idx += nt) {
                     const int x = idx / n_so, a2 = idx - x * n_so;
                     R[idx] -= cRp[a2] * w1[x];
@@ -589,6 +1067,7 @@ __global__ void __launch_bounds__(512) k_sweep(Tab T, Wk S, int64_t W, int mode,
                     const int x2 = idx / ne, x = idx - x2 * ne;
                     B[idx] -= cBp[x] * w1[x2];
                 }
+                if (tid == 0) md[MD_HNN] += dh + T.hdiag[a] - T.hdiag[i];
             } else {
                 const double* Rq = R + q * n_so;
                 const double c00 = Rp[a], c01 = Rq[a], c10 = Rp[b], c11 = Rq[b];
@@ -608,7 +1087,7 @@ __global__ void __launch_bounds__(512) k_sweep(Tab T, Wk S, int64_t W, int mode,
                     cBq[x] = B[q * ne + x];
                 }
                 if (tid == 0 && fabs(det) < 1e-8) mi[MI_ST] |= (int)VMC_ST_SMALLDEN;
-                __syncthreads();
+                dh = block_total(dh, red);
                 for (int idx = tid; idx < n_so * ne; idx += nt) {
                     const int x = idx / n_so, a2 = idx - x * n_so;
                     R[idx] -= cRp[a2] * w1[x] + cRq[a2] * w2[x];
@@ -617,6 +1096,9 @@ __global__ void __launch_bounds__(512) k_sweep(Tab T, Wk S, int64_t W, int mode,
                     const int x2 = idx / ne, x = idx - x2 * ne;
                     B[idx] -= cBp[x] * w1[x2] + cBq[x] * w2[x2];
                 }
+                if (tid == 0)
+                    md[MD_HNN] += dh + T.hdiag[a] + T.hdiag[b] - T.hdiag[i] - T.hdiag[j] +
+                                  T.D[(size_t)a * n_so + b] - T.D[(size_t)i * n_so + j];
             }
             // Jastrow sums s_p += J_pa [p!=a] - J_pi [p!=i] (+ the same for b, j)
             const double* Ja = T.J + (size_t)a * n_so;
@@ -656,6 +1138,7 @@ __global__ void __launch_bounds__(512) k_sweep(Tab T, Wk S, int64_t W, int mode,
         // ------------------------------------------------------- refresh
         if (refresh_period > 0 && ((gstep + 1) % (uint64_t)refresh_period) == 0) {
             refresh_state(T, slot, B, R, s, fcol, ipiv, mi, red);
+            hnn_full();
         }
     }
 
@@ -676,7 +1159,7 @@ __global__ void __launch_bounds__(512) k_sweep(Tab T, Wk S, int64_t W, int mode,
         }
     }
     if (tid == 0) {
-        S.hnn[w] = hnn;
+        S.hnn[w] = md[MD_HNN];
         S.status[w] = (uint32_t)mi[MI_ST];
         if (mode != MODE_INIT) {
             S.eloc[w] = el_last;
@@ -728,7 +1211,7 @@ __global__ void __launch_bounds__(64) k_excitations(Tab T, Wk S, int64_t w, int3
                     h = single_h(T, Gr, e, occl);
                 } else {
                     r = double_ratio(T, Gr, e, R, es, a, b);
-                    h = T.dv[Gr.base + e];
+                    h = T.dvK[2 * (size_t)(Gr.base + e)];
                 }
                 if (pos < cap) {
                     ijab[5 * pos + 0] = Gr.type;
@@ -761,7 +1244,7 @@ __global__ void k_dense_J(const double* Jp, double* J, int n_so) {
 }
 
 // exp(J_aa + J_bb + J_ab - J_ii - J_jj + J_ij - J_ai - J_aj - J_bi - J_bj) per doubles entry
-__global__ void k_doubles_K(const uint32_t* row_off, const uint32_t* dab, const double* J, double* dK, int n_so) {
+__global__ void k_doubles_K(const uint32_t* row_off, const uint32_t* dab, const double* J, double* dvK, int n_so) {
     const int row = blockIdx.x;
     const int i = row / n_so, j = row - i * n_so;
     if (j <= i) return;
@@ -774,7 +1257,7 @@ __global__ void k_doubles_K(const uint32_t* row_off, const uint32_t* dab, const 
         const double* Ja = J + (size_t)a * n_so;
         const double* Jb = J + (size_t)b * n_so;
         const double kap = Ja[a] + Jb[b] + Ja[b] - Ji[i] - Jj[j] + Ji[j] - Ja[i] - Ja[j] - Jb[i] - Jb[j];
-        dK[e] = exp(kap);
+        dvK[2 * (size_t)e + 1] = exp(kap);
     }
 }
 
@@ -891,7 +1374,8 @@ struct vmc_ctx {
     int block_threads = 0;  // 0 = automatic
     int64_t n_dent = 0, n_sent = 0;
     uint32_t *d_row_off = nullptr, *d_dab = nullptr, *d_s_off = nullptr, *d_sa = nullptr;
-    double *d_dv = nullptr, *d_dK = nullptr, *d_sh = nullptr, *d_sV = nullptr, *d_sK = nullptr, *d_D = nullptr,
+    uint64_t* d_dmask = nullptr;
+    double *d_dvK = nullptr, *d_sh = nullptr, *d_sV = nullptr, *d_sK = nullptr, *d_D = nullptr,
            *d_hdiag = nullptr, *d_J = nullptr, *d_theta = nullptr, *d_part = nullptr;
     int64_t part_cap = 0;
     bool params_set = false;
@@ -926,8 +1410,8 @@ Tab make_tab(const vmc_ctx* h) {
     T.eps = h->eps;
     T.row_off = h->d_row_off;
     T.dab = h->d_dab;
-    T.dv = h->d_dv;
-    T.dK = h->d_dK;
+    T.dmask = h->d_dmask;
+    T.dvK = h->d_dvK;
     T.s_off = h->d_s_off;
     T.sa = h->d_sa;
     T.sh = h->d_sh;
@@ -940,7 +1424,7 @@ Tab make_tab(const vmc_ctx* h) {
     return T;
 }
 
-int64_t scratch_bytes(const vmc_ctx* h) { return (int64_t)al16((size_t)h->G * 8); }
+int64_t scratch_bytes(const vmc_ctx* h) { return (int64_t)scratch_layout_bytes(h->ne); }
 
 vmc_status check_walkers(vmc_ctx* h, const vmc_walkers* w) {
     if (!w) return fail(h, VMC_E_ARG, "walkers is NULL");
@@ -972,29 +1456,40 @@ Wk make_wk(const vmc_ctx* h, const vmc_walkers* w) {
 
 constexpr size_t kMaxLds = 64 * 1024;
 
+// Size specialisations of the sweep kernel: (n_so, Ne, threads).
+struct SweepSpec {
+    int n_so, ne, nt;
+};
+constexpr SweepSpec kSpecs[] = {{16, 8, 64}, {16, 8, 128}, {40, 20, 128}, {40, 20, 256}, {64, 32, 256}};
+
+template <int NSO, int NE, int NT, bool NW1, bool SM>
+void launch_one(dim3 grid, dim3 block, size_t lds, hipStream_t st, const Tab& T, const Wk& S, const vmc_walkers* w,
+                int mode, int n_steps, double* eh, double* th, int64_t* ph, const vmc_ctx* h) {
+    hipLaunchKernelGGL((k_sweep<NSO, NE, NT, NW1, SM>), grid, block, lds, st, T, S, w->n_walkers, mode, n_steps,
+                       w->step, h->seed, h->refresh, eh, th, ph);
+}
+
 vmc_status launch_sweep(vmc_ctx* h, vmc_walkers* w, int mode, int n_steps, double* eh, double* th, int64_t* ph,
                         hipStream_t st) {
     int nt = h->block_threads;
-    if (nt <= 0) nt = (h->ne <= 32) ? 128 : 256;
-    bool small = lds_layout(h->n_so, h->ne, h->nw, h->G, nt, true).total <= kMaxLds;
-    const size_t lds = lds_layout(h->n_so, h->ne, h->nw, h->G, nt, small).total;
+    if (nt <= 0) nt = 256;
+    bool small = lds_layout(h->n_so, h->ne, h->nw, nt, true).total <= kMaxLds;
+    const size_t lds = lds_layout(h->n_so, h->ne, h->nw, nt, small).total;
     if (lds > kMaxLds) return fail(h, VMC_E_UNSUPPORTED, "system too large for the per-walker LDS budget");
     const bool nw1 = (h->nw == 1);
     const Tab T = make_tab(h);
     const Wk S = make_wk(h, w);
     const dim3 grid((unsigned)w->n_walkers), block((unsigned)nt);
-    if (nw1 && small)
-        hipLaunchKernelGGL((k_sweep<true, true>), grid, block, lds, st, T, S, w->n_walkers, mode, n_steps, w->step,
-                           h->seed, h->refresh, eh, th, ph);
-    else if (nw1)
-        hipLaunchKernelGGL((k_sweep<true, false>), grid, block, lds, st, T, S, w->n_walkers, mode, n_steps, w->step,
-                           h->seed, h->refresh, eh, th, ph);
-    else if (small)
-        hipLaunchKernelGGL((k_sweep<false, true>), grid, block, lds, st, T, S, w->n_walkers, mode, n_steps, w->step,
-                           h->seed, h->refresh, eh, th, ph);
-    else
-        hipLaunchKernelGGL((k_sweep<false, false>), grid, block, lds, st, T, S, w->n_walkers, mode, n_steps, w->step,
-                           h->seed, h->refresh, eh, th, ph);
+    auto spec = [&](int a, int b, int c) { return small && h->n_so == a && h->ne == b && nt == c; };
+    if (spec(16, 8, 64)) launch_one<16, 8, 64, true, true>(grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
+    else if (spec(16, 8, 128)) launch_one<16, 8, 128, true, true>(grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
+    else if (spec(40, 20, 128)) launch_one<40, 20, 128, true, true>(grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
+    else if (spec(40, 20, 256)) launch_one<40, 20, 256, true, true>(grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
+    else if (spec(64, 32, 256)) launch_one<64, 32, 256, true, true>(grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
+    else if (nw1 && small) launch_one<0, 0, 0, true, true>(grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
+    else if (nw1) launch_one<0, 0, 0, true, false>(grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
+    else if (small) launch_one<0, 0, 0, false, true>(grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
+    else launch_one<0, 0, 0, false, false>(grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
     HIP_OR_FAIL(h, hipGetLastError());
     return VMC_OK;
 }
@@ -1009,7 +1504,7 @@ vmc_status upload(vmc_ctx* h, T** dst, const std::vector<T>& src, hipStream_t st
 
 void free_ctx(vmc_ctx* h) {
     if (!h) return;
-    void* ptrs[] = {h->d_row_off, h->d_dab, h->d_s_off, h->d_sa, h->d_dv, h->d_dK, h->d_sh, h->d_sV,
+    void* ptrs[] = {h->d_row_off, h->d_dab, h->d_dmask, h->d_s_off, h->d_sa, h->d_dvK, h->d_sh, h->d_sV,
                     h->d_sK,      h->d_D,   h->d_hdiag, h->d_J,  h->d_theta, h->d_part};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -1128,11 +1623,19 @@ vmc_status vmc_init(const vmc_system_desc* desc, const double* h1, const vmc_eri
     for (size_t k = 0; k < T.dv.size(); ++k) dab[k] = (uint32_t)T.dab[2 * k] | ((uint32_t)T.dab[2 * k + 1] << 16);
     std::vector<uint32_t> s_off(T.s_off.begin(), T.s_off.end());
     std::vector<uint32_t> sa(T.sa.begin(), T.sa.end());
-    std::vector<double> zerosd(T.dv.size(), 0.0), zeross(T.sa.size(), 0.0);
+    std::vector<double> dvK(2 * T.dv.size(), 0.0), zeross(T.sa.size(), 0.0);
+    for (size_t k = 0; k < T.dv.size(); ++k) dvK[2 * k] = T.dv[k];
+    // occupancy masks of the doubles targets, for systems that fit one 64-bit word
+    std::vector<uint64_t> dmask;
+    if (h->n_so <= 64) {
+        dmask.resize(T.dv.size());
+        for (size_t k = 0; k < T.dv.size(); ++k)
+            dmask[k] = (1ull << T.dab[2 * k]) | (1ull << T.dab[2 * k + 1]);
+    }
     vmc_status u = VMC_OK;
     if ((u = upload(h, &h->d_row_off, row_off, stream)) != VMC_OK ||
-        (u = upload(h, &h->d_dab, dab, stream)) != VMC_OK || (u = upload(h, &h->d_dv, T.dv, stream)) != VMC_OK ||
-        (u = upload(h, &h->d_dK, zerosd, stream)) != VMC_OK || (u = upload(h, &h->d_s_off, s_off, stream)) != VMC_OK ||
+        (u = upload(h, &h->d_dab, dab, stream)) != VMC_OK ||
+        (h->n_so <= 64 && (u = upload(h, &h->d_dmask, dmask, stream)) != VMC_OK) || (u = upload(h, &h->d_dvK, dvK, stream)) != VMC_OK || (u = upload(h, &h->d_s_off, s_off, stream)) != VMC_OK ||
         (u = upload(h, &h->d_sa, sa, stream)) != VMC_OK || (u = upload(h, &h->d_sh, T.sh, stream)) != VMC_OK ||
         (u = upload(h, &h->d_sV, T.sV, stream)) != VMC_OK || (u = upload(h, &h->d_sK, zeross, stream)) != VMC_OK ||
         (u = upload(h, &h->d_D, T.D, stream)) != VMC_OK || (u = upload(h, &h->d_hdiag, T.hdiag, stream)) != VMC_OK) {
@@ -1161,7 +1664,7 @@ vmc_status vmc_set_params(vmc_handle h, const double* J_dev, const double* theta
     hipLaunchKernelGGL(k_dense_J, dim3(n_so), dim3(256), 0, st, J_dev, h->d_J, n_so);
     HIP_OR_FAIL(h, hipGetLastError());
     if (h->n_dent > 0) {
-        hipLaunchKernelGGL(k_doubles_K, dim3(n_so * n_so), dim3(64), 0, st, h->d_row_off, h->d_dab, h->d_J, h->d_dK,
+        hipLaunchKernelGGL(k_doubles_K, dim3(n_so * n_so), dim3(64), 0, st, h->d_row_off, h->d_dab, h->d_J, h->d_dvK,
                            n_so);
         HIP_OR_FAIL(h, hipGetLastError());
     }
@@ -1279,6 +1782,14 @@ vmc_status vmc_amsgrad(int64_t n, double* p, double* m, double* v, double* vh, c
     hipLaunchKernelGGL(k_amsgrad, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, p, m, v, vh, g, lr, b1, b2,
                        delta, (int)literal);
     HIP_OR_FAIL(nullptr, hipGetLastError());
+    return VMC_OK;
+}
+
+vmc_status vmc_set_launch(vmc_handle h, int32_t block_threads) {
+    if (!h) return fail(nullptr, VMC_E_ARG, "handle is NULL");
+    if (block_threads != 0 && (block_threads < 64 || block_threads > 512 || (block_threads & 63) != 0))
+        return fail(h, VMC_E_ARG, "block_threads must be 0 or a multiple of 64 in 64..512");
+    h->block_threads = block_threads;
     return VMC_OK;
 }
 

@@ -73,6 +73,7 @@ def load_library() -> C.CDLL:
         "vmc_uniforms": ([u64, i64, u64, P, P], i32),
         "vmc_decode_pick": ([i64, P], None),
         "vmc_table_info": ([P, P], i32),
+        "vmc_set_launch": ([P, i32], i32),
         "vmc_destroy": ([P], i32),
         "vmc_last_error": ([P], C.c_char_p),
         "vmc_host_tables_build": ([P, P, P, d, P], i32),
@@ -191,6 +192,10 @@ def vmc_table_info(handle):
     out = (C.c_int64 * 3)()
     _check(load_library().vmc_table_info(handle, out), handle, "vmc_table_info")
     return {"double_entries": int(out[0]), "single_entries": int(out[1]), "groups": int(out[2])}
+
+
+def vmc_set_launch(handle, block_threads: int) -> None:
+    _check(load_library().vmc_set_launch(handle, int(block_threads)), handle, "vmc_set_launch")
 
 
 def vmc_destroy(handle) -> None:
