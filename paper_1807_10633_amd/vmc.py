@@ -27,7 +27,7 @@ EXPORTED = (
     "vmc_init", "vmc_set_params", "vmc_walker_bytes", "vmc_walkers_init", "vmc_local_energy", "vmc_ctmc_step",
     "vmc_logderiv", "vmc_amsgrad", "vmc_excitations", "vmc_uniforms", "vmc_decode_pick", "vmc_table_info",
     "vmc_destroy", "vmc_last_error", "vmc_host_tables_build", "vmc_host_tables_sizes", "vmc_host_tables_get",
-    "vmc_host_tables_free",
+    "vmc_host_tables_free", "vmc_set_launch",
 )
 
 
