@@ -34,6 +34,30 @@ if ROOT not in sys.path:
 METRIC = "walker-steps/s (E_L+CTMC) at stated E_L error vs FP64 oracle; % HBM/MFMA peak"
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
+# HBM bytes per sweep launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of
+# `bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-check`, scaled by the
+# readings of a plain 1 GiB device copy (FETCH_SIZE reads 0.5 KiB per KiB
+# moved, WRITE_SIZE 1 KiB per KiB).  Keyed by the SHA-256 of the kernel sources
+# and the workload: any other kernel source or workload reports null.
+KERNEL_SOURCES = ("paper_1807_10633_amd/csrc/vmc.hip", "paper_1807_10633_amd/csrc/device.hpp")
+COUNTED_TRAFFIC = {
+    ("a28f8870b82a7900864fd36b84c791557118bbaf1c36a6ee1f43042fde10b74b",
+     "c129dedeae63596985a6c0e8630863b22050f8f8418fb19f4f3b2993ab2aab7f", "hchain20", 4096, 50, 0):
+        {"fetch_kib": 33695.1, "fetch_factor": 2.0, "write_kib": 41856.9, "write_factor": 1.0},
+}
+
+
+def counted_traffic(config, walkers, sweep, threads):
+    import hashlib
+
+    key = tuple(hashlib.sha256(open(os.path.join(ROOT, f), "rb").read()).hexdigest() for f in KERNEL_SOURCES)
+    rec = COUNTED_TRAFFIC.get(key + (config, walkers, sweep, threads))
+    if rec is None:
+        return None, None
+    fetch = rec["fetch_kib"] * 1024 * rec["fetch_factor"]
+    write = rec["write_kib"] * 1024 * rec["write_factor"]
+    return fetch + write, {"fetch_bytes": fetch, "write_bytes": write}
+
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -47,7 +71,24 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the E_L check against the oracle")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (reference kernel for the HBM byte "
+                         "counters) and exit")
     return ap.parse_args()
+
+
+def copy_calibration(mib):
+    """A plain device-to-device copy of known size: its FETCH_SIZE / WRITE_SIZE
+    readings give the factor that turns those counters into bytes."""
+    import torch
+
+    n = mib * (1 << 20) // 8
+    x = torch.arange(n, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": n * 8, "bytes_written": n * 8}), flush=True)
 
 
 def main():
@@ -58,6 +99,10 @@ def main():
                                    "would shard them with one gradient all-reduce per iteration, which is not "
                                    "implemented here; run with --gpus 1"}), flush=True)
         sys.exit(2)
+
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
 
     import numpy as np
     import torch
@@ -144,6 +189,7 @@ def main():
     flops = (10.0 * K_d + (ne + 7.0) * K_s + ne * (ne - 1) / 2 + ne + 2 * 1.5 * (n_so * ne + ne * ne) + 3 * n_so
              + (2.0 * ne ** 3 + 2.0 * n_so * ne * ne) / S)
     achieved_tflops = flops * W * S / (sweep_ms * 1e-3) / 1e12
+    traffic, traffic_split = counted_traffic(args.config, W, S, args.threads)
     roofline = {
         "bound": "alu",
         "kernel": "k_sweep (persistent E_L + CTMC + Sherman-Morrison, state in LDS)",
@@ -151,7 +197,9 @@ def main():
         "peak": FP64_VECTOR_PEAK_TFLOPS,
         "unit": "TFLOP/s",
         "frac": achieved_tflops / FP64_VECTOR_PEAK_TFLOPS,
-        "traffic": None,
+        "traffic": traffic,
+        "traffic_split": traffic_split,
+        "hbm_gbs_measured": (traffic / (sweep_ms * 1e-3) / 1e9) if traffic else None,
         "flop_per_walker_step": flops,
         "K_singles": K_s,
         "K_doubles": K_d,
@@ -186,8 +234,8 @@ def main():
         orc0.ctmc_batch(wl.occ[:threads], wl.ctmc_seed, 0, 2, ORC_LEMMA, threads)
         per = (time.perf_counter() - c0) / (2 * threads)  # wall s per walker-step at full thread use
         n_ws = max(threads, int(args.cpu_seconds / max(per, 1e-9)))
-        n_steps_cpu = 5
-        n_w = max(threads, min(W, n_ws // n_steps_cpu))
+        n_w = max(threads, min(W, n_ws // 5))
+        n_steps_cpu = max(5, n_ws // n_w)
         c0 = time.perf_counter()
         orc0.ctmc_batch(wl.occ[:n_w], wl.ctmc_seed, 0, n_steps_cpu, ORC_LEMMA, threads)
         cpu_wall = time.perf_counter() - c0
