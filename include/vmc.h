@@ -79,7 +79,11 @@ typedef struct {
     int32_t n_orb;          /* spatial orbitals n (n_so = 2n <= 1024) */
     int32_t n_alpha;        /* alpha electrons */
     int32_t n_beta;         /* beta electrons */
-    int32_t precision;      /* VMC_FP64 (VMC_MIXED is not accepted by this build) */
+    int32_t precision;      /* VMC_FP64: every quantity in FP64.
+                               VMC_MIXED: R stored and updated in FP32, ratios formed from FP32 minors,
+                               refresh GEMM R = theta B on the FP32 matrix cores; B = theta[N]^-1, its
+                               re-inversion, the update denominators (recomputed as theta[a,:] B in FP64),
+                               E_L, T and all accumulations stay FP64 */
     int32_t refresh_period; /* re-invert theta[N] from scratch every this many CTMC steps (>= 1) */
     int32_t reserved;       /* must be 0 */
     uint64_t seed;          /* Philox key word 0 for CTMC draws */
@@ -97,7 +101,7 @@ enum {
     VMC_F_SLOT_ORB,  /* int32  [W][Ne]     orbital held by each slot */
     VMC_F_ORB_SLOT,  /* int32  [W][n_so]   slot of each orbital, -1 when empty */
     VMC_F_AINV,      /* double [W][Ne][Ne] B = theta[N]^-1, column by slot */
-    VMC_F_R,         /* double [W][Ne][n_so] R, column by slot */
+    VMC_F_R,         /* double (VMC_FP64) or float (VMC_MIXED) [W][Ne][n_so] R, column by slot */
     VMC_F_JSUM,      /* double [W][n_so]   s_p = sum_{q != p} J_pq n_q */
     VMC_F_HNN,       /* double [W]         H_NN */
     VMC_F_ELOC,      /* double [W]         last local energy */

@@ -35,7 +35,7 @@ struct Wk {
     int32_t* slot_orb;
     int32_t* orb_slot;
     double* B;
-    double* R;
+    void* R;  // double (FP64 form) or float (mixed form)
     double* s;
     double* hnn;
     double* eloc;

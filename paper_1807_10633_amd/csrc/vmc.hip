@@ -144,10 +144,11 @@ __device__ __forceinline__ Group group_of(const Tab& T, int g, const int* occl, 
 }
 
 // Ratio and matrix element of candidate e of group Gr (slot convention).
-__device__ __forceinline__ double single_ratio(const Tab& T, const Group& Gr, uint32_t e, const double* R,
+template <typename RT>
+__device__ __forceinline__ double single_ratio(const Tab& T, const Group& Gr, uint32_t e, const RT* R,
                                                const double* es, int& a) {
     a = (int)T.sa[Gr.base + e];
-    return R[Gr.p * T.n_so + a] * es[a] * Gr.fac * T.sK[Gr.base + e];
+    return (double)R[Gr.p * T.n_so + a] * es[a] * Gr.fac * T.sK[Gr.base + e];
 }
 __device__ __forceinline__ double single_h(const Tab& T, const Group& Gr, uint32_t e, const int* occl) {
     const double* V = T.sV + (size_t)(Gr.base + e) * T.n_so;
@@ -155,15 +156,16 @@ __device__ __forceinline__ double single_h(const Tab& T, const Group& Gr, uint32
     for (int y = 0; y < T.ne; ++y) h += V[occl[y]];
     return h;
 }
-__device__ __forceinline__ double double_ratio(const Tab& T, const Group& Gr, uint32_t e, const double* R,
+template <typename RT>
+__device__ __forceinline__ double double_ratio(const Tab& T, const Group& Gr, uint32_t e, const RT* R,
                                                const double* es, int& a, int& b) {
     const uint32_t ab = T.dab[Gr.base + e];
     a = (int)(ab & 0xFFFFu);
     b = (int)(ab >> 16);
-    const double* Rp = R + Gr.p * T.n_so;
-    const double* Rq = R + Gr.q * T.n_so;
-    const double det = Rp[a] * Rq[b] - Rp[b] * Rq[a];
-    return det * es[a] * es[b] * T.dvK[2 * (size_t)(Gr.base + e) + 1] * Gr.fac;
+    const RT* Rp = R + Gr.p * T.n_so;
+    const RT* Rq = R + Gr.q * T.n_so;
+    const RT det = Rp[a] * Rq[b] - Rp[b] * Rq[a];
+    return (double)det * es[a] * es[b] * T.dvK[2 * (size_t)(Gr.base + e) + 1] * Gr.fac;
 }
 
 // Block-wide deterministic sum (every thread gets the same value).
@@ -195,7 +197,8 @@ __host__ __device__ inline size_t desc_bytes(int ne) {
     const size_t gd = (size_t)ne * (ne - 1) / 2;
     return al16(gd * 4) * 4 + al16(gd * 8);
 }
-__host__ __device__ __forceinline__ Lds lds_layout(int n_so, int ne, int nw, int nt, bool small) {
+// rb: bytes per R element (8 for the FP64 form, 4 for the mixed form)
+__host__ __device__ __forceinline__ Lds lds_layout(int n_so, int ne, int nw, int nt, bool small, int rb) {
     Lds L;
     size_t o = 0;
     const int nwv = nt / 64;
@@ -226,8 +229,8 @@ __host__ __device__ __forceinline__ Lds lds_layout(int n_so, int ne, int nw, int
     L.sfac = take((size_t)ne * 8);
     L.w1 = take((size_t)ne * 8);
     L.w2 = take((size_t)ne * 8);
-    L.cRp = take((size_t)n_so * 8);
-    L.cRq = take((size_t)n_so * 8);
+    L.cRp = take((size_t)n_so * rb);
+    L.cRq = take((size_t)n_so * rb);
     L.cBp = take((size_t)ne * 8);
     L.cBq = take((size_t)ne * 8);
     L.ipiv = take((size_t)ne * 4);
@@ -238,9 +241,9 @@ __host__ __device__ __forceinline__ Lds lds_layout(int n_so, int ne, int nw, int
         L.dvend = take(gd * 4);
         L.dpq = take(gd * 4);
         L.dfac = 0;
-        L.R = take((size_t)n_so * ne * 8);
+        L.R = take((size_t)n_so * ne * rb);
         L.B = take((size_t)ne * ne * 8);
-        L.Rh = take((size_t)n_so * ne * 8);
+        L.Rh = take((size_t)n_so * ne * rb);
     } else {
         L.dgend = L.ddelta = L.dvend = L.dpq = L.dfac = L.R = L.B = L.Rh = 0;
     }
@@ -256,10 +259,61 @@ enum { MD_T = 0, MD_BASE, MD_EL, MD_HNN, MD_TARGET };
 // per-wave state: entries of the two batch logs and the stream ranges
 enum { WS_NS = 0, WS_R1S = 3, WS_ND = 4, WS_R1D = 7 };
 
+// 16x16x4 matrix-core step in the precision of R.  Operands: lane l holds
+// A[l % 16][l / 16] and B[l / 16][l % 16]; element j of the accumulator of lane
+// l is D[row(l / 16, j)][l % 16] (the FP32 and FP64 instructions order the
+// rows differently).
+template <typename RT>
+struct Mma;
+template <>
+struct Mma<float> {
+    typedef float acc_t __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ acc_t step(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int kq, int j) { return 4 * kq + j; }
+};
+template <>
+struct Mma<double> {
+    typedef double acc_t __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ acc_t step(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int kq, int j) { return kq + 4 * j; }
+};
+
+// R[p][a] = sum_x B[p][x] theta[a][x] (p < Ne slots, a < n_so orbitals, x < Ne)
+// on the matrix cores: 16x16 output tiles dealt round-robin to the waves,
+// operands rounded to the precision of R, accumulation in that precision.
+template <typename RT>
+__device__ __forceinline__ void r_gemm(const Tab& T, const double* B, RT* R) {
+    const int ne = T.ne, n_so = T.n_so, l = lane_id();
+    const int wv = (int)__builtin_amdgcn_readfirstlane((uint32_t)(threadIdx.x >> 6)), nwv = blockDim.x >> 6;
+    const int mt = (ne + 15) >> 4, nt16 = (n_so + 15) >> 4;
+    const int m = l & 15, kq = l >> 4;
+    for (int t = wv; t < mt * nt16; t += nwv) {
+        const int pt = t / nt16, at = t - pt * nt16;
+        const int p = pt * 16 + m, a = at * 16 + m;
+        typename Mma<RT>::acc_t acc = {0, 0, 0, 0};
+        for (int k0 = 0; k0 < ne; k0 += 4) {
+            const int x = k0 + kq;
+            const RT av = (p < ne && x < ne) ? (RT)B[p * ne + x] : (RT)0;
+            const RT bv = (a < n_so && x < ne) ? (RT)T.theta[(size_t)a * n_so + x] : (RT)0;
+            acc = Mma<RT>::step(av, bv, acc);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int pr = pt * 16 + Mma<RT>::row(kq, j);
+            if (pr < ne && a < n_so) R[pr * n_so + a] = acc[j];
+        }
+    }
+}
+
 // Rebuild B = theta[N]^-1 (Gauss-Jordan, partial pivoting, FP64), R and s from
 // the slot list.  B is stored column by slot (B[x][p] at B[p*ne + x]): the
 // elimination works on A^T, whose inverse laid out row-major is exactly that.
-__device__ __forceinline__ void refresh_state(const Tab& T, const int* slot, double* B, double* R, double* s, double* fcol, int* ipiv,
+template <typename RT>
+__device__ __forceinline__ void refresh_state(const Tab& T, const int* slot, double* B, RT* R, double* s, double* fcol, int* ipiv,
                               int* mi, double* red) {
     const int tid = threadIdx.x, nt = blockDim.x, ne = T.ne, n_so = T.n_so;
     const int wv = tid >> 6, nwv = nt >> 6;
@@ -324,14 +378,7 @@ __device__ __forceinline__ void refresh_state(const Tab& T, const int* slot, dou
             }
         __syncthreads();
     }
-    for (int idx = tid; idx < n_so * ne; idx += nt) {
-        const int p = idx / n_so, a = idx - p * n_so;
-        const double* th = T.theta + (size_t)a * n_so;
-        const double* Bp = B + p * ne;
-        double acc = 0.0;
-        for (int x = 0; x < ne; ++x) acc += th[x] * Bp[x];
-        R[idx] = acc;
-    }
+    r_gemm<RT>(T, B, R);
     for (int pp = tid; pp < n_so; pp += nt) {
         const double* Jr = T.J + (size_t)pp * n_so;
         double acc = 0.0;
@@ -433,10 +480,11 @@ __device__ __forceinline__ double block_total(double v, double* red) {
 // concatenation of its groups' table rows (singles: one group per occupied
 // orbital; doubles: one per occupied pair), each padded to a multiple of 64
 // positions so that a 64-lane chunk lies within one group.
+template <typename RT>
 struct StepView {
     const int* occl;
     const double* es;     // exp(s_p)          (unscaled path)
-    const double* R;      // R (unscaled path) or Rh[p][a] = R[a][p] exp(s_a - s_orb(p)) (scaled path)
+    const RT* R;          // R (unscaled path) or Rh[p][a] = R[a][p] exp(s_a - s_orb(p)) (scaled path)
     const uint32_t* sgend;  // singles: padded inclusive stream ends per occupied index
     const uint32_t* sdelta; //          table offset = stream position + delta
     const uint32_t* svend;  //          end of the group's valid positions
@@ -452,8 +500,8 @@ struct StepView {
 // Ratio psi(M)/psi(N) (and, when WANT_H, the local-energy term H_NM * ratio)
 // of a queued candidate: table offset `off`, group g, targets in `ab` (a
 // 64-bit occupancy mask when MASK, else a | b << 16 / a).
-template <bool DOUBLES, bool WANT_H, bool MASK, bool SCALED>
-__device__ __forceinline__ double cand_eval(const Tab& T, const StepView& V, uint32_t off, uint32_t g, uint64_t ab,
+template <bool DOUBLES, bool WANT_H, bool MASK, bool SCALED, typename RT>
+__device__ __forceinline__ double cand_eval(const Tab& T, const StepView<RT>& V, uint32_t off, uint32_t g, uint64_t ab,
                                             double2 vk, double& term, int& cp, int& cq, int& ca, int& cb) {
     const int n_so = T.n_so;
     if (DOUBLES) {
@@ -467,9 +515,9 @@ __device__ __forceinline__ double cand_eval(const Tab& T, const StepView& V, uin
             a = (int)(ab & 0xFFFFu);
             b = (int)((ab >> 16) & 0xFFFFu);
         }
-        const double* Rp = V.R + p * n_so;
-        const double* Rq = V.R + q * n_so;
-        const double det = Rp[a] * Rq[b] - Rp[b] * Rq[a];
+        const RT* Rp = V.R + p * n_so;
+        const RT* Rq = V.R + q * n_so;
+        const double det = (double)(Rp[a] * Rq[b] - Rp[b] * Rq[a]);
         const double ratio = SCALED ? det * vk.y : det * V.es[a] * V.es[b] * vk.y * V.dfac[g];
         if (WANT_H) term = vk.x * ratio;
         cp = p; cq = q; ca = a; cb = b;
@@ -477,7 +525,8 @@ __device__ __forceinline__ double cand_eval(const Tab& T, const StepView& V, uin
     } else {
         const int p = (int)V.spq[g];
         const int a = (int)ab;
-        const double ratio = SCALED ? V.R[p * n_so + a] * T.sK[off] : V.R[p * n_so + a] * V.es[a] * V.sfac[g] * T.sK[off];
+        const double r1 = (double)V.R[p * n_so + a];
+        const double ratio = SCALED ? r1 * T.sK[off] : r1 * V.es[a] * V.sfac[g] * T.sK[off];
         if (WANT_H) {
             const double* Vr = T.sV + (size_t)off * n_so;
             double h = T.sh[off];
@@ -536,8 +585,8 @@ struct BatchLog {
 // the last positive-rate candidate); pick = {type, p, q, a, b}; returns true
 // if found.
 // The table loads of kUnroll chunks are issued together before they are consumed.
-template <bool DOUBLES, bool PICK, bool NW1, bool SCALED>
-__device__ __forceinline__ bool stream_pass(const Tab& T, const StepView& V, uint64_t occ0, const uint64_t* occw, uint32_t c0,
+template <bool DOUBLES, bool PICK, bool NW1, bool SCALED, typename RT>
+__device__ __forceinline__ bool stream_pass(const Tab& T, const StepView<RT>& V, uint64_t occ0, const uint64_t* occw, uint32_t c0,
                             uint32_t c1, uint32_t g0, uint32_t first, uint64_t* q64, uint64_t* qab, double2* qvk,
                             double& el, double* log_sum, uint32_t* log_off, uint32_t* log_grp, int log_cap, int& log_n,
                             double base, double target, bool fallback, int* pick) {
@@ -718,7 +767,9 @@ enum { MODE_ELOC = 0, MODE_CTMC = 1, MODE_INIT = 2 };
 // NSO_T, NE_T, NT_T: compile-time n_so, Ne and workgroup size of a size
 // specialisation (0 = taken from the arguments at run time).  With them the
 // LDS layout and loop bounds fold to constants.
-template <int NSO_T, int NE_T, int NT_T, bool NW1, bool SMALL>
+// RT: element type of R (double: FP64 form; float: mixed form, where B, the
+// update denominators and every accumulation stay FP64).
+template <int NSO_T, int NE_T, int NT_T, bool NW1, bool SMALL, typename RT>
 __global__ void __launch_bounds__(NT_T ? NT_T : 512) VMC_SWEEP_ATTR
 k_sweep(Tab Targ, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, uint64_t seed, int refresh_period,
         double* eloc_hist, double* t_hist, int64_t* pick_hist) {
@@ -738,7 +789,8 @@ k_sweep(Tab Targ, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, uint64
     const int n_so = T.n_so, ne = T.ne, nw = T.nw;
     const int gd = ne * (ne - 1) / 2;
     T.G = ne + gd;
-    const Lds L = lds_layout(n_so, ne, nw, nt, SMALL);
+    const Lds L = lds_layout(n_so, ne, nw, nt, SMALL, (int)sizeof(RT));
+    constexpr bool MIXED = sizeof(RT) < sizeof(double);
     uint64_t* occw = (uint64_t*)(smem + L.occw);
     int* occl = (int*)(smem + L.occl);
     int* slot = (int*)(smem + L.slot);
@@ -765,25 +817,26 @@ k_sweep(Tab Targ, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, uint64
     double* sfac = (double*)(smem + L.sfac);
     double* w1 = (double*)(smem + L.w1);
     double* w2 = (double*)(smem + L.w2);
-    double* cRp = (double*)(smem + L.cRp);
-    double* cRq = (double*)(smem + L.cRq);
+    RT* cRp = (RT*)(smem + L.cRp);
+    RT* cRq = (RT*)(smem + L.cRq);
     double* cBp = (double*)(smem + L.cBp);
     double* cBq = (double*)(smem + L.cBq);
     int* ipiv = (int*)(smem + L.ipiv);
     double* fcol = (double*)(smem + L.fcol);
-    double *R, *B, *Rh, *dfac;
+    RT *R, *Rh;
+    double *B, *dfac;
     uint32_t *dgend, *ddelta, *dvend, *dpq;
     if (SMALL) {
-        R = (double*)(smem + L.R);
+        R = (RT*)(smem + L.R);
         B = (double*)(smem + L.B);
-        Rh = (double*)(smem + L.Rh);
+        Rh = (RT*)(smem + L.Rh);
         dgend = (uint32_t*)(smem + L.dgend);
         ddelta = (uint32_t*)(smem + L.ddelta);
         dvend = (uint32_t*)(smem + L.dvend);
         dpq = (uint32_t*)(smem + L.dpq);
         dfac = nullptr;
     } else {
-        R = S.R + (size_t)w * n_so * ne;
+        R = (RT*)S.R + (size_t)w * n_so * ne;
         B = S.B + (size_t)w * ne * ne;
         Rh = R;
         uint8_t* sc = S.scratch + (size_t)w * S.scratch_stride;
@@ -794,7 +847,7 @@ k_sweep(Tab Targ, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, uint64
         dpq = (uint32_t*)(sc + 3 * st4);
         dfac = (double*)(sc + 4 * st4);
     }
-    const StepView V{occl, es, SMALL ? Rh : R, sgend, sdelta, svend, spq, sfac, dgend, ddelta, dvend, dpq, dfac};
+    const StepView<RT> V{occl, es, SMALL ? Rh : R, sgend, sdelta, svend, spq, sfac, dgend, ddelta, dvend, dpq, dfac};
 
     // ---------------------------------------------------------------- load
     for (int k = tid; k < nw; k += nt) occw[k] = S.occ[(size_t)w * nw + k];
@@ -830,7 +883,7 @@ k_sweep(Tab Targ, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, uint64
             s[pp] = S.s[(size_t)w * n_so + pp];
         }
         if (SMALL) {
-            const double* Rg = S.R + (size_t)w * n_so * ne;
+            const RT* Rg = (const RT*)S.R + (size_t)w * n_so * ne;
             const double* Bg = S.B + (size_t)w * ne * ne;
             for (int k = tid; k < n_so * ne; k += nt) R[k] = Rg[k];
             for (int k = tid; k < ne * ne; k += nt) B[k] = Bg[k];
@@ -875,7 +928,7 @@ k_sweep(Tab Targ, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, uint64
             // of R (they factor out of every 1x1 and 2x2 minor)
             for (int idx = tid; idx < n_so * ne; idx += nt) {
                 const int p = idx / n_so, a = idx - p * n_so;
-                Rh[idx] = R[idx] * es[a] * ies[slot[p]];
+                Rh[idx] = (RT)((double)R[idx] * es[a] * ies[slot[p]]);
             }
         }
         // group descriptors: row lengths padded to 64 (scanned into stream
@@ -1043,7 +1096,38 @@ k_sweep(Tab Targ, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, uint64
         if (ptype != 0) {
             const int p = mi[MI_PP], q = mi[MI_PQ], a = mi[MI_PA], b = mi[MI_PB];
             const int i = slot[p], j = (ptype == 2) ? slot[q] : -1;
-            const double* Rp = R + p * n_so;
+            // rows a (and b) of R over the slots, in FP64: read from R in the
+            // FP64 form; recomputed as theta[a, 0:Ne] B in the mixed form, so
+            // that the update denominators and B stay FP64-exact
+            for (int x = tid; x < ne; x += nt) {
+                double ra, rb = 0.0;
+                if (MIXED) {
+                    const double* tha = T.theta + (size_t)a * n_so;
+                    const double* Bx = B + x * ne;
+                    ra = 0.0;
+                    for (int c = 0; c < ne; ++c) ra += tha[c] * Bx[c];
+                    if (ptype == 2) {
+                        const double* thb = T.theta + (size_t)b * n_so;
+                        for (int c = 0; c < ne; ++c) rb += thb[c] * Bx[c];
+                    }
+                } else {
+                    ra = (double)R[x * n_so + a];
+                    if (ptype == 2) rb = (double)R[x * n_so + b];
+                }
+                w1[x] = ra;
+                w2[x] = rb;
+            }
+            const RT* Rp = R + p * n_so;
+            const RT* Rq = R + q * n_so;
+            if (!MIXED)
+                for (int a2 = tid; a2 < n_so; a2 += nt) {
+                    cRp[a2] = Rp[a2];
+                    if (ptype == 2) cRq[a2] = Rq[a2];
+                }
+            for (int x = tid; x < ne; x += nt) {
+                cBp[x] = B[p * ne + x];
+                if (ptype == 2) cBq[x] = B[q * ne + x];
+            }
             // change of H_NN (sum over the unchanged occupied orbitals)
             double dh = 0.0;
             for (int x = tid; x < ne; x += nt) {
@@ -1052,46 +1136,40 @@ k_sweep(Tab Targ, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, uint64
                 dh += T.D[(size_t)a * n_so + kk] - T.D[(size_t)i * n_so + kk];
                 if (ptype == 2) dh += T.D[(size_t)b * n_so + kk] - T.D[(size_t)j * n_so + kk];
             }
+            dh = block_total(dh, red);  // its barriers also publish the rows and copies above
             if (ptype == 1) {
-                const double rho = Rp[a];
-                for (int x = tid; x < ne; x += nt) w1[x] = (R[x * n_so + a] - (x == p ? 1.0 : 0.0)) / rho;
-                for (int a2 = tid; a2 < n_so; a2 += nt) cRp[a2] = Rp[a2];
-                for (int x = tid; x < ne; x += nt) cBp[x] = B[p * ne + x];
+                const double rho = w1[p];
                 if (tid == 0 && fabs(rho) < 1e-8) mi[MI_ST] |= (int)VMC_ST_SMALLDEN;
-                dh = block_total(dh, red);  // its barriers also order the w/column writes before use
-                for (int idx = tid; idx < n_so * ne; idx += nt) {
-                    const int x = idx / n_so, a2 = idx - x * n_so;
-                    R[idx] -= cRp[a2] * w1[x];
-                }
+                __syncthreads();
+                for (int x = tid; x < ne; x += nt) w1[x] = (w1[x] - (x == p ? 1.0 : 0.0)) / rho;
+                __syncthreads();
+                if (!MIXED)
+                    for (int idx = tid; idx < n_so * ne; idx += nt) {
+                        const int x = idx / n_so, a2 = idx - x * n_so;
+                        R[idx] -= cRp[a2] * w1[x];
+                    }
                 for (int idx = tid; idx < ne * ne; idx += nt) {
                     const int x2 = idx / ne, x = idx - x2 * ne;
                     B[idx] -= cBp[x] * w1[x2];
                 }
                 if (tid == 0) md[MD_HNN] += dh + T.hdiag[a] - T.hdiag[i];
             } else {
-                const double* Rq = R + q * n_so;
-                const double c00 = Rp[a], c01 = Rq[a], c10 = Rp[b], c11 = Rq[b];
+                const double c00 = w1[p], c01 = w1[q], c10 = w2[p], c11 = w2[q];
                 const double det = c00 * c11 - c10 * c01;
+                if (tid == 0 && fabs(det) < 1e-8) mi[MI_ST] |= (int)VMC_ST_SMALLDEN;
+                __syncthreads();
                 for (int x = tid; x < ne; x += nt) {
-                    const double ra = R[x * n_so + a] - (x == p ? 1.0 : 0.0);
-                    const double rb = R[x * n_so + b] - (x == q ? 1.0 : 0.0);
+                    const double ra = w1[x] - (x == p ? 1.0 : 0.0);
+                    const double rb = w2[x] - (x == q ? 1.0 : 0.0);
                     w1[x] = (c11 * ra - c01 * rb) / det;
                     w2[x] = (-c10 * ra + c00 * rb) / det;
                 }
-                for (int a2 = tid; a2 < n_so; a2 += nt) {
-                    cRp[a2] = Rp[a2];
-                    cRq[a2] = Rq[a2];
-                }
-                for (int x = tid; x < ne; x += nt) {
-                    cBp[x] = B[p * ne + x];
-                    cBq[x] = B[q * ne + x];
-                }
-                if (tid == 0 && fabs(det) < 1e-8) mi[MI_ST] |= (int)VMC_ST_SMALLDEN;
-                dh = block_total(dh, red);
-                for (int idx = tid; idx < n_so * ne; idx += nt) {
-                    const int x = idx / n_so, a2 = idx - x * n_so;
-                    R[idx] -= cRp[a2] * w1[x] + cRq[a2] * w2[x];
-                }
+                __syncthreads();
+                if (!MIXED)
+                    for (int idx = tid; idx < n_so * ne; idx += nt) {
+                        const int x = idx / n_so, a2 = idx - x * n_so;
+                        R[idx] -= cRp[a2] * w1[x] + cRq[a2] * w2[x];
+                    }
                 for (int idx = tid; idx < ne * ne; idx += nt) {
                     const int x2 = idx / ne, x = idx - x2 * ne;
                     B[idx] -= cBp[x] * w1[x2] + cBq[x] * w2[x2];
@@ -1099,6 +1177,14 @@ k_sweep(Tab Targ, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, uint64
                 if (tid == 0)
                     md[MD_HNN] += dh + T.hdiag[a] + T.hdiag[b] - T.hdiag[i] - T.hdiag[j] +
                                   T.D[(size_t)a * n_so + b] - T.D[(size_t)i * n_so + j];
+            }
+            if (MIXED) {
+                // FP32 R is not carried by the update (its rounding would be
+                // amplified by |w| every move): it is re-formed from the
+                // FP64-exact B on the matrix cores, which costs one small
+                // GEMM per move
+                __syncthreads();
+                r_gemm<RT>(T, B, R);
             }
             // Jastrow sums s_p += J_pa [p!=a] - J_pi [p!=i] (+ the same for b, j)
             const double* Ja = T.J + (size_t)a * n_so;
@@ -1152,7 +1238,7 @@ k_sweep(Tab Targ, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, uint64
             S.s[(size_t)w * n_so + pp] = s[pp];
         }
         if (SMALL) {
-            double* Rg = S.R + (size_t)w * n_so * ne;
+            RT* Rg = (RT*)S.R + (size_t)w * n_so * ne;
             double* Bg = S.B + (size_t)w * ne * ne;
             for (int k = tid; k < n_so * ne; k += nt) Rg[k] = R[k];
             for (int k = tid; k < ne * ne; k += nt) Bg[k] = B[k];
@@ -1171,6 +1257,7 @@ k_sweep(Tab Targ, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, uint64
 }
 
 // Canonical candidate list of one walker (single wave, groups in order).
+template <typename RT>
 __global__ void __launch_bounds__(64) k_excitations(Tab T, Wk S, int64_t w, int32_t* ijab, double* hval, double* ratio,
                                                     int64_t cap, int64_t* count) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1197,7 +1284,7 @@ __global__ void __launch_bounds__(64) k_excitations(Tab T, Wk S, int64_t w, int3
             occl[rank] = pp;
         }
     __syncthreads();
-    const double* R = S.R + (size_t)w * n_so * ne;
+    const RT* R = (const RT*)S.R + (size_t)w * n_so * ne;
     int64_t off = 0;
     for (int g = 0; g < T.G; ++g) {
         const Group Gr = group_of(T, g, occl, oslot, ies);
@@ -1426,6 +1513,9 @@ Tab make_tab(const vmc_ctx* h) {
 
 int64_t scratch_bytes(const vmc_ctx* h) { return (int64_t)scratch_layout_bytes(h->ne); }
 
+// bytes per element of R: FP64 form 8, mixed form 4
+size_t r_bytes(const vmc_ctx* h) { return h->precision == VMC_MIXED ? 4 : 8; }
+
 vmc_status check_walkers(vmc_ctx* h, const vmc_walkers* w) {
     if (!w) return fail(h, VMC_E_ARG, "walkers is NULL");
     if (w->n_walkers <= 0 || w->n_walkers > (int64_t)INT_MAX) return fail(h, VMC_E_ARG, "n_walkers out of range");
@@ -1442,7 +1532,7 @@ Wk make_wk(const vmc_ctx* h, const vmc_walkers* w) {
     S.slot_orb = (int32_t*)w->slot_orb;
     S.orb_slot = (int32_t*)w->orb_slot;
     S.B = (double*)w->ainv;
-    S.R = (double*)w->r;
+    S.R = w->r;
     S.s = (double*)w->jsum;
     S.hnn = (double*)w->hnn;
     S.eloc = (double*)w->eloc;
@@ -1462,34 +1552,45 @@ struct SweepSpec {
 };
 constexpr SweepSpec kSpecs[] = {{16, 8, 64}, {16, 8, 128}, {40, 20, 128}, {40, 20, 256}, {64, 32, 256}};
 
-template <int NSO, int NE, int NT, bool NW1, bool SM>
+template <int NSO, int NE, int NT, bool NW1, bool SM, typename RT>
 void launch_one(dim3 grid, dim3 block, size_t lds, hipStream_t st, const Tab& T, const Wk& S, const vmc_walkers* w,
                 int mode, int n_steps, double* eh, double* th, int64_t* ph, const vmc_ctx* h) {
-    hipLaunchKernelGGL((k_sweep<NSO, NE, NT, NW1, SM>), grid, block, lds, st, T, S, w->n_walkers, mode, n_steps,
+    hipLaunchKernelGGL((k_sweep<NSO, NE, NT, NW1, SM, RT>), grid, block, lds, st, T, S, w->n_walkers, mode, n_steps,
                        w->step, h->seed, h->refresh, eh, th, ph);
+}
+
+template <typename RT>
+void launch_prec(bool small, bool nw1, int nt, dim3 grid, dim3 block, size_t lds, hipStream_t st, const Tab& T,
+                 const Wk& S, const vmc_walkers* w, int mode, int n_steps, double* eh, double* th, int64_t* ph,
+                 const vmc_ctx* h) {
+    auto spec = [&](int a, int b, int c) { return small && h->n_so == a && h->ne == b && nt == c; };
+    if (spec(16, 8, 64)) launch_one<16, 8, 64, true, true, RT>(grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
+    else if (spec(16, 8, 128)) launch_one<16, 8, 128, true, true, RT>(grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
+    else if (spec(40, 20, 128)) launch_one<40, 20, 128, true, true, RT>(grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
+    else if (spec(40, 20, 256)) launch_one<40, 20, 256, true, true, RT>(grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
+    else if (spec(64, 32, 256)) launch_one<64, 32, 256, true, true, RT>(grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
+    else if (nw1 && small) launch_one<0, 0, 0, true, true, RT>(grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
+    else if (nw1) launch_one<0, 0, 0, true, false, RT>(grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
+    else if (small) launch_one<0, 0, 0, false, true, RT>(grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
+    else launch_one<0, 0, 0, false, false, RT>(grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
 }
 
 vmc_status launch_sweep(vmc_ctx* h, vmc_walkers* w, int mode, int n_steps, double* eh, double* th, int64_t* ph,
                         hipStream_t st) {
     int nt = h->block_threads;
     if (nt <= 0) nt = 256;
-    bool small = lds_layout(h->n_so, h->ne, h->nw, nt, true).total <= kMaxLds;
-    const size_t lds = lds_layout(h->n_so, h->ne, h->nw, nt, small).total;
+    const int rb = (int)r_bytes(h);
+    bool small = lds_layout(h->n_so, h->ne, h->nw, nt, true, rb).total <= kMaxLds;
+    const size_t lds = lds_layout(h->n_so, h->ne, h->nw, nt, small, rb).total;
     if (lds > kMaxLds) return fail(h, VMC_E_UNSUPPORTED, "system too large for the per-walker LDS budget");
     const bool nw1 = (h->nw == 1);
     const Tab T = make_tab(h);
     const Wk S = make_wk(h, w);
     const dim3 grid((unsigned)w->n_walkers), block((unsigned)nt);
-    auto spec = [&](int a, int b, int c) { return small && h->n_so == a && h->ne == b && nt == c; };
-    if (spec(16, 8, 64)) launch_one<16, 8, 64, true, true>(grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
-    else if (spec(16, 8, 128)) launch_one<16, 8, 128, true, true>(grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
-    else if (spec(40, 20, 128)) launch_one<40, 20, 128, true, true>(grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
-    else if (spec(40, 20, 256)) launch_one<40, 20, 256, true, true>(grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
-    else if (spec(64, 32, 256)) launch_one<64, 32, 256, true, true>(grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
-    else if (nw1 && small) launch_one<0, 0, 0, true, true>(grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
-    else if (nw1) launch_one<0, 0, 0, true, false>(grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
-    else if (small) launch_one<0, 0, 0, false, true>(grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
-    else launch_one<0, 0, 0, false, false>(grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
+    if (h->precision == VMC_MIXED)
+        launch_prec<float>(small, nw1, nt, grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
+    else
+        launch_prec<double>(small, nw1, nt, grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
     HIP_OR_FAIL(h, hipGetLastError());
     return VMC_OK;
 }
@@ -1519,7 +1620,8 @@ vmc_status validate_desc(const vmc_system_desc* d) {
         return fail(nullptr, VMC_E_ARG, "electron counts out of range");
     if (d->n_alpha + d->n_beta > 2 * d->n_orb - 1)
         return fail(nullptr, VMC_E_ARG, "at least one empty spin-orbital is required");
-    if (d->precision != VMC_FP64) return fail(nullptr, VMC_E_UNSUPPORTED, "only VMC_FP64 is supported by this build");
+    if (d->precision != VMC_FP64 && d->precision != VMC_MIXED)
+        return fail(nullptr, VMC_E_ARG, "precision must be VMC_FP64 or VMC_MIXED");
     if (d->refresh_period < 1) return fail(nullptr, VMC_E_ARG, "refresh_period must be >= 1");
     if (d->reserved != 0) return fail(nullptr, VMC_E_ARG, "reserved must be 0");
     return VMC_OK;
@@ -1684,7 +1786,7 @@ vmc_status vmc_walker_bytes(vmc_handle h, int64_t W, size_t fb[VMC_NFIELDS]) {
     fb[VMC_F_SLOT_ORB] = w * h->ne * 4;
     fb[VMC_F_ORB_SLOT] = w * h->n_so * 4;
     fb[VMC_F_AINV] = w * h->ne * h->ne * 8;
-    fb[VMC_F_R] = w * h->ne * h->n_so * 8;
+    fb[VMC_F_R] = w * h->ne * h->n_so * r_bytes(h);
     fb[VMC_F_JSUM] = w * h->n_so * 8;
     fb[VMC_F_HNN] = w * 8;
     fb[VMC_F_ELOC] = w * 8;
@@ -1730,8 +1832,12 @@ vmc_status vmc_excitations(vmc_handle h, const vmc_walkers* w, int64_t walker, i
     if (!count || cap < 0 || (cap > 0 && (!ijab || !hval || !ratio))) return fail(h, VMC_E_ARG, "bad output buffers");
     const size_t lds = al16((size_t)h->nw * 8) + al16((size_t)h->ne * 4) + al16((size_t)h->n_so * 4) +
                        2 * (size_t)h->n_so * 8 + (size_t)kQueue * 4;
-    hipLaunchKernelGGL(k_excitations, dim3(1), dim3(64), lds, st, make_tab(h), make_wk(h, w), walker, ijab, hval,
-                       ratio, cap, count);
+    if (h->precision == VMC_MIXED)
+        hipLaunchKernelGGL(k_excitations<float>, dim3(1), dim3(64), lds, st, make_tab(h), make_wk(h, w), walker, ijab,
+                           hval, ratio, cap, count);
+    else
+        hipLaunchKernelGGL(k_excitations<double>, dim3(1), dim3(64), lds, st, make_tab(h), make_wk(h, w), walker, ijab,
+                           hval, ratio, cap, count);
     HIP_OR_FAIL(h, hipGetLastError());
     return VMC_OK;
 }

@@ -275,6 +275,7 @@ class System:
         self.n_words = (self.n_so + 63) // 64
         self.n_params = self.n_so * (self.n_so + 1) // 2 + self.n_so * self.n_so
         self.device = device
+        self.precision = int(precision)
         self.handle = vmc_init(n_orb, n_alpha, n_beta, h1, eri_idx, eri_val, eps, precision=precision,
                                refresh_period=refresh_period, seed=seed)
 
@@ -299,6 +300,13 @@ class System:
         w.view("occ_bits", torch.int64)[: occ.size].copy_(torch.from_numpy(occ.view(np.int64).reshape(-1)))
         vmc_walkers_init(self.handle, w)
         return w
+
+    @property
+    def r_dtype(self):
+        """Element type of the walkers' R buffer: float32 in the mixed form."""
+        import torch
+
+        return torch.float32 if self.precision == VMC_MIXED else torch.float64
 
     def table_info(self):
         return vmc_table_info(self.handle)

@@ -71,6 +71,7 @@ def teacher_forced_check(orc: OracleSystem, seed, occ0, step0, eh, th, ph, walke
 
     n_steps = eh.shape[0]
     dE = []
+    T_or = []
     dt_rel = []
     n_pick = 0
     n_exempt = 0
@@ -81,6 +82,7 @@ def teacher_forced_check(orc: OracleSystem, seed, occ0, step0, eh, th, ph, walke
             new, el, t, pick, margin, rc = orc.ctmc_step(bits, seed, int(w), int(step0 + k), mode)
             assert rc == 0, f"oracle failed on walker {w} step {k} ({rc})"
             dE.append(abs(el - eh[k, w]))
+            T_or.append(1.0 / t)
             dt_rel.append(abs(t - th[k, w]) / t)
             gpu_pick = vmc_decode_pick(int(ph[k, w]))
             if margin < PICK_MARGIN:
@@ -98,4 +100,6 @@ def teacher_forced_check(orc: OracleSystem, seed, occ0, step0, eh, th, ph, walke
         "picks_compared": n_pick,
         "picks_exempt": n_exempt,
         "mismatches": mismatches,
+        "dE_all": dE,
+        "T_all": np.array(T_or),
     }
