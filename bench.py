@@ -42,16 +42,16 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 KERNEL_SOURCES = ("paper_1807_10633_amd/csrc/vmc.hip", "paper_1807_10633_amd/csrc/device.hpp")
 COUNTED_TRAFFIC = {
     ("a28f8870b82a7900864fd36b84c791557118bbaf1c36a6ee1f43042fde10b74b",
-     "c129dedeae63596985a6c0e8630863b22050f8f8418fb19f4f3b2993ab2aab7f", "hchain20", 4096, 50, 0):
+     "c129dedeae63596985a6c0e8630863b22050f8f8418fb19f4f3b2993ab2aab7f", "hchain20", 4096, 50, 0, "fp64"):
         {"fetch_kib": 33695.1, "fetch_factor": 2.0, "write_kib": 41856.9, "write_factor": 1.0},
 }
 
 
-def counted_traffic(config, walkers, sweep, threads):
+def counted_traffic(config, walkers, sweep, threads, precision):
     import hashlib
 
     key = tuple(hashlib.sha256(open(os.path.join(ROOT, f), "rb").read()).hexdigest() for f in KERNEL_SOURCES)
-    rec = COUNTED_TRAFFIC.get(key + (config, walkers, sweep, threads))
+    rec = COUNTED_TRAFFIC.get(key + (config, walkers, sweep, threads, precision))
     if rec is None:
         return None, None
     fetch = rec["fetch_kib"] * 1024 * rec["fetch_factor"]
@@ -71,6 +71,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the E_L check against the oracle")
+    ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
+                    help="form of the headline number (the other form is measured beside it)")
+    ap.add_argument("--no-other-form", action="store_true", help="do not measure the other precision form")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (reference kernel for the HBM byte "
                          "counters) and exit")
@@ -114,56 +117,94 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     wl = make_config(args.config, n_walkers=args.walkers)
-    sysm = vmc.System.from_workload(wl, refresh_period=args.sweep)
-    if args.threads:
-        vmc.vmc_set_launch(sysm.handle, args.threads)
-    walkers = sysm.walkers(wl.occ)
     W, S = args.walkers, args.sweep
-    nj = sysm.n_so * (sysm.n_so + 1) // 2
-    params = torch.cat([sysm.J, sysm.theta.reshape(-1)]).clone()
-    m = torch.zeros_like(params)
-    v = torch.zeros_like(params)
-    vh = torch.zeros_like(params)
-    G = torch.zeros_like(params)
-    stream = torch.cuda.current_stream()
-    sweep_events = []
+    head_prec = vmc.VMC_MIXED if args.precision == "mixed" else vmc.VMC_FP64
 
-    def one_step(timed):
-        if timed:
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-        vmc.vmc_ctmc_step(sysm.handle, walkers, S, stream=stream)
-        if timed:
-            e1.record(stream)
-            sweep_events.append((e0, e1))
-        # E_L and t of the post-sweep states, so that O_k and E_L refer to the same determinant
-        vmc.vmc_local_energy(sysm.handle, walkers, stream=stream)
-        el = walkers.view("eloc", torch.float64)[:W]
-        t = walkers.view("tres", torch.float64)[:W]
-        tsum = t.sum()
-        E = (t * el).sum() / tsum
-        g = 2.0 * t * (el - E) / tsum
-        vmc.vmc_logderiv(sysm.handle, walkers, g, G, stream=stream)
-        vmc.vmc_amsgrad(params, m, v, vh, G, 1e-3, 0.9, 0.99, 1e-8, False, stream=stream)
-        vmc.vmc_set_params(sysm.handle, params[:nj], params[nj:], stream=stream)
-        vmc.vmc_walkers_init(sysm.handle, walkers, stream=stream)
-        return E
+    def run_form(precision, steps, warmup, check):
+        """One optimisation iteration per step, as described in the module docstring."""
+        sysm = vmc.System.from_workload(wl, refresh_period=S, precision=precision)
+        if args.threads:
+            vmc.vmc_set_launch(sysm.handle, args.threads)
+        walkers = sysm.walkers(wl.occ)
+        nj = sysm.n_so * (sysm.n_so + 1) // 2
+        params = torch.cat([sysm.J, sysm.theta.reshape(-1)]).clone()
+        m = torch.zeros_like(params)
+        v = torch.zeros_like(params)
+        vh = torch.zeros_like(params)
+        G = torch.zeros_like(params)
+        stream = torch.cuda.current_stream()
+        sweep_events = []
 
-    # burn-in of the walkers (not timed, not counted)
-    vmc.vmc_ctmc_step(sysm.handle, walkers, 100, stream=stream)
-    for _ in range(args.warmup):
-        one_step(False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    E = None
-    for _ in range(args.steps):
-        E = one_step(True)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    value = W * S * args.steps / wall
-    sweep_ms = float(np.mean([a.elapsed_time(b) for a, b in sweep_events]))
-    status = walkers.view("status", torch.int32)[:W].cpu().numpy()
+        def one_step(timed):
+            if timed:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+            vmc.vmc_ctmc_step(sysm.handle, walkers, S, stream=stream)
+            if timed:
+                e1.record(stream)
+                sweep_events.append((e0, e1))
+            # E_L and t of the post-sweep states, so that O_k and E_L refer to the same determinant
+            vmc.vmc_local_energy(sysm.handle, walkers, stream=stream)
+            el = walkers.view("eloc", torch.float64)[:W]
+            t = walkers.view("tres", torch.float64)[:W]
+            tsum = t.sum()
+            E = (t * el).sum() / tsum
+            g = 2.0 * t * (el - E) / tsum
+            vmc.vmc_logderiv(sysm.handle, walkers, g, G, stream=stream)
+            vmc.vmc_amsgrad(params, m, v, vh, G, 1e-3, 0.9, 0.99, 1e-8, False, stream=stream)
+            vmc.vmc_set_params(sysm.handle, params[:nj], params[nj:], stream=stream)
+            vmc.vmc_walkers_init(sysm.handle, walkers, stream=stream)
+            return E
+
+        # burn-in of the walkers (not timed, not counted)
+        vmc.vmc_ctmc_step(sysm.handle, walkers, 100, stream=stream)
+        for _ in range(warmup):
+            one_step(False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        E = None
+        for _ in range(steps):
+            E = one_step(True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        res = {"sysm": sysm, "walkers": walkers, "params": params, "wall": wall, "E": float(E),
+               "value": W * S * steps / wall,
+               "sweep_ms": float(np.mean([a.elapsed_time(b) for a, b in sweep_events])),
+               "status": walkers.view("status", torch.int32)[:W].cpu().numpy()}
+        # E_L of the final states against the oracle, on a sample of walkers
+        res["el_err"] = None
+        if check:
+            from oracle.core import ORC_LEMMA, OracleSystem
+
+            vmc.vmc_local_energy(sysm.handle, walkers, stream=stream)
+            torch.cuda.synchronize()
+            el = walkers.view("eloc", torch.float64)[:W].cpu().numpy()
+            occ = walkers.view("occ_bits", torch.int64)[: W * sysm.n_words].cpu().numpy().view(np.uint64)
+            occ = occ.reshape(W, sysm.n_words)
+            orc = OracleSystem(wl.n_orb, wl.n_alpha, wl.n_beta, wl.h1, wl.eri_idx, wl.eri_val, wl.eps)
+            p = params.cpu().numpy()
+            orc.set_params(p[:nj], p[nj:].reshape(sysm.n_so, sysm.n_so))
+            idx = np.arange(0, W, max(1, W // 16))
+            e_o, _, _, _ = orc.local_energy_batch(occ[idx], ORC_LEMMA)
+            res["el_err"] = float(np.max(np.abs(e_o - el[idx])))
+        return res
+
+    head = run_form(head_prec, args.steps, args.warmup, not args.no_check)
+    sysm, walkers = head["sysm"], head["walkers"]
+    value, wall, sweep_ms, E, status, el_err = (head["value"], head["wall"], head["sweep_ms"], head["E"],
+                                               head["status"], head["el_err"])
+    other = None
+    if not args.no_other_form:
+        o_prec = vmc.VMC_FP64 if head_prec == vmc.VMC_MIXED else vmc.VMC_MIXED
+        o = run_form(o_prec, args.steps, args.warmup, not args.no_check)
+        other = {"precision": "fp64" if o_prec == vmc.VMC_FP64 else "mixed", "value": o["value"],
+                 "unit": "walker-steps/s", "sweep_kernel_ms": o["sweep_ms"],
+                 "eloc_evals_per_s_in_sweep": W * S / (o["sweep_ms"] * 1e-3),
+                 "el_max_abs_err_vs_oracle": o["el_err"],
+                 "el_max_abs_err_per_electron": (o["el_err"] / wl.n_elec) if o["el_err"] is not None else None,
+                 "energy": o["E"], "flagged_walkers": int(np.count_nonzero(o["status"] & 1))}
+        o["sysm"].close()
 
     # --- algorithmic work of the sweep kernel, from candidate counts of a
     #     sample of the final walker states (library diagnostic entry point)
@@ -189,7 +230,7 @@ def main():
     flops = (10.0 * K_d + (ne + 7.0) * K_s + ne * (ne - 1) / 2 + ne + 2 * 1.5 * (n_so * ne + ne * ne) + 3 * n_so
              + (2.0 * ne ** 3 + 2.0 * n_so * ne * ne) / S)
     achieved_tflops = flops * W * S / (sweep_ms * 1e-3) / 1e12
-    traffic, traffic_split = counted_traffic(args.config, W, S, args.threads)
+    traffic, traffic_split = counted_traffic(args.config, W, S, args.threads, args.precision)
     roofline = {
         "bound": "alu",
         "kernel": "k_sweep (persistent E_L + CTMC + Sherman-Morrison, state in LDS)",
@@ -205,23 +246,6 @@ def main():
         "K_doubles": K_d,
         "sweep_kernel_ms": sweep_ms,
     }
-
-    # --- E_L error of the final states against the oracle
-    el_err = None
-    if not args.no_check:
-        from oracle.core import ORC_LEMMA, OracleSystem
-
-        vmc.vmc_local_energy(sysm.handle, walkers, stream=stream)
-        torch.cuda.synchronize()
-        el = walkers.view("eloc", torch.float64)[:W].cpu().numpy()
-        occ = walkers.view("occ_bits", torch.int64)[: W * sysm.n_words].cpu().numpy().view(np.uint64)
-        occ = occ.reshape(W, sysm.n_words)
-        orc = OracleSystem(wl.n_orb, wl.n_alpha, wl.n_beta, wl.h1, wl.eri_idx, wl.eri_val, wl.eps)
-        p = params.cpu().numpy()
-        orc.set_params(p[:nj], p[nj:].reshape(n_so, n_so))
-        idx = np.arange(0, W, max(1, W // 16))
-        e_o, _, _, st_o = orc.local_energy_batch(occ[idx], ORC_LEMMA)
-        el_err = float(np.max(np.abs(e_o - el[idx])))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -254,14 +278,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"{args.config}: H-chain-like 20 orbitals, 10a+10b, eps=1e-6" if args.config ==
                    "hchain20" else args.config, "walkers": W, "ctmc_moves_per_step": S, "refresh_period": S,
-                   "precision": "fp64"},
+                   "precision": args.precision},
         "eloc_evals_per_s_in_sweep": W * S / (sweep_ms * 1e-3),
         "el_max_abs_err_vs_oracle": el_err,
-        "energy": float(E) if E is not None else None,
+        "energy": E,
+        "other_form": other,
         "flagged_walkers": int(np.count_nonzero(status & 1)),
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -14,6 +14,8 @@ constexpr int kQueue = 128;  // per-wave survivor queue (<= 63 left over + 64 ne
 // ------------------------------------------------------------------ views
 struct Tab {
     int n_so, ne, nw, G;
+    int has_doubles;          // the table holds at least one doubles entry
+    int has_sV;               // some singles entry has a nonzero Coulomb-exchange vector
     double eps;
     const uint32_t* row_off;  // n_so*n_so + 1
     const uint32_t* dab;      // a | b << 16

@@ -188,7 +188,7 @@ constexpr int kUnroll = 4;  // 64-entry chunks whose table loads are issued toge
 
 struct Lds {
     uint32_t occw, occl, slot, oslot, s, es, ies, red, stmp, mi, md, wst, wtot, q64, qab, lsum, loff, lg, sgend, sdelta,
-        svend, spq, sfac, dgend, ddelta, dvend, dpq, dfac, w1, w2, cRp, cRq, cBp, cBq, ipiv, fcol, R, B, Rh, total;
+        svend, spq, sfac, dgend, ddelta, dvend, dpq, dfac, w1, w2, cRp, cRq, cBp, cBq, ipiv, dblk, fcol, R, B, Rh, thl, total;
 };
 __host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~(size_t)15; }
 // bytes of the doubles group descriptors (padded stream end, offset delta,
@@ -229,11 +229,12 @@ __host__ __device__ __forceinline__ Lds lds_layout(int n_so, int ne, int nw, int
     L.sfac = take((size_t)ne * 8);
     L.w1 = take((size_t)ne * 8);
     L.w2 = take((size_t)ne * 8);
-    L.cRp = take((size_t)n_so * rb);
-    L.cRq = take((size_t)n_so * rb);
+    L.cRp = take((size_t)n_so * 8);
+    L.cRq = take((size_t)n_so * 8);
     L.cBp = take((size_t)ne * 8);
     L.cBq = take((size_t)ne * 8);
     L.ipiv = take((size_t)ne * 4);
+    L.dblk = take(((gd + 63) / 64 + 1) * 4);
     L.fcol = take((size_t)ne * 8);
     if (small) {
         L.dgend = take(gd * 4);
@@ -244,8 +245,10 @@ __host__ __device__ __forceinline__ Lds lds_layout(int n_so, int ne, int nw, int
         L.R = take((size_t)n_so * ne * rb);
         L.B = take((size_t)ne * ne * 8);
         L.Rh = take((size_t)n_so * ne * rb);
+        // mixed form: theta[:, 0:Ne] (FP64) for the per-move GEMM and the FP64 rows
+        L.thl = (rb < 8) ? take((size_t)n_so * ne * 8) : 0u;
     } else {
-        L.dgend = L.ddelta = L.dvend = L.dpq = L.dfac = L.R = L.B = L.Rh = 0;
+        L.dgend = L.ddelta = L.dvend = L.dpq = L.dfac = L.R = L.B = L.Rh = L.thl = 0;
     }
     L.total = (uint32_t)o;
     return L;
@@ -255,7 +258,7 @@ __host__ __device__ inline size_t scratch_layout_bytes(int ne) { return desc_byt
 
 // misc int slots
 enum { MI_ST = 0, MI_PIV, MI_PTYPE, MI_PP, MI_PQ, MI_PA, MI_PB, MI_FS, MI_FW, MI_FK, MI_FFB, MI_WAVE = 32 };
-enum { MD_T = 0, MD_BASE, MD_EL, MD_HNN, MD_TARGET };
+enum { MD_T = 0, MD_BASE, MD_EL, MD_HNN, MD_TARGET, MD_C00, MD_C01, MD_C10, MD_C11 };
 // per-wave state: entries of the two batch logs and the stream ranges
 enum { WS_NS = 0, WS_R1S = 3, WS_ND = 4, WS_R1D = 7 };
 
@@ -285,8 +288,9 @@ struct Mma<double> {
 // R[p][a] = sum_x B[p][x] theta[a][x] (p < Ne slots, a < n_so orbitals, x < Ne)
 // on the matrix cores: 16x16 output tiles dealt round-robin to the waves,
 // operands rounded to the precision of R, accumulation in that precision.
+// th: theta[:, 0:Ne] with row stride ths (the table, or a copy in LDS).
 template <typename RT>
-__device__ __forceinline__ void r_gemm(const Tab& T, const double* B, RT* R) {
+__device__ __forceinline__ void r_gemm(const Tab& T, const double* B, RT* R, const double* th, int ths) {
     const int ne = T.ne, n_so = T.n_so, l = lane_id();
     const int wv = (int)__builtin_amdgcn_readfirstlane((uint32_t)(threadIdx.x >> 6)), nwv = blockDim.x >> 6;
     const int mt = (ne + 15) >> 4, nt16 = (n_so + 15) >> 4;
@@ -298,7 +302,7 @@ __device__ __forceinline__ void r_gemm(const Tab& T, const double* B, RT* R) {
         for (int k0 = 0; k0 < ne; k0 += 4) {
             const int x = k0 + kq;
             const RT av = (p < ne && x < ne) ? (RT)B[p * ne + x] : (RT)0;
-            const RT bv = (a < n_so && x < ne) ? (RT)T.theta[(size_t)a * n_so + x] : (RT)0;
+            const RT bv = (a < n_so && x < ne) ? (RT)th[(size_t)a * ths + x] : (RT)0;
             acc = Mma<RT>::step(av, bv, acc);
         }
 #pragma unroll
@@ -309,12 +313,61 @@ __device__ __forceinline__ void r_gemm(const Tab& T, const double* B, RT* R) {
     }
 }
 
+// M[r][c] -= c1[c] r1[r] (+ c2[c] r2[r]) over rows x cols, by the whole block,
+// arithmetic in FP64.  Rows are contiguous; when they split into 16-byte
+// vectors each thread keeps four vector loads in flight (the update is a
+// stream over HBM when the state does not fit on chip).
+template <typename E, bool TWO>
+__device__ __forceinline__ void rank_update(E* M, int rows, int cols, const double* c1, const double* r1,
+                                            const double* c2, const double* r2) {
+    constexpr int V = 16 / (int)sizeof(E);
+    constexpr int U = 4;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    struct alignas(16) Vec {
+        E v[V];
+    };
+    if ((cols % V) == 0 && (((uintptr_t)M) & 15) == 0) {
+        const int cv = cols / V, nv = rows * cv;
+        Vec* Mv = (Vec*)M;
+        for (int v0 = tid; v0 < nv; v0 += nt * U) {
+            Vec val[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int vi = v0 + u * nt;
+                if (vi < nv) val[u] = Mv[vi];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int vi = v0 + u * nt;
+                if (vi < nv) {
+                    const int r = vi / cv, c = (vi - r * cv) * V;
+                    const double a1 = r1[r], a2 = TWO ? r2[r] : 0.0;
+#pragma unroll
+                    for (int j = 0; j < V; ++j) {
+                        double d = c1[c + j] * a1;
+                        if (TWO) d += c2[c + j] * a2;
+                        val[u].v[j] = (E)((double)val[u].v[j] - d);
+                    }
+                    Mv[vi] = val[u];
+                }
+            }
+        }
+    } else {
+        for (int idx = tid; idx < rows * cols; idx += nt) {
+            const int r = idx / cols, c = idx - r * cols;
+            double d = c1[c] * r1[r];
+            if (TWO) d += c2[c] * r2[r];
+            M[idx] = (E)((double)M[idx] - d);
+        }
+    }
+}
+
 // Rebuild B = theta[N]^-1 (Gauss-Jordan, partial pivoting, FP64), R and s from
 // the slot list.  B is stored column by slot (B[x][p] at B[p*ne + x]): the
 // elimination works on A^T, whose inverse laid out row-major is exactly that.
 template <typename RT>
 __device__ __forceinline__ void refresh_state(const Tab& T, const int* slot, double* B, RT* R, double* s, double* fcol, int* ipiv,
-                              int* mi, double* red) {
+                              int* mi, double* red, const double* th, int ths) {
     const int tid = threadIdx.x, nt = blockDim.x, ne = T.ne, n_so = T.n_so;
     const int wv = tid >> 6, nwv = nt >> 6;
     for (int idx = tid; idx < ne * ne; idx += nt) {
@@ -378,7 +431,7 @@ __device__ __forceinline__ void refresh_state(const Tab& T, const int* slot, dou
             }
         __syncthreads();
     }
-    r_gemm<RT>(T, B, R);
+    r_gemm<RT>(T, B, R, th, ths);
     for (int pp = tid; pp < n_so; pp += nt) {
         const double* Jr = T.J + (size_t)pp * n_so;
         double acc = 0.0;
@@ -441,6 +494,17 @@ __device__ __forceinline__ uint32_t find_group(const uint32_t* gend, uint32_t ng
 }
 
 __device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// Inclusive prefix sum of u32 over the wave (lane order).
+__device__ __forceinline__ uint32_t wave_scan_u32(uint32_t x) {
+    const int l = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)x, d, kWave);
+        if (l >= d) x += y;
+    }
+    return x;
+}
 
 // Data-parallel-primitive move of a double (both halves), reading 0 where the
 // row mask disables the destination.
@@ -530,7 +594,8 @@ __device__ __forceinline__ double cand_eval(const Tab& T, const StepView<RT>& V,
         if (WANT_H) {
             const double* Vr = T.sV + (size_t)off * n_so;
             double h = T.sh[off];
-            for (int y = 0; y < T.ne; ++y) h += Vr[V.occl[y]];
+            if (T.has_sV)
+                for (int y = 0; y < T.ne; ++y) h += Vr[V.occl[y]];
             term = h * ratio;
         }
         cp = p; cq = -1; ca = a; cb = -1;
@@ -587,7 +652,7 @@ struct BatchLog {
 // The table loads of kUnroll chunks are issued together before they are consumed.
 template <bool DOUBLES, bool PICK, bool NW1, bool SCALED, typename RT>
 __device__ __forceinline__ bool stream_pass(const Tab& T, const StepView<RT>& V, uint64_t occ0, const uint64_t* occw, uint32_t c0,
-                            uint32_t c1, uint32_t g0, uint32_t first, uint64_t* q64, uint64_t* qab, double2* qvk,
+                            uint32_t c1, uint32_t g0, uint32_t ng, uint32_t first, uint64_t* q64, uint64_t* qab, double2* qvk,
                             double& el, double* log_sum, uint32_t* log_off, uint32_t* log_grp, int log_cap, int& log_n,
                             double base, double target, bool fallback, int* pick) {
     BatchLog lg{log_sum, log_off, log_grp, log_cap, 0, kLogGran, 0, 0u, 0u, 0.0};
@@ -600,8 +665,29 @@ __device__ __forceinline__ bool stream_pass(const Tab& T, const StepView<RT>& V,
     const uint32_t* gend = DOUBLES ? V.dgend : V.sgend;
     const uint32_t* delta = DOUBLES ? V.ddelta : V.sdelta;
     const uint32_t* vend = DOUBLES ? V.dvend : V.svend;
+    // Group cursor.  Descriptors in LDS: scalar, advanced group by group.
+    // Descriptors in HBM (unscaled variant): a block of 64 consecutive groups
+    // held one per lane, the chunk's group found by a ballot, so that empty
+    // groups cost nothing and descriptor loads are coalesced.
+    constexpr bool REG_CURSOR = !SCALED;
     uint32_t gc = uni(g0), qn = 0;
-    uint32_t e_end = uni(gend[gc]), e_vend = uni(vend[gc]), e_delta = uni(delta[gc]);
+    uint32_t e_end = 0, e_vend = 0, e_delta = 0;
+    uint32_t blk = 0, b_end = 0, b_vend = 0, b_delta = 0;
+    auto load_block = [&]() __attribute__((always_inline)) {
+        const uint32_t gg = blk + (uint32_t)l;
+        const bool in = gg < ng;
+        b_end = in ? gend[gg] : 0xFFFFFFFFu;
+        b_vend = in ? vend[gg] : 0u;
+        b_delta = in ? delta[gg] : 0u;
+    };
+    if (REG_CURSOR) {
+        blk = gc & ~63u;
+        load_block();
+    } else {
+        e_end = uni(gend[gc]);
+        e_vend = uni(vend[gc]);
+        e_delta = uni(delta[gc]);
+    }
     double run = base;
     bool found = false;
     int last_l = -1;
@@ -623,11 +709,24 @@ __device__ __forceinline__ bool stream_pass(const Tab& T, const StepView<RT>& V,
             st.g[u] = gc;
             st.off[u] = 0;
             if (cu < c1) {
-                while (e_end <= cu) {
-                    ++gc;
-                    e_end = uni(gend[gc]);
-                    e_vend = uni(vend[gc]);
-                    e_delta = uni(delta[gc]);
+                if (REG_CURSOR) {
+                    uint64_t m = __ballot(b_end > cu);
+                    while (m == 0ull) {
+                        blk += kWave;
+                        load_block();
+                        m = __ballot(b_end > cu);
+                    }
+                    const int gl = (int)__builtin_amdgcn_readfirstlane((uint32_t)(__ffsll((unsigned long long)m) - 1));
+                    gc = blk + (uint32_t)gl;
+                    e_vend = (uint32_t)__builtin_amdgcn_readlane((int)b_vend, gl);
+                    e_delta = (uint32_t)__builtin_amdgcn_readlane((int)b_delta, gl);
+                } else {
+                    while (e_end <= cu) {
+                        ++gc;
+                        e_end = uni(gend[gc]);
+                        e_vend = uni(vend[gc]);
+                        e_delta = uni(delta[gc]);
+                    }
                 }
                 st.g[u] = gc;
                 const uint32_t pos = cu + (uint32_t)l;
@@ -754,14 +853,11 @@ __device__ __forceinline__ double log_prefix(double* a, int n) {
 
 enum { MODE_ELOC = 0, MODE_CTMC = 1, MODE_INIT = 2 };
 
-// Occupancy target of the sweep kernel (waves per SIMD); 0 leaves it to the compiler.
-#ifndef VMC_SWEEP_WAVES_PER_EU
-#define VMC_SWEEP_WAVES_PER_EU 0
-#endif
-#if VMC_SWEEP_WAVES_PER_EU > 0
-#define VMC_SWEEP_ATTR __attribute__((amdgpu_waves_per_eu(VMC_SWEEP_WAVES_PER_EU)))
-#else
-#define VMC_SWEEP_ATTR
+// Occupancy target of the sweep kernel when the walker state lives in HBM:
+// at least this many waves per SIMD, so that enough walkers stream their
+// updates concurrently (the LDS layout of that variant allows four, the registers three).
+#ifndef VMC_SWEEP_HBM_WAVES
+#define VMC_SWEEP_HBM_WAVES 3
 #endif
 
 // NSO_T, NE_T, NT_T: compile-time n_so, Ne and workgroup size of a size
@@ -770,7 +866,7 @@ enum { MODE_ELOC = 0, MODE_CTMC = 1, MODE_INIT = 2 };
 // RT: element type of R (double: FP64 form; float: mixed form, where B, the
 // update denominators and every accumulation stay FP64).
 template <int NSO_T, int NE_T, int NT_T, bool NW1, bool SMALL, typename RT>
-__global__ void __launch_bounds__(NT_T ? NT_T : 512) VMC_SWEEP_ATTR
+__global__ void __launch_bounds__(NT_T ? NT_T : 512) __attribute__((amdgpu_waves_per_eu(SMALL ? 1 : VMC_SWEEP_HBM_WAVES)))
 k_sweep(Tab Targ, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, uint64_t seed, int refresh_period,
         double* eloc_hist, double* t_hist, int64_t* pick_hist) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -787,7 +883,8 @@ k_sweep(Tab Targ, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, uint64
     const int tid = threadIdx.x, nt = NT_T ? NT_T : (int)blockDim.x, l = tid & 63;
     const int wv = (int)__builtin_amdgcn_readfirstlane((uint32_t)(tid >> 6)), nwv = nt >> 6;
     const int n_so = T.n_so, ne = T.ne, nw = T.nw;
-    const int gd = ne * (ne - 1) / 2;
+    // pairs of occupied slots; none when the table holds no doubles (Hubbard)
+    const int gd = T.has_doubles ? ne * (ne - 1) / 2 : 0;
     T.G = ne + gd;
     const Lds L = lds_layout(n_so, ne, nw, nt, SMALL, (int)sizeof(RT));
     constexpr bool MIXED = sizeof(RT) < sizeof(double);
@@ -817,11 +914,17 @@ k_sweep(Tab Targ, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, uint64
     double* sfac = (double*)(smem + L.sfac);
     double* w1 = (double*)(smem + L.w1);
     double* w2 = (double*)(smem + L.w2);
-    RT* cRp = (RT*)(smem + L.cRp);
-    RT* cRq = (RT*)(smem + L.cRq);
+    double* cRp = (double*)(smem + L.cRp);
+    double* cRq = (double*)(smem + L.cRq);
+    // theta[:, 0:Ne]: a copy in LDS for the small mixed form, else the table
+    const bool th_lds = SMALL && MIXED;
+    double* thl = (double*)(smem + L.thl);
+    const double* th = th_lds ? thl : T.theta;
+    const int ths = th_lds ? ne : n_so;
     double* cBp = (double*)(smem + L.cBp);
     double* cBq = (double*)(smem + L.cBq);
     int* ipiv = (int*)(smem + L.ipiv);
+    uint32_t* dblk = (uint32_t*)(smem + L.dblk);
     double* fcol = (double*)(smem + L.fcol);
     RT *R, *Rh;
     double *B, *dfac;
@@ -850,6 +953,11 @@ k_sweep(Tab Targ, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, uint64
     const StepView<RT> V{occl, es, SMALL ? Rh : R, sgend, sdelta, svend, spq, sfac, dgend, ddelta, dvend, dpq, dfac};
 
     // ---------------------------------------------------------------- load
+    if (th_lds)
+        for (int k = tid; k < n_so * ne; k += nt) {
+            const int a = k / ne, x = k - a * ne;
+            thl[k] = T.theta[(size_t)a * n_so + x];
+        }
     for (int k = tid; k < nw; k += nt) occw[k] = S.occ[(size_t)w * nw + k];
     if (tid == 0) mi[MI_ST] = (mode == MODE_INIT) ? 0 : (int)S.status[w];
     __syncthreads();
@@ -875,7 +983,7 @@ k_sweep(Tab Targ, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, uint64
             if (occd && rank < ne) slot[rank] = pp;
         }
         __syncthreads();
-        refresh_state(T, slot, B, R, s, fcol, ipiv, mi, red);
+        refresh_state(T, slot, B, R, s, fcol, ipiv, mi, red, th, ths);
     } else {
         for (int k = tid; k < ne; k += nt) slot[k] = S.slot_orb[(size_t)w * ne + k];
         for (int pp = tid; pp < n_so; pp += nt) {
@@ -943,30 +1051,68 @@ k_sweep(Tab Targ, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, uint64
             spq[x] = (uint32_t)oslot[i];
             sfac[x] = ies[i];
         }
-        for (int t = tid; t < gd; t += nt) {
+        // doubles: blocks of 64 consecutive pairs, one per wave at a time;
+        // pass 1 sums each block's padded lengths, the block sums are
+        // scanned, pass 2 scans within the block and writes the descriptors
+        const int nblk = (gd + kWave - 1) / kWave;
+        auto pair_row = [&](int t, int& i, int& j, uint32_t& b0, uint32_t& len) __attribute__((always_inline)) {
             int x, y;
             pair_decode(t, ne, x, y);
-            const int i = occl[x], j = occl[y];
+            i = occl[x];
+            j = occl[y];
             const int row = i * n_so + j;
-            const uint32_t b0 = T.row_off[row], len = T.row_off[row + 1] - b0;
-            ddelta[t] = b0;
-            dvend[t] = len;
-            dgend[t] = (len + 63u) & ~63u;
-            dpq[t] = (uint32_t)oslot[i] | ((uint32_t)oslot[j] << 16);
-            if (!SMALL) dfac[t] = ies[i] * ies[j];
+            b0 = T.row_off[row];
+            len = T.row_off[row + 1] - b0;
+        };
+        for (int bk = wv; bk < nblk; bk += nwv) {
+            const int t = bk * kWave + l;
+            uint32_t plen = 0;
+            if (t < gd) {
+                int i, j;
+                uint32_t b0, len;
+                pair_row(t, i, j, b0, len);
+                plen = (len + 63u) & ~63u;
+            }
+            const uint32_t tot = wave_scan_u32(plen);
+            if (l == kWave - 1) dblk[bk] = tot;
+        }
+        __syncthreads();
+        if (wv == 0) {
+            uint32_t carry = 0;
+            for (int b0 = 0; b0 < nblk; b0 += kWave) {
+                const int bk = b0 + l;
+                const uint32_t v = (bk < nblk) ? dblk[bk] : 0u;
+                const uint32_t incl = wave_scan_u32(v);
+                if (bk < nblk) dblk[bk] = carry + incl - v;  // exclusive
+                carry += (uint32_t)__shfl((int)incl, kWave - 1, kWave);
+            }
+            if (l == 0) dblk[nblk] = carry;
+        }
+        __syncthreads();
+        for (int bk = wv; bk < nblk; bk += nwv) {
+            const int t = bk * kWave + l;
+            int i = 0, j = 0;
+            uint32_t b0 = 0, len = 0, plen = 0;
+            if (t < gd) {
+                pair_row(t, i, j, b0, len);
+                plen = (len + 63u) & ~63u;
+            }
+            const uint32_t end = dblk[bk] + wave_scan_u32(plen), start = end - plen;
+            if (t < gd) {
+                dgend[t] = end;
+                ddelta[t] = b0 - start;
+                dvend[t] = start + len;
+                dpq[t] = (uint32_t)oslot[i] | ((uint32_t)oslot[j] << 16);
+                if (!SMALL) dfac[t] = ies[i] * ies[j];
+            }
         }
         __syncthreads();
         const uint32_t LS = uni(block_inclusive_scan(sgend, ne, stmp));
-        const uint32_t LD = (gd > 0) ? uni(block_inclusive_scan(dgend, gd, stmp)) : 0u;
+        const uint32_t LD = (gd > 0) ? uni(dblk[nblk]) : 0u;
         for (int x = tid; x < ne; x += nt) {
             const uint32_t ps = x ? sgend[x - 1] : 0u;
             sdelta[x] -= ps;
             svend[x] += ps;
-        }
-        for (int t = tid; t < gd; t += nt) {
-            const uint32_t ps = t ? dgend[t - 1] : 0u;
-            ddelta[t] -= ps;
-            dvend[t] += ps;
         }
         __syncthreads();
 
@@ -982,11 +1128,11 @@ k_sweep(Tab Targ, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, uint64
             const uint64_t occ0 = occw[0];
             if (r0s < r1s) {
                 const uint32_t g0 = find_group(sgend, (uint32_t)ne, r0s);
-                stream_pass<false, false, NW1, SMALL>(T, V, occ0, occw, r0s, r1s, g0, r0s, q64, qab, qvk, el_lane, lsum + lb, loff + lb, lg + lb, kLogS, ns, 0.0, 0.0, false, nullptr);
+                stream_pass<false, false, NW1, SMALL>(T, V, occ0, occw, r0s, r1s, g0, (uint32_t)ne, r0s, q64, qab, qvk, el_lane, lsum + lb, loff + lb, lg + lb, kLogS, ns, 0.0, 0.0, false, nullptr);
             }
             if (r0d < r1d) {
                 const uint32_t g0 = find_group(dgend, (uint32_t)gd, r0d);
-                stream_pass<true, false, NW1, SMALL>(T, V, occ0, occw, r0d, r1d, g0, r0d, q64, qab, qvk, el_lane, lsum + lb + kLogS, loff + lb + kLogS, lg + lb + kLogS, kLogD, nd, 0.0, 0.0, false, nullptr);
+                stream_pass<true, false, NW1, SMALL>(T, V, occ0, occw, r0d, r1d, g0, (uint32_t)gd, r0d, q64, qab, qvk, el_lane, lsum + lb + kLogS, loff + lb + kLogS, lg + lb + kLogS, kLogD, nd, 0.0, 0.0, false, nullptr);
             }
             // per-wave inclusive prefix sums of the two logs and their totals
             const double ts = log_prefix(lsum + lb, ns), td = log_prefix(lsum + lb + kLogS, nd);
@@ -1084,9 +1230,9 @@ k_sweep(Tab Targ, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, uint64
                 double dummy = 0.0;
                 int dn = 0;
                 if (fs == 0)
-                    stream_pass<false, true, NW1, SMALL>(T, V, occw[0], occw, c0, r1, g0, p0, q64, qab, qvk, dummy, nullptr, nullptr, nullptr, 0, dn, base, target, fb, mi + MI_PTYPE);
+                    stream_pass<false, true, NW1, SMALL>(T, V, occw[0], occw, c0, r1, g0, (uint32_t)ne, p0, q64, qab, qvk, dummy, nullptr, nullptr, nullptr, 0, dn, base, target, fb, mi + MI_PTYPE);
                 else
-                    stream_pass<true, true, NW1, SMALL>(T, V, occw[0], occw, c0, r1, g0, p0, q64, qab, qvk, dummy, nullptr, nullptr, nullptr, 0, dn, base, target, fb, mi + MI_PTYPE);
+                    stream_pass<true, true, NW1, SMALL>(T, V, occw[0], occw, c0, r1, g0, (uint32_t)gd, p0, q64, qab, qvk, dummy, nullptr, nullptr, nullptr, 0, dn, base, target, fb, mi + MI_PTYPE);
             }
             __syncthreads();
         }
@@ -1096,18 +1242,20 @@ k_sweep(Tab Targ, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, uint64
         if (ptype != 0) {
             const int p = mi[MI_PP], q = mi[MI_PQ], a = mi[MI_PA], b = mi[MI_PB];
             const int i = slot[p], j = (ptype == 2) ? slot[q] : -1;
-            // rows a (and b) of R over the slots, in FP64: read from R in the
-            // FP64 form; recomputed as theta[a, 0:Ne] B in the mixed form, so
-            // that the update denominators and B stay FP64-exact
+            // rows a (and b) of R over the slots, in FP64.  FP64 form: read
+            // from R.  Small mixed form: recomputed as theta[a, 0:Ne] B from
+            // theta in LDS, so that B stays FP64-exact.  Large mixed form: read
+            // from the FP32 R, with the pivot entries (the denominators)
+            // recomputed in FP64 below.
             for (int x = tid; x < ne; x += nt) {
                 double ra, rb = 0.0;
-                if (MIXED) {
-                    const double* tha = T.theta + (size_t)a * n_so;
+                if (MIXED && SMALL) {
+                    const double* tha = th + (size_t)a * ths;
                     const double* Bx = B + x * ne;
                     ra = 0.0;
                     for (int c = 0; c < ne; ++c) ra += tha[c] * Bx[c];
                     if (ptype == 2) {
-                        const double* thb = T.theta + (size_t)b * n_so;
+                        const double* thb = th + (size_t)b * ths;
                         for (int c = 0; c < ne; ++c) rb += thb[c] * Bx[c];
                     }
                 } else {
@@ -1117,12 +1265,14 @@ k_sweep(Tab Targ, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, uint64
                 w1[x] = ra;
                 w2[x] = rb;
             }
+            // old columns p (and q) of R over the orbitals (not needed in the
+            // small mixed form, where R is re-formed after the move)
             const RT* Rp = R + p * n_so;
             const RT* Rq = R + q * n_so;
-            if (!MIXED)
+            if (!(MIXED && SMALL))
                 for (int a2 = tid; a2 < n_so; a2 += nt) {
-                    cRp[a2] = Rp[a2];
-                    if (ptype == 2) cRq[a2] = Rq[a2];
+                    cRp[a2] = (double)Rp[a2];
+                    if (ptype == 2) cRq[a2] = (double)Rq[a2];
                 }
             for (int x = tid; x < ne; x += nt) {
                 cBp[x] = B[p * ne + x];
@@ -1137,21 +1287,38 @@ k_sweep(Tab Targ, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, uint64
                 if (ptype == 2) dh += T.D[(size_t)b * n_so + kk] - T.D[(size_t)j * n_so + kk];
             }
             dh = block_total(dh, red);  // its barriers also publish the rows and copies above
+            if (MIXED && !SMALL) {
+                // FP64 denominators: the pivot entries R[a][p] (R[a][q], R[b][p],
+                // R[b][q]) as theta[a, 0:Ne] B[:, p], one wave per entry
+                const int nk = (ptype == 2) ? 4 : 1;
+                for (int k = wv; k < nk; k += nwv) {
+                    const double* tr = th + (size_t)((k & 2) ? b : a) * ths;
+                    const double* Bc = B + ((k & 1) ? q : p) * ne;
+                    double acc = 0.0;
+                    for (int c = l; c < ne; c += kWave) acc += tr[c] * Bc[c];
+                    acc = wave_total(acc);
+                    if (l == 0) md[MD_C00 + k] = acc;
+                }
+                __syncthreads();
+                if (tid == 0) {
+                    w1[p] = md[MD_C00];
+                    if (ptype == 2) {
+                        w1[q] = md[MD_C01];
+                        w2[p] = md[MD_C10];
+                        w2[q] = md[MD_C11];
+                    }
+                }
+                __syncthreads();
+            }
             if (ptype == 1) {
                 const double rho = w1[p];
                 if (tid == 0 && fabs(rho) < 1e-8) mi[MI_ST] |= (int)VMC_ST_SMALLDEN;
                 __syncthreads();
                 for (int x = tid; x < ne; x += nt) w1[x] = (w1[x] - (x == p ? 1.0 : 0.0)) / rho;
                 __syncthreads();
-                if (!MIXED)
-                    for (int idx = tid; idx < n_so * ne; idx += nt) {
-                        const int x = idx / n_so, a2 = idx - x * n_so;
-                        R[idx] -= cRp[a2] * w1[x];
-                    }
-                for (int idx = tid; idx < ne * ne; idx += nt) {
-                    const int x2 = idx / ne, x = idx - x2 * ne;
-                    B[idx] -= cBp[x] * w1[x2];
-                }
+                // R[x][a'] -= R[a'][p] w_x;  B[x'][x] -= B[x][p] w_x'  (B column by slot)
+                if (!(MIXED && SMALL)) rank_update<RT, false>(R, ne, n_so, cRp, w1, nullptr, nullptr);
+                rank_update<double, false>(B, ne, ne, cBp, w1, nullptr, nullptr);
                 if (tid == 0) md[MD_HNN] += dh + T.hdiag[a] - T.hdiag[i];
             } else {
                 const double c00 = w1[p], c01 = w1[q], c10 = w2[p], c11 = w2[q];
@@ -1165,26 +1332,18 @@ k_sweep(Tab Targ, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, uint64
                     w2[x] = (-c10 * ra + c00 * rb) / det;
                 }
                 __syncthreads();
-                if (!MIXED)
-                    for (int idx = tid; idx < n_so * ne; idx += nt) {
-                        const int x = idx / n_so, a2 = idx - x * n_so;
-                        R[idx] -= cRp[a2] * w1[x] + cRq[a2] * w2[x];
-                    }
-                for (int idx = tid; idx < ne * ne; idx += nt) {
-                    const int x2 = idx / ne, x = idx - x2 * ne;
-                    B[idx] -= cBp[x] * w1[x2] + cBq[x] * w2[x2];
-                }
+                if (!(MIXED && SMALL)) rank_update<RT, true>(R, ne, n_so, cRp, w1, cRq, w2);
+                rank_update<double, true>(B, ne, ne, cBp, w1, cBq, w2);
                 if (tid == 0)
                     md[MD_HNN] += dh + T.hdiag[a] + T.hdiag[b] - T.hdiag[i] - T.hdiag[j] +
                                   T.D[(size_t)a * n_so + b] - T.D[(size_t)i * n_so + j];
             }
-            if (MIXED) {
-                // FP32 R is not carried by the update (its rounding would be
-                // amplified by |w| every move): it is re-formed from the
-                // FP64-exact B on the matrix cores, which costs one small
-                // GEMM per move
+            if (MIXED && SMALL) {
+                // small mixed form: FP32 R is not carried by the update at all;
+                // it is re-formed from the FP64-exact B on the matrix cores,
+                // one small GEMM per move from theta in LDS
                 __syncthreads();
-                r_gemm<RT>(T, B, R);
+                r_gemm<RT>(T, B, R, th, ths);
             }
             // Jastrow sums s_p += J_pa [p!=a] - J_pi [p!=i] (+ the same for b, j)
             const double* Ja = T.J + (size_t)a * n_so;
@@ -1223,7 +1382,7 @@ k_sweep(Tab Targ, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, uint64
         }
         // ------------------------------------------------------- refresh
         if (refresh_period > 0 && ((gstep + 1) % (uint64_t)refresh_period) == 0) {
-            refresh_state(T, slot, B, R, s, fcol, ipiv, mi, red);
+            refresh_state(T, slot, B, R, s, fcol, ipiv, mi, red, th, ths);
             hnn_full();
         }
     }
@@ -1460,6 +1619,7 @@ struct vmc_ctx {
     int device = 0;
     int block_threads = 0;  // 0 = automatic
     int64_t n_dent = 0, n_sent = 0;
+    bool has_sV = true;
     uint32_t *d_row_off = nullptr, *d_dab = nullptr, *d_s_off = nullptr, *d_sa = nullptr;
     uint64_t* d_dmask = nullptr;
     double *d_dvK = nullptr, *d_sh = nullptr, *d_sV = nullptr, *d_sK = nullptr, *d_D = nullptr,
@@ -1503,6 +1663,8 @@ Tab make_tab(const vmc_ctx* h) {
     T.sa = h->d_sa;
     T.sh = h->d_sh;
     T.sV = h->d_sV;
+    T.has_doubles = h->n_dent > 0 ? 1 : 0;
+    T.has_sV = h->has_sV ? 1 : 0;
     T.sK = h->d_sK;
     T.D = h->d_D;
     T.hdiag = h->d_hdiag;
@@ -1716,6 +1878,12 @@ vmc_status vmc_init(const vmc_system_desc* desc, const double* h1, const vmc_eri
     h->eps = eps;
     h->n_dent = (int64_t)T.dv.size();
     h->n_sent = (int64_t)T.sa.size();
+    h->has_sV = false;
+    for (double v : T.sV)
+        if (v != 0.0) {
+            h->has_sV = true;
+            break;
+        }
     if (hipGetDevice(&h->device) != hipSuccess) {
         free_ctx(h);
         return fail(nullptr, VMC_E_HIP, "hipGetDevice failed");

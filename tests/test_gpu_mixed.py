@@ -125,17 +125,20 @@ def test_mixed_ctmc_trajectory(torch, name, W, burn, steps, sample):
     assert len(res["mismatches"]) <= 0.01 * n_all
 
 
-def test_mixed_b_stays_fp64_exact_and_r_is_its_fp32_image(torch):
-    """In the mixed form B is carried by FP64 updates whose denominators come
-    from theta B, so it equals a fresh FP64 inverse to FP64 accuracy; R is
-    re-formed from it after every move, so it stays within FP32 rounding of
-    theta[:, :Ne] B and does not drift."""
-    wl = make_config("hchain20", n_walkers=64)
+@pytest.mark.parametrize("name,b_tol,r_tol", [("hchain20", 1e-9, 1e-5), ("hchain40", 5e-3, 5e-3)])
+def test_mixed_state_after_updates(torch, name, b_tol, r_tol):
+    """State carried by the mixed-form updates against a fresh FP64 inverse.
+
+    With LDS room (20 orbitals) the rows that form w are FP64 (theta B), so B
+    stays FP64-exact, and R is re-formed from it after every move: no drift.
+    Without (40 orbitals) w comes from the FP32 R, with FP64 denominators, so B
+    and R carry FP32-level rounding until the next refresh."""
+    wl = make_config(name, n_walkers=64)
     sysm = gpu_system(wl, refresh_period=1000, precision=_mixed())
     walkers = sysm.walkers(wl.occ)
     ne, n_so = wl.n_elec, wl.n_so
 
-    def compare(tag, rtol):
+    def compare(tag, btol, rtol):
         slot = field(sysm, walkers, "slot_orb", torch.int32, ne)
         B = field(sysm, walkers, "ainv", torch.float64, ne * ne)
         R = field(sysm, walkers, "r", torch.float32, ne * n_so)
@@ -148,9 +151,9 @@ def test_mixed_b_stays_fp64_exact_and_r_is_its_fp32_image(torch):
             Rg = R[w].reshape(ne, n_so).T.astype(np.float64)
             worst_r = max(worst_r, np.max(np.abs(Rg - Rf)) / np.max(np.abs(Rf)))
         _say(f"    {tag}: max rel |dB| {worst_b:.2e}, |dR| {worst_r:.2e}")
-        assert worst_b < 1e-9
+        assert worst_b < btol
         assert worst_r < rtol
 
-    compare("fresh", 1e-5)
+    compare("fresh", 1e-9, 1e-5)
     run_sweep(sysm, walkers, 37)
-    compare("37 updates", 1e-5)
+    compare("37 updates", b_tol, r_tol)
