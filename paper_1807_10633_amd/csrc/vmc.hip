@@ -21,6 +21,7 @@
 // whole multi-step launch; otherwise they live in the caller's buffers.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cmath>
 #include <cstdio>
@@ -31,6 +32,7 @@
 #include "device.hpp"
 #include "tables.hpp"
 #include "vmc.h"
+
 
 using namespace vmc;
 
@@ -657,6 +659,8 @@ __device__ __forceinline__ bool stream_pass(const Tab& T, const StepView<RT>& V,
                             double base, double target, bool fallback, int* pick) {
     BatchLog lg{log_sum, log_off, log_grp, log_cap, 0, kLogGran, 0, 0u, 0u, 0.0};
     BatchLog* log = &lg;
+    // Survival test of a doubles entry: with one occupancy word, one AND of
+    // the entry's target-orbital mask; otherwise two occupancy bit tests.
     constexpr bool MASK = DOUBLES && NW1;
     const int l = lane_id();
     c0 = uni(c0);
@@ -745,8 +749,8 @@ __device__ __forceinline__ bool stream_pass(const Tab& T, const StepView<RT>& V,
         wave_lds_sync();
         const bool act = l < k;
         const uint64_t og = act ? q64[l] : 0ull;
-        const uint64_t ab = act ? qab[l] : 0ull;
         const uint32_t off = (uint32_t)og, g = (uint32_t)(og >> 32);
+        const uint64_t ab = act ? qab[l] : 0ull;
         double2 vk = make_double2(0.0, 0.0);
         if (DOUBLES && act) vk = *(const double2*)(T.dvK + 2 * (size_t)off);
         double term = 0.0, r = 0.0;
@@ -859,6 +863,11 @@ enum { MODE_ELOC = 0, MODE_CTMC = 1, MODE_INIT = 2 };
 #ifndef VMC_SWEEP_HBM_WAVES
 #define VMC_SWEEP_HBM_WAVES 3
 #endif
+// Walker state in LDS: small systems (up to 16 spin-orbitals) fit four waves
+// per SIMD without spills; larger ones are left to the compiler (1).
+constexpr int sweep_waves_target(int nso_t, bool small) {
+    return small ? ((nso_t > 0 && nso_t <= 16) ? 4 : 1) : VMC_SWEEP_HBM_WAVES;
+}
 
 // NSO_T, NE_T, NT_T: compile-time n_so, Ne and workgroup size of a size
 // specialisation (0 = taken from the arguments at run time).  With them the
@@ -866,7 +875,7 @@ enum { MODE_ELOC = 0, MODE_CTMC = 1, MODE_INIT = 2 };
 // RT: element type of R (double: FP64 form; float: mixed form, where B, the
 // update denominators and every accumulation stay FP64).
 template <int NSO_T, int NE_T, int NT_T, bool NW1, bool SMALL, typename RT>
-__global__ void __launch_bounds__(NT_T ? NT_T : 512) __attribute__((amdgpu_waves_per_eu(SMALL ? 1 : VMC_SWEEP_HBM_WAVES)))
+__global__ void __launch_bounds__(NT_T ? NT_T : 512) __attribute__((amdgpu_waves_per_eu(sweep_waves_target(NSO_T, SMALL))))
 k_sweep(Tab Targ, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, uint64_t seed, int refresh_period,
         double* eloc_hist, double* t_hist, int64_t* pick_hist) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -983,7 +992,8 @@ k_sweep(Tab Targ, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, uint64
             if (occd && rank < ne) slot[rank] = pp;
         }
         __syncthreads();
-        refresh_state(T, slot, B, R, s, fcol, ipiv, mi, red, th, ths);
+        // refresh_period 0: the caller runs the separate refresh kernel next
+        if (refresh_period > 0) refresh_state(T, slot, B, R, s, fcol, ipiv, mi, red, th, ths);
     } else {
         for (int k = tid; k < ne; k += nt) slot[k] = S.slot_orb[(size_t)w * ne + k];
         for (int pp = tid; pp < n_so; pp += nt) {
@@ -1415,6 +1425,58 @@ k_sweep(Tab Targ, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, uint64
     }
 }
 
+// LDS bytes of the refresh kernel: B (Ne x Ne FP64) and its work arrays.
+__host__ __device__ inline size_t refresh_lds_bytes(int ne, int nt) {
+    const int nwv = nt / 64;
+    return al16((size_t)ne * ne * 8) + al16((size_t)ne * 8) + al16((size_t)(nwv + 2) * 8) + al16((size_t)ne * 4) * 2 +
+           al16((size_t)(32 + nwv) * 4);
+}
+
+// Periodic (and initial) re-inversion for walkers whose state lives in HBM:
+// the same Gauss-Jordan elimination with partial pivoting as the sweep
+// kernel's in-LDS refresh, with B held in LDS for the elimination (up to
+// 160 KB per workgroup), then R = theta B on the matrix cores, s and H_NN.
+template <typename RT>
+__global__ void __launch_bounds__(256) k_refresh(Tab T, Wk S, int64_t W) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int64_t w = blockIdx.x;
+    if (w >= W) return;
+    const int tid = threadIdx.x, nt = blockDim.x, nwv = nt >> 6;
+    const int ne = T.ne, n_so = T.n_so;
+    size_t o = 0;
+    double* B = (double*)(smem + o);
+    o += al16((size_t)ne * ne * 8);
+    double* fcol = (double*)(smem + o);
+    o += al16((size_t)ne * 8);
+    double* red = (double*)(smem + o);
+    o += al16((size_t)(nwv + 2) * 8);
+    int* slot = (int*)(smem + o);
+    o += al16((size_t)ne * 4);
+    int* ipiv = (int*)(smem + o);
+    o += al16((size_t)ne * 4);
+    int* mi = (int*)(smem + o);
+    for (int k = tid; k < ne; k += nt) slot[k] = S.slot_orb[(size_t)w * ne + k];
+    if (tid == 0) mi[MI_ST] = (int)S.status[w];
+    __syncthreads();
+    RT* R = (RT*)S.R + (size_t)w * n_so * ne;
+    double* s = S.s + (size_t)w * n_so;
+    refresh_state(T, slot, B, R, s, fcol, ipiv, mi, red, T.theta, n_so);
+    double* Bg = S.B + (size_t)w * ne * ne;
+    for (int k = tid; k < ne * ne; k += nt) Bg[k] = B[k];
+    double hp = 0.0;
+    for (int x = tid; x < ne; x += nt) {
+        const int i = slot[x];
+        const double* Di = T.D + (size_t)i * n_so;
+        hp += T.hdiag[i];
+        for (int y = x + 1; y < ne; ++y) hp += Di[slot[y]];
+    }
+    const double hnn = block_total(hp, red);
+    if (tid == 0) {
+        S.hnn[w] = hnn;
+        S.status[w] = (uint32_t)mi[MI_ST];
+    }
+}
+
 // Canonical candidate list of one walker (single wave, groups in order).
 template <typename RT>
 __global__ void __launch_bounds__(64) k_excitations(Tab T, Wk S, int64_t w, int32_t* ijab, double* hval, double* ratio,
@@ -1714,45 +1776,86 @@ struct SweepSpec {
 };
 constexpr SweepSpec kSpecs[] = {{16, 8, 64}, {16, 8, 128}, {40, 20, 128}, {40, 20, 256}, {64, 32, 256}};
 
+struct SweepArgs {
+    int mode, n_steps, refresh;
+    uint64_t step0;
+    double *eh, *th;
+    int64_t* ph;
+};
+
 template <int NSO, int NE, int NT, bool NW1, bool SM, typename RT>
 void launch_one(dim3 grid, dim3 block, size_t lds, hipStream_t st, const Tab& T, const Wk& S, const vmc_walkers* w,
-                int mode, int n_steps, double* eh, double* th, int64_t* ph, const vmc_ctx* h) {
-    hipLaunchKernelGGL((k_sweep<NSO, NE, NT, NW1, SM, RT>), grid, block, lds, st, T, S, w->n_walkers, mode, n_steps,
-                       w->step, h->seed, h->refresh, eh, th, ph);
+                const SweepArgs& a, const vmc_ctx* h) {
+    hipLaunchKernelGGL((k_sweep<NSO, NE, NT, NW1, SM, RT>), grid, block, lds, st, T, S, w->n_walkers, a.mode,
+                       a.n_steps, a.step0, h->seed, a.refresh, a.eh, a.th, a.ph);
 }
 
 template <typename RT>
 void launch_prec(bool small, bool nw1, int nt, dim3 grid, dim3 block, size_t lds, hipStream_t st, const Tab& T,
-                 const Wk& S, const vmc_walkers* w, int mode, int n_steps, double* eh, double* th, int64_t* ph,
-                 const vmc_ctx* h) {
-    auto spec = [&](int a, int b, int c) { return small && h->n_so == a && h->ne == b && nt == c; };
-    if (spec(16, 8, 64)) launch_one<16, 8, 64, true, true, RT>(grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
-    else if (spec(16, 8, 128)) launch_one<16, 8, 128, true, true, RT>(grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
-    else if (spec(40, 20, 128)) launch_one<40, 20, 128, true, true, RT>(grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
-    else if (spec(40, 20, 256)) launch_one<40, 20, 256, true, true, RT>(grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
-    else if (spec(64, 32, 256)) launch_one<64, 32, 256, true, true, RT>(grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
-    else if (nw1 && small) launch_one<0, 0, 0, true, true, RT>(grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
-    else if (nw1) launch_one<0, 0, 0, true, false, RT>(grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
-    else if (small) launch_one<0, 0, 0, false, true, RT>(grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
-    else launch_one<0, 0, 0, false, false, RT>(grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
+                 const Wk& S, const vmc_walkers* w, const SweepArgs& a, const vmc_ctx* h) {
+    auto spec = [&](int n_so, int ne, int c) { return small && h->n_so == n_so && h->ne == ne && nt == c; };
+    if (spec(16, 8, 64)) launch_one<16, 8, 64, true, true, RT>(grid, block, lds, st, T, S, w, a, h);
+    else if (spec(16, 8, 128)) launch_one<16, 8, 128, true, true, RT>(grid, block, lds, st, T, S, w, a, h);
+    else if (spec(40, 20, 128)) launch_one<40, 20, 128, true, true, RT>(grid, block, lds, st, T, S, w, a, h);
+    else if (spec(40, 20, 256)) launch_one<40, 20, 256, true, true, RT>(grid, block, lds, st, T, S, w, a, h);
+    else if (spec(64, 32, 256)) launch_one<64, 32, 256, true, true, RT>(grid, block, lds, st, T, S, w, a, h);
+    else if (nw1 && small) launch_one<0, 0, 0, true, true, RT>(grid, block, lds, st, T, S, w, a, h);
+    else if (nw1) launch_one<0, 0, 0, true, false, RT>(grid, block, lds, st, T, S, w, a, h);
+    else if (small) launch_one<0, 0, 0, false, true, RT>(grid, block, lds, st, T, S, w, a, h);
+    else launch_one<0, 0, 0, false, false, RT>(grid, block, lds, st, T, S, w, a, h);
 }
 
-vmc_status launch_sweep(vmc_ctx* h, vmc_walkers* w, int mode, int n_steps, double* eh, double* th, int64_t* ph,
-                        hipStream_t st) {
-    int nt = h->block_threads;
-    if (nt <= 0) nt = 256;
+// Geometry of the sweep launch for this system.
+struct SweepGeom {
+    int nt;
+    bool small;
+    size_t lds;
+};
+SweepGeom sweep_geom(const vmc_ctx* h) {
+    SweepGeom g;
+    g.nt = h->block_threads > 0 ? h->block_threads : 256;
     const int rb = (int)r_bytes(h);
-    bool small = lds_layout(h->n_so, h->ne, h->nw, nt, true, rb).total <= kMaxLds;
-    const size_t lds = lds_layout(h->n_so, h->ne, h->nw, nt, small, rb).total;
-    if (lds > kMaxLds) return fail(h, VMC_E_UNSUPPORTED, "system too large for the per-walker LDS budget");
+    g.small = lds_layout(h->n_so, h->ne, h->nw, g.nt, true, rb).total <= kMaxLds;
+    g.lds = lds_layout(h->n_so, h->ne, h->nw, g.nt, g.small, rb).total;
+    return g;
+}
+
+// Walkers whose state lives in HBM are re-inverted by the separate refresh
+// kernel when B fits its LDS budget.
+constexpr size_t kMaxRefreshLds = 160 * 1024;
+bool use_refresh_kernel(const vmc_ctx* h) {
+    return !sweep_geom(h).small && refresh_lds_bytes(h->ne, 256) <= kMaxRefreshLds;
+}
+
+vmc_status launch_refresh(vmc_ctx* h, vmc_walkers* w, hipStream_t st) {
+    const size_t lds = refresh_lds_bytes(h->ne, 256);
+    const Tab T = make_tab(h);
+    const Wk S = make_wk(h, w);
+    const dim3 grid((unsigned)w->n_walkers), block(256);
+    if (h->precision == VMC_MIXED) {
+        HIP_OR_FAIL(h, hipFuncSetAttribute((const void*)k_refresh<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds));
+        hipLaunchKernelGGL(k_refresh<float>, grid, block, lds, st, T, S, w->n_walkers);
+    } else {
+        HIP_OR_FAIL(h, hipFuncSetAttribute((const void*)k_refresh<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds));
+        hipLaunchKernelGGL(k_refresh<double>, grid, block, lds, st, T, S, w->n_walkers);
+    }
+    HIP_OR_FAIL(h, hipGetLastError());
+    return VMC_OK;
+}
+
+vmc_status launch_sweep(vmc_ctx* h, vmc_walkers* w, const SweepArgs& a, hipStream_t st) {
+    const SweepGeom g = sweep_geom(h);
+    if (g.lds > kMaxLds) return fail(h, VMC_E_UNSUPPORTED, "system too large for the per-walker LDS budget");
     const bool nw1 = (h->nw == 1);
     const Tab T = make_tab(h);
     const Wk S = make_wk(h, w);
-    const dim3 grid((unsigned)w->n_walkers), block((unsigned)nt);
+    const dim3 grid((unsigned)w->n_walkers), block((unsigned)g.nt);
     if (h->precision == VMC_MIXED)
-        launch_prec<float>(small, nw1, nt, grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
+        launch_prec<float>(g.small, nw1, g.nt, grid, block, g.lds, st, T, S, w, a, h);
     else
-        launch_prec<double>(small, nw1, nt, grid, block, lds, st, T, S, w, mode, n_steps, eh, th, ph, h);
+        launch_prec<double>(g.small, nw1, g.nt, grid, block, g.lds, st, T, S, w, a, h);
     HIP_OR_FAIL(h, hipGetLastError());
     return VMC_OK;
 }
@@ -1969,14 +2072,18 @@ vmc_status vmc_walkers_init(vmc_handle h, vmc_walkers* w, hipStream_t st) {
     if (!h) return fail(nullptr, VMC_E_ARG, "handle is NULL");
     vmc_status s = check_walkers(h, w);
     if (s != VMC_OK) return s;
-    return launch_sweep(h, w, MODE_INIT, 1, nullptr, nullptr, nullptr, st);
+    if (use_refresh_kernel(h)) {
+        s = launch_sweep(h, w, SweepArgs{MODE_INIT, 1, 0, w->step, nullptr, nullptr, nullptr}, st);
+        return s != VMC_OK ? s : launch_refresh(h, w, st);
+    }
+    return launch_sweep(h, w, SweepArgs{MODE_INIT, 1, h->refresh, w->step, nullptr, nullptr, nullptr}, st);
 }
 
 vmc_status vmc_local_energy(vmc_handle h, vmc_walkers* w, hipStream_t st) {
     if (!h) return fail(nullptr, VMC_E_ARG, "handle is NULL");
     vmc_status s = check_walkers(h, w);
     if (s != VMC_OK) return s;
-    return launch_sweep(h, w, MODE_ELOC, 1, nullptr, nullptr, nullptr, st);
+    return launch_sweep(h, w, SweepArgs{MODE_ELOC, 1, h->refresh, w->step, nullptr, nullptr, nullptr}, st);
 }
 
 vmc_status vmc_ctmc_step(vmc_handle h, vmc_walkers* w, int32_t n_steps, double* eh, double* th, int64_t* ph,
@@ -1986,9 +2093,28 @@ vmc_status vmc_ctmc_step(vmc_handle h, vmc_walkers* w, int32_t n_steps, double* 
     if (s != VMC_OK) return s;
     if (n_steps < 0) return fail(h, VMC_E_ARG, "n_steps must be >= 0");
     if (n_steps == 0) return VMC_OK;
-    s = launch_sweep(h, w, MODE_CTMC, n_steps, eh, th, ph, st);
-    if (s == VMC_OK) w->step += (uint64_t)n_steps;
-    return s;
+    if (!use_refresh_kernel(h)) {
+        s = launch_sweep(h, w, SweepArgs{MODE_CTMC, n_steps, h->refresh, w->step, eh, th, ph}, st);
+        if (s == VMC_OK) w->step += (uint64_t)n_steps;
+        return s;
+    }
+    // segments that end at the refresh boundaries (after the move whose
+    // global step g has (g + 1) % refresh_period == 0), each followed by the
+    // refresh kernel
+    const int64_t W = w->n_walkers;
+    int k = 0;
+    while (k < n_steps) {
+        const uint64_t g = w->step;
+        const int to_b = h->refresh - (int)(g % (uint64_t)h->refresh);
+        const int seg = std::min(n_steps - k, to_b);
+        s = launch_sweep(h, w, SweepArgs{MODE_CTMC, seg, 0, g, eh ? eh + (size_t)k * W : nullptr,
+                                         th ? th + (size_t)k * W : nullptr, ph ? ph + (size_t)k * W : nullptr}, st);
+        if (s != VMC_OK) return s;
+        w->step += (uint64_t)seg;
+        if (seg == to_b && (s = launch_refresh(h, w, st)) != VMC_OK) return s;
+        k += seg;
+    }
+    return VMC_OK;
 }
 
 vmc_status vmc_excitations(vmc_handle h, const vmc_walkers* w, int64_t walker, int32_t* ijab, double* hval,

@@ -205,3 +205,41 @@ def test_run_to_run_determinism(torch):
         eh, th, ph = run_sweep(sysm, walkers, 30)
         outs.append((eh.tobytes(), th.tobytes(), ph.tobytes(), occ_of(sysm, walkers).tobytes()))
     assert outs[0] == outs[1]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_refresh_kernel_state_and_energy(torch, prec):
+    """Walkers whose state lives in HBM (40 orbitals) are re-inverted by the
+    separate refresh kernel at every refresh boundary: after 20 moves with a
+    refresh period of 7 (two refreshes, then six updates), B and R match a
+    fresh inverse and E_L matches the oracle."""
+    from paper_1807_10633_amd.vmc import VMC_FP64, VMC_MIXED, vmc_local_energy
+
+    wl = make_config("hchain40", n_walkers=64)
+    mixed = prec == "mixed"
+    sysm = gpu_system(wl, refresh_period=7, precision=VMC_MIXED if mixed else VMC_FP64)
+    walkers = sysm.walkers(wl.occ)
+    eh, th, ph = run_sweep(sysm, walkers, 20)
+    assert walkers.step == 20
+    ne, n_so = wl.n_elec, wl.n_so
+    slot = field(sysm, walkers, "slot_orb", torch.int32, ne)
+    B = field(sysm, walkers, "ainv", torch.float64, ne * ne)
+    R = field(sysm, walkers, "r", torch.float32 if mixed else torch.float64, ne * n_so)
+    worst_b = worst_r = 0.0
+    for w in range(64):
+        Binv = np.linalg.inv(wl.theta[slot[w]][:, :ne])
+        worst_b = max(worst_b, np.max(np.abs(B[w].reshape(ne, ne).T - Binv)) / np.max(np.abs(Binv)))
+        Rf = wl.theta[:, :ne] @ Binv
+        worst_r = max(worst_r, np.max(np.abs(R[w].reshape(ne, n_so).T.astype(np.float64) - Rf)) / np.max(np.abs(Rf)))
+    _say(f"    {prec}: 6 updates after a refresh: max rel |dB| {worst_b:.2e}, |dR| {worst_r:.2e}")
+    assert worst_b < (1e-4 if mixed else 1e-9)
+    assert worst_r < (1e-4 if mixed else 1e-9)
+    vmc_local_energy(sysm.handle, walkers)
+    torch.cuda.synchronize()
+    el = field(sysm, walkers, "eloc", torch.float64, 1)[:, 0]
+    occ = occ_of(sysm, walkers)
+    orc = OracleSystem.from_workload(wl)
+    for w in (0, 21, 42, 63):
+        r = orc.local_energy(occ[w], ORC_LEMMA, with_candidates=False)
+        tol = (1e-6 * ne if mixed else EL_TOL) * max(1.0, r["T"] / 100.0)
+        assert abs(el[w] - r["eloc"]) <= tol, (w, el[w], r["eloc"], r["T"])
