@@ -33,6 +33,7 @@ if ROOT not in sys.path:
 
 METRIC = "walker-steps/s (E_L+CTMC) at stated E_L error vs FP64 oracle; % HBM/MFMA peak"
 FP64_VECTOR_PEAK_TFLOPS = 78.6
+HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per sweep launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of
 # `bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-check`, scaled by the
@@ -41,9 +42,9 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 # and the workload: any other kernel source or workload reports null.
 KERNEL_SOURCES = ("paper_1807_10633_amd/csrc/vmc.hip", "paper_1807_10633_amd/csrc/device.hpp")
 COUNTED_TRAFFIC = {
-    ("a28f8870b82a7900864fd36b84c791557118bbaf1c36a6ee1f43042fde10b74b",
-     "c129dedeae63596985a6c0e8630863b22050f8f8418fb19f4f3b2993ab2aab7f", "hchain20", 4096, 50, 0, "fp64"):
-        {"fetch_kib": 33695.1, "fetch_factor": 2.0, "write_kib": 41856.9, "write_factor": 1.0},
+    ("c76cb221f8dbf5a0759cb817d00e66ca95a7a482848dd68e1b1006b0ad1d6de3",
+     "6f0c5114f3b6a499710c41ef439984968e3cb925d4ff09f97ec429e9daca3055", "hchain20", 4096, 50, 0, "fp64"):
+        {"fetch_kib": 33779.7, "fetch_factor": 2.0, "write_kib": 41857.9, "write_factor": 1.0},
 }
 
 
@@ -224,28 +225,38 @@ def main():
     K_s, K_d = float(np.mean(ks)), float(np.mean(kd))
     # FP64 flops per walker-step: doubles 10 (2x2 minor 3, Jastrow 4, E_L 2,
     # rate 1); singles Ne + 7; H_NN Ne(Ne-1)/2 + Ne; update 2*1.5*(|R|+|B|)
-    # (1.5 = mean electrons moved, measured by the double/single pick mix is
-    # not tracked, the midpoint is used); Jastrow sums 3 n_so; refresh amortised
-    # over the sweep: GJ 2 Ne^3 + R 2 n_so Ne^2.
+    # (1.5 = mean electrons moved: the single/double pick mix is not tracked,
+    # the midpoint is used); Jastrow sums 3 n_so; refresh amortised over the
+    # sweep: GJ 2 Ne^3 + R 2 n_so Ne^2.
     flops = (10.0 * K_d + (ne + 7.0) * K_s + ne * (ne - 1) / 2 + ne + 2 * 1.5 * (n_so * ne + ne * ne) + 3 * n_so
              + (2.0 * ne ** 3 + 2.0 * n_so * ne * ne) / S)
-    achieved_tflops = flops * W * S / (sweep_ms * 1e-3) / 1e12
+    info = vmc.vmc_launch_info(sysm.handle)
+    rbytes = 4 if args.precision == "mixed" else 8
+    # HBM bytes per walker-step when the state stays in HBM: R and B read and
+    # written once per move
+    state_bytes = 2.0 * (n_so * ne * rbytes + ne * ne * 8)
+    sweep_s = sweep_ms * 1e-3
+    achieved_tflops = flops * W * S / sweep_s / 1e12
     traffic, traffic_split = counted_traffic(args.config, W, S, args.threads, args.precision)
-    roofline = {
-        "bound": "alu",
-        "kernel": "k_sweep (persistent E_L + CTMC + Sherman-Morrison, state in LDS)",
-        "achieved": achieved_tflops,
-        "peak": FP64_VECTOR_PEAK_TFLOPS,
-        "unit": "TFLOP/s",
-        "frac": achieved_tflops / FP64_VECTOR_PEAK_TFLOPS,
+    common = {
+        "kernel": ("k_sweep (persistent E_L + CTMC + Sherman-Morrison, walker state in LDS)" if info["state_in_lds"]
+                   else "k_sweep segments + k_refresh (walker state in HBM), one vmc_ctmc_step"),
         "traffic": traffic,
         "traffic_split": traffic_split,
-        "hbm_gbs_measured": (traffic / (sweep_ms * 1e-3) / 1e9) if traffic else None,
+        "hbm_gbs_measured": (traffic / sweep_s / 1e9) if traffic else None,
         "flop_per_walker_step": flops,
         "K_singles": K_s,
         "K_doubles": K_d,
         "sweep_kernel_ms": sweep_ms,
+        "launch": info,
     }
+    if info["state_in_lds"]:
+        roofline = {"bound": "alu", "achieved": achieved_tflops, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": achieved_tflops / FP64_VECTOR_PEAK_TFLOPS, **common}
+    else:
+        gbs = state_bytes * W * S / sweep_s / 1e9
+        roofline = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                    "bytes_per_walker_step": state_bytes, "fp64_tflops": achieved_tflops, **common}
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -215,6 +215,14 @@ vmc_status vmc_set_launch(vmc_handle h, int32_t block_threads);
  * per walker (Ne + Ne(Ne-1)/2). */
 vmc_status vmc_table_info(vmc_handle h, int64_t out[3]);
 
+/* Launch geometry of the sweep kernel for this system and the current
+ * vmc_set_launch setting: out[0] = threads per walker (workgroup size),
+ * out[1] = 1 when the walker state (R, B, descriptors) is held in LDS for the
+ * whole sweep, 0 when it stays in the caller's HBM buffers, out[2] = LDS bytes
+ * per workgroup, out[3] = 1 when re-inversion runs in the separate refresh
+ * kernel (HBM-resident walkers whose B fits 160 KB of LDS). */
+vmc_status vmc_launch_info(vmc_handle h, int64_t out[4]);
+
 vmc_status vmc_destroy(vmc_handle h);
 
 /* Message of the last failed call on h (or of the last failed vmc_init /

@@ -2201,6 +2201,16 @@ vmc_status vmc_table_info(vmc_handle h, int64_t out[3]) {
     return VMC_OK;
 }
 
+vmc_status vmc_launch_info(vmc_handle h, int64_t out[4]) {
+    if (!h || !out) return fail(h, VMC_E_ARG, "NULL argument");
+    const SweepGeom g = sweep_geom(h);
+    out[0] = g.nt;
+    out[1] = g.small ? 1 : 0;
+    out[2] = (int64_t)g.lds;
+    out[3] = use_refresh_kernel(h) ? 1 : 0;
+    return VMC_OK;
+}
+
 vmc_status vmc_destroy(vmc_handle h) {
     if (!h) return fail(nullptr, VMC_E_ARG, "handle is NULL");
     free_ctx(h);

@@ -27,7 +27,7 @@ EXPORTED = (
     "vmc_init", "vmc_set_params", "vmc_walker_bytes", "vmc_walkers_init", "vmc_local_energy", "vmc_ctmc_step",
     "vmc_logderiv", "vmc_amsgrad", "vmc_excitations", "vmc_uniforms", "vmc_decode_pick", "vmc_table_info",
     "vmc_destroy", "vmc_last_error", "vmc_host_tables_build", "vmc_host_tables_sizes", "vmc_host_tables_get",
-    "vmc_host_tables_free", "vmc_set_launch",
+    "vmc_host_tables_free", "vmc_set_launch", "vmc_launch_info",
 )
 
 
@@ -73,6 +73,7 @@ def load_library() -> C.CDLL:
         "vmc_uniforms": ([u64, i64, u64, P, P], i32),
         "vmc_decode_pick": ([i64, P], None),
         "vmc_table_info": ([P, P], i32),
+        "vmc_launch_info": ([P, P], i32),
         "vmc_set_launch": ([P, i32], i32),
         "vmc_destroy": ([P], i32),
         "vmc_last_error": ([P], C.c_char_p),
@@ -192,6 +193,13 @@ def vmc_table_info(handle):
     out = (C.c_int64 * 3)()
     _check(load_library().vmc_table_info(handle, out), handle, "vmc_table_info")
     return {"double_entries": int(out[0]), "single_entries": int(out[1]), "groups": int(out[2])}
+
+
+def vmc_launch_info(handle):
+    out = (C.c_int64 * 4)()
+    _check(load_library().vmc_launch_info(handle, out), handle, "vmc_launch_info")
+    return {"threads": int(out[0]), "state_in_lds": bool(out[1]), "lds_bytes": int(out[2]),
+            "refresh_kernel": bool(out[3])}
 
 
 def vmc_set_launch(handle, block_threads: int) -> None:
