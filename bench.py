@@ -10,8 +10,8 @@ One timed step is one optimisation iteration of the hot path:
     CTMC moves of every walker -- screened singles/doubles enumeration,
     ratios, local energy, rates, pick, Sherman-Morrison updates, and the
     periodic re-inversion at the end of the sweep;
-  * vmc_local_energy of the post-sweep states, their residence-time weighted
-    energy and the contraction weights;
+  * vmc_local_energy of the post-sweep states, and vmc_estimate: their
+    residence-time weighted energy and the contraction weights;
   * vmc_logderiv (contracted backward), vmc_amsgrad, vmc_set_params (Jastrow
     factors folded into the tables) and vmc_walkers_init (fresh inverses for
     the new parameters).
@@ -133,6 +133,8 @@ def main():
         v = torch.zeros_like(params)
         vh = torch.zeros_like(params)
         G = torch.zeros_like(params)
+        est = torch.zeros(4, dtype=torch.float64, device=dev)
+        g = torch.zeros(W, dtype=torch.float64, device=dev)
         stream = torch.cuda.current_stream()
         sweep_events = []
 
@@ -147,16 +149,12 @@ def main():
                 sweep_events.append((e0, e1))
             # E_L and t of the post-sweep states, so that O_k and E_L refer to the same determinant
             vmc.vmc_local_energy(sysm.handle, walkers, stream=stream)
-            el = walkers.view("eloc", torch.float64)[:W]
-            t = walkers.view("tres", torch.float64)[:W]
-            tsum = t.sum()
-            E = (t * el).sum() / tsum
-            g = 2.0 * t * (el - E) / tsum
+            vmc.vmc_estimate(sysm.handle, walkers, est, g, stream=stream)
             vmc.vmc_logderiv(sysm.handle, walkers, g, G, stream=stream)
             vmc.vmc_amsgrad(params, m, v, vh, G, 1e-3, 0.9, 0.99, 1e-8, False, stream=stream)
             vmc.vmc_set_params(sysm.handle, params[:nj], params[nj:], stream=stream)
             vmc.vmc_walkers_init(sysm.handle, walkers, stream=stream)
-            return E
+            return est[2]
 
         # burn-in of the walkers (not timed, not counted)
         vmc.vmc_ctmc_step(sysm.handle, walkers, 100, stream=stream)

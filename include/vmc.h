@@ -180,6 +180,19 @@ vmc_status vmc_ctmc_step(vmc_handle h, vmc_walkers* w, int32_t n_steps, double* 
 vmc_status vmc_logderiv(vmc_handle h, const vmc_walkers* w, const double* g_dev, double* out_dev,
                         hipStream_t stream);
 
+/*
+ * Residence-time weighted energy of the walkers' current E_L and t (as left by
+ * vmc_local_energy or vmc_ctmc_step): E = sum_w t_w E_L,w / sum_w t_w, the
+ * CTMC estimate of Eq. eq:vmc (section "Continuous time Monte Carlo for
+ * sampling determinants").  out (device, 4 doubles) = {sum t, sum t E_L, E,
+ * number of walkers counted}.  When g (device, W doubles) is non-NULL it
+ * receives the contraction weights of the gradient estimator of Eq. eq:grad,
+ * g_w = 2 t_w (E_L,w - E) / sum t, ready for vmc_logderiv.  Walkers with t <= 0
+ * or a non-finite E_L (flagged states) carry no weight and get g_w = 0.  One
+ * workgroup, fixed summation order: deterministic.  Asynchronous on stream.
+ */
+vmc_status vmc_estimate(vmc_handle h, const vmc_walkers* w, double* out, double* g, hipStream_t stream);
+
 /* One AMSGrad step over n parameters, all pointers device (Eqs. eq:m1, eq:m2,
  * in the Reddi form with standard betas: m = b1 m + (1-b1) g, v = b2 v +
  * (1-b2) g^2, vhat = max(vhat, v), p -= lr m / (sqrt(vhat) + delta)).
@@ -224,6 +237,30 @@ vmc_status vmc_table_info(vmc_handle h, int64_t out[3]);
 vmc_status vmc_launch_info(vmc_handle h, int64_t out[4]);
 
 vmc_status vmc_destroy(vmc_handle h);
+
+/*
+ * Batches: systems of different sizes (each with its own tables, parameters
+ * and walker set) swept by ONE kernel launch; workgroups are dealt to the
+ * systems in order.  Every system runs the variant that keeps the walker
+ * state in its HBM buffers and re-inverts in place every refresh_period
+ * moves; the LDS of the launch is sized for the largest system.
+ *
+ * vmc_batch_create: 1..8 systems with the same precision whose parameters are
+ * set; the batch refers to the handles (which must outlive it) and owns
+ * nothing on the device.  walkers[e] is the walker set of systems[e] (already
+ * initialised with vmc_walkers_init).  vmc_batch_local_energy and
+ * vmc_batch_ctmc_step compute exactly what vmc_local_energy / vmc_ctmc_step
+ * (without histories) compute for each system alone with the same launch
+ * variant; each walker set's step counter advances by n_steps.
+ * vmc_batch_set_launch: workgroup size for the whole batch (64..512).
+ * Errors are reported through vmc_last_error(NULL).
+ */
+typedef struct vmc_batch_ctx* vmc_batch;
+vmc_status vmc_batch_create(const vmc_handle* systems, int32_t n, vmc_batch* out);
+vmc_status vmc_batch_set_launch(vmc_batch b, int32_t block_threads);
+vmc_status vmc_batch_local_energy(vmc_batch b, vmc_walkers* const* walkers, hipStream_t stream);
+vmc_status vmc_batch_ctmc_step(vmc_batch b, vmc_walkers* const* walkers, int32_t n_steps, hipStream_t stream);
+vmc_status vmc_batch_destroy(vmc_batch b);
 
 /* Message of the last failed call on h (or of the last failed vmc_init /
  * handle-free call when h is NULL).  Valid until the next call on h. */

@@ -7,8 +7,8 @@ mean: it is the VMC gradient estimator of Eq. eq:grad,
 G_k = 2 < O_k (E_L - E) >, computed by the library's contracted backward with
 g_w = 2 t_w (E_L,w - E) / sum t and returned as gradients of J (packed) and
 theta.  Local energies come from the library's kernels (vmc_local_energy), the
-contraction from vmc_logderiv; torch only holds memory and does the three
-scalar reductions of E.
+weighted mean and the weights g from vmc_estimate, the contraction from
+vmc_logderiv; torch only holds memory.
 """
 from __future__ import annotations
 
@@ -24,21 +24,19 @@ class _VMCEnergy(torch.autograd.Function):
             raise RuntimeError("vmc_energy runs on the GPU only")
         _vmc.vmc_local_energy(system.handle, walkers)
         W = walkers.n_walkers
-        el = walkers.view("eloc", torch.float64)[:W]
-        t = walkers.view("tres", torch.float64)[:W]
-        tsum = t.sum()
-        E = (t * el).sum() / tsum
+        est = torch.empty(4, dtype=torch.float64, device=J.device)
+        g = torch.empty(W, dtype=torch.float64, device=J.device)
+        _vmc.vmc_estimate(system.handle, walkers, est, g)
         ctx.system = system
         ctx.walkers = walkers
-        ctx.save_for_backward(el.clone(), t.clone(), E.detach().clone(), tsum.clone())
+        ctx.save_for_backward(g)
         ctx.shapes = (J.shape, theta.shape)
-        return E
+        return est[2].clone()
 
     @staticmethod
     def backward(ctx, grad_out):
-        el, t, E, tsum = ctx.saved_tensors
+        (g,) = ctx.saved_tensors
         system, walkers = ctx.system, ctx.walkers
-        g = (2.0 * t * (el - E) / tsum).contiguous()
         G = torch.empty(system.n_params, dtype=torch.float64, device=g.device)
         _vmc.vmc_logderiv(system.handle, walkers, g, G)
         nj = system.n_so * (system.n_so + 1) // 2

@@ -874,13 +874,13 @@ constexpr int sweep_waves_target(int nso_t, bool small) {
 // LDS layout and loop bounds fold to constants.
 // RT: element type of R (double: FP64 form; float: mixed form, where B, the
 // update denominators and every accumulation stay FP64).
+// sweep_body runs walker w of the walker set S (W walkers) on the calling
+// workgroup.
 template <int NSO_T, int NE_T, int NT_T, bool NW1, bool SMALL, typename RT>
-__global__ void __launch_bounds__(NT_T ? NT_T : 512) __attribute__((amdgpu_waves_per_eu(sweep_waves_target(NSO_T, SMALL))))
-k_sweep(Tab Targ, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, uint64_t seed, int refresh_period,
-        double* eloc_hist, double* t_hist, int64_t* pick_hist) {
+__device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t W, int64_t w, int mode, int n_steps,
+                                           uint64_t step0, uint64_t seed, int refresh_period, double* eloc_hist,
+                                           double* t_hist, int64_t* pick_hist) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int64_t w = blockIdx.x;
-    if (w >= W) return;
     Tab T = Targ;
     if (NSO_T) {
         T.n_so = NSO_T;
@@ -1425,6 +1425,49 @@ k_sweep(Tab Targ, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, uint64
     }
 }
 
+// One workgroup per walker of one system.
+template <int NSO_T, int NE_T, int NT_T, bool NW1, bool SMALL, typename RT>
+__global__ void __launch_bounds__(NT_T ? NT_T : 512) __attribute__((amdgpu_waves_per_eu(sweep_waves_target(NSO_T, SMALL))))
+k_sweep(Tab T, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, uint64_t seed, int refresh_period,
+        double* eloc_hist, double* t_hist, int64_t* pick_hist) {
+    const int64_t w = blockIdx.x;
+    if (w >= W) return;
+    sweep_body<NSO_T, NE_T, NT_T, NW1, SMALL, RT>(T, S, W, w, mode, n_steps, step0, seed, refresh_period, eloc_hist,
+                                                  t_hist, pick_hist);
+}
+
+// Several systems of different sizes in one launch: workgroups [block0,
+// block0 + W) of the grid belong to entry e.  Every system runs the variant
+// with the walker state in HBM (any size, one layout per system, LDS sized
+// for the largest) and refreshes in place.
+constexpr int kMaxBatch = 8;
+struct BatchEntry {
+    Tab T;
+    Wk S;
+    int64_t W, block0;
+    uint64_t seed, step0;
+    int refresh;
+    double *eh, *th;
+    int64_t* ph;
+};
+struct BatchArgs {
+    BatchEntry e[kMaxBatch];
+    int n;
+};
+
+template <typename RT>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(VMC_SWEEP_HBM_WAVES)))
+k_sweep_batch(BatchArgs A, int mode, int n_steps) {
+    const int64_t b = blockIdx.x;
+    int e = 0;
+    while (e + 1 < A.n && A.e[e + 1].block0 <= b) ++e;
+    const int64_t w = b - A.e[e].block0;
+    if (w >= A.e[e].W) return;
+    const BatchEntry& E = A.e[e];
+    sweep_body<0, 0, 0, false, false, RT>(E.T, E.S, E.W, w, mode, n_steps, E.step0, E.seed, E.refresh, E.eh, E.th,
+                                          E.ph);
+}
+
 // LDS bytes of the refresh kernel: B (Ne x Ne FP64) and its work arrays.
 __host__ __device__ inline size_t refresh_lds_bytes(int ne, int nt) {
     const int nwv = nt / 64;
@@ -1669,6 +1712,54 @@ __global__ void k_amsgrad(int64_t n, double* p, double* m, double* v, double* vh
     p[k] -= lr * mk / (sqrt(vhk) + delta);
 }
 
+// Residence-time weighted energy of the current states (one workgroup, fixed
+// summation order): out = {sum t, sum t E_L, E = sum t E_L / sum t, walkers
+// counted}; with g, the contraction weights of the covariance gradient
+// g_w = 2 t_w (E_L,w - E) / sum t.  Walkers whose t is not positive or whose
+// E_L is not finite (flagged states) carry no weight and get g_w = 0.
+__global__ void __launch_bounds__(1024) k_estimate(const double* eloc, const double* tres, int64_t W, double* out,
+                                                   double* g) {
+    __shared__ double red[2][16];
+    const int tid = threadIdx.x, nt = blockDim.x, l = tid & 63, wv = tid >> 6, nwv = nt >> 6;
+    double st = 0.0, se = 0.0, sn = 0.0;
+    for (int64_t k = tid; k < W; k += nt) {
+        const double t = tres[k], e = eloc[k];
+        if (t > 0.0 && isfinite(e)) {
+            st += t;
+            se += t * e;
+            sn += 1.0;
+        }
+    }
+    st = wave_total(st);
+    se = wave_total(se);
+    sn = wave_total(sn);
+    __shared__ double rn[16];
+    if (l == 0) {
+        red[0][wv] = st;
+        red[1][wv] = se;
+        rn[wv] = sn;
+    }
+    __syncthreads();
+    double T = 0.0, TE = 0.0, N = 0.0;
+    for (int q = 0; q < nwv; ++q) {
+        T += red[0][q];
+        TE += red[1][q];
+        N += rn[q];
+    }
+    const double E = (T > 0.0) ? TE / T : NAN;
+    if (tid == 0) {
+        out[0] = T;
+        out[1] = TE;
+        out[2] = E;
+        out[3] = N;
+    }
+    if (g)
+        for (int64_t k = tid; k < W; k += nt) {
+            const double t = tres[k], e = eloc[k];
+            g[k] = (t > 0.0 && isfinite(e) && T > 0.0) ? 2.0 * t * (e - E) / T : 0.0;
+        }
+}
+
 }  // namespace
 
 // =============================================================================
@@ -1693,6 +1784,12 @@ struct vmc_ctx {
 
 struct vmc_host_tables {
     vmc::HostTables t;
+};
+
+struct vmc_batch_ctx {
+    std::vector<vmc_ctx*> sys;
+    int nt = 256;
+    int precision = 0;
 };
 
 namespace {
@@ -2176,6 +2273,16 @@ vmc_status vmc_logderiv(vmc_handle h, const vmc_walkers* w, const double* g, dou
     return VMC_OK;
 }
 
+vmc_status vmc_estimate(vmc_handle h, const vmc_walkers* w, double* out, double* g, hipStream_t st) {
+    if (!h) return fail(nullptr, VMC_E_ARG, "handle is NULL");
+    if (!w || w->n_walkers <= 0 || !w->eloc || !w->tres) return fail(h, VMC_E_ARG, "bad walkers");
+    if (!out) return fail(h, VMC_E_ARG, "out is NULL");
+    hipLaunchKernelGGL(k_estimate, dim3(1), dim3(1024), 0, st, (const double*)w->eloc, (const double*)w->tres,
+                       w->n_walkers, out, g);
+    HIP_OR_FAIL(h, hipGetLastError());
+    return VMC_OK;
+}
+
 vmc_status vmc_amsgrad(int64_t n, double* p, double* m, double* v, double* vh, const double* g, double lr, double b1,
                        double b2, double delta, int32_t literal, hipStream_t st) {
     if (n <= 0 || !p || !m || !v || !vh || !g) return fail(nullptr, VMC_E_ARG, "bad arguments");
@@ -2208,6 +2315,85 @@ vmc_status vmc_launch_info(vmc_handle h, int64_t out[4]) {
     out[1] = g.small ? 1 : 0;
     out[2] = (int64_t)g.lds;
     out[3] = use_refresh_kernel(h) ? 1 : 0;
+    return VMC_OK;
+}
+
+// ------------------------------------------------------------------ batches
+vmc_status vmc_batch_create(const vmc_handle* systems, int32_t n, vmc_batch* out) {
+    if (!out) return fail(nullptr, VMC_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!systems || n < 1 || n > kMaxBatch)
+        return fail(nullptr, VMC_E_ARG, "a batch holds 1.." + std::to_string(kMaxBatch) + " systems");
+    for (int e = 0; e < n; ++e) {
+        if (!systems[e]) return fail(nullptr, VMC_E_ARG, "system handle is NULL");
+        if (systems[e]->precision != systems[0]->precision)
+            return fail(nullptr, VMC_E_ARG, "all systems of a batch must have the same precision");
+        if (!systems[e]->params_set) return fail(nullptr, VMC_E_ARG, "vmc_set_params has not been called");
+    }
+    vmc_batch_ctx* b = new vmc_batch_ctx;
+    b->sys.assign(systems, systems + n);
+    b->precision = systems[0]->precision;
+    *out = b;
+    return VMC_OK;
+}
+
+vmc_status vmc_batch_set_launch(vmc_batch b, int32_t block_threads) {
+    if (!b) return fail(nullptr, VMC_E_ARG, "batch is NULL");
+    if (block_threads < 64 || block_threads > 512 || (block_threads % 64) != 0)
+        return fail(nullptr, VMC_E_ARG, "block_threads must be a multiple of 64 in 64..512");
+    b->nt = block_threads;
+    return VMC_OK;
+}
+
+static vmc_status launch_batch(vmc_batch b, vmc_walkers* const* ws, int mode, int n_steps, hipStream_t st) {
+    if (!b) return fail(nullptr, VMC_E_ARG, "batch is NULL");
+    if (!ws) return fail(nullptr, VMC_E_ARG, "walkers array is NULL");
+    BatchArgs A;
+    std::memset(&A, 0, sizeof(A));
+    A.n = (int)b->sys.size();
+    int64_t blocks = 0;
+    size_t lds = 0;
+    for (int e = 0; e < A.n; ++e) {
+        vmc_ctx* h = b->sys[e];
+        vmc_status s = check_walkers(h, ws[e]);
+        if (s != VMC_OK) return fail(nullptr, s, "system " + std::to_string(e) + ": " + h->err);
+        BatchEntry& E = A.e[e];
+        E.T = make_tab(h);
+        E.S = make_wk(h, ws[e]);
+        E.W = ws[e]->n_walkers;
+        E.block0 = blocks;
+        E.seed = h->seed;
+        E.step0 = ws[e]->step;
+        E.refresh = h->refresh;
+        blocks += E.W;
+        lds = std::max(lds, (size_t)lds_layout(h->n_so, h->ne, h->nw, b->nt, false, (int)r_bytes(h)).total);
+    }
+    if (lds > kMaxLds) return fail(nullptr, VMC_E_UNSUPPORTED, "a batched system exceeds the per-walker LDS budget");
+    if (blocks > (int64_t)INT_MAX) return fail(nullptr, VMC_E_ARG, "too many walkers in the batch");
+    const dim3 grid((unsigned)blocks), block((unsigned)b->nt);
+    if (b->precision == VMC_MIXED)
+        hipLaunchKernelGGL(k_sweep_batch<float>, grid, block, lds, st, A, mode, n_steps);
+    else
+        hipLaunchKernelGGL(k_sweep_batch<double>, grid, block, lds, st, A, mode, n_steps);
+    HIP_OR_FAIL(nullptr, hipGetLastError());
+    if (mode == MODE_CTMC)
+        for (int e = 0; e < A.n; ++e) ws[e]->step += (uint64_t)n_steps;
+    return VMC_OK;
+}
+
+vmc_status vmc_batch_local_energy(vmc_batch b, vmc_walkers* const* walkers, hipStream_t st) {
+    return launch_batch(b, walkers, MODE_ELOC, 1, st);
+}
+
+vmc_status vmc_batch_ctmc_step(vmc_batch b, vmc_walkers* const* walkers, int32_t n_steps, hipStream_t st) {
+    if (n_steps < 0) return fail(nullptr, VMC_E_ARG, "n_steps must be >= 0");
+    if (n_steps == 0) return VMC_OK;
+    return launch_batch(b, walkers, MODE_CTMC, n_steps, st);
+}
+
+vmc_status vmc_batch_destroy(vmc_batch b) {
+    if (!b) return fail(nullptr, VMC_E_ARG, "batch is NULL");
+    delete b;
     return VMC_OK;
 }
 

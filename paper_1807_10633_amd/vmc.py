@@ -27,7 +27,8 @@ EXPORTED = (
     "vmc_init", "vmc_set_params", "vmc_walker_bytes", "vmc_walkers_init", "vmc_local_energy", "vmc_ctmc_step",
     "vmc_logderiv", "vmc_amsgrad", "vmc_excitations", "vmc_uniforms", "vmc_decode_pick", "vmc_table_info",
     "vmc_destroy", "vmc_last_error", "vmc_host_tables_build", "vmc_host_tables_sizes", "vmc_host_tables_get",
-    "vmc_host_tables_free", "vmc_set_launch", "vmc_launch_info",
+    "vmc_host_tables_free", "vmc_set_launch", "vmc_launch_info", "vmc_estimate", "vmc_batch_create",
+    "vmc_batch_set_launch", "vmc_batch_local_energy", "vmc_batch_ctmc_step", "vmc_batch_destroy",
 )
 
 
@@ -74,6 +75,12 @@ def load_library() -> C.CDLL:
         "vmc_decode_pick": ([i64, P], None),
         "vmc_table_info": ([P, P], i32),
         "vmc_launch_info": ([P, P], i32),
+        "vmc_estimate": ([P, P, P, P, P], i32),
+        "vmc_batch_create": ([P, i32, P], i32),
+        "vmc_batch_set_launch": ([P, i32], i32),
+        "vmc_batch_local_energy": ([P, P, P], i32),
+        "vmc_batch_ctmc_step": ([P, P, i32, P], i32),
+        "vmc_batch_destroy": ([P], i32),
         "vmc_set_launch": ([P, i32], i32),
         "vmc_destroy": ([P], i32),
         "vmc_last_error": ([P], C.c_char_p),
@@ -164,6 +171,13 @@ def vmc_logderiv(handle, walkers: "Walkers", g_dev, out_dev, stream=None) -> Non
                                        _stream_ptr(stream)), handle, "vmc_logderiv")
 
 
+def vmc_estimate(handle, walkers: "Walkers", out_dev, g_dev=None, stream=None) -> None:
+    """out_dev (4 FP64, device) <- {sum t, sum t E_L, E, count}; g_dev (W FP64) <- gradient weights."""
+    _check(load_library().vmc_estimate(handle, C.byref(walkers.cstruct), _dev_ptr(out_dev),
+                                       _dev_ptr(g_dev) if g_dev is not None else None, _stream_ptr(stream)),
+           handle, "vmc_estimate")
+
+
 def vmc_amsgrad(params, m, v, vhat, grad, lr: float, beta1: float, beta2: float, delta: float = 1e-8,
                 paper_literal: bool = False, stream=None) -> None:
     n = params.numel()
@@ -244,6 +258,35 @@ def vmc_host_tables(n_orb: int, n_alpha: int, n_beta: int, h1: np.ndarray, eri_i
         return out
     finally:
         lib.vmc_host_tables_free(t)
+
+
+def vmc_batch_create(handles) -> int:
+    arr = (C.c_void_p * len(handles))(*handles)
+    out = C.c_void_p()
+    _check(load_library().vmc_batch_create(arr, len(handles), C.byref(out)), None, "vmc_batch_create")
+    return out.value
+
+
+def vmc_batch_set_launch(batch, block_threads: int) -> None:
+    _check(load_library().vmc_batch_set_launch(batch, int(block_threads)), None, "vmc_batch_set_launch")
+
+
+def _walker_array(walkers):
+    return (C.c_void_p * len(walkers))(*[C.cast(C.pointer(w.cstruct), C.c_void_p) for w in walkers])
+
+
+def vmc_batch_local_energy(batch, walkers, stream=None) -> None:
+    _check(load_library().vmc_batch_local_energy(batch, _walker_array(walkers), _stream_ptr(stream)), None,
+           "vmc_batch_local_energy")
+
+
+def vmc_batch_ctmc_step(batch, walkers, n_steps: int, stream=None) -> None:
+    _check(load_library().vmc_batch_ctmc_step(batch, _walker_array(walkers), int(n_steps), _stream_ptr(stream)), None,
+           "vmc_batch_ctmc_step")
+
+
+def vmc_batch_destroy(batch) -> None:
+    _check(load_library().vmc_batch_destroy(batch), None, "vmc_batch_destroy")
 
 
 # ----------------------------------------------------------------------------

@@ -148,3 +148,36 @@ def test_amsgrad_kernel_matches_oracle(torch, literal):
     torch.cuda.synchronize()
     assert np.allclose(P.cpu().numpy(), p_ref, rtol=1e-14, atol=1e-15)
     assert np.allclose(vh.cpu().numpy(), opt.vhat, rtol=1e-14, atol=0)
+
+
+def test_estimate_kernel_matches_oracle_weights(torch):
+    """vmc_estimate: the t-weighted energy and the gradient weights, against the
+    oracle's definitions, on the walkers' own E_L and t after a sweep, and with
+    flagged entries (t = 0, non-finite E_L) that must carry no weight."""
+    from paper_1807_10633_amd.vmc import vmc_estimate
+
+    wl = make_config("hchain20", n_walkers=1000)
+    sysm = gpu_system(wl)
+    walkers = sysm.walkers(wl.occ)
+    run_sweep(sysm, walkers, 20)
+    W = walkers.n_walkers
+    el_t = walkers.view("eloc", torch.float64)[:W]
+    t_t = walkers.view("tres", torch.float64)[:W]
+    for flagged in (False, True):
+        if flagged:
+            el_t[3] = float("nan")
+            t_t[7] = 0.0
+            el_t[11] = float("inf")
+        out = torch.zeros(4, dtype=torch.float64, device="cuda")
+        g = torch.zeros(W, dtype=torch.float64, device="cuda")
+        vmc_estimate(sysm.handle, walkers, out, g)
+        torch.cuda.synchronize()
+        el, t = el_t.cpu().numpy(), t_t.cpu().numpy()
+        keep = (t > 0) & np.isfinite(el)
+        E = weighted_energy(el[keep], t[keep])
+        o = out.cpu().numpy()
+        assert o[3] == np.count_nonzero(keep)
+        assert o[2] == pytest.approx(E, rel=1e-13, abs=1e-13)
+        gw = np.zeros(W)
+        gw[keep] = contraction_weights(el[keep], t[keep])
+        np.testing.assert_allclose(g.cpu().numpy(), gw, rtol=1e-11, atol=1e-16)
