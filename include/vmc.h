@@ -262,6 +262,18 @@ vmc_status vmc_batch_local_energy(vmc_batch b, vmc_walkers* const* walkers, hipS
 vmc_status vmc_batch_ctmc_step(vmc_batch b, vmc_walkers* const* walkers, int32_t n_steps, hipStream_t stream);
 vmc_status vmc_batch_destroy(vmc_batch b);
 
+/*
+ * Launch-shape autotuner: times CTMC sweeps of n_moves moves at each
+ * workgroup size in {64, 128, 256, 512} threads per walker that fits the LDS
+ * budget (best of two sweeps each, HIP events on `stream`), keeps the fastest
+ * (as vmc_set_launch / vmc_batch_set_launch would) and returns it in *chosen
+ * (nullable).  The timed sweeps are real moves: every walker set advances by
+ * 8 * n_moves moves (use it as burn-in).  Blocks until the timing is done.
+ */
+vmc_status vmc_autotune(vmc_handle h, vmc_walkers* w, int32_t n_moves, int32_t* chosen, hipStream_t stream);
+vmc_status vmc_batch_autotune(vmc_batch b, vmc_walkers* const* walkers, int32_t n_moves, int32_t* chosen,
+                              hipStream_t stream);
+
 /* Message of the last failed call on h (or of the last failed vmc_init /
  * handle-free call when h is NULL).  Valid until the next call on h. */
 const char* vmc_last_error(vmc_handle h);

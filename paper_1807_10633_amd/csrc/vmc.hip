@@ -2300,6 +2300,101 @@ vmc_status vmc_set_launch(vmc_handle h, int32_t block_threads) {
     return VMC_OK;
 }
 
+// Time one launch configuration: best of `reps` sweeps of n_moves moves.
+static vmc_status time_sweeps(vmc_ctx* h, vmc_walkers* w, vmc_batch b, vmc_walkers* const* ws, int n_moves, int reps,
+                              hipStream_t st, float* best_ms) {
+    hipEvent_t e0, e1;
+    HIP_OR_FAIL(h, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(h, VMC_E_HIP, "hipEventCreate failed");
+    }
+    vmc_status s = VMC_OK;
+    *best_ms = 3.0e38f;
+    for (int r = 0; r < reps && s == VMC_OK; ++r) {
+        if (hipEventRecord(e0, st) != hipSuccess) { s = fail(h, VMC_E_HIP, "hipEventRecord failed"); break; }
+        s = b ? vmc_batch_ctmc_step(b, ws, n_moves, st) : vmc_ctmc_step(h, w, n_moves, nullptr, nullptr, nullptr, st);
+        if (s != VMC_OK) break;
+        float ms = 0.0f;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            s = fail(h, VMC_E_HIP, "event timing failed");
+            break;
+        }
+        *best_ms = std::min(*best_ms, ms);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return s;
+}
+
+static const int kTuneThreads[] = {64, 128, 256, 512};
+
+vmc_status vmc_autotune(vmc_handle h, vmc_walkers* w, int32_t n_moves, int32_t* chosen, hipStream_t st) {
+    if (!h) return fail(nullptr, VMC_E_ARG, "handle is NULL");
+    vmc_status s = check_walkers(h, w);
+    if (s != VMC_OK) return s;
+    if (n_moves < 1) return fail(h, VMC_E_ARG, "n_moves must be >= 1");
+    const int keep = h->block_threads;
+    int best_nt = 0;
+    float best = 3.0e38f;
+    for (int nt : kTuneThreads) {
+        h->block_threads = nt;
+        const SweepGeom g = sweep_geom(h);
+        if (g.lds > kMaxLds) continue;
+        float ms = 0.0f;
+        s = time_sweeps(h, w, nullptr, nullptr, n_moves, 2, st, &ms);
+        if (s != VMC_OK) {
+            h->block_threads = keep;
+            return s;
+        }
+        if (ms < best) {
+            best = ms;
+            best_nt = nt;
+        }
+    }
+    if (best_nt == 0) {
+        h->block_threads = keep;
+        return fail(h, VMC_E_UNSUPPORTED, "no workgroup size fits the LDS budget");
+    }
+    h->block_threads = best_nt;
+    if (chosen) *chosen = best_nt;
+    return VMC_OK;
+}
+
+vmc_status vmc_batch_autotune(vmc_batch b, vmc_walkers* const* walkers, int32_t n_moves, int32_t* chosen,
+                              hipStream_t st) {
+    if (!b) return fail(nullptr, VMC_E_ARG, "batch is NULL");
+    if (n_moves < 1) return fail(nullptr, VMC_E_ARG, "n_moves must be >= 1");
+    const int keep = b->nt;
+    int best_nt = 0;
+    float best = 3.0e38f;
+    for (int nt : kTuneThreads) {
+        size_t lds = 0;
+        for (vmc_ctx* h : b->sys)
+            lds = std::max(lds, (size_t)lds_layout(h->n_so, h->ne, h->nw, nt, false, (int)r_bytes(h)).total);
+        if (lds > kMaxLds) continue;
+        b->nt = nt;
+        float ms = 0.0f;
+        vmc_status s = time_sweeps(nullptr, nullptr, b, walkers, n_moves, 2, st, &ms);
+        if (s != VMC_OK) {
+            b->nt = keep;
+            return s;
+        }
+        if (ms < best) {
+            best = ms;
+            best_nt = nt;
+        }
+    }
+    if (best_nt == 0) {
+        b->nt = keep;
+        return fail(nullptr, VMC_E_UNSUPPORTED, "no workgroup size fits the LDS budget");
+    }
+    b->nt = best_nt;
+    if (chosen) *chosen = best_nt;
+    return VMC_OK;
+}
+
 vmc_status vmc_table_info(vmc_handle h, int64_t out[3]) {
     if (!h || !out) return fail(h, VMC_E_ARG, "NULL argument");
     out[0] = h->n_dent;

@@ -28,7 +28,8 @@ EXPORTED = (
     "vmc_logderiv", "vmc_amsgrad", "vmc_excitations", "vmc_uniforms", "vmc_decode_pick", "vmc_table_info",
     "vmc_destroy", "vmc_last_error", "vmc_host_tables_build", "vmc_host_tables_sizes", "vmc_host_tables_get",
     "vmc_host_tables_free", "vmc_set_launch", "vmc_launch_info", "vmc_estimate", "vmc_batch_create",
-    "vmc_batch_set_launch", "vmc_batch_local_energy", "vmc_batch_ctmc_step", "vmc_batch_destroy",
+    "vmc_batch_set_launch", "vmc_batch_local_energy", "vmc_batch_ctmc_step", "vmc_batch_destroy", "vmc_autotune",
+    "vmc_batch_autotune",
 )
 
 
@@ -81,6 +82,8 @@ def load_library() -> C.CDLL:
         "vmc_batch_local_energy": ([P, P, P], i32),
         "vmc_batch_ctmc_step": ([P, P, i32, P], i32),
         "vmc_batch_destroy": ([P], i32),
+        "vmc_autotune": ([P, P, i32, P, P], i32),
+        "vmc_batch_autotune": ([P, P, i32, P, P], i32),
         "vmc_set_launch": ([P, i32], i32),
         "vmc_destroy": ([P], i32),
         "vmc_last_error": ([P], C.c_char_p),
@@ -283,6 +286,20 @@ def vmc_batch_local_energy(batch, walkers, stream=None) -> None:
 def vmc_batch_ctmc_step(batch, walkers, n_steps: int, stream=None) -> None:
     _check(load_library().vmc_batch_ctmc_step(batch, _walker_array(walkers), int(n_steps), _stream_ptr(stream)), None,
            "vmc_batch_ctmc_step")
+
+
+def vmc_autotune(handle, walkers: "Walkers", n_moves: int = 5, stream=None) -> int:
+    out = C.c_int32(0)
+    _check(load_library().vmc_autotune(handle, C.byref(walkers.cstruct), int(n_moves), C.byref(out),
+                                       _stream_ptr(stream)), handle, "vmc_autotune")
+    return int(out.value)
+
+
+def vmc_batch_autotune(batch, walkers, n_moves: int = 5, stream=None) -> int:
+    out = C.c_int32(0)
+    _check(load_library().vmc_batch_autotune(batch, _walker_array(walkers), int(n_moves), C.byref(out),
+                                             _stream_ptr(stream)), None, "vmc_batch_autotune")
+    return int(out.value)
 
 
 def vmc_batch_destroy(batch) -> None:

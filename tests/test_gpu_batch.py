@@ -173,3 +173,27 @@ def test_batch_gradient_and_amsgrad_all_parameters(torch, batch_setup):
     opt = AMSGrad(pall.size, lr=1e-3, beta1=0.9, beta2=0.99)
     ref = opt.step(pall.copy(), Gall)
     np.testing.assert_allclose(p_d.cpu().numpy(), ref, rtol=0, atol=1e-15)
+
+
+def test_batch_autotune(torch):
+    from paper_1807_10633_amd.vmc import (vmc_batch_autotune, vmc_batch_create, vmc_batch_destroy,
+                                          vmc_batch_local_energy)
+
+    wls = [make_config(n, n_walkers=128) for n in ("hchain40", "hchain80")]
+    systems = [gpu_system(wl) for wl in wls]
+    wks = [s.walkers(wl.occ) for s, wl in zip(systems, wls)]
+    b = vmc_batch_create([s.handle for s in systems])
+    try:
+        nt = vmc_batch_autotune(b, wks, 2)
+        vmc_batch_local_energy(b, wks)
+    finally:
+        vmc_batch_destroy(b)
+    torch.cuda.synchronize()
+    assert nt in (64, 128, 256, 512)
+    for wl, s, wk in zip(wls, systems, wks):
+        assert wk.step == 16
+        el = field(s, wk, "eloc", torch.float64, 1)[:, 0]
+        orc = OracleSystem.from_workload(wl)
+        r = orc.local_energy(occ_of(s, wk)[5], ORC_LEMMA, with_candidates=False)
+        assert abs(el[5] - r["eloc"]) <= EL_TOL * max(1.0, r["T"] / 100.0)
+    _say(f"    batch autotuned workgroup: {nt}")

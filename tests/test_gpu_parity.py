@@ -243,3 +243,26 @@ def test_refresh_kernel_state_and_energy(torch, prec):
         r = orc.local_energy(occ[w], ORC_LEMMA, with_candidates=False)
         tol = (1e-6 * ne if mixed else EL_TOL) * max(1.0, r["T"] / 100.0)
         assert abs(el[w] - r["eloc"]) <= tol, (w, el[w], r["eloc"], r["T"])
+
+
+def test_autotune_picks_a_valid_shape_and_keeps_walkers_valid(torch):
+    """The launch autotuner times real sweeps: the walkers advance by 8 * n_moves
+    moves and stay valid (E_L against the oracle afterwards)."""
+    from paper_1807_10633_amd.vmc import vmc_autotune, vmc_launch_info, vmc_local_energy
+
+    wl = make_config("hchain20", n_walkers=512)
+    sysm = gpu_system(wl)
+    walkers = sysm.walkers(wl.occ)
+    nt = vmc_autotune(sysm.handle, walkers, 3)
+    assert nt in (64, 128, 256, 512)
+    assert vmc_launch_info(sysm.handle)["threads"] == nt
+    assert walkers.step == 24
+    vmc_local_energy(sysm.handle, walkers)
+    torch.cuda.synchronize()
+    el = field(sysm, walkers, "eloc", torch.float64, 1)[:, 0]
+    occ = occ_of(sysm, walkers)
+    orc = OracleSystem.from_workload(wl)
+    for w in (0, 255, 511):
+        r = orc.local_energy(occ[w], ORC_LEMMA, with_candidates=False)
+        assert abs(el[w] - r["eloc"]) <= EL_TOL * max(1.0, r["T"] / 100.0)
+    _say(f"    autotuned workgroup: {nt} threads per walker")
