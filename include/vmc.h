@@ -170,6 +170,21 @@ vmc_status vmc_ctmc_step(vmc_handle h, vmc_walkers* w, int32_t n_steps, double* 
                          int64_t* pick_hist, hipStream_t stream);
 
 /*
+ * vmc_ctmc_step with the global step counter in device memory instead of
+ * w->step: the first move of the call uses *step_dev (read on the device when
+ * the kernel runs), and a one-thread kernel adds n_steps to it after the
+ * sweep.  Nothing is allocated, synchronised or read back, so the call can be
+ * captured in a hipGraph and replayed: every replay draws the next uniforms.
+ * w->step is not used or changed; no histories.  Refresh: as vmc_ctmc_step
+ * when the walker state fits LDS (by the global step); for walkers whose state
+ * lives in HBM, n_steps must be a multiple of refresh_period, and the separate
+ * refresh kernel runs after every refresh_period moves of the call (aligned
+ * with vmc_ctmc_step when *step_dev is a multiple of refresh_period).
+ * step_dev: device, 8 bytes, caller-owned.
+ */
+vmc_status vmc_ctmc_step_dev(vmc_handle h, vmc_walkers* w, int32_t n_steps, uint64_t* step_dev, hipStream_t stream);
+
+/*
  * Gradient ratios O_k of each walker's current state, N_p = n_so(n_so+1)/2 +
  * n_so^2 (Jastrow part packed like J, then theta row-major):
  * O_{J_pq} = n_p n_q, O_{theta_kx} = B[x][slot(k)] for occupied k and x < Ne,

@@ -1428,12 +1428,19 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
 // One workgroup per walker of one system.
 template <int NSO_T, int NE_T, int NT_T, bool NW1, bool SMALL, typename RT>
 __global__ void __launch_bounds__(NT_T ? NT_T : 512) __attribute__((amdgpu_waves_per_eu(sweep_waves_target(NSO_T, SMALL))))
-k_sweep(Tab T, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, uint64_t seed, int refresh_period,
-        double* eloc_hist, double* t_hist, int64_t* pick_hist) {
+k_sweep(Tab T, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, const uint64_t* step_dev, uint64_t seed,
+        int refresh_period, double* eloc_hist, double* t_hist, int64_t* pick_hist) {
     const int64_t w = blockIdx.x;
     if (w >= W) return;
-    sweep_body<NSO_T, NE_T, NT_T, NW1, SMALL, RT>(T, S, W, w, mode, n_steps, step0, seed, refresh_period, eloc_hist,
+    // global step of the first move: step0, plus a device-resident counter
+    // when the caller keeps one (graph replays advance it)
+    const uint64_t s0 = step_dev ? step0 + *step_dev : step0;
+    sweep_body<NSO_T, NE_T, NT_T, NW1, SMALL, RT>(T, S, W, w, mode, n_steps, s0, seed, refresh_period, eloc_hist,
                                                   t_hist, pick_hist);
+}
+
+__global__ void k_step_advance(uint64_t* step_dev, uint64_t n) {
+    if (threadIdx.x == 0) *step_dev += n;
 }
 
 // Several systems of different sizes in one launch: workgroups [block0,
@@ -1878,13 +1885,14 @@ struct SweepArgs {
     uint64_t step0;
     double *eh, *th;
     int64_t* ph;
+    const uint64_t* step_dev;
 };
 
 template <int NSO, int NE, int NT, bool NW1, bool SM, typename RT>
 void launch_one(dim3 grid, dim3 block, size_t lds, hipStream_t st, const Tab& T, const Wk& S, const vmc_walkers* w,
                 const SweepArgs& a, const vmc_ctx* h) {
     hipLaunchKernelGGL((k_sweep<NSO, NE, NT, NW1, SM, RT>), grid, block, lds, st, T, S, w->n_walkers, a.mode,
-                       a.n_steps, a.step0, h->seed, a.refresh, a.eh, a.th, a.ph);
+                       a.n_steps, a.step0, a.step_dev, h->seed, a.refresh, a.eh, a.th, a.ph);
 }
 
 template <typename RT>
@@ -1929,15 +1937,10 @@ vmc_status launch_refresh(vmc_ctx* h, vmc_walkers* w, hipStream_t st) {
     const Tab T = make_tab(h);
     const Wk S = make_wk(h, w);
     const dim3 grid((unsigned)w->n_walkers), block(256);
-    if (h->precision == VMC_MIXED) {
-        HIP_OR_FAIL(h, hipFuncSetAttribute((const void*)k_refresh<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds));
+    if (h->precision == VMC_MIXED)
         hipLaunchKernelGGL(k_refresh<float>, grid, block, lds, st, T, S, w->n_walkers);
-    } else {
-        HIP_OR_FAIL(h, hipFuncSetAttribute((const void*)k_refresh<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds));
+    else
         hipLaunchKernelGGL(k_refresh<double>, grid, block, lds, st, T, S, w->n_walkers);
-    }
     HIP_OR_FAIL(h, hipGetLastError());
     return VMC_OK;
 }
@@ -2122,6 +2125,20 @@ vmc_status vmc_init(const vmc_system_desc* desc, const double* h1, const vmc_eri
         free_ctx(h);
         return fail(nullptr, VMC_E_HIP, "table upload failed");
     }
+    // dynamic LDS beyond 64 KB for the refresh kernel, set here once so that
+    // later calls (possibly under graph capture) only launch
+    if (refresh_lds_bytes(h->ne, 256) <= kMaxRefreshLds) {
+        const int lds = (int)refresh_lds_bytes(h->ne, 256);
+        const hipError_t e = (h->precision == VMC_MIXED)
+                                 ? hipFuncSetAttribute((const void*)k_refresh<float>,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds)
+                                 : hipFuncSetAttribute((const void*)k_refresh<double>,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) {
+            free_ctx(h);
+            return fail(nullptr, VMC_E_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+        }
+    }
     *out = h;
     return VMC_OK;
 }
@@ -2170,17 +2187,17 @@ vmc_status vmc_walkers_init(vmc_handle h, vmc_walkers* w, hipStream_t st) {
     vmc_status s = check_walkers(h, w);
     if (s != VMC_OK) return s;
     if (use_refresh_kernel(h)) {
-        s = launch_sweep(h, w, SweepArgs{MODE_INIT, 1, 0, w->step, nullptr, nullptr, nullptr}, st);
+        s = launch_sweep(h, w, SweepArgs{MODE_INIT, 1, 0, w->step, nullptr, nullptr, nullptr, nullptr}, st);
         return s != VMC_OK ? s : launch_refresh(h, w, st);
     }
-    return launch_sweep(h, w, SweepArgs{MODE_INIT, 1, h->refresh, w->step, nullptr, nullptr, nullptr}, st);
+    return launch_sweep(h, w, SweepArgs{MODE_INIT, 1, h->refresh, w->step, nullptr, nullptr, nullptr, nullptr}, st);
 }
 
 vmc_status vmc_local_energy(vmc_handle h, vmc_walkers* w, hipStream_t st) {
     if (!h) return fail(nullptr, VMC_E_ARG, "handle is NULL");
     vmc_status s = check_walkers(h, w);
     if (s != VMC_OK) return s;
-    return launch_sweep(h, w, SweepArgs{MODE_ELOC, 1, h->refresh, w->step, nullptr, nullptr, nullptr}, st);
+    return launch_sweep(h, w, SweepArgs{MODE_ELOC, 1, h->refresh, w->step, nullptr, nullptr, nullptr, nullptr}, st);
 }
 
 vmc_status vmc_ctmc_step(vmc_handle h, vmc_walkers* w, int32_t n_steps, double* eh, double* th, int64_t* ph,
@@ -2191,7 +2208,7 @@ vmc_status vmc_ctmc_step(vmc_handle h, vmc_walkers* w, int32_t n_steps, double* 
     if (n_steps < 0) return fail(h, VMC_E_ARG, "n_steps must be >= 0");
     if (n_steps == 0) return VMC_OK;
     if (!use_refresh_kernel(h)) {
-        s = launch_sweep(h, w, SweepArgs{MODE_CTMC, n_steps, h->refresh, w->step, eh, th, ph}, st);
+        s = launch_sweep(h, w, SweepArgs{MODE_CTMC, n_steps, h->refresh, w->step, eh, th, ph, nullptr}, st);
         if (s == VMC_OK) w->step += (uint64_t)n_steps;
         return s;
     }
@@ -2205,12 +2222,37 @@ vmc_status vmc_ctmc_step(vmc_handle h, vmc_walkers* w, int32_t n_steps, double* 
         const int to_b = h->refresh - (int)(g % (uint64_t)h->refresh);
         const int seg = std::min(n_steps - k, to_b);
         s = launch_sweep(h, w, SweepArgs{MODE_CTMC, seg, 0, g, eh ? eh + (size_t)k * W : nullptr,
-                                         th ? th + (size_t)k * W : nullptr, ph ? ph + (size_t)k * W : nullptr}, st);
+                                         th ? th + (size_t)k * W : nullptr, ph ? ph + (size_t)k * W : nullptr,
+                                         nullptr}, st);
         if (s != VMC_OK) return s;
         w->step += (uint64_t)seg;
         if (seg == to_b && (s = launch_refresh(h, w, st)) != VMC_OK) return s;
         k += seg;
     }
+    return VMC_OK;
+}
+
+vmc_status vmc_ctmc_step_dev(vmc_handle h, vmc_walkers* w, int32_t n_steps, uint64_t* step_dev, hipStream_t st) {
+    if (!h) return fail(nullptr, VMC_E_ARG, "handle is NULL");
+    vmc_status s = check_walkers(h, w);
+    if (s != VMC_OK) return s;
+    if (!step_dev) return fail(h, VMC_E_ARG, "step_dev is NULL");
+    if (n_steps < 0) return fail(h, VMC_E_ARG, "n_steps must be >= 0");
+    if (n_steps == 0) return VMC_OK;
+    if (!use_refresh_kernel(h)) {
+        s = launch_sweep(h, w, SweepArgs{MODE_CTMC, n_steps, h->refresh, 0, nullptr, nullptr, nullptr, step_dev}, st);
+    } else {
+        if (n_steps % h->refresh != 0)
+            return fail(h, VMC_E_ARG, "with the separate refresh kernel, n_steps must be a multiple of refresh_period");
+        for (int k = 0; k < n_steps && s == VMC_OK; k += h->refresh) {
+            s = launch_sweep(h, w, SweepArgs{MODE_CTMC, h->refresh, 0, (uint64_t)k, nullptr, nullptr, nullptr, step_dev},
+                             st);
+            if (s == VMC_OK) s = launch_refresh(h, w, st);
+        }
+    }
+    if (s != VMC_OK) return s;
+    hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(64), 0, st, step_dev, (uint64_t)n_steps);
+    HIP_OR_FAIL(h, hipGetLastError());
     return VMC_OK;
 }
 

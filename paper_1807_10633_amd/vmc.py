@@ -29,7 +29,7 @@ EXPORTED = (
     "vmc_destroy", "vmc_last_error", "vmc_host_tables_build", "vmc_host_tables_sizes", "vmc_host_tables_get",
     "vmc_host_tables_free", "vmc_set_launch", "vmc_launch_info", "vmc_estimate", "vmc_batch_create",
     "vmc_batch_set_launch", "vmc_batch_local_energy", "vmc_batch_ctmc_step", "vmc_batch_destroy", "vmc_autotune",
-    "vmc_batch_autotune",
+    "vmc_batch_autotune", "vmc_ctmc_step_dev",
 )
 
 
@@ -83,6 +83,7 @@ def load_library() -> C.CDLL:
         "vmc_batch_ctmc_step": ([P, P, i32, P], i32),
         "vmc_batch_destroy": ([P], i32),
         "vmc_autotune": ([P, P, i32, P, P], i32),
+        "vmc_ctmc_step_dev": ([P, P, i32, P, P], i32),
         "vmc_batch_autotune": ([P, P, i32, P, P], i32),
         "vmc_set_launch": ([P, i32], i32),
         "vmc_destroy": ([P], i32),
@@ -167,6 +168,12 @@ def vmc_ctmc_step(handle, walkers: "Walkers", n_steps: int, eloc_hist=None, t_hi
     _check(load_library().vmc_ctmc_step(handle, C.byref(walkers.cstruct), int(n_steps), _dev_ptr(eloc_hist),
                                         _dev_ptr(t_hist), _dev_ptr(pick_hist), _stream_ptr(stream)), handle,
            "vmc_ctmc_step")
+
+
+def vmc_ctmc_step_dev(handle, walkers: "Walkers", n_steps: int, step_dev, stream=None) -> None:
+    """CTMC moves with the step counter in device memory (graph-capturable)."""
+    _check(load_library().vmc_ctmc_step_dev(handle, C.byref(walkers.cstruct), int(n_steps), _dev_ptr(step_dev),
+                                            _stream_ptr(stream)), handle, "vmc_ctmc_step_dev")
 
 
 def vmc_logderiv(handle, walkers: "Walkers", g_dev, out_dev, stream=None) -> None:
