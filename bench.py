@@ -75,6 +75,7 @@ def parse():
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
                     help="form of the headline number (the other form is measured beside it)")
     ap.add_argument("--no-other-form", action="store_true", help="do not measure the other precision form")
+    ap.add_argument("--no-graph", action="store_true", help="do not time the hipGraph-replayed iteration")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (reference kernel for the HBM byte "
                          "counters) and exit")
@@ -170,7 +171,38 @@ def main():
             E = one_step(True)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        # the same iteration captured once in a HIP graph and replayed (CTMC
+        # moves with the device-resident step counter)
+        graph_value = None
+        if not args.no_graph:
+            step_dev = torch.tensor([walkers.step], dtype=torch.int64, device=dev)
+
+            def graph_step(st):
+                vmc.vmc_ctmc_step_dev(sysm.handle, walkers, S, step_dev, stream=st)
+                vmc.vmc_local_energy(sysm.handle, walkers, stream=st)
+                vmc.vmc_estimate(sysm.handle, walkers, est, g, stream=st)
+                vmc.vmc_logderiv(sysm.handle, walkers, g, G, stream=st)
+                vmc.vmc_amsgrad(params, m, v, vh, G, 1e-3, 0.9, 0.99, 1e-8, False, stream=st)
+                vmc.vmc_set_params(sysm.handle, params[:nj], params[nj:], stream=st)
+                vmc.vmc_walkers_init(sysm.handle, walkers, stream=st)
+
+            graph = torch.cuda.CUDAGraph()
+            cs = torch.cuda.Stream()
+            cs.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(cs):
+                with torch.cuda.graph(graph, stream=cs):
+                    graph_step(torch.cuda.current_stream())
+            torch.cuda.current_stream().wait_stream(cs)
+            graph.replay()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                graph.replay()
+            torch.cuda.synchronize()
+            graph_value = W * S * steps / (time.perf_counter() - t0)
+            walkers.step = int(step_dev.item())
         res = {"sysm": sysm, "walkers": walkers, "params": params, "wall": wall, "E": float(E),
+               "graph_value": graph_value,
                "value": W * S * steps / wall,
                "sweep_ms": float(np.mean([a.elapsed_time(b) for a, b in sweep_events])),
                "status": walkers.view("status", torch.int32)[:W].cpu().numpy()}
@@ -205,7 +237,8 @@ def main():
                  "eloc_evals_per_s_in_sweep": W * S / (o["sweep_ms"] * 1e-3),
                  "el_max_abs_err_vs_oracle": o["el_err"],
                  "el_max_abs_err_per_electron": (o["el_err"] / wl.n_elec) if o["el_err"] is not None else None,
-                 "energy": o["E"], "flagged_walkers": int(np.count_nonzero(o["status"] & 1))}
+                 "energy": o["E"], "flagged_walkers": int(np.count_nonzero(o["status"] & 1)),
+                 "graph_replay_value": o["graph_value"]}
         o["sysm"].close()
 
     # --- algorithmic work of the sweep kernel, from candidate counts of a
@@ -296,6 +329,7 @@ def main():
                    "hchain20" else args.config, "walkers": W, "ctmc_moves_per_step": S, "refresh_period": S,
                    "precision": args.precision},
         "eloc_evals_per_s_in_sweep": W * S / (sweep_ms * 1e-3),
+        "graph_replay_value": head["graph_value"],
         "el_max_abs_err_vs_oracle": el_err,
         "energy": E,
         "other_form": other,
