@@ -301,6 +301,7 @@ __device__ __forceinline__ void r_gemm(const Tab& T, const double* B, RT* R, con
         const int pt = t / nt16, at = t - pt * nt16;
         const int p = pt * 16 + m, a = at * 16 + m;
         typename Mma<RT>::acc_t acc = {0, 0, 0, 0};
+#pragma unroll 4
         for (int k0 = 0; k0 < ne; k0 += 4) {
             const int x = k0 + kq;
             const RT av = (p < ne && x < ne) ? (RT)B[p * ne + x] : (RT)0;
@@ -1482,12 +1483,95 @@ __host__ __device__ inline size_t refresh_lds_bytes(int ne, int nt) {
            al16((size_t)(32 + nwv) * 4);
 }
 
-// Periodic (and initial) re-inversion for walkers whose state lives in HBM:
-// the same Gauss-Jordan elimination with partial pivoting as the sweep
-// kernel's in-LDS refresh, with B held in LDS for the elimination (up to
-// 160 KB per workgroup), then R = theta B on the matrix cores, s and H_NN.
-template <typename RT>
-__global__ void __launch_bounds__(256) k_refresh(Tab T, Wk S, int64_t W) {
+// Newton-Schulz re-inversion of a carried inverse, on the FP64 matrix cores.
+// With A = theta[occ, 0:Ne] and X = A^-1 approximated by the carried B
+// (B[p][x] = X[x][p]): F = I - X A, then X <- X + F X, i.e. B <- B + B F^T.
+// Each step squares the residual, so one step takes a carried FP64 inverse to
+// working precision and three take an FP32-accurate one there.  F lives in
+// LDS; B is updated in place in HBM, each wave owning 16-row blocks of B.
+// Returns false when the residual max|F| exceeds 1/2 at the start (or does not
+// fall below 1e-10 within four steps): the caller then inverts from scratch.
+constexpr int kNsMaxTiles = 10;  // Ne <= 160
+__device__ __forceinline__ bool newton_schulz(const Tab& T, const int* slot, double* Bg, double* F, double* red) {
+    const int ne = T.ne, n_so = T.n_so, tid = threadIdx.x, l = lane_id();
+    const int wv = (int)__builtin_amdgcn_readfirstlane((uint32_t)(tid >> 6)), nwv = blockDim.x >> 6;
+    const int m = l & 15, kq = l >> 4, nb = (ne + 15) >> 4;
+    typedef Mma<double> M;
+    for (int it = 0; it < 4; ++it) {
+        // F = I - B^T A  (F[x][y] = delta_xy - sum_p B[p][x] theta[slot p][y])
+        double lmax = 0.0;
+        for (int t = wv; t < nb * nb; t += nwv) {
+            const int xt = t / nb, yt = t - xt * nb;
+            const int x = xt * 16 + m, y = yt * 16 + m;
+            M::acc_t acc = {0, 0, 0, 0};
+#pragma unroll 4
+            for (int k0 = 0; k0 < ne; k0 += 4) {
+                const int p = k0 + kq;
+                const double av = (p < ne && x < ne) ? Bg[p * ne + x] : 0.0;
+                const double bv = (p < ne && y < ne) ? T.theta[(size_t)slot[p] * n_so + y] : 0.0;
+                acc = M::step(av, bv, acc);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int xr = xt * 16 + M::row(kq, j);
+                if (xr < ne && y < ne) {
+                    const double f = (xr == y ? 1.0 : 0.0) - acc[j];
+                    F[xr * ne + y] = f;
+                    lmax = fmax(lmax, fabs(f));
+                }
+            }
+        }
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) lmax = fmax(lmax, __shfl_xor(lmax, d, kWave));
+        if (l == 0) red[wv] = lmax;
+        __syncthreads();
+        double r = 0.0;
+        for (int q = 0; q < nwv; ++q) r = fmax(r, red[q]);
+        __syncthreads();
+        if (!(r <= 0.5) && it == 0) return false;  // includes NaN
+        if (it > 0 && r < 1e-10) return true;
+        // B += B F^T  (B[q][x] += sum_y B[q][y] F[x][y]); a wave reads only its
+        // own row block of B, so it may write it once all its tiles are summed
+        for (int qt = wv; qt < nb; qt += nwv) {
+            M::acc_t acc[kNsMaxTiles];
+#pragma unroll
+            for (int xt = 0; xt < kNsMaxTiles; ++xt) acc[xt] = M::acc_t{0, 0, 0, 0};
+            const int q = qt * 16 + m;
+#pragma unroll 2
+            for (int k0 = 0; k0 < ne; k0 += 4) {
+                const int y = k0 + kq;
+                const double av = (q < ne && y < ne) ? Bg[q * ne + y] : 0.0;
+#pragma unroll
+                for (int xt = 0; xt < kNsMaxTiles; ++xt)
+                    if (xt < nb) {
+                        const int x = xt * 16 + m;
+                        const double bv = (x < ne && y < ne) ? F[x * ne + y] : 0.0;
+                        acc[xt] = M::step(av, bv, acc[xt]);
+                    }
+            }
+#pragma unroll
+            for (int xt = 0; xt < kNsMaxTiles; ++xt)
+                if (xt < nb)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int qr = qt * 16 + M::row(kq, j), xc = xt * 16 + m;
+                        if (qr < ne && xc < ne) Bg[qr * ne + xc] += acc[xt][j];
+                    }
+        }
+        __syncthreads();
+    }
+    return false;
+}
+
+// Periodic (and initial) re-inversion for walkers whose state lives in HBM.
+// NS (periodic refresh): Newton-Schulz from the carried B on the matrix
+// cores.  Otherwise, or when that does not converge: the same Gauss-Jordan
+// elimination with partial pivoting as the sweep kernel's in-LDS refresh, with
+// B held in LDS (up to 160 KB per workgroup).  Then R = theta B on the matrix
+// cores, s and H_NN.
+constexpr int kRefreshThreads = 512;
+template <typename RT, bool NS>
+__global__ void __launch_bounds__(kRefreshThreads) k_refresh(Tab T, Wk S, int64_t W) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int64_t w = blockIdx.x;
     if (w >= W) return;
@@ -1510,9 +1594,25 @@ __global__ void __launch_bounds__(256) k_refresh(Tab T, Wk S, int64_t W) {
     __syncthreads();
     RT* R = (RT*)S.R + (size_t)w * n_so * ne;
     double* s = S.s + (size_t)w * n_so;
-    refresh_state(T, slot, B, R, s, fcol, ipiv, mi, red, T.theta, n_so);
     double* Bg = S.B + (size_t)w * ne * ne;
-    for (int k = tid; k < ne * ne; k += nt) Bg[k] = B[k];
+    bool done = false;
+    if (NS && ne <= 16 * kNsMaxTiles && !(mi[MI_ST] & (int)VMC_ST_SINGULAR)) done = newton_schulz(T, slot, Bg, B, red);
+    if (done) {
+        r_gemm<RT>(T, Bg, R, T.theta, n_so);
+        for (int pp = tid; pp < n_so; pp += nt) {
+            const double* Jr = T.J + (size_t)pp * n_so;
+            double acc = 0.0;
+            for (int k = 0; k < ne; ++k) {
+                const int q = slot[k];
+                if (q != pp) acc += Jr[q];
+            }
+            s[pp] = acc;
+        }
+        __syncthreads();
+    } else {
+        refresh_state(T, slot, B, R, s, fcol, ipiv, mi, red, T.theta, n_so);
+        for (int k = tid; k < ne * ne; k += nt) Bg[k] = B[k];
+    }
     double hp = 0.0;
     for (int x = tid; x < ne; x += nt) {
         const int i = slot[x];
@@ -1929,18 +2029,21 @@ SweepGeom sweep_geom(const vmc_ctx* h) {
 // kernel when B fits its LDS budget.
 constexpr size_t kMaxRefreshLds = 160 * 1024;
 bool use_refresh_kernel(const vmc_ctx* h) {
-    return !sweep_geom(h).small && refresh_lds_bytes(h->ne, 256) <= kMaxRefreshLds;
+    return !sweep_geom(h).small && refresh_lds_bytes(h->ne, kRefreshThreads) <= kMaxRefreshLds;
 }
 
-vmc_status launch_refresh(vmc_ctx* h, vmc_walkers* w, hipStream_t st) {
-    const size_t lds = refresh_lds_bytes(h->ne, 256);
+vmc_status launch_refresh(vmc_ctx* h, vmc_walkers* w, bool ns, hipStream_t st) {
+    const size_t lds = refresh_lds_bytes(h->ne, kRefreshThreads);
     const Tab T = make_tab(h);
     const Wk S = make_wk(h, w);
-    const dim3 grid((unsigned)w->n_walkers), block(256);
-    if (h->precision == VMC_MIXED)
-        hipLaunchKernelGGL(k_refresh<float>, grid, block, lds, st, T, S, w->n_walkers);
-    else
-        hipLaunchKernelGGL(k_refresh<double>, grid, block, lds, st, T, S, w->n_walkers);
+    const dim3 grid((unsigned)w->n_walkers), block(kRefreshThreads);
+    if (h->precision == VMC_MIXED) {
+        if (ns) hipLaunchKernelGGL((k_refresh<float, true>), grid, block, lds, st, T, S, w->n_walkers);
+        else hipLaunchKernelGGL((k_refresh<float, false>), grid, block, lds, st, T, S, w->n_walkers);
+    } else {
+        if (ns) hipLaunchKernelGGL((k_refresh<double, true>), grid, block, lds, st, T, S, w->n_walkers);
+        else hipLaunchKernelGGL((k_refresh<double, false>), grid, block, lds, st, T, S, w->n_walkers);
+    }
     HIP_OR_FAIL(h, hipGetLastError());
     return VMC_OK;
 }
@@ -2127,13 +2230,15 @@ vmc_status vmc_init(const vmc_system_desc* desc, const double* h1, const vmc_eri
     }
     // dynamic LDS beyond 64 KB for the refresh kernel, set here once so that
     // later calls (possibly under graph capture) only launch
-    if (refresh_lds_bytes(h->ne, 256) <= kMaxRefreshLds) {
-        const int lds = (int)refresh_lds_bytes(h->ne, 256);
-        const hipError_t e = (h->precision == VMC_MIXED)
-                                 ? hipFuncSetAttribute((const void*)k_refresh<float>,
-                                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds)
-                                 : hipFuncSetAttribute((const void*)k_refresh<double>,
-                                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (refresh_lds_bytes(h->ne, kRefreshThreads) <= kMaxRefreshLds) {
+        const int lds = (int)refresh_lds_bytes(h->ne, kRefreshThreads);
+        const void* fns[2] = {(h->precision == VMC_MIXED) ? (const void*)k_refresh<float, false>
+                                                          : (const void*)k_refresh<double, false>,
+                               (h->precision == VMC_MIXED) ? (const void*)k_refresh<float, true>
+                                                          : (const void*)k_refresh<double, true>};
+        hipError_t e = hipSuccess;
+        for (const void* f : fns)
+            if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e != hipSuccess) {
             free_ctx(h);
             return fail(nullptr, VMC_E_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
@@ -2188,7 +2293,7 @@ vmc_status vmc_walkers_init(vmc_handle h, vmc_walkers* w, hipStream_t st) {
     if (s != VMC_OK) return s;
     if (use_refresh_kernel(h)) {
         s = launch_sweep(h, w, SweepArgs{MODE_INIT, 1, 0, w->step, nullptr, nullptr, nullptr, nullptr}, st);
-        return s != VMC_OK ? s : launch_refresh(h, w, st);
+        return s != VMC_OK ? s : launch_refresh(h, w, false, st);
     }
     return launch_sweep(h, w, SweepArgs{MODE_INIT, 1, h->refresh, w->step, nullptr, nullptr, nullptr, nullptr}, st);
 }
@@ -2226,7 +2331,7 @@ vmc_status vmc_ctmc_step(vmc_handle h, vmc_walkers* w, int32_t n_steps, double* 
                                          nullptr}, st);
         if (s != VMC_OK) return s;
         w->step += (uint64_t)seg;
-        if (seg == to_b && (s = launch_refresh(h, w, st)) != VMC_OK) return s;
+        if (seg == to_b && (s = launch_refresh(h, w, true, st)) != VMC_OK) return s;
         k += seg;
     }
     return VMC_OK;
@@ -2247,7 +2352,7 @@ vmc_status vmc_ctmc_step_dev(vmc_handle h, vmc_walkers* w, int32_t n_steps, uint
         for (int k = 0; k < n_steps && s == VMC_OK; k += h->refresh) {
             s = launch_sweep(h, w, SweepArgs{MODE_CTMC, h->refresh, 0, (uint64_t)k, nullptr, nullptr, nullptr, step_dev},
                              st);
-            if (s == VMC_OK) s = launch_refresh(h, w, st);
+            if (s == VMC_OK) s = launch_refresh(h, w, true, st);
         }
     }
     if (s != VMC_OK) return s;
