@@ -1978,7 +1978,7 @@ constexpr size_t kMaxLds = 64 * 1024;
 struct SweepSpec {
     int n_so, ne, nt;
 };
-constexpr SweepSpec kSpecs[] = {{16, 8, 64}, {16, 8, 128}, {40, 20, 128}, {40, 20, 256}, {64, 32, 256}};
+constexpr SweepSpec kSpecs[] = {{16, 8, 64}, {16, 8, 128}, {16, 8, 256}, {40, 20, 128}, {40, 20, 256}, {64, 32, 256}};
 
 struct SweepArgs {
     int mode, n_steps, refresh;
@@ -2001,6 +2001,7 @@ void launch_prec(bool small, bool nw1, int nt, dim3 grid, dim3 block, size_t lds
     auto spec = [&](int n_so, int ne, int c) { return small && h->n_so == n_so && h->ne == ne && nt == c; };
     if (spec(16, 8, 64)) launch_one<16, 8, 64, true, true, RT>(grid, block, lds, st, T, S, w, a, h);
     else if (spec(16, 8, 128)) launch_one<16, 8, 128, true, true, RT>(grid, block, lds, st, T, S, w, a, h);
+    else if (spec(16, 8, 256)) launch_one<16, 8, 256, true, true, RT>(grid, block, lds, st, T, S, w, a, h);
     else if (spec(40, 20, 128)) launch_one<40, 20, 128, true, true, RT>(grid, block, lds, st, T, S, w, a, h);
     else if (spec(40, 20, 256)) launch_one<40, 20, 256, true, true, RT>(grid, block, lds, st, T, S, w, a, h);
     else if (spec(64, 32, 256)) launch_one<64, 32, 256, true, true, RT>(grid, block, lds, st, T, S, w, a, h);
