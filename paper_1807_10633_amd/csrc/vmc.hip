@@ -864,10 +864,11 @@ enum { MODE_ELOC = 0, MODE_CTMC = 1, MODE_INIT = 2 };
 #ifndef VMC_SWEEP_HBM_WAVES
 #define VMC_SWEEP_HBM_WAVES 3
 #endif
-// Walker state in LDS: small systems (up to 16 spin-orbitals) fit four waves
-// per SIMD without spills; larger ones are left to the compiler (1).
+// Walker state in LDS: four waves per SIMD (measured faster than the
+// compiler's own choice of three up to 40 spin-orbitals, a few spills
+// included); the 64-spin-orbital specialisation is left to the compiler (1).
 constexpr int sweep_waves_target(int nso_t, bool small) {
-    return small ? ((nso_t > 0 && nso_t <= 16) ? 4 : 1) : VMC_SWEEP_HBM_WAVES;
+    return small ? ((nso_t <= 40) ? 4 : 1) : VMC_SWEEP_HBM_WAVES;
 }
 
 // NSO_T, NE_T, NT_T: compile-time n_so, Ne and workgroup size of a size
