@@ -1973,7 +1973,11 @@ Wk make_wk(const vmc_ctx* h, const vmc_walkers* w) {
     return S;
 }
 
+// LDS per workgroup: the walker state is kept on chip when it fits 64 KB
+// (several walkers per CU); otherwise the per-walker work arrays alone may use
+// up to the 160 KB a gfx950 workgroup can address.
 constexpr size_t kMaxLds = 64 * 1024;
+constexpr size_t kMaxLdsHbm = 160 * 1024;
 
 // Size specialisations of the sweep kernel: (n_so, Ne, threads).
 struct SweepSpec {
@@ -2052,7 +2056,7 @@ vmc_status launch_refresh(vmc_ctx* h, vmc_walkers* w, bool ns, hipStream_t st) {
 
 vmc_status launch_sweep(vmc_ctx* h, vmc_walkers* w, const SweepArgs& a, hipStream_t st) {
     const SweepGeom g = sweep_geom(h);
-    if (g.lds > kMaxLds) return fail(h, VMC_E_UNSUPPORTED, "system too large for the per-walker LDS budget");
+    if (g.lds > kMaxLdsHbm) return fail(h, VMC_E_UNSUPPORTED, "system too large for the per-walker LDS budget");
     const bool nw1 = (h->nw == 1);
     const Tab T = make_tab(h);
     const Wk S = make_wk(h, w);
@@ -2230,8 +2234,22 @@ vmc_status vmc_init(const vmc_system_desc* desc, const double* h1, const vmc_eri
         free_ctx(h);
         return fail(nullptr, VMC_E_HIP, "table upload failed");
     }
-    // dynamic LDS beyond 64 KB for the refresh kernel, set here once so that
-    // later calls (possibly under graph capture) only launch
+    // dynamic LDS beyond 64 KB for the kernels that may need it, set here once
+    // so that later calls (possibly under graph capture) only launch
+    {
+        const void* big[] = {(const void*)k_sweep<0, 0, 0, false, false, double>,
+                             (const void*)k_sweep<0, 0, 0, true, false, double>,
+                             (const void*)k_sweep<0, 0, 0, false, false, float>,
+                             (const void*)k_sweep<0, 0, 0, true, false, float>,
+                             (const void*)k_sweep_batch<double>, (const void*)k_sweep_batch<float>};
+        for (const void* f : big) {
+            const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLdsHbm);
+            if (e != hipSuccess) {
+                free_ctx(h);
+                return fail(nullptr, VMC_E_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+            }
+        }
+    }
     if (refresh_lds_bytes(h->ne, kRefreshThreads) <= kMaxRefreshLds) {
         const int lds = (int)refresh_lds_bytes(h->ne, kRefreshThreads);
         const void* fns[2] = {(h->precision == VMC_MIXED) ? (const void*)k_refresh<float, false>
@@ -2490,7 +2508,7 @@ vmc_status vmc_autotune(vmc_handle h, vmc_walkers* w, int32_t n_moves, int32_t* 
     for (int nt : kTuneThreads) {
         h->block_threads = nt;
         const SweepGeom g = sweep_geom(h);
-        if (g.lds > kMaxLds) continue;
+        if (g.lds > kMaxLdsHbm) continue;
         float ms = 0.0f;
         s = time_sweeps(h, w, nullptr, nullptr, n_moves, 2, st, &ms);
         if (s != VMC_OK) {
@@ -2522,7 +2540,7 @@ vmc_status vmc_batch_autotune(vmc_batch b, vmc_walkers* const* walkers, int32_t 
         size_t lds = 0;
         for (vmc_ctx* h : b->sys)
             lds = std::max(lds, (size_t)lds_layout(h->n_so, h->ne, h->nw, nt, false, (int)r_bytes(h)).total);
-        if (lds > kMaxLds) continue;
+        if (lds > kMaxLdsHbm) continue;
         b->nt = nt;
         float ms = 0.0f;
         vmc_status s = time_sweeps(nullptr, nullptr, b, walkers, n_moves, 2, st, &ms);
@@ -2612,7 +2630,7 @@ static vmc_status launch_batch(vmc_batch b, vmc_walkers* const* ws, int mode, in
         blocks += E.W;
         lds = std::max(lds, (size_t)lds_layout(h->n_so, h->ne, h->nw, b->nt, false, (int)r_bytes(h)).total);
     }
-    if (lds > kMaxLds) return fail(nullptr, VMC_E_UNSUPPORTED, "a batched system exceeds the per-walker LDS budget");
+    if (lds > kMaxLdsHbm) return fail(nullptr, VMC_E_UNSUPPORTED, "a batched system exceeds the per-walker LDS budget");
     if (blocks > (int64_t)INT_MAX) return fail(nullptr, VMC_E_ARG, "too many walkers in the batch");
     const dim3 grid((unsigned)blocks), block((unsigned)b->nt);
     if (b->precision == VMC_MIXED)
