@@ -675,7 +675,8 @@ __device__ __forceinline__ bool stream_pass(const Tab& T, const StepView<RT>& V,
     // held one per lane, the chunk's group found by a ballot, so that empty
     // groups cost nothing and descriptor loads are coalesced.
     constexpr bool REG_CURSOR = !SCALED;
-    uint32_t gc = uni(g0), qn = 0;
+    // survivor queue: a ring of kQueue entries, head qh, qn entries queued
+    uint32_t gc = uni(g0), qn = 0, qh = 0;
     uint32_t e_end = 0, e_vend = 0, e_delta = 0;
     uint32_t blk = 0, b_end = 0, b_vend = 0, b_delta = 0;
     auto load_block = [&]() __attribute__((always_inline)) {
@@ -749,9 +750,10 @@ __device__ __forceinline__ bool stream_pass(const Tab& T, const StepView<RT>& V,
     auto batch = [&](int k) __attribute__((always_inline)) -> bool {
         wave_lds_sync();
         const bool act = l < k;
-        const uint64_t og = act ? q64[l] : 0ull;
+        const uint32_t qi = (qh + (uint32_t)l) & (kQueue - 1);
+        const uint64_t og = act ? q64[qi] : 0ull;
         const uint32_t off = (uint32_t)og, g = (uint32_t)(og >> 32);
-        const uint64_t ab = act ? qab[l] : 0ull;
+        const uint64_t ab = act ? qab[qi] : 0ull;
         double2 vk = make_double2(0.0, 0.0);
         if (DOUBLES && act) vk = *(const double2*)(T.dvK + 2 * (size_t)off);
         double term = 0.0, r = 0.0;
@@ -797,23 +799,16 @@ __device__ __forceinline__ bool stream_pass(const Tab& T, const StepView<RT>& V,
             surv = surv && !found;
             const uint64_t m = __ballot(surv);
             if (surv) {
-                const uint32_t sq = qn + mask_below(m);
+                const uint32_t sq = (qh + qn + mask_below(m)) & (kQueue - 1);
                 q64[sq] = (uint64_t)st.off[u] | ((uint64_t)st.g[u] << 32);
                 qab[sq] = st.ab[u];
             }
             qn += (uint32_t)__popcll(m);
             if (qn >= (uint32_t)kWave) {
                 found = batch(kWave);
-                wave_lds_sync();
-                const bool mv = (uint32_t)l + kWave < qn;
-                const uint64_t r64 = mv ? q64[l + kWave] : 0ull;
-                const uint64_t rab = mv ? qab[l + kWave] : 0ull;
-                wave_lds_sync();
+                wave_lds_sync();  // the batch's queue reads precede later writes
+                qh = (qh + kWave) & (kQueue - 1);
                 qn -= kWave;
-                if ((uint32_t)l < qn) {
-                    q64[l] = r64;
-                    qab[l] = rab;
-                }
             }
         }
     };
