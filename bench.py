@@ -67,7 +67,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--walkers", type=int, default=4096)
     ap.add_argument("--sweep", type=int, default=50, help="CTMC moves per step (= refresh period)")
-    ap.add_argument("--config", default="hchain20")
+    ap.add_argument("--config", default="hchain20",
+                    help="hchain20 (default), hubbard8, hubbard10x10, hchain40, hchain80, hchain160, or batch "
+                         "(40/80/160 orbitals in one launch)")
     ap.add_argument("--threads", type=int, default=0, help="workgroup size of the sweep kernel (0 = autotuned)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -96,6 +98,75 @@ def copy_calibration(mib):
     print(json.dumps({"copy_calibration_bytes_read": n * 8, "bytes_written": n * 8}), flush=True)
 
 
+def batch_bench(args):
+    """The uneven batch in one launch: H-chain-like systems of 40, 80 and 160
+    orbitals (half filled, eps = 1e-5), 2048 walkers each, swept together by
+    vmc_batch_ctmc_step.  value = walker-steps/s summed over the three systems.
+    The walker state of every system stays in HBM, so the roofline is HBM with
+    R and B read and written once per move."""
+    import numpy as np
+    import torch
+
+    from paper_1807_10633_amd import vmc
+    from workloads import make_config
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    names = ("hchain40", "hchain80", "hchain160")
+    Wb = 2048
+    S = args.sweep
+    prec = vmc.VMC_MIXED if args.precision == "mixed" else vmc.VMC_FP64
+    wls = [make_config(n, n_walkers=Wb) for n in names]
+    systems = [vmc.System.from_workload(wl, refresh_period=S, precision=prec) for wl in wls]
+    walkers = [s.walkers(wl.occ) for s, wl in zip(systems, wls)]
+    b = vmc.vmc_batch_create([s.handle for s in systems])
+    try:
+        nt = args.threads or vmc.vmc_batch_autotune(b, walkers, 2)
+        if args.threads:
+            vmc.vmc_batch_set_launch(b, nt)
+        stream = torch.cuda.current_stream()
+        vmc.vmc_batch_ctmc_step(b, walkers, S, stream=stream)  # burn-in
+        for _ in range(args.warmup):
+            vmc.vmc_batch_ctmc_step(b, walkers, S, stream=stream)
+        torch.cuda.synchronize()
+        evs = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            vmc.vmc_batch_ctmc_step(b, walkers, S, stream=stream)
+            e1.record(stream)
+            evs.append((e0, e1))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = float(np.mean([a.elapsed_time(c) for a, c in evs]))
+        vmc.vmc_batch_local_energy(b, walkers, stream=stream)
+        torch.cuda.synchronize()
+    finally:
+        vmc.vmc_batch_destroy(b)
+    total_w = Wb * len(names)
+    rb = 4 if prec == vmc.VMC_MIXED else 8
+    bytes_per_move = sum(2.0 * (s.n_so * s.ne * rb + s.ne * s.ne * 8) * Wb for s in systems)
+    gbs = bytes_per_move * S / (ms * 1e-3) / 1e9
+    flagged = sum(int(np.count_nonzero(w.view("status", torch.int32)[:Wb].cpu().numpy() & 1)) for w in walkers)
+    out = {
+        "metric": METRIC, "value": total_w * S * args.steps / wall, "unit": "walker-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64", "data": "synthetic",
+        "config": {"workload": "uneven batch in one launch: H-chain-like 40/80/160 orbitals, half filled, eps=1e-5",
+                   "walkers": [Wb] * len(names), "ctmc_moves_per_step": S, "threads": nt,
+                   "precision": args.precision},
+        "flagged_walkers": flagged,
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "k_sweep_batch (one launch)",
+                     "sweep_kernel_ms": ms, "bytes_per_move_all_walkers": bytes_per_move},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -107,6 +178,9 @@ def main():
 
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.config == "batch":
+        batch_bench(args)
         return
 
     import numpy as np
@@ -157,11 +231,12 @@ def main():
             vmc.vmc_logderiv(sysm.handle, walkers, g, G, stream=stream)
             vmc.vmc_amsgrad(params, m, v, vh, G, 1e-3, 0.9, 0.99, 1e-8, False, stream=stream)
             vmc.vmc_set_params(sysm.handle, params[:nj], params[nj:], stream=stream)
-            vmc.vmc_walkers_init(sysm.handle, walkers, stream=stream)
+            vmc.vmc_walkers_refresh(sysm.handle, walkers, stream=stream)
             return est[2]
 
-        # burn-in of the walkers (not timed, not counted)
-        vmc.vmc_ctmc_step(sysm.handle, walkers, 100, stream=stream)
+        # burn-in of the walkers (not timed, not counted), ending on a refresh
+        # boundary so that each timed sweep is one segment plus one refresh
+        vmc.vmc_ctmc_step(sysm.handle, walkers, 100 + (-(walkers.step + 100)) % S, stream=stream)
         for _ in range(warmup):
             one_step(False)
         torch.cuda.synchronize()
@@ -184,7 +259,7 @@ def main():
                 vmc.vmc_logderiv(sysm.handle, walkers, g, G, stream=st)
                 vmc.vmc_amsgrad(params, m, v, vh, G, 1e-3, 0.9, 0.99, 1e-8, False, stream=st)
                 vmc.vmc_set_params(sysm.handle, params[:nj], params[nj:], stream=st)
-                vmc.vmc_walkers_init(sysm.handle, walkers, stream=st)
+                vmc.vmc_walkers_refresh(sysm.handle, walkers, stream=st)
 
             graph = torch.cuda.CUDAGraph()
             cs = torch.cuda.Stream()

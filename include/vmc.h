@@ -153,6 +153,16 @@ vmc_status vmc_walker_bytes(vmc_handle h, int64_t n_walkers, size_t field_bytes[
  * section "Local energy and Gradient ratios"), R, s, H_NN; clears status. */
 vmc_status vmc_walkers_init(vmc_handle h, vmc_walkers* w, hipStream_t stream);
 
+/* Re-inversion after new parameters (vmc_set_params) for walkers that already
+ * hold a valid state of this system (from vmc_walkers_init or moves): the
+ * occupations and slot order are kept and B, R, s, H_NN recomputed for the
+ * current theta and J.  Walkers whose state lives in HBM are inverted afresh
+ * by the refresh kernel in their current slot order; the others are
+ * re-initialised as by vmc_walkers_init.  Errors: VMC_E_ARG for a NULL handle
+ * or walkers of another system; launch failures as VMC_E_HIP.  The walkers
+ * must not be in use by work on another stream. */
+vmc_status vmc_walkers_refresh(vmc_handle h, vmc_walkers* w, hipStream_t stream);
+
 /* E_L and t = 1/T for every walker from its current state; no state change. */
 vmc_status vmc_local_energy(vmc_handle h, vmc_walkers* w, hipStream_t stream);
 

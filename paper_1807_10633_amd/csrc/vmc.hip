@@ -1485,8 +1485,9 @@ __host__ __device__ inline size_t refresh_lds_bytes(int ne, int nt) {
 // Each step squares the residual, so one step takes a carried FP64 inverse to
 // working precision and three take an FP32-accurate one there.  F lives in
 // LDS; B is updated in place in HBM, each wave owning 16-row blocks of B.
-// Returns false when the residual max|F| exceeds 1/2 at the start (or does not
-// fall below 1e-10 within four steps): the caller then inverts from scratch.
+// Returns true after the step taken from a residual max|F| below 1e-10, false
+// when max|F| exceeds 1/2 at any step or four steps do not reach 1e-10: the
+// caller then inverts from scratch.
 constexpr int kNsMaxTiles = 10;  // Ne <= 160
 __device__ __forceinline__ bool newton_schulz(const Tab& T, const int* slot, double* Bg, double* F, double* red) {
     const int ne = T.ne, n_so = T.n_so, tid = threadIdx.x, l = lane_id();
@@ -1524,8 +1525,7 @@ __device__ __forceinline__ bool newton_schulz(const Tab& T, const int* slot, dou
         double r = 0.0;
         for (int q = 0; q < nwv; ++q) r = fmax(r, red[q]);
         __syncthreads();
-        if (!(r <= 0.5) && it == 0) return false;  // includes NaN
-        if (it > 0 && r < 1e-10) return true;
+        if (!(r <= 0.5)) return false;  // includes NaN
         // B += B F^T  (B[q][x] += sum_y B[q][y] F[x][y]); a wave reads only its
         // own row block of B, so it may write it once all its tiles are summed
         for (int qt = wv; qt < nb; qt += nwv) {
@@ -1555,6 +1555,8 @@ __device__ __forceinline__ bool newton_schulz(const Tab& T, const int* slot, dou
                     }
         }
         __syncthreads();
+        // the step leaves I - B^T A = F^2 up to rounding: below Ne * 1e-20 here
+        if (r < 1e-10) return true;
     }
     return false;
 }
@@ -2310,6 +2312,18 @@ vmc_status vmc_walkers_init(vmc_handle h, vmc_walkers* w, hipStream_t st) {
         s = launch_sweep(h, w, SweepArgs{MODE_INIT, 1, 0, w->step, nullptr, nullptr, nullptr, nullptr}, st);
         return s != VMC_OK ? s : launch_refresh(h, w, false, st);
     }
+    return launch_sweep(h, w, SweepArgs{MODE_INIT, 1, h->refresh, w->step, nullptr, nullptr, nullptr, nullptr}, st);
+}
+
+vmc_status vmc_walkers_refresh(vmc_handle h, vmc_walkers* w, hipStream_t st) {
+    if (!h) return fail(nullptr, VMC_E_ARG, "handle is NULL");
+    vmc_status s = check_walkers(h, w);
+    if (s != VMC_OK) return s;
+    // HBM-resident walkers: Gauss-Jordan in the refresh kernel with the slots
+    // kept (a parameter step of optimiser size leaves the carried B a residual
+    // of 1e-3 or more, three Newton-Schulz steps, which cost more than one
+    // inversion); otherwise a fresh initialisation
+    if (use_refresh_kernel(h)) return launch_refresh(h, w, false, st);
     return launch_sweep(h, w, SweepArgs{MODE_INIT, 1, h->refresh, w->step, nullptr, nullptr, nullptr, nullptr}, st);
 }
 

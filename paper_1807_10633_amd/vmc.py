@@ -29,7 +29,7 @@ EXPORTED = (
     "vmc_destroy", "vmc_last_error", "vmc_host_tables_build", "vmc_host_tables_sizes", "vmc_host_tables_get",
     "vmc_host_tables_free", "vmc_set_launch", "vmc_launch_info", "vmc_estimate", "vmc_batch_create",
     "vmc_batch_set_launch", "vmc_batch_local_energy", "vmc_batch_ctmc_step", "vmc_batch_destroy", "vmc_autotune",
-    "vmc_batch_autotune", "vmc_ctmc_step_dev",
+    "vmc_batch_autotune", "vmc_ctmc_step_dev", "vmc_walkers_refresh",
 )
 
 
@@ -67,6 +67,7 @@ def load_library() -> C.CDLL:
         "vmc_set_params": ([P, P, P, P], i32),
         "vmc_walker_bytes": ([P, i64, P], i32),
         "vmc_walkers_init": ([P, P, P], i32),
+        "vmc_walkers_refresh": ([P, P, P], i32),
         "vmc_local_energy": ([P, P, P], i32),
         "vmc_ctmc_step": ([P, P, i32, P, P, P, P], i32),
         "vmc_logderiv": ([P, P, P, P, P], i32),
@@ -156,6 +157,11 @@ def vmc_walker_bytes(handle, n_walkers: int) -> Dict[str, int]:
 def vmc_walkers_init(handle, walkers: "Walkers", stream=None) -> None:
     _check(load_library().vmc_walkers_init(handle, C.byref(walkers.cstruct), _stream_ptr(stream)), handle,
            "vmc_walkers_init")
+
+
+def vmc_walkers_refresh(handle, walkers: "Walkers", stream=None) -> None:
+    _check(load_library().vmc_walkers_refresh(handle, C.byref(walkers.cstruct), _stream_ptr(stream)), handle,
+           "vmc_walkers_refresh")
 
 
 def vmc_local_energy(handle, walkers: "Walkers", stream=None) -> None:

@@ -268,3 +268,50 @@ def test_autotune_picks_a_valid_shape_and_keeps_walkers_valid(torch):
         r = orc.local_energy(occ[w], ORC_LEMMA, with_candidates=False)
         assert abs(el[w] - r["eloc"]) <= EL_TOL * max(1.0, r["T"] / 100.0)
     _say(f"    autotuned workgroup: {nt} threads per walker")
+
+
+@pytest.mark.parametrize("name,scale", [("hchain40", 1e-3), ("hchain40", 1.0), ("hchain20", 1e-3)])
+def test_walkers_refresh_after_new_parameters(torch, name, scale):
+    """vmc_walkers_refresh after vmc_set_params: B is the inverse of the new
+    theta rows, R = theta B, and E_L matches the oracle at the new parameters.
+    Walkers whose state lives in HBM (40 orbitals) keep their slot order (a
+    small step of the parameters, and parameters replaced outright); the
+    LDS-resident ones (20 orbitals) are re-initialised."""
+    from paper_1807_10633_amd.vmc import vmc_launch_info, vmc_local_energy, vmc_walkers_refresh
+
+    wl = make_config(name, n_walkers=64)
+    sysm = gpu_system(wl)
+    walkers = sysm.walkers(wl.occ)
+    run_sweep(sysm, walkers, 9)
+    ne, n_so = wl.n_elec, wl.n_so
+    in_hbm = not vmc_launch_info(sysm.handle)["state_in_lds"]
+    slot0 = field(sysm, walkers, "slot_orb", torch.int32, ne)
+    rng = np.random.default_rng(3)
+    theta = wl.theta + scale * rng.standard_normal(wl.theta.shape) * np.abs(wl.theta).mean()
+    J = wl.jastrow + 0.1 * scale * rng.standard_normal(wl.jastrow.shape)
+    sysm.set_params(torch.as_tensor(J, device="cuda"), torch.as_tensor(theta, device="cuda"))
+    vmc_walkers_refresh(sysm.handle, walkers)
+    vmc_local_energy(sysm.handle, walkers)
+    torch.cuda.synchronize()
+    slot = field(sysm, walkers, "slot_orb", torch.int32, ne)
+    st = field(sysm, walkers, "status", torch.int32, 1)[:, 0]
+    if in_hbm:
+        assert np.array_equal(slot, slot0)
+    B = field(sysm, walkers, "ainv", torch.float64, ne * ne)
+    R = field(sysm, walkers, "r", torch.float64, ne * n_so)
+    worst_b = worst_r = 0.0
+    for w in range(64):
+        assert (st[w] & 1) == 0
+        Binv = np.linalg.inv(theta[slot[w]][:, :ne])
+        worst_b = max(worst_b, np.max(np.abs(B[w].reshape(ne, ne).T - Binv)) / np.max(np.abs(Binv)))
+        Rf = theta[:, :ne] @ Binv
+        worst_r = max(worst_r, np.max(np.abs(R[w].reshape(ne, n_so).T - Rf)) / np.max(np.abs(Rf)))
+    _say(f"    {name} scale {scale}: max rel |dB| {worst_b:.2e}, |dR| {worst_r:.2e}")
+    assert worst_b < 1e-9 and worst_r < 1e-9
+    el = field(sysm, walkers, "eloc", torch.float64, 1)[:, 0]
+    occ = occ_of(sysm, walkers)
+    orc = OracleSystem(wl.n_orb, wl.n_alpha, wl.n_beta, wl.h1, wl.eri_idx, wl.eri_val, wl.eps)
+    orc.set_params(J, theta)
+    for w in (0, 21, 42, 63):
+        r = orc.local_energy(occ[w], ORC_LEMMA, with_candidates=False)
+        assert abs(el[w] - r["eloc"]) <= EL_TOL * max(1.0, r["T"] / 100.0), (w, el[w], r["eloc"], r["T"])
