@@ -316,6 +316,42 @@ __device__ __forceinline__ void r_gemm(const Tab& T, const double* B, RT* R, con
     }
 }
 
+// The same product with each wave holding a 16-orbital tile of theta in
+// registers (KS k-steps, Ne <= 4 KS) across all slot tiles, so that theta is
+// read once per walker instead of once per output tile; B in LDS.
+template <typename RT, int KS>
+__device__ __forceinline__ void r_gemm_theta_regs(const Tab& T, const double* B, RT* R, const double* th, int ths) {
+    const int ne = T.ne, n_so = T.n_so, l = lane_id();
+    const int wv = (int)__builtin_amdgcn_readfirstlane((uint32_t)(threadIdx.x >> 6)), nwv = blockDim.x >> 6;
+    const int mt = (ne + 15) >> 4, nt16 = (n_so + 15) >> 4;
+    const int m = l & 15, kq = l >> 4;
+    for (int at = wv; at < nt16; at += nwv) {
+        const int a = at * 16 + m;
+        RT tr[KS];
+#pragma unroll
+        for (int st = 0; st < KS; ++st) {
+            const int x = 4 * st + kq;
+            tr[st] = (a < n_so && x < ne) ? (RT)th[(size_t)a * ths + x] : (RT)0;
+        }
+        for (int pt = 0; pt < mt; ++pt) {
+            const int p = pt * 16 + m;
+            typename Mma<RT>::acc_t acc = {0, 0, 0, 0};
+#pragma unroll
+            for (int st = 0; st < KS; ++st)
+                if (4 * st < ne) {
+                    const int x = 4 * st + kq;
+                    const RT av = (p < ne && x < ne) ? (RT)B[p * ne + x] : (RT)0;
+                    acc = Mma<RT>::step(av, tr[st], acc);
+                }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int pr = pt * 16 + Mma<RT>::row(kq, j);
+                if (pr < ne && a < n_so) R[pr * n_so + a] = acc[j];
+            }
+        }
+    }
+}
+
 // M[r][c] -= c1[c] r1[r] (+ c2[c] r2[r]) over rows x cols, by the whole block,
 // arithmetic in FP64.  Rows are contiguous; when they split into 16-byte
 // vectors each thread keeps four vector loads in flight (the update is a
@@ -529,6 +565,27 @@ __device__ __forceinline__ double wave_total(double x) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(x), 63);
     const int hi = __builtin_amdgcn_readlane(__double2hiint(x), 63);
     return __hiloint2double(hi, lo);
+}
+
+// Largest u64 over the 64 lanes (same lane pattern as wave_total), returned
+// as a wave-uniform value.
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, CTRL, ROW_MASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(x >> 32), CTRL, ROW_MASK, 0xF, false);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+__device__ __forceinline__ uint64_t umax64(uint64_t a, uint64_t b) { return a > b ? a : b; }
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t x) {
+    x = umax64(x, dpp_u64<0xB1>(x));
+    x = umax64(x, dpp_u64<0x4E>(x));
+    x = umax64(x, dpp_u64<0x124>(x));
+    x = umax64(x, dpp_u64<0x128>(x));
+    x = umax64(x, dpp_u64<0x142, 0xA>(x));
+    x = umax64(x, dpp_u64<0x143, 0xC>(x));
+    const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)x, 63);
+    const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), 63);
+    return ((uint64_t)hi << 32) | lo;
 }
 
 // Block-wide deterministic sum (every thread gets the same value).
@@ -1479,96 +1536,12 @@ __host__ __device__ inline size_t refresh_lds_bytes(int ne, int nt) {
            al16((size_t)(32 + nwv) * 4);
 }
 
-// Newton-Schulz re-inversion of a carried inverse, on the FP64 matrix cores.
-// With A = theta[occ, 0:Ne] and X = A^-1 approximated by the carried B
-// (B[p][x] = X[x][p]): F = I - X A, then X <- X + F X, i.e. B <- B + B F^T.
-// Each step squares the residual, so one step takes a carried FP64 inverse to
-// working precision and three take an FP32-accurate one there.  F lives in
-// LDS; B is updated in place in HBM, each wave owning 16-row blocks of B.
-// Returns true after the step taken from a residual max|F| below 1e-10, false
-// when max|F| exceeds 1/2 at any step or four steps do not reach 1e-10: the
-// caller then inverts from scratch.
-constexpr int kNsMaxTiles = 10;  // Ne <= 160
-__device__ __forceinline__ bool newton_schulz(const Tab& T, const int* slot, double* Bg, double* F, double* red) {
-    const int ne = T.ne, n_so = T.n_so, tid = threadIdx.x, l = lane_id();
-    const int wv = (int)__builtin_amdgcn_readfirstlane((uint32_t)(tid >> 6)), nwv = blockDim.x >> 6;
-    const int m = l & 15, kq = l >> 4, nb = (ne + 15) >> 4;
-    typedef Mma<double> M;
-    for (int it = 0; it < 4; ++it) {
-        // F = I - B^T A  (F[x][y] = delta_xy - sum_p B[p][x] theta[slot p][y])
-        double lmax = 0.0;
-        for (int t = wv; t < nb * nb; t += nwv) {
-            const int xt = t / nb, yt = t - xt * nb;
-            const int x = xt * 16 + m, y = yt * 16 + m;
-            M::acc_t acc = {0, 0, 0, 0};
-#pragma unroll 4
-            for (int k0 = 0; k0 < ne; k0 += 4) {
-                const int p = k0 + kq;
-                const double av = (p < ne && x < ne) ? Bg[p * ne + x] : 0.0;
-                const double bv = (p < ne && y < ne) ? T.theta[(size_t)slot[p] * n_so + y] : 0.0;
-                acc = M::step(av, bv, acc);
-            }
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int xr = xt * 16 + M::row(kq, j);
-                if (xr < ne && y < ne) {
-                    const double f = (xr == y ? 1.0 : 0.0) - acc[j];
-                    F[xr * ne + y] = f;
-                    lmax = fmax(lmax, fabs(f));
-                }
-            }
-        }
-#pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) lmax = fmax(lmax, __shfl_xor(lmax, d, kWave));
-        if (l == 0) red[wv] = lmax;
-        __syncthreads();
-        double r = 0.0;
-        for (int q = 0; q < nwv; ++q) r = fmax(r, red[q]);
-        __syncthreads();
-        if (!(r <= 0.5)) return false;  // includes NaN
-        // B += B F^T  (B[q][x] += sum_y B[q][y] F[x][y]); a wave reads only its
-        // own row block of B, so it may write it once all its tiles are summed
-        for (int qt = wv; qt < nb; qt += nwv) {
-            M::acc_t acc[kNsMaxTiles];
-#pragma unroll
-            for (int xt = 0; xt < kNsMaxTiles; ++xt) acc[xt] = M::acc_t{0, 0, 0, 0};
-            const int q = qt * 16 + m;
-#pragma unroll 2
-            for (int k0 = 0; k0 < ne; k0 += 4) {
-                const int y = k0 + kq;
-                const double av = (q < ne && y < ne) ? Bg[q * ne + y] : 0.0;
-#pragma unroll
-                for (int xt = 0; xt < kNsMaxTiles; ++xt)
-                    if (xt < nb) {
-                        const int x = xt * 16 + m;
-                        const double bv = (x < ne && y < ne) ? F[x * ne + y] : 0.0;
-                        acc[xt] = M::step(av, bv, acc[xt]);
-                    }
-            }
-#pragma unroll
-            for (int xt = 0; xt < kNsMaxTiles; ++xt)
-                if (xt < nb)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int qr = qt * 16 + M::row(kq, j), xc = xt * 16 + m;
-                        if (qr < ne && xc < ne) Bg[qr * ne + xc] += acc[xt][j];
-                    }
-        }
-        __syncthreads();
-        // the step leaves I - B^T A = F^2 up to rounding: below Ne * 1e-20 here
-        if (r < 1e-10) return true;
-    }
-    return false;
-}
-
-// Periodic (and initial) re-inversion for walkers whose state lives in HBM.
-// NS (periodic refresh): Newton-Schulz from the carried B on the matrix
-// cores.  Otherwise, or when that does not converge: the same Gauss-Jordan
-// elimination with partial pivoting as the sweep kernel's in-LDS refresh, with
-// B held in LDS (up to 160 KB per workgroup).  Then R = theta B on the matrix
-// cores, s and H_NN.
+// Periodic (and initial) re-inversion for walkers whose state lives in HBM,
+// for Ne above 128: the same Gauss-Jordan elimination with partial pivoting
+// as the sweep kernel's in-LDS refresh, with B held in LDS (up to 160 KB per
+// workgroup), then R = theta B on the matrix cores, s and H_NN.
 constexpr int kRefreshThreads = 512;
-template <typename RT, bool NS>
+template <typename RT>
 __global__ void __launch_bounds__(kRefreshThreads) k_refresh(Tab T, Wk S, int64_t W) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int64_t w = blockIdx.x;
@@ -1593,24 +1566,8 @@ __global__ void __launch_bounds__(kRefreshThreads) k_refresh(Tab T, Wk S, int64_
     RT* R = (RT*)S.R + (size_t)w * n_so * ne;
     double* s = S.s + (size_t)w * n_so;
     double* Bg = S.B + (size_t)w * ne * ne;
-    bool done = false;
-    if (NS && ne <= 16 * kNsMaxTiles && !(mi[MI_ST] & (int)VMC_ST_SINGULAR)) done = newton_schulz(T, slot, Bg, B, red);
-    if (done) {
-        r_gemm<RT>(T, Bg, R, T.theta, n_so);
-        for (int pp = tid; pp < n_so; pp += nt) {
-            const double* Jr = T.J + (size_t)pp * n_so;
-            double acc = 0.0;
-            for (int k = 0; k < ne; ++k) {
-                const int q = slot[k];
-                if (q != pp) acc += Jr[q];
-            }
-            s[pp] = acc;
-        }
-        __syncthreads();
-    } else {
-        refresh_state(T, slot, B, R, s, fcol, ipiv, mi, red, T.theta, n_so);
-        for (int k = tid; k < ne * ne; k += nt) Bg[k] = B[k];
-    }
+    refresh_state(T, slot, B, R, s, fcol, ipiv, mi, red, T.theta, n_so);
+    for (int k = tid; k < ne * ne; k += nt) Bg[k] = B[k];
     double hp = 0.0;
     for (int x = tid; x < ne; x += nt) {
         const int i = slot[x];
@@ -1622,6 +1579,201 @@ __global__ void __launch_bounds__(kRefreshThreads) k_refresh(Tab T, Wk S, int64_
     if (tid == 0) {
         S.hnn[w] = hnn;
         S.status[w] = (uint32_t)mi[MI_ST];
+    }
+}
+
+// Re-inversion with the matrix held in registers: Gauss-Jordan elimination
+// with partial pivoting in exchange form (pivot rows are marked used, never
+// swapped), on G = A^T, A = theta[occ, 0:Ne] (G[r][c] = theta[slot c][r]).
+// Lane l holds rows l and l + 64, wave w the columns w, w + 8, ...: the owner
+// wave of column k keeps it in register 0 (it rotates its registers by one
+// after each column it owns), finds the pivot row p with a wave reduction,
+// and publishes the column and 1/pivot in LDS; after one block barrier every
+// wave reads the pivot row from its own lane p with readlane and updates its
+// registers.  Step k exchanges x_k with y_{p_k}; after Ne steps
+// M'[p_k][j] = G^-1[k][p_j].  The pivot row's own entry in the published
+// column is pivot + 1, which turns the common update into the exchanged pivot
+// row (v - (pv + 1) v / pv = -v / pv) with no per-lane case; G is scaled by a
+// power of two to max |G| in [1/2, 1) so that the pivots, and the rounding of
+// that form, stay of order one.
+__device__ __forceinline__ uint64_t pivot_key(double v, int r) {
+    const double a = fabs(v);
+    const uint64_t bits = (a >= 0.0) ? (uint64_t)__double_as_longlong(a) : 0x7FF0000000000000ull;
+    return (bits & ~127ull) | (uint64_t)(127 - r);
+}
+
+__device__ __forceinline__ double readlane_d(double x, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+    return __hiloint2double(hi, lo);
+}
+
+__host__ __device__ inline size_t refresh_gj_lds_bytes(int ne) {
+    const size_t mat = (size_t)ne * ne * 8, bufs = (2 * 128 + 4 + 2) * 8;
+    return al16(mat > bufs ? mat : bufs) + 3 * al16((size_t)ne * 4) + al16((size_t)(kRefreshThreads / 64 + 2) * 8) +
+           16;
+}
+
+template <typename RT, int H, int JC>
+__global__ void __launch_bounds__(kRefreshThreads) __attribute__((amdgpu_waves_per_eu(4))) k_refresh_gj(Tab T, Wk S,
+                                                                                                      int64_t W) {
+    constexpr int NW = kRefreshThreads / 64;
+    static_assert(H * 64 <= 128 && NW * JC <= 128, "at most 128 rows and columns");
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int64_t w = blockIdx.x;
+    if (w >= W) return;
+    const int tid = threadIdx.x, ne = T.ne, n_so = T.n_so, l = lane_id();
+    const int wv = (int)uni((uint32_t)(tid >> 6));
+    const size_t mat = (size_t)ne * ne * 8, bufs = (2 * 128 + 4 + 2) * 8;
+    size_t o = 0;
+    double* Bs = (double*)smem;     // B (slot layout) once the elimination is done
+    double* col = Bs;               // during it: the pivot column, two buffers
+    double* pvb = Bs + 2 * 128;     // pivot and its reciprocal, two buffers
+    int* pivb = (int*)(pvb + 4);    // pivot row, two buffers
+    o += al16(mat > bufs ? mat : bufs);
+    int* slot = (int*)(smem + o);
+    o += al16((size_t)ne * 4);
+    int* pk = (int*)(smem + o);  // pivot row of step k
+    o += al16((size_t)ne * 4);
+    int* qr = (int*)(smem + o);  // step at which row r was the pivot
+    o += al16((size_t)ne * 4);
+    double* red = (double*)(smem + o);
+    o += al16((size_t)(kRefreshThreads / 64 + 2) * 8);
+    int* flag = (int*)(smem + o);
+    for (int k = tid; k < ne; k += kRefreshThreads) slot[k] = S.slot_orb[(size_t)w * ne + k];
+    if (tid == 0) flag[0] = (int)S.status[w];
+    __syncthreads();
+    double g[H][JC];
+    double mx = 0.0;
+#pragma unroll
+    for (int j = 0; j < JC; ++j) {
+        const int c = wv + NW * j;
+        const double* tc = T.theta + (size_t)(c < ne ? slot[c] : 0) * n_so;
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            const int r = l + 64 * h;
+            g[h][j] = (r < ne && c < ne) ? tc[r] : 0.0;
+            mx = fmax(mx, fabs(g[h][j]));
+        }
+    }
+    // scale by 2^-e with max |G| = m 2^e, m in [1/2, 1) (exact)
+    mx = __longlong_as_double((long long)wave_max_u64((uint64_t)__double_as_longlong(mx)));
+    if (l == 0) red[wv] = mx;
+    __syncthreads();
+    for (int q = 0; q < NW; ++q) mx = fmax(mx, red[q]);
+    int ex = 0;
+    if (mx > 0.0 && mx < INFINITY) frexp(mx, &ex);
+    const double scale = ldexp(1.0, -ex);
+#pragma unroll
+    for (int h = 0; h < H; ++h)
+#pragma unroll
+        for (int j = 0; j < JC; ++j) g[h][j] *= scale;
+    uint64_t used0 = 0, used1 = 0;  // identical in every wave
+    bool singular = false;
+    int owned = 0;
+    for (int k = 0; k < ne; ++k) {
+        const int b = k & 1, ow = k % NW;
+        if (wv == ow) {
+            // pivot: the largest |G[r][k]| over unused rows as a u64 key (the
+            // bits of |G[r][k]|, whose order is that of the values, with the
+            // low 7 mantissa bits replaced by 127 - r: values within 2^-45 of
+            // each other tie and the lowest r wins; a NaN counts as the largest,
+            // so a poisoned matrix still pivots on an unused row)
+            uint64_t key = 0;
+            if (l < ne && !((used0 >> l) & 1)) key = pivot_key(g[0][0], l);
+            if (H > 1 && l + 64 < ne && !((used1 >> l) & 1)) key = umax64(key, pivot_key(g[H - 1][0], l + 64));
+            const int p = 127 - (int)(wave_max_u64(key) & 127u);
+            const double pv = (H > 1 && p >= 64) ? readlane_d(g[H - 1][0], p - 64) : readlane_d(g[0][0], p);
+            const double ipv = (pv != 0.0) ? 1.0 / pv : 0.0;
+            double* cw = col + b * 128;
+            cw[l] = (l == p) ? pv + 1.0 : g[0][0];
+            if (H > 1) cw[l + 64] = (l + 64 == p) ? pv + 1.0 : g[H - 1][0];
+            if (l == 0) {
+                pvb[2 * b] = pv;
+                pvb[2 * b + 1] = ipv;
+                pivb[b] = p;
+                pk[k] = p;
+                qr[p] = k;
+            }
+        }
+        __syncthreads();
+        const int piv = (int)uni((uint32_t)pivb[b]);
+        const double pv = pvb[2 * b], ipv = pvb[2 * b + 1];
+        if (piv < 64) used0 |= 1ull << piv;
+        else used1 |= 1ull << (piv - 64);
+        singular |= !(fabs(pv) > 0.0);
+        // every row: G[r][c] -= (G[r][k] / pv) G[p][c]; the pivot row reads
+        // pv + 1 for G[p][k] and so becomes -G[p][c] / pv
+        double t[H];
+#pragma unroll
+        for (int h = 0; h < H; ++h) t[h] = col[b * 128 + l + 64 * h] * ipv;
+        double v[JC];
+        const int pl = piv & 63;
+        if (H > 1 && piv >= 64) {
+#pragma unroll
+            for (int j = 0; j < JC; ++j) v[j] = readlane_d(g[H - 1][j], pl);
+        } else {
+#pragma unroll
+            for (int j = 0; j < JC; ++j) v[j] = readlane_d(g[0][j], pl);
+        }
+#pragma unroll
+        for (int h = 0; h < H; ++h)
+#pragma unroll
+            for (int j = 0; j < JC; ++j) g[h][j] = fma(-t[h], v[j], g[h][j]);
+        if (wv == ow) {  // column k becomes G[r][k] / pv, 1 / pv on the pivot row
+#pragma unroll
+            for (int h = 0; h < H; ++h) {
+                const double nk = (l + 64 * h == piv) ? ipv : t[h];
+#pragma unroll
+                for (int j = 0; j + 1 < JC; ++j) g[h][j] = g[h][j + 1];
+                g[h][JC - 1] = nk;
+            }
+            ++owned;
+        }
+    }
+    if (singular && tid == 0) flag[0] |= (int)VMC_ST_SINGULAR;
+    __syncthreads();
+    // B[p][x] = A^-1[x][p] = G^-1[p][x]: lane (r), register j (column c) holds
+    // G^-1[q_r][p_c]; the registers have been rotated by the number of
+    // columns this wave owned
+#pragma unroll
+    for (int j = 0; j < JC; ++j) {
+        const int c = wv + NW * ((j + owned) % JC);
+        if (c < ne) {
+            const int pc = pk[c];
+#pragma unroll
+            for (int h = 0; h < H; ++h) {
+                const int r = l + 64 * h;
+                if (r < ne) Bs[(size_t)qr[r] * ne + pc] = g[h][j] * scale;
+            }
+        }
+    }
+    __syncthreads();
+    double* Bg = S.B + (size_t)w * ne * ne;
+    for (int k = tid; k < ne * ne; k += kRefreshThreads) Bg[k] = Bs[k];
+    RT* R = (RT*)S.R + (size_t)w * n_so * ne;
+    r_gemm_theta_regs<RT, 16 * H>(T, Bs, R, T.theta, n_so);
+    double* sv = S.s + (size_t)w * n_so;
+    for (int pp = tid; pp < n_so; pp += kRefreshThreads) {
+        const double* Jr = T.J + (size_t)pp * n_so;
+        double acc = 0.0;
+        for (int k = 0; k < ne; ++k) {
+            const int q = slot[k];
+            if (q != pp) acc += Jr[q];
+        }
+        sv[pp] = acc;
+    }
+    double hp = 0.0;
+    for (int x = tid; x < ne; x += kRefreshThreads) {
+        const int i = slot[x];
+        const double* Di = T.D + (size_t)i * n_so;
+        hp += T.hdiag[i];
+        for (int y = x + 1; y < ne; ++y) hp += Di[slot[y]];
+    }
+    const double hnn = block_total(hp, red);
+    if (tid == 0) {
+        S.hnn[w] = hnn;
+        S.status[w] = (uint32_t)flag[0];
     }
 }
 
@@ -2035,17 +2187,33 @@ bool use_refresh_kernel(const vmc_ctx* h) {
     return !sweep_geom(h).small && refresh_lds_bytes(h->ne, kRefreshThreads) <= kMaxRefreshLds;
 }
 
-vmc_status launch_refresh(vmc_ctx* h, vmc_walkers* w, bool ns, hipStream_t st) {
+// Register Gauss-Jordan shape: 1 (Ne <= 64) or 2 (Ne <= 128) rows per lane,
+// 0 where Ne is larger (B in LDS instead).
+int refresh_gj_rows(int ne) { return ne <= 64 ? 1 : ne <= 128 ? 2 : 0; }
+
+vmc_status launch_refresh(vmc_ctx* h, vmc_walkers* w, hipStream_t st) {
     const size_t lds = refresh_lds_bytes(h->ne, kRefreshThreads);
     const Tab T = make_tab(h);
     const Wk S = make_wk(h, w);
     const dim3 grid((unsigned)w->n_walkers), block(kRefreshThreads);
+    const int rows = refresh_gj_rows(h->ne);
+    if (rows != 0) {
+        const bool mixed = h->precision == VMC_MIXED;
+        const size_t b = refresh_gj_lds_bytes(h->ne);
+        if (rows == 1) {
+            if (mixed) hipLaunchKernelGGL((k_refresh_gj<float, 1, 8>), grid, block, b, st, T, S, w->n_walkers);
+            else hipLaunchKernelGGL((k_refresh_gj<double, 1, 8>), grid, block, b, st, T, S, w->n_walkers);
+        } else {
+            if (mixed) hipLaunchKernelGGL((k_refresh_gj<float, 2, 16>), grid, block, b, st, T, S, w->n_walkers);
+            else hipLaunchKernelGGL((k_refresh_gj<double, 2, 16>), grid, block, b, st, T, S, w->n_walkers);
+        }
+        HIP_OR_FAIL(h, hipGetLastError());
+        return VMC_OK;
+    }
     if (h->precision == VMC_MIXED) {
-        if (ns) hipLaunchKernelGGL((k_refresh<float, true>), grid, block, lds, st, T, S, w->n_walkers);
-        else hipLaunchKernelGGL((k_refresh<float, false>), grid, block, lds, st, T, S, w->n_walkers);
+        hipLaunchKernelGGL((k_refresh<float>), grid, block, lds, st, T, S, w->n_walkers);
     } else {
-        if (ns) hipLaunchKernelGGL((k_refresh<double, true>), grid, block, lds, st, T, S, w->n_walkers);
-        else hipLaunchKernelGGL((k_refresh<double, false>), grid, block, lds, st, T, S, w->n_walkers);
+        hipLaunchKernelGGL((k_refresh<double>), grid, block, lds, st, T, S, w->n_walkers);
     }
     HIP_OR_FAIL(h, hipGetLastError());
     return VMC_OK;
@@ -2249,13 +2417,19 @@ vmc_status vmc_init(const vmc_system_desc* desc, const double* h1, const vmc_eri
     }
     if (refresh_lds_bytes(h->ne, kRefreshThreads) <= kMaxRefreshLds) {
         const int lds = (int)refresh_lds_bytes(h->ne, kRefreshThreads);
-        const void* fns[2] = {(h->precision == VMC_MIXED) ? (const void*)k_refresh<float, false>
-                                                          : (const void*)k_refresh<double, false>,
-                               (h->precision == VMC_MIXED) ? (const void*)k_refresh<float, true>
-                                                          : (const void*)k_refresh<double, true>};
-        hipError_t e = hipSuccess;
-        for (const void* f : fns)
-            if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        hipError_t e = hipFuncSetAttribute((h->precision == VMC_MIXED) ? (const void*)k_refresh<float>
+                                                                       : (const void*)k_refresh<double>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        const bool mixed = h->precision == VMC_MIXED;
+        const int gj = (int)refresh_gj_lds_bytes(h->ne);
+        if (e == hipSuccess && refresh_gj_rows(h->ne) == 1)
+            e = hipFuncSetAttribute(mixed ? (const void*)k_refresh_gj<float, 1, 8>
+                                          : (const void*)k_refresh_gj<double, 1, 8>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, gj);
+        if (e == hipSuccess && refresh_gj_rows(h->ne) == 2)
+            e = hipFuncSetAttribute(mixed ? (const void*)k_refresh_gj<float, 2, 16>
+                                          : (const void*)k_refresh_gj<double, 2, 16>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, gj);
         if (e != hipSuccess) {
             free_ctx(h);
             return fail(nullptr, VMC_E_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
@@ -2310,7 +2484,7 @@ vmc_status vmc_walkers_init(vmc_handle h, vmc_walkers* w, hipStream_t st) {
     if (s != VMC_OK) return s;
     if (use_refresh_kernel(h)) {
         s = launch_sweep(h, w, SweepArgs{MODE_INIT, 1, 0, w->step, nullptr, nullptr, nullptr, nullptr}, st);
-        return s != VMC_OK ? s : launch_refresh(h, w, false, st);
+        return s != VMC_OK ? s : launch_refresh(h, w, st);
     }
     return launch_sweep(h, w, SweepArgs{MODE_INIT, 1, h->refresh, w->step, nullptr, nullptr, nullptr, nullptr}, st);
 }
@@ -2319,11 +2493,9 @@ vmc_status vmc_walkers_refresh(vmc_handle h, vmc_walkers* w, hipStream_t st) {
     if (!h) return fail(nullptr, VMC_E_ARG, "handle is NULL");
     vmc_status s = check_walkers(h, w);
     if (s != VMC_OK) return s;
-    // HBM-resident walkers: Gauss-Jordan in the refresh kernel with the slots
-    // kept (a parameter step of optimiser size leaves the carried B a residual
-    // of 1e-3 or more, three Newton-Schulz steps, which cost more than one
-    // inversion); otherwise a fresh initialisation
-    if (use_refresh_kernel(h)) return launch_refresh(h, w, false, st);
+    // HBM-resident walkers: the refresh kernel, slots kept; otherwise a fresh
+    // initialisation
+    if (use_refresh_kernel(h)) return launch_refresh(h, w, st);
     return launch_sweep(h, w, SweepArgs{MODE_INIT, 1, h->refresh, w->step, nullptr, nullptr, nullptr, nullptr}, st);
 }
 
@@ -2360,7 +2532,7 @@ vmc_status vmc_ctmc_step(vmc_handle h, vmc_walkers* w, int32_t n_steps, double* 
                                          nullptr}, st);
         if (s != VMC_OK) return s;
         w->step += (uint64_t)seg;
-        if (seg == to_b && (s = launch_refresh(h, w, true, st)) != VMC_OK) return s;
+        if (seg == to_b && (s = launch_refresh(h, w, st)) != VMC_OK) return s;
         k += seg;
     }
     return VMC_OK;
@@ -2381,7 +2553,7 @@ vmc_status vmc_ctmc_step_dev(vmc_handle h, vmc_walkers* w, int32_t n_steps, uint
         for (int k = 0; k < n_steps && s == VMC_OK; k += h->refresh) {
             s = launch_sweep(h, w, SweepArgs{MODE_CTMC, h->refresh, 0, (uint64_t)k, nullptr, nullptr, nullptr, step_dev},
                              st);
-            if (s == VMC_OK) s = launch_refresh(h, w, true, st);
+            if (s == VMC_OK) s = launch_refresh(h, w, st);
         }
     }
     if (s != VMC_OK) return s;
