@@ -234,9 +234,8 @@ def main():
             vmc.vmc_walkers_refresh(sysm.handle, walkers, stream=stream)
             return est[2]
 
-        # burn-in of the walkers (not timed, not counted), ending on a refresh
-        # boundary so that each timed sweep is one segment plus one refresh
-        vmc.vmc_ctmc_step(sysm.handle, walkers, 100 + (-(walkers.step + 100)) % S, stream=stream)
+        # burn-in of the walkers (not timed, not counted)
+        vmc.vmc_ctmc_step(sysm.handle, walkers, 100, stream=stream)
         for _ in range(warmup):
             one_step(False)
         torch.cuda.synchronize()

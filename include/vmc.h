@@ -127,6 +127,9 @@ typedef struct {
     void* status;
     void* scratch;
     uint64_t step;          /* host-side global CTMC step counter, advanced by vmc_ctmc_step */
+    uint64_t since_inv;     /* moves since B and R were last inverted from scratch (state in HBM;
+                               set to 0 by vmc_walkers_init, vmc_walkers_refresh and every
+                               re-inversion) */
 } vmc_walkers;
 
 /*
@@ -171,10 +174,15 @@ vmc_status vmc_local_energy(vmc_handle h, vmc_walkers* w, hipStream_t stream);
  * walker i draws u from Philox4x64-10 with counter (w->step + k, 0, 0, 0) and
  * key (seed, i) (first output word, 53 high bits), picks the smallest
  * candidate index whose running rate sum exceeds u*T, and updates B, R, s and
- * the occupation; every refresh_period global steps B and R are recomputed
- * from scratch.  Optional device outputs (NULL to skip), each [n_steps][W]:
- * eloc_hist (E_L before the move), t_hist (residence time), pick_hist (packed
- * move).  Advances w->step by n_steps.
+ * the occupation.  B and R are recomputed from scratch at a fixed interval:
+ * when the walker state fits LDS, after every move whose global step g has
+ * (g + 1) % refresh_period == 0; when it lives in HBM, before a move once
+ * refresh_period moves have been made since the last inversion (counted in
+ * w->since_inv), so that a re-inversion due after the last move of a call is
+ * made by the next call, or not at all when vmc_walkers_refresh comes first.
+ * Optional device outputs (NULL to skip), each [n_steps][W]: eloc_hist (E_L
+ * before the move), t_hist (residence time), pick_hist (packed move).
+ * Advances w->step by n_steps.
  */
 vmc_status vmc_ctmc_step(vmc_handle h, vmc_walkers* w, int32_t n_steps, double* eloc_hist, double* t_hist,
                          int64_t* pick_hist, hipStream_t stream);
@@ -188,8 +196,9 @@ vmc_status vmc_ctmc_step(vmc_handle h, vmc_walkers* w, int32_t n_steps, double* 
  * w->step is not used or changed; no histories.  Refresh: as vmc_ctmc_step
  * when the walker state fits LDS (by the global step); for walkers whose state
  * lives in HBM, n_steps must be a multiple of refresh_period, and the separate
- * refresh kernel runs after every refresh_period moves of the call (aligned
- * with vmc_ctmc_step when *step_dev is a multiple of refresh_period).
+ * refresh kernel runs after every refresh_period moves of the call, whatever
+ * w->since_inv holds (a replayed graph repeats the same launches), then sets it
+ * to 0.
  * step_dev: device, 8 bytes, caller-owned.
  */
 vmc_status vmc_ctmc_step_dev(vmc_handle h, vmc_walkers* w, int32_t n_steps, uint64_t* step_dev, hipStream_t stream);

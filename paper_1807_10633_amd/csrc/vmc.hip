@@ -2482,6 +2482,7 @@ vmc_status vmc_walkers_init(vmc_handle h, vmc_walkers* w, hipStream_t st) {
     if (!h) return fail(nullptr, VMC_E_ARG, "handle is NULL");
     vmc_status s = check_walkers(h, w);
     if (s != VMC_OK) return s;
+    w->since_inv = 0;
     if (use_refresh_kernel(h)) {
         s = launch_sweep(h, w, SweepArgs{MODE_INIT, 1, 0, w->step, nullptr, nullptr, nullptr, nullptr}, st);
         return s != VMC_OK ? s : launch_refresh(h, w, st);
@@ -2495,6 +2496,7 @@ vmc_status vmc_walkers_refresh(vmc_handle h, vmc_walkers* w, hipStream_t st) {
     if (s != VMC_OK) return s;
     // HBM-resident walkers: the refresh kernel, slots kept; otherwise a fresh
     // initialisation
+    w->since_inv = 0;
     if (use_refresh_kernel(h)) return launch_refresh(h, w, st);
     return launch_sweep(h, w, SweepArgs{MODE_INIT, 1, h->refresh, w->step, nullptr, nullptr, nullptr, nullptr}, st);
 }
@@ -2518,21 +2520,24 @@ vmc_status vmc_ctmc_step(vmc_handle h, vmc_walkers* w, int32_t n_steps, double* 
         if (s == VMC_OK) w->step += (uint64_t)n_steps;
         return s;
     }
-    // segments that end at the refresh boundaries (after the move whose
-    // global step g has (g + 1) % refresh_period == 0), each followed by the
-    // refresh kernel
+    // segments of at most refresh_period moves since the last inversion; the
+    // refresh kernel runs before a move that would exceed that
     const int64_t W = w->n_walkers;
+    const uint64_t S = (uint64_t)h->refresh;
     int k = 0;
     while (k < n_steps) {
+        if (w->since_inv >= S) {
+            if ((s = launch_refresh(h, w, st)) != VMC_OK) return s;
+            w->since_inv = 0;
+        }
         const uint64_t g = w->step;
-        const int to_b = h->refresh - (int)(g % (uint64_t)h->refresh);
-        const int seg = std::min(n_steps - k, to_b);
+        const int seg = (int)std::min<uint64_t>((uint64_t)(n_steps - k), S - w->since_inv);
         s = launch_sweep(h, w, SweepArgs{MODE_CTMC, seg, 0, g, eh ? eh + (size_t)k * W : nullptr,
                                          th ? th + (size_t)k * W : nullptr, ph ? ph + (size_t)k * W : nullptr,
                                          nullptr}, st);
         if (s != VMC_OK) return s;
         w->step += (uint64_t)seg;
-        if (seg == to_b && (s = launch_refresh(h, w, st)) != VMC_OK) return s;
+        w->since_inv += (uint64_t)seg;
         k += seg;
     }
     return VMC_OK;
@@ -2555,6 +2560,7 @@ vmc_status vmc_ctmc_step_dev(vmc_handle h, vmc_walkers* w, int32_t n_steps, uint
                              st);
             if (s == VMC_OK) s = launch_refresh(h, w, st);
         }
+        w->since_inv = 0;
     }
     if (s != VMC_OK) return s;
     hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(64), 0, st, step_dev, (uint64_t)n_steps);

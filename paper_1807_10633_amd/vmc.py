@@ -47,7 +47,8 @@ class EriList(C.Structure):
 
 
 class WalkersStruct(C.Structure):
-    _fields_ = [("n_walkers", C.c_int64)] + [(f, C.c_void_p) for f in FIELDS] + [("step", C.c_uint64)]
+    _fields_ = ([("n_walkers", C.c_int64)] + [(f, C.c_void_p) for f in FIELDS] +
+                [("step", C.c_uint64), ("since_inv", C.c_uint64)])
 
 
 _lib = None
@@ -331,7 +332,7 @@ class Walkers:
         self.n_walkers = int(n_walkers)
         sizes = vmc_walker_bytes(handle, self.n_walkers)
         self.buffers = {f: torch.empty(max(sizes[f], 16), dtype=torch.uint8, device=device) for f in FIELDS}
-        self.cstruct = WalkersStruct(self.n_walkers, *[self.buffers[f].data_ptr() for f in FIELDS], 0)
+        self.cstruct = WalkersStruct(self.n_walkers, *[self.buffers[f].data_ptr() for f in FIELDS], 0, 0)
 
     @property
     def step(self) -> int:
@@ -340,6 +341,10 @@ class Walkers:
     @step.setter
     def step(self, v: int) -> None:
         self.cstruct.step = int(v)
+
+    @property
+    def since_inv(self) -> int:
+        return int(self.cstruct.since_inv)
 
     def view(self, field: str, dtype):
         return self.buffers[field].view(dtype)

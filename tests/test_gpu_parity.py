@@ -315,3 +315,41 @@ def test_walkers_refresh_after_new_parameters(torch, name, scale):
     for w in (0, 21, 42, 63):
         r = orc.local_energy(occ[w], ORC_LEMMA, with_candidates=False)
         assert abs(el[w] - r["eloc"]) <= EL_TOL * max(1.0, r["T"] / 100.0), (w, el[w], r["eloc"], r["T"])
+
+
+def test_refresh_schedule_counts_moves_since_inversion(torch):
+    """Walkers whose state lives in HBM are re-inverted before the move that
+    would exceed refresh_period moves since their last inversion: a call that
+    ends on the boundary leaves the re-inversion to the next call, and
+    vmc_walkers_refresh (new parameters) makes it unnecessary.  The state after
+    the moves matches a fresh inverse and the oracle either way."""
+    from paper_1807_10633_amd.vmc import vmc_ctmc_step, vmc_local_energy, vmc_walkers_refresh
+
+    wl = make_config("hchain40", n_walkers=64)
+    sysm = gpu_system(wl, refresh_period=7)
+    walkers = sysm.walkers(wl.occ)
+    assert walkers.since_inv == 0
+    vmc_ctmc_step(sysm.handle, walkers, 7)
+    assert walkers.since_inv == 7 and walkers.step == 7  # due, not yet made
+    vmc_ctmc_step(sysm.handle, walkers, 10)
+    assert walkers.since_inv == 3 and walkers.step == 17  # made before move 8, then 7 + 3 moves
+    vmc_walkers_refresh(sysm.handle, walkers)
+    assert walkers.since_inv == 0
+    vmc_ctmc_step(sysm.handle, walkers, 5)
+    assert walkers.since_inv == 5
+    vmc_local_energy(sysm.handle, walkers)
+    torch.cuda.synchronize()
+    ne, n_so = wl.n_elec, wl.n_so
+    slot = field(sysm, walkers, "slot_orb", torch.int32, ne)
+    B = field(sysm, walkers, "ainv", torch.float64, ne * ne)
+    worst = 0.0
+    for w in range(64):
+        Binv = np.linalg.inv(wl.theta[slot[w]][:, :ne])
+        worst = max(worst, np.max(np.abs(B[w].reshape(ne, ne).T - Binv)) / np.max(np.abs(Binv)))
+    assert worst < 1e-9
+    el = field(sysm, walkers, "eloc", torch.float64, 1)[:, 0]
+    occ = occ_of(sysm, walkers)
+    orc = OracleSystem.from_workload(wl)
+    for w in (0, 63):
+        r = orc.local_energy(occ[w], ORC_LEMMA, with_candidates=False)
+        assert abs(el[w] - r["eloc"]) <= EL_TOL * max(1.0, r["T"] / 100.0)
