@@ -24,7 +24,7 @@ struct Tab {
     const uint32_t* s_off;    // n_so + 1
     const uint32_t* sa;       // target orbital a
     const double* sh;         // h_ia
-    const double* sV;         // n_so per entry
+    const double* sV;         // n_so per entry; row of orbital i: V_e[j] at s_off[i] n_so + j len_i + e
     const double* sK;         // exp(J_aa - J_ii - J_ai) per singles entry
     const double* D;          // n_so*n_so
     const double* hdiag;      // n_so

@@ -111,12 +111,16 @@ std::string build_host_tables(int n, int na, int nb, const double* h1, int64_t n
             if (u.first != w.first) return u.first > w.first;
             return u.second < w.second;
         });
-        for (auto& e : order) {
-            T.sa.push_back(e.second);
-            T.sS.push_back(e.first);
-            T.sh.push_back(I.h(i, e.second));
-            const double* V = &Vrow[(size_t)e.second * nso];
-            T.sV.insert(T.sV.end(), V, V + nso);
+        // V of the row's entries, j-major: V_e[j] at (s_off[i] nso + j len + e)
+        const size_t len = order.size(), v0 = T.sV.size();
+        T.sV.resize(v0 + len * (size_t)nso);
+        for (size_t e = 0; e < len; ++e) {
+            const int a = order[e].second;
+            T.sa.push_back(a);
+            T.sS.push_back(order[e].first);
+            T.sh.push_back(I.h(i, a));
+            const double* V = &Vrow[(size_t)a * nso];
+            for (int j = 0; j < nso; ++j) T.sV[v0 + (size_t)j * len + e] = V[j];
         }
         T.s_off[i + 1] = (int64_t)T.sa.size();
     }

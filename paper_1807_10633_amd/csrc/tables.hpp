@@ -31,7 +31,7 @@ struct HostTables {
     std::vector<int32_t> sa;       // per singles entry
     std::vector<double> sS;        // S_ia per singles entry
     std::vector<double> sh;        // h_ia per singles entry
-    std::vector<double> sV;        // n_so per singles entry
+    std::vector<double> sV;        // n_so per singles entry, j-major within each orbital's row
     std::vector<double> D;         // n_so * n_so
     std::vector<double> hdiag;     // n_so
 };

@@ -153,9 +153,9 @@ __device__ __forceinline__ double single_ratio(const Tab& T, const Group& Gr, ui
     return (double)R[Gr.p * T.n_so + a] * es[a] * Gr.fac * T.sK[Gr.base + e];
 }
 __device__ __forceinline__ double single_h(const Tab& T, const Group& Gr, uint32_t e, const int* occl) {
-    const double* V = T.sV + (size_t)(Gr.base + e) * T.n_so;
+    const double* V = T.sV + (size_t)Gr.base * T.n_so + e;
     double h = T.sh[Gr.base + e];
-    for (int y = 0; y < T.ne; ++y) h += V[occl[y]];
+    for (int y = 0; y < T.ne; ++y) h += V[(size_t)occl[y] * Gr.len];
     return h;
 }
 template <typename RT>
@@ -652,10 +652,16 @@ __device__ __forceinline__ double cand_eval(const Tab& T, const StepView<RT>& V,
         const double r1 = (double)V.R[p * n_so + a];
         const double ratio = SCALED ? r1 * T.sK[off] : r1 * V.es[a] * V.sfac[g] * T.sK[off];
         if (WANT_H) {
-            const double* Vr = T.sV + (size_t)off * n_so;
             double h = T.sh[off];
-            if (T.has_sV)
-                for (int y = 0; y < T.ne; ++y) h += Vr[V.occl[y]];
+            if (T.has_sV) {
+                // the row of orbital i stores V[j] of its entries contiguously
+                // for each j, so the lanes of one group read together
+                const int i = V.occl[g];
+                const uint32_t b0 = T.s_off[i], len = T.s_off[i + 1] - b0;
+                const double* Vr = T.sV + (size_t)b0 * n_so + (off - b0);
+#pragma unroll 4
+                for (int y = 0; y < T.ne; ++y) h += Vr[(size_t)V.occl[y] * len];
+            }
             term = h * ratio;
         }
         cp = p; cq = -1; ca = a; cb = -1;
