@@ -36,15 +36,22 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per sweep launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of
-# `bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-check`, scaled by the
+# `bench.py [--config hubbard10x10 --walkers 16384] --steps 2 --warmup 1
+# --no-cpu-baseline --no-check --no-other-form --no-graph`, scaled by the
 # readings of a plain 1 GiB device copy (FETCH_SIZE reads 0.5 KiB per KiB
 # moved, WRITE_SIZE 1 KiB per KiB).  Keyed by the SHA-256 of the kernel sources
 # and the workload: any other kernel source or workload reports null.
-KERNEL_SOURCES = ("paper_1807_10633_amd/csrc/vmc.hip", "paper_1807_10633_amd/csrc/device.hpp")
+KERNEL_SOURCES = ("paper_1807_10633_amd/csrc/vmc.hip", "paper_1807_10633_amd/csrc/device.hpp",
+                  "paper_1807_10633_amd/csrc/tables.cpp")
 COUNTED_TRAFFIC = {
-    ("c76cb221f8dbf5a0759cb817d00e66ca95a7a482848dd68e1b1006b0ad1d6de3",
-     "6f0c5114f3b6a499710c41ef439984968e3cb925d4ff09f97ec429e9daca3055", "hchain20", 4096, 50, 256, "fp64"):
-        {"fetch_kib": 33779.7, "fetch_factor": 2.0, "write_kib": 41857.9, "write_factor": 1.0},
+    ("4855d77dc01baf0d63b2579a87bfa67d2fdc1af3d90cc26cc089f417175031a3",
+     "769edbfb386e269240a511822f4a97b0c1092caec56fbcb07664cf0d53b24099",
+     "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d", "hchain20", 4096, 50, 256, "fp64"):
+        {"fetch_kib": 52857.8, "fetch_factor": 2.0, "write_kib": 62353.4, "write_factor": 1.0},
+    ("4855d77dc01baf0d63b2579a87bfa67d2fdc1af3d90cc26cc089f417175031a3",
+     "769edbfb386e269240a511822f4a97b0c1092caec56fbcb07664cf0d53b24099",
+     "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d", "hubbard10x10", 16384, 50, 256, "fp64"):
+        {"fetch_kib": 112029297.5, "fetch_factor": 2.0, "write_kib": 191981727.6, "write_factor": 1.0},
 }
 
 
@@ -348,7 +355,8 @@ def main():
     traffic, traffic_split = counted_traffic(args.config, W, S, info["threads"], args.precision)
     common = {
         "kernel": ("k_sweep (persistent E_L + CTMC + Sherman-Morrison, walker state in LDS)" if info["state_in_lds"]
-                   else "k_sweep segments + k_refresh (walker state in HBM), one vmc_ctmc_step"),
+                   else "k_sweep (walker state in HBM), one vmc_ctmc_step; the re-inversion after each parameter "
+                        "update (k_refresh_gj) is outside the timed sweep but inside the step"),
         "traffic": traffic,
         "traffic_split": traffic_split,
         "hbm_gbs_measured": (traffic / sweep_s / 1e9) if traffic else None,
