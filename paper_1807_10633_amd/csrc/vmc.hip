@@ -623,13 +623,17 @@ struct StepView {
 
 // Ratio psi(M)/psi(N) (and, when WANT_H, the local-energy term H_NM * ratio)
 // of a queued candidate: table offset `off`, group g, targets in `ab` (a
-// 64-bit occupancy mask when MASK, else a | b << 16 / a).
+// 64-bit occupancy mask when MASK, else a | b << 16 / a in the low word).
+// Unscaled without MASK (group descriptors in HBM), the high word of `ab`
+// carries the group's slots p | q << 16 / p, so the R loads need no
+// descriptor load first.
 template <bool DOUBLES, bool WANT_H, bool MASK, bool SCALED, typename RT>
 __device__ __forceinline__ double cand_eval(const Tab& T, const StepView<RT>& V, uint32_t off, uint32_t g, uint64_t ab,
                                             double2 vk, double& term, int& cp, int& cq, int& ca, int& cb) {
+    constexpr bool QPQ = !SCALED && !MASK;
     const int n_so = T.n_so;
     if (DOUBLES) {
-        const uint32_t pq = V.dpq[g];
+        const uint32_t pq = QPQ ? (uint32_t)(ab >> 32) : V.dpq[g];
         const int p = (int)(pq & 0xFFFFu), q = (int)(pq >> 16);
         int a, b;
         if (MASK) {
@@ -647,8 +651,8 @@ __device__ __forceinline__ double cand_eval(const Tab& T, const StepView<RT>& V,
         cp = p; cq = q; ca = a; cb = b;
         return ratio;
     } else {
-        const int p = (int)V.spq[g];
-        const int a = (int)ab;
+        const int p = QPQ ? (int)(ab >> 32) : (int)V.spq[g];
+        const int a = (int)(uint32_t)ab;
         const double r1 = (double)V.R[p * n_so + a];
         const double ratio = SCALED ? r1 * T.sK[off] : r1 * V.es[a] * V.sfac[g] * T.sK[off];
         if (WANT_H) {
@@ -738,16 +742,20 @@ __device__ __forceinline__ bool stream_pass(const Tab& T, const StepView<RT>& V,
     // held one per lane, the chunk's group found by a ballot, so that empty
     // groups cost nothing and descriptor loads are coalesced.
     constexpr bool REG_CURSOR = !SCALED;
+    // queue entries carry the group's slots (see cand_eval)
+    constexpr bool QPQ = REG_CURSOR && !MASK;
+    const uint32_t* gpq = DOUBLES ? V.dpq : V.spq;
     // survivor queue: a ring of kQueue entries, head qh, qn entries queued
     uint32_t gc = uni(g0), qn = 0, qh = 0;
-    uint32_t e_end = 0, e_vend = 0, e_delta = 0;
-    uint32_t blk = 0, b_end = 0, b_vend = 0, b_delta = 0;
+    uint32_t e_end = 0, e_vend = 0, e_delta = 0, e_pq = 0;
+    uint32_t blk = 0, b_end = 0, b_vend = 0, b_delta = 0, b_pq = 0;
     auto load_block = [&]() __attribute__((always_inline)) {
         const uint32_t gg = blk + (uint32_t)l;
         const bool in = gg < ng;
         b_end = in ? gend[gg] : 0xFFFFFFFFu;
         b_vend = in ? vend[gg] : 0u;
         b_delta = in ? delta[gg] : 0u;
+        if (QPQ) b_pq = in ? gpq[gg] : 0u;
     };
     if (REG_CURSOR) {
         blk = gc & ~63u;
@@ -764,7 +772,7 @@ __device__ __forceinline__ bool stream_pass(const Tab& T, const StepView<RT>& V,
     uint64_t last_ab = 0;
 
     struct Stage {
-        uint32_t g[kUnroll], off[kUnroll];
+        uint32_t g[kUnroll], off[kUnroll], pq[kUnroll];
         bool ok[kUnroll];
         uint64_t ab[kUnroll];
     };
@@ -777,6 +785,7 @@ __device__ __forceinline__ bool stream_pass(const Tab& T, const StepView<RT>& V,
             st.ok[u] = false;
             st.g[u] = gc;
             st.off[u] = 0;
+            st.pq[u] = 0;
             if (cu < c1) {
                 if (REG_CURSOR) {
                     uint64_t m = __ballot(b_end > cu);
@@ -789,6 +798,7 @@ __device__ __forceinline__ bool stream_pass(const Tab& T, const StepView<RT>& V,
                     gc = blk + (uint32_t)gl;
                     e_vend = (uint32_t)__builtin_amdgcn_readlane((int)b_vend, gl);
                     e_delta = (uint32_t)__builtin_amdgcn_readlane((int)b_delta, gl);
+                    if (QPQ) e_pq = (uint32_t)__builtin_amdgcn_readlane((int)b_pq, gl);
                 } else {
                     while (e_end <= cu) {
                         ++gc;
@@ -798,6 +808,7 @@ __device__ __forceinline__ bool stream_pass(const Tab& T, const StepView<RT>& V,
                     }
                 }
                 st.g[u] = gc;
+                st.pq[u] = e_pq;
                 const uint32_t pos = cu + (uint32_t)l;
                 st.ok[u] = pos < e_vend && pos >= first;
                 st.off[u] = st.ok[u] ? pos + e_delta : 0u;  // entry 0 stands in for lanes without a candidate
@@ -864,7 +875,7 @@ __device__ __forceinline__ bool stream_pass(const Tab& T, const StepView<RT>& V,
             if (surv) {
                 const uint32_t sq = (qh + qn + mask_below(m)) & (kQueue - 1);
                 q64[sq] = (uint64_t)st.off[u] | ((uint64_t)st.g[u] << 32);
-                qab[sq] = st.ab[u];
+                qab[sq] = QPQ ? (st.ab[u] & 0xFFFFFFFFull) | ((uint64_t)st.pq[u] << 32) : st.ab[u];
             }
             qn += (uint32_t)__popcll(m);
             if (qn >= (uint32_t)kWave) {
