@@ -44,22 +44,50 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("paper_1807_10633_amd/csrc/vmc.hip", "paper_1807_10633_amd/csrc/device.hpp",
                   "paper_1807_10633_amd/csrc/tables.cpp")
 COUNTED_TRAFFIC = {
-    ("4855d77dc01baf0d63b2579a87bfa67d2fdc1af3d90cc26cc089f417175031a3",
+    ("a7245320acbf248cd7d2247533468aac5f61f229ccb098e88cc0d97d0c8f5552",
      "769edbfb386e269240a511822f4a97b0c1092caec56fbcb07664cf0d53b24099",
      "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d", "hchain20", 4096, 50, 256, "fp64"):
-        {"fetch_kib": 52857.8, "fetch_factor": 2.0, "write_kib": 62353.4, "write_factor": 1.0},
-    ("4855d77dc01baf0d63b2579a87bfa67d2fdc1af3d90cc26cc089f417175031a3",
+        {"fetch_kib": 47603.45, "fetch_factor": 2.0, "write_kib": 62362.35, "write_factor": 1.0},
+    ("a7245320acbf248cd7d2247533468aac5f61f229ccb098e88cc0d97d0c8f5552",
      "769edbfb386e269240a511822f4a97b0c1092caec56fbcb07664cf0d53b24099",
      "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d", "hubbard10x10", 16384, 50, 256, "fp64"):
-        {"fetch_kib": 112029297.5, "fetch_factor": 2.0, "write_kib": 191981727.6, "write_factor": 1.0},
+        {"fetch_kib": 111983063.35, "fetch_factor": 2.0, "write_kib": 191985196.85, "write_factor": 1.0},
 }
 
 
-def counted_traffic(config, walkers, sweep, threads, precision):
+# VALU wave-instructions per sweep launch (rocprofv3 --pmc SQ_INSTS_VALU ...
+# SQ_ACTIVE_INST_VALU GRBM_GUI_ACTIVE on the same bench command as the HBM
+# counters), keyed like COUNTED_TRAFFIC.  The issue peak is one wave64 VALU
+# instruction per SIMD every 4 cycles (16 lanes): 256 CUs x 4 SIMDs x 2.4 GHz / 4.
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
+COUNTED_ISSUE = {
+    ("a7245320acbf248cd7d2247533468aac5f61f229ccb098e88cc0d97d0c8f5552",
+     "769edbfb386e269240a511822f4a97b0c1092caec56fbcb07664cf0d53b24099",
+     "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d", "hchain20", 4096, 50, 256, "fp64"):
+        {"valu_insts": 4924712844.5, "salu_insts": 2743900085.0, "lds_insts": 548778024.5,
+         "vmem_rd_insts": 169411016.5, "valu_busy_pct": 63.75},
+}
+
+
+def _source_key():
     import hashlib
 
-    key = tuple(hashlib.sha256(open(os.path.join(ROOT, f), "rb").read()).hexdigest() for f in KERNEL_SOURCES)
-    rec = COUNTED_TRAFFIC.get(key + (config, walkers, sweep, threads, precision))
+    return tuple(hashlib.sha256(open(os.path.join(ROOT, f), "rb").read()).hexdigest() for f in KERNEL_SOURCES)
+
+
+def counted_issue(config, walkers, sweep, threads, precision, sweep_s):
+    rec = COUNTED_ISSUE.get(_source_key() + (config, walkers, sweep, threads, precision))
+    if rec is None:
+        return None
+    rate = rec["valu_insts"] / sweep_s
+    return {"valu_insts_per_launch": rec["valu_insts"], "salu_insts_per_launch": rec["salu_insts"],
+            "lds_insts_per_launch": rec["lds_insts"], "vmem_rd_insts_per_launch": rec["vmem_rd_insts"],
+            "valu_busy_pct": rec["valu_busy_pct"], "valu_issue_per_s": rate, "valu_issue_peak_per_s": VALU_ISSUE_PEAK,
+            "valu_issue_frac": rate / VALU_ISSUE_PEAK}
+
+
+def counted_traffic(config, walkers, sweep, threads, precision):
+    rec = COUNTED_TRAFFIC.get(_source_key() + (config, walkers, sweep, threads, precision))
     if rec is None:
         return None, None
     fetch = rec["fetch_kib"] * 1024 * rec["fetch_factor"]
@@ -364,6 +392,7 @@ def main():
         "K_singles": K_s,
         "K_doubles": K_d,
         "sweep_kernel_ms": sweep_ms,
+        "issue": counted_issue(args.config, W, S, info["threads"], args.precision, sweep_s),
         "launch": info,
     }
     if info["state_in_lds"]:
