@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 from oracle.core import ORC_DET, ORC_LEMMA, OracleSystem, uniform
-from workloads import hubbard_2d, hubbard_ring, init_theta, make_config
+from workloads import hubbard_2d, hubbard_ring, init_jastrow, init_theta, init_walkers, make_config
 
 from gpu_common import EL_TOL, field, gpu_system, occ_of, run_sweep, teacher_forced_check
 
@@ -353,3 +353,44 @@ def test_refresh_schedule_counts_moves_since_inversion(torch):
     for w in (0, 63):
         r = orc.local_energy(occ[w], ORC_LEMMA, with_candidates=False)
         assert abs(el[w] - r["eloc"]) <= EL_TOL * max(1.0, r["T"] / 100.0)
+
+
+def test_refresh_kernel_lds_path_above_128_electrons(torch):
+    """134 electrons (ring of 136 sites, 67+67): the state lives in HBM and the
+    re-inversion runs in the LDS form of the refresh kernel (B of 140 KB), above
+    the register form's 128 rows.  Across two re-inversions and two updates, B
+    inverts A to the rounding its condition allows and E_L matches the oracle."""
+    from paper_1807_10633_amd.vmc import System, vmc_launch_info, vmc_local_energy
+
+    L, na, nb, W = 136, 67, 67, 32
+    h1, ei, ev = hubbard_ring(L, 1.0, 4.0)
+    theta = init_theta(h1, na, nb, 0.01, 71)
+    jas = init_jastrow(2 * L, 0.05, 71)
+    sysm = System(L, na, nb, h1, ei, ev, 0.0, refresh_period=5, seed=73)
+    sysm.set_params(torch.as_tensor(jas, device="cuda"), torch.as_tensor(theta, device="cuda"))
+    info = vmc_launch_info(sysm.handle)
+    assert not info["state_in_lds"] and info["refresh_kernel"]
+    walkers = sysm.walkers(init_walkers(L, na, nb, W, 72))
+    run_sweep(sysm, walkers, 12)
+    assert walkers.since_inv == 2
+    vmc_local_energy(sysm.handle, walkers)
+    torch.cuda.synchronize()
+    ne, n_so = na + nb, 2 * L
+    slot = field(sysm, walkers, "slot_orb", torch.int32, ne)
+    B = field(sysm, walkers, "ainv", torch.float64, ne * ne)
+    st = field(sysm, walkers, "status", torch.int32, 1)[:, 0]
+    worst = 0.0
+    for w in range(W):
+        assert (st[w] & 1) == 0
+        A = theta[slot[w]][:, :ne]
+        res = np.max(np.abs(B[w].reshape(ne, ne).T @ A - np.eye(ne)))
+        worst = max(worst, res / (1e-12 * np.linalg.cond(A)))
+    _say(f"    max |B A - I| / (1e-12 cond A) = {worst:.3g}")
+    assert worst <= 1.0
+    el = field(sysm, walkers, "eloc", torch.float64, 1)[:, 0]
+    occ = occ_of(sysm, walkers)
+    orc = OracleSystem(L, na, nb, h1, ei, ev, 0.0)
+    orc.set_params(jas, theta)
+    for w in (0, 13, 31):
+        r = orc.local_energy(occ[w], ORC_LEMMA, with_candidates=False)
+        assert abs(el[w] - r["eloc"]) <= EL_TOL * max(1.0, r["T"] / 100.0), (w, el[w], r["eloc"], r["T"])
