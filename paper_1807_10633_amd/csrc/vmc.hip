@@ -170,18 +170,6 @@ __device__ __forceinline__ double double_ratio(const Tab& T, const Group& Gr, ui
     return (double)det * es[a] * es[b] * T.dvK[2 * (size_t)(Gr.base + e) + 1] * Gr.fac;
 }
 
-// Block-wide deterministic sum (every thread gets the same value).
-__device__ __forceinline__ double block_sum(double v, double* red) {
-    const int wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
-    v = wave_sum(v);
-    if (lane_id() == 0) red[wv] = v;
-    __syncthreads();
-    double t = 0.0;
-    for (int k = 0; k < nwv; ++k) t += red[k];
-    __syncthreads();
-    return t;
-}
-
 // --------------------------------------------------------------- LDS layout
 constexpr int kLogS = 32;   // batch-log entries per wave, singles stream
 constexpr int kLogD = 64;   // batch-log entries per wave, doubles stream
@@ -722,7 +710,7 @@ struct BatchLog {
 // The table loads of kUnroll chunks are issued together before they are consumed.
 template <bool DOUBLES, bool PICK, bool NW1, bool SCALED, typename RT>
 __device__ __forceinline__ bool stream_pass(const Tab& T, const StepView<RT>& V, uint64_t occ0, const uint64_t* occw, uint32_t c0,
-                            uint32_t c1, uint32_t g0, uint32_t ng, uint32_t first, uint64_t* q64, uint64_t* qab, double2* qvk,
+                            uint32_t c1, uint32_t g0, uint32_t ng, uint32_t first, uint64_t* q64, uint64_t* qab,
                             double& el, double* log_sum, uint32_t* log_off, uint32_t* log_grp, int log_cap, int& log_n,
                             double base, double target, bool fallback, int* pick) {
     BatchLog lg{log_sum, log_off, log_grp, log_cap, 0, kLogGran, 0, 0u, 0u, 0.0};
@@ -982,7 +970,6 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
     int* wst = (int*)(smem + L.wst);
     uint64_t* q64 = (uint64_t*)(smem + L.q64) + wv * kQueue;
     uint64_t* qab = (uint64_t*)(smem + L.qab) + wv * kQueue;
-    double2* qvk = nullptr;
     double* wtot = (double*)(smem + L.wtot);
     double* lsum = (double*)(smem + L.lsum);
     uint32_t* loff = (uint32_t*)(smem + L.loff);
@@ -1209,11 +1196,11 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
             const uint64_t occ0 = occw[0];
             if (r0s < r1s) {
                 const uint32_t g0 = find_group(sgend, (uint32_t)ne, r0s);
-                stream_pass<false, false, NW1, SMALL>(T, V, occ0, occw, r0s, r1s, g0, (uint32_t)ne, r0s, q64, qab, qvk, el_lane, lsum + lb, loff + lb, lg + lb, kLogS, ns, 0.0, 0.0, false, nullptr);
+                stream_pass<false, false, NW1, SMALL>(T, V, occ0, occw, r0s, r1s, g0, (uint32_t)ne, r0s, q64, qab, el_lane, lsum + lb, loff + lb, lg + lb, kLogS, ns, 0.0, 0.0, false, nullptr);
             }
             if (r0d < r1d) {
                 const uint32_t g0 = find_group(dgend, (uint32_t)gd, r0d);
-                stream_pass<true, false, NW1, SMALL>(T, V, occ0, occw, r0d, r1d, g0, (uint32_t)gd, r0d, q64, qab, qvk, el_lane, lsum + lb + kLogS, loff + lb + kLogS, lg + lb + kLogS, kLogD, nd, 0.0, 0.0, false, nullptr);
+                stream_pass<true, false, NW1, SMALL>(T, V, occ0, occw, r0d, r1d, g0, (uint32_t)gd, r0d, q64, qab, el_lane, lsum + lb + kLogS, loff + lb + kLogS, lg + lb + kLogS, kLogD, nd, 0.0, 0.0, false, nullptr);
             }
             // per-wave inclusive prefix sums of the two logs and their totals
             const double ts = log_prefix(lsum + lb, ns), td = log_prefix(lsum + lb + kLogS, nd);
@@ -1311,9 +1298,9 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
                 double dummy = 0.0;
                 int dn = 0;
                 if (fs == 0)
-                    stream_pass<false, true, NW1, SMALL>(T, V, occw[0], occw, c0, r1, g0, (uint32_t)ne, p0, q64, qab, qvk, dummy, nullptr, nullptr, nullptr, 0, dn, base, target, fb, mi + MI_PTYPE);
+                    stream_pass<false, true, NW1, SMALL>(T, V, occw[0], occw, c0, r1, g0, (uint32_t)ne, p0, q64, qab, dummy, nullptr, nullptr, nullptr, 0, dn, base, target, fb, mi + MI_PTYPE);
                 else
-                    stream_pass<true, true, NW1, SMALL>(T, V, occw[0], occw, c0, r1, g0, (uint32_t)gd, p0, q64, qab, qvk, dummy, nullptr, nullptr, nullptr, 0, dn, base, target, fb, mi + MI_PTYPE);
+                    stream_pass<true, true, NW1, SMALL>(T, V, occw[0], occw, c0, r1, g0, (uint32_t)gd, p0, q64, qab, dummy, nullptr, nullptr, nullptr, 0, dn, base, target, fb, mi + MI_PTYPE);
             }
             __syncthreads();
         }
