@@ -1,0 +1,130 @@
+"""The energy-minimisation loop: sample, estimate, backward, AMSGrad, repeat.
+
+Each iteration (section "AMSGrad algorithm for optimizing the energy") is
+  1. `moves` CTMC moves of every walker (vmc_ctmc_step);
+  2. E_L and t of the final states (vmc_local_energy) and the weighted energy
+     E = sum t E_L / sum t with the gradient weights g_w (vmc_estimate,
+     Eq. eq:vmc with residence-time weights);
+  3. the gradient G = sum_w g_w O_w (vmc_logderiv, Eq. eq:grad);
+  4. one AMSGrad step (vmc_amsgrad, Eqs. eq:m1, eq:m2) with the step size of
+     the schedule;
+  5. the new parameters into the tables (vmc_set_params) and the walkers'
+     inverses recomputed for them (vmc_walkers_refresh).
+
+Every step runs in the library's kernels; this module only sequences the calls
+on one stream and holds the device buffers.  The default schedule is the
+paper's for its larger chains (section "Performance of the optimizer"):
+alpha = 0.001 for the first 5 iterations, then 0.01.  beta1 = 0.9 and beta2 =
+0.99 in the standard convention are the paper's beta1 = 0.1, beta2 = 0.01;
+`paper_literal` selects the paper's own form of Eq. eq:m2.
+
+    python -m paper_1807_10633_amd.optimize --config hubbard8 --iters 40
+prints one JSON line per iteration.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+from typing import Callable, List, Optional
+
+import torch
+
+from . import vmc as _vmc
+
+
+def paper_schedule(i: int) -> float:
+    """Step size of iteration i (0-based): 0.001 for 5 iterations, then 0.01."""
+    return 0.001 if i < 5 else 0.01
+
+
+class Optimizer:
+    """Energy minimisation of one system's Jastrow and orbital parameters.
+
+    system: a vmc.System; walkers: its vmc.Walkers (initialised); J, theta:
+    device float64 tensors (packed Jastrow upper triangle, n_so x n_so theta),
+    copied into one parameter vector that the optimiser owns.
+    """
+
+    def __init__(self, system, walkers, J, theta, *, moves: int = 50,
+                 schedule: Callable[[int], float] = paper_schedule, beta1: float = 0.9, beta2: float = 0.99,
+                 delta: float = 1e-8, paper_literal: bool = False, stream=None):
+        if not J.is_cuda or not theta.is_cuda:
+            raise RuntimeError("the optimiser runs on the GPU only")
+        self.system, self.walkers = system, walkers
+        self.moves, self.schedule = int(moves), schedule
+        self.beta1, self.beta2, self.delta, self.paper_literal = beta1, beta2, delta, paper_literal
+        self.stream = stream
+        dev = J.device
+        self.nj = system.n_so * (system.n_so + 1) // 2
+        self.params = torch.cat([J.reshape(-1).to(torch.float64), theta.reshape(-1).to(torch.float64)]).contiguous()
+        assert self.params.numel() == system.n_params
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.vhat = torch.zeros_like(self.params)
+        self.G = torch.zeros_like(self.params)
+        self.est = torch.zeros(4, dtype=torch.float64, device=dev)
+        self.g = torch.zeros(walkers.n_walkers, dtype=torch.float64, device=dev)
+        self.iteration = 0
+        self._apply()
+
+    @property
+    def J(self):
+        return self.params[: self.nj]
+
+    @property
+    def theta(self):
+        return self.params[self.nj:].view(self.system.n_so, self.system.n_so)
+
+    def _apply(self) -> None:
+        h, st = self.system.handle, self.stream
+        _vmc.vmc_set_params(h, self.params[: self.nj], self.params[self.nj:], stream=st)
+        _vmc.vmc_walkers_refresh(h, self.walkers, stream=st)
+
+    def step(self) -> torch.Tensor:
+        """One iteration; returns the device scalar E of the sampled states
+        (estimated before the parameter update)."""
+        h, st, w = self.system.handle, self.stream, self.walkers
+        _vmc.vmc_ctmc_step(h, w, self.moves, stream=st)
+        _vmc.vmc_local_energy(h, w, stream=st)
+        _vmc.vmc_estimate(h, w, self.est, self.g, stream=st)
+        _vmc.vmc_logderiv(h, w, self.g, self.G, stream=st)
+        _vmc.vmc_amsgrad(self.params, self.m, self.v, self.vhat, self.G, self.schedule(self.iteration), self.beta1,
+                         self.beta2, self.delta, self.paper_literal, stream=st)
+        self._apply()
+        self.iteration += 1
+        return self.est[2].clone()
+
+    def run(self, n_iter: int) -> List[float]:
+        return [float(self.step().item()) for _ in range(n_iter)]
+
+
+def _main(argv: Optional[List[str]] = None) -> int:
+    from workloads import make_config
+
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--config", default="hubbard8")
+    ap.add_argument("--walkers", type=int, default=0, help="0: the configuration's walker count")
+    ap.add_argument("--iters", type=int, default=40)
+    ap.add_argument("--moves", type=int, default=50)
+    ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
+    ap.add_argument("--paper-literal", action="store_true")
+    args = ap.parse_args(argv)
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "needs a GPU"}))
+        return 2
+    wl = make_config(args.config, n_walkers=args.walkers or None)
+    prec = _vmc.VMC_MIXED if args.precision == "mixed" else _vmc.VMC_FP64
+    system = _vmc.System.from_workload(wl, precision=prec, refresh_period=args.moves)
+    walkers = system.walkers(wl.occ)
+    opt = Optimizer(system, walkers, torch.as_tensor(wl.jastrow, device="cuda"),
+                    torch.as_tensor(wl.theta, device="cuda"), moves=args.moves, paper_literal=args.paper_literal)
+    for i in range(args.iters):
+        E = float(opt.step().item())
+        print(json.dumps({"iteration": i, "alpha": paper_schedule(i), "energy": E,
+                          "energy_per_electron": E / wl.n_elec}), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(_main())

@@ -1,0 +1,108 @@
+"""The energy-minimisation loop (paper_1807_10633_amd.optimize) on the GPU.
+
+* Each iteration's algebra against the oracle, on the states the GPU sampled:
+  E (Eq. eq:vmc with residence-time weights), G = 2<O (E_L - E)> (Eq. eq:grad),
+  and the AMSGrad step with the paper's schedule (alpha 0.001 for 5 iterations,
+  then 0.01; section "Performance of the optimizer"), in the standard and in
+  the paper-literal form of Eq. eq:m2.  Over 7 iterations the parameters, the
+  tables and the walkers' inverses are carried by the library alone.
+* The loop lowers the exact variational energy of the 8-site ring: <psi|H|psi>
+  from the brute-force Hamiltonian goes from -1.16 to -4.31 in 40 iterations
+  (ground state -4.60), and never below the ground state.
+"""
+import numpy as np
+import pytest
+
+from oracle.brute import BruteSystem
+from oracle.core import ORC_LEMMA, OracleSystem
+from oracle.optim import AMSGrad, gradient, weighted_energy
+from workloads import eri_dense_spatial, make_config
+
+from gpu_common import field, gpu_system, occ_of
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return torch
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("paper_literal", [False, True])
+def test_iterations_match_oracle_algebra(torch, paper_literal):
+    from paper_1807_10633_amd.optimize import Optimizer, paper_schedule
+
+    wl = make_config("hubbard8", n_walkers=64)
+    sysm = gpu_system(wl, refresh_period=20)
+    walkers = sysm.walkers(wl.occ)
+    opt = Optimizer(sysm, walkers, torch.as_tensor(wl.jastrow, device="cuda"), torch.as_tensor(wl.theta, device="cuda"),
+                    moves=20, paper_literal=paper_literal)
+    orc = OracleSystem(wl.n_orb, wl.n_alpha, wl.n_beta, wl.h1, wl.eri_idx, wl.eri_val, wl.eps)
+    nj = opt.nj
+    ref = AMSGrad(sysm.n_params, lr=0.0, beta1=0.9, beta2=0.99, delta=1e-8, paper_literal=paper_literal)
+    p = opt.params.cpu().numpy().copy()
+    for it in range(7):
+        E_gpu = float(opt.step().item())
+        torch.cuda.synchronize()
+        occ = occ_of(sysm, walkers)
+        G_gpu = opt.G.cpu().numpy()
+        p_gpu = opt.params.cpu().numpy()
+        # the oracle on the same states, at the parameters of this iteration
+        orc.set_params(p[:nj], p[nj:].reshape(sysm.n_so, sysm.n_so))
+        el, t, O = [], [], []
+        for w in range(64):
+            r = orc.local_energy(occ[w], ORC_LEMMA, with_candidates=False)
+            el.append(r["eloc"])
+            t.append(1.0 / r["T"])
+            O.append(orc.logderiv(occ[w]))
+        el, t, O = np.array(el), np.array(t), np.array(O)
+        E_ref = weighted_energy(el, t)
+        G_ref = gradient(O, el, t)
+        assert abs(E_gpu - E_ref) <= 1e-10 * max(1.0, abs(E_ref)), (it, E_gpu, E_ref)
+        np.testing.assert_allclose(G_gpu, G_ref, rtol=1e-9, atol=1e-12 * np.max(np.abs(G_ref)))
+        # AMSGrad with the schedule's step size, fed the GPU's gradient
+        ref.lr = paper_schedule(it)
+        p_ref = ref.step(p, G_gpu)
+        np.testing.assert_allclose(p_gpu, p_ref, rtol=0, atol=1e-15)
+        p = p_gpu.copy()
+        _say(f"    iteration {it}: alpha {paper_schedule(it)}, E {E_gpu:.6f}, |G| {np.linalg.norm(G_gpu):.3e}")
+    # the walkers' state follows the parameters: E_L of the final states at the
+    # last parameters against the oracle
+    from paper_1807_10633_amd.vmc import vmc_local_energy
+
+    vmc_local_energy(sysm.handle, walkers)
+    torch.cuda.synchronize()
+    orc.set_params(p[:nj], p[nj:].reshape(sysm.n_so, sysm.n_so))
+    el = field(sysm, walkers, "eloc", torch.float64, 1)[:, 0]
+    occ = occ_of(sysm, walkers)
+    for w in (0, 31, 63):
+        r = orc.local_energy(occ[w], ORC_LEMMA, with_candidates=False)
+        assert abs(el[w] - r["eloc"]) <= 1e-10 * max(1.0, r["T"] / 100.0)
+
+
+def test_loop_lowers_exact_energy_of_the_ring(torch):
+    from paper_1807_10633_amd.optimize import Optimizer
+
+    wl = make_config("hubbard8", n_walkers=1024)
+    br = BruteSystem(wl.n_orb, wl.n_alpha, wl.n_beta, wl.h1, eri_dense_spatial(wl.n_orb, wl.eri_idx, wl.eri_val))
+    e0 = br.ground_energy()
+    e_start = br.energy(br.psi(wl.theta, wl.jastrow))
+    sysm = gpu_system(wl)
+    walkers = sysm.walkers(wl.occ)
+    opt = Optimizer(sysm, walkers, torch.as_tensor(wl.jastrow, device="cuda"), torch.as_tensor(wl.theta, device="cuda"),
+                    moves=50)
+    sampled = opt.run(40)
+    p = opt.params.cpu().numpy()
+    e_end = br.energy(br.psi(p[opt.nj:].reshape(sysm.n_so, sysm.n_so), p[: opt.nj]))
+    _say(f"    exact E0 {e0:.6f}; <H> start {e_start:.6f}, after 40 iterations {e_end:.6f}; "
+         f"sampled E first {np.mean(sampled[:3]):.4f}, last {np.mean(sampled[-5:]):.4f}")
+    assert e_end >= e0 - 1e-9
+    # 40 iterations recover most of the gap to the ground state (91 % here)
+    assert e_end < e_start - 0.8 * (e_start - e0)
