@@ -106,6 +106,7 @@ def parse():
                     help="hchain20 (default), hubbard8, hubbard10x10, hchain40, hchain80, hchain160, or batch "
                          "(40/80/160 orbitals in one launch)")
     ap.add_argument("--threads", type=int, default=0, help="workgroup size of the sweep kernel (0 = autotuned)")
+    ap.add_argument("--eps", type=float, default=None, help="screening threshold (default: the workload's own)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the E_L check against the oracle")
@@ -227,7 +228,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    wl = make_config(args.config, n_walkers=args.walkers)
+    wl = make_config(args.config, n_walkers=args.walkers, eps=args.eps)
     W, S = args.walkers, args.sweep
     head_prec = vmc.VMC_MIXED if args.precision == "mixed" else vmc.VMC_FP64
 
@@ -380,7 +381,9 @@ def main():
     state_bytes = 2.0 * (n_so * ne * rbytes + ne * ne * 8)
     sweep_s = sweep_ms * 1e-3
     achieved_tflops = flops * W * S / sweep_s / 1e12
-    traffic, traffic_split = counted_traffic(args.config, W, S, info["threads"], args.precision)
+    # counted figures belong to the workload as defined, not to another screening threshold
+    ckey = args.config if args.eps is None else f"{args.config}:eps={args.eps:g}"
+    traffic, traffic_split = counted_traffic(ckey, W, S, info["threads"], args.precision)
     common = {
         "kernel": ("k_sweep (persistent E_L + CTMC + Sherman-Morrison, walker state in LDS)" if info["state_in_lds"]
                    else "k_sweep (walker state in HBM), one vmc_ctmc_step; the re-inversion after each parameter "
@@ -392,7 +395,7 @@ def main():
         "K_singles": K_s,
         "K_doubles": K_d,
         "sweep_kernel_ms": sweep_ms,
-        "issue": counted_issue(args.config, W, S, info["threads"], args.precision, sweep_s),
+        "issue": counted_issue(ckey, W, S, info["threads"], args.precision, sweep_s),
         "launch": info,
     }
     if info["state_in_lds"]:
@@ -437,8 +440,8 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"{args.config}: H-chain-like 20 orbitals, 10a+10b, eps=1e-6" if args.config ==
-                   "hchain20" else args.config, "walkers": W, "ctmc_moves_per_step": S, "refresh_period": S,
-                   "precision": args.precision},
+                   "hchain20" and args.eps is None else args.config, "walkers": W, "ctmc_moves_per_step": S,
+                   "refresh_period": S, "precision": args.precision, "eps": wl.eps},
         "eloc_evals_per_s_in_sweep": W * S / (sweep_ms * 1e-3),
         "graph_replay_value": head["graph_value"],
         "el_max_abs_err_vs_oracle": el_err,
