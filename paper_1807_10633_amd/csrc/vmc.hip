@@ -174,7 +174,7 @@ __device__ __forceinline__ double double_ratio(const Tab& T, const Group& Gr, ui
 constexpr int kLogS = 32;   // batch-log entries per wave, singles stream
 constexpr int kLogD = 64;   // batch-log entries per wave, doubles stream
 constexpr int kLogGran = 2; // initial batches per log entry
-constexpr int kUnroll = 4;  // 64-entry chunks whose table loads are issued together
+constexpr int kUnroll = 6;  // 64-entry chunks whose table loads are issued together
 
 struct Lds {
     uint32_t occw, occl, slot, oslot, s, es, ies, red, stmp, mi, md, wst, wtot, q64, qab, lsum, loff, lg, sgend, sdelta,
