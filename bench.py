@@ -52,6 +52,10 @@ COUNTED_TRAFFIC = {
      "769edbfb386e269240a511822f4a97b0c1092caec56fbcb07664cf0d53b24099",
      "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d", "hubbard10x10", 16384, 50, 256, "fp64"):
         {"fetch_kib": 112305924.5, "fetch_factor": 2.0, "write_kib": 191992792.1, "write_factor": 1.0},
+    ("d2f3b00006ec2972cf79c13416a8f985d2124ea86227051d8e3c364bb40cae36",
+     "769edbfb386e269240a511822f4a97b0c1092caec56fbcb07664cf0d53b24099",
+     "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d", "hubbard10x10", 16384, 50, 256, "mixed"):
+        {"fetch_kib": 80082749.65, "fetch_factor": 2.0, "write_kib": 128005414.15, "write_factor": 1.0},
 }
 
 
