@@ -22,7 +22,7 @@ Conventions shared by every consumer of these inputs
 
 The Hubbard and H-chain-like models stand in for the paper's benchmark systems
 (2-D Hubbard lattices and sto-6g hydrogen chains), whose integrals cannot be
-produced here; see the design doc for the recipe of each configuration.
+produced here; `make_config` documents the recipe of each configuration.
 """
 from .generators import (  # noqa: F401
     Workload,
