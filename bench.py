@@ -211,7 +211,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only: walkers are independent and a multi-GPU run "
+        print(json.dumps({"error": "the library runs on one GPU: walkers are independent and a multi-GPU run "
                                    "would shard them with one gradient all-reduce per iteration, which is not "
                                    "implemented here; run with --gpus 1"}), flush=True)
         sys.exit(2)

@@ -62,7 +62,7 @@ typedef enum {
     VMC_E_HIP = -3,         /* a HIP runtime call failed */
     VMC_E_SINGULAR = -4,    /* reserved */
     VMC_E_STATE = -5,       /* reserved */
-    VMC_E_UNSUPPORTED = -6  /* size or mode outside what this build supports */
+    VMC_E_UNSUPPORTED = -6  /* size or mode outside what the library supports */
 } vmc_status;
 
 enum { VMC_FP64 = 0, VMC_MIXED = 1 };
