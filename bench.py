@@ -44,18 +44,18 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("paper_1807_10633_amd/csrc/vmc.hip", "paper_1807_10633_amd/csrc/device.hpp",
                   "paper_1807_10633_amd/csrc/tables.cpp")
 COUNTED_TRAFFIC = {
-    ("d2f3b00006ec2972cf79c13416a8f985d2124ea86227051d8e3c364bb40cae36",
+    ("2dd0bbf23395396a50ce6507379f252bebba5d30cf02c27cd7f1a16012edf940",
      "769edbfb386e269240a511822f4a97b0c1092caec56fbcb07664cf0d53b24099",
      "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d", "hchain20", 4096, 50, 256, "fp64"):
-        {"fetch_kib": 57819.15, "fetch_factor": 2.0, "write_kib": 62358.6, "write_factor": 1.0},
-    ("d2f3b00006ec2972cf79c13416a8f985d2124ea86227051d8e3c364bb40cae36",
+        {"fetch_kib": 58840.8, "fetch_factor": 2.0, "write_kib": 62363.25, "write_factor": 1.0},
+    ("2dd0bbf23395396a50ce6507379f252bebba5d30cf02c27cd7f1a16012edf940",
      "769edbfb386e269240a511822f4a97b0c1092caec56fbcb07664cf0d53b24099",
      "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d", "hubbard10x10", 16384, 50, 256, "fp64"):
-        {"fetch_kib": 112305924.5, "fetch_factor": 2.0, "write_kib": 191992792.1, "write_factor": 1.0},
-    ("d2f3b00006ec2972cf79c13416a8f985d2124ea86227051d8e3c364bb40cae36",
+        {"fetch_kib": 112214545.8, "fetch_factor": 2.0, "write_kib": 191987012.75, "write_factor": 1.0},
+    ("2dd0bbf23395396a50ce6507379f252bebba5d30cf02c27cd7f1a16012edf940",
      "769edbfb386e269240a511822f4a97b0c1092caec56fbcb07664cf0d53b24099",
      "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d", "hubbard10x10", 16384, 50, 256, "mixed"):
-        {"fetch_kib": 80082749.65, "fetch_factor": 2.0, "write_kib": 128005414.15, "write_factor": 1.0},
+        {"fetch_kib": 80064124.8, "fetch_factor": 2.0, "write_kib": 128007679.25, "write_factor": 1.0},
 }
 
 
@@ -65,11 +65,11 @@ COUNTED_TRAFFIC = {
 # instruction per SIMD every 4 cycles (16 lanes): 256 CUs x 4 SIMDs x 2.4 GHz / 4.
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 COUNTED_ISSUE = {
-    ("d2f3b00006ec2972cf79c13416a8f985d2124ea86227051d8e3c364bb40cae36",
+    ("2dd0bbf23395396a50ce6507379f252bebba5d30cf02c27cd7f1a16012edf940",
      "769edbfb386e269240a511822f4a97b0c1092caec56fbcb07664cf0d53b24099",
      "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d", "hchain20", 4096, 50, 256, "fp64"):
         {"valu_insts": 4890615390.0, "salu_insts": 2665121788.0, "lds_insts": 548790633.5,
-         "vmem_rd_insts": 168605103.5, "valu_busy_pct": 64.95},
+         "vmem_rd_insts": 168605103.5, "valu_busy_pct": 64.45},
 }
 
 

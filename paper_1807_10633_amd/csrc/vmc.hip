@@ -1921,6 +1921,7 @@ __global__ void k_grad_J(Tab T, Wk S, int64_t W, const double* g, double* part, 
     const int64_t start = (int64_t)p * n_so - (int64_t)p * (p - 1) / 2;
     for (int q = p + threadIdx.x; q < n_so; q += blockDim.x) {
         double acc = 0.0;
+#pragma unroll 4
         for (int64_t w = w0; w < w1; ++w) {
             const uint64_t* occ = S.occ + (size_t)w * nw;
             if (((occ[p >> 6] >> (p & 63)) & 1ull) && ((occ[q >> 6] >> (q & 63)) & 1ull)) acc += g[w];
@@ -1938,6 +1939,7 @@ __global__ void k_grad_theta(Tab T, Wk S, int64_t W, const double* g, double* pa
     for (int x = threadIdx.x; x < n_so; x += blockDim.x) {
         double acc = 0.0;
         if (x < ne)
+#pragma unroll 4
             for (int64_t w = w0; w < w1; ++w) {
                 const int sl = S.orb_slot[(size_t)w * n_so + k];
                 if (sl >= 0) acc += g[w] * S.B[(size_t)w * ne * ne + (size_t)sl * ne + x];
@@ -2612,7 +2614,9 @@ vmc_status vmc_logderiv(vmc_handle h, const vmc_walkers* w, const double* g, dou
         HIP_OR_FAIL(h, hipGetLastError());
         return VMC_OK;
     }
-    const int nsplit = 16;
+    // walker ranges of about 128 walkers (16 to 128 of them), enough blocks to
+    // keep the serial loads of each range overlapped across the chip
+    const int nsplit = (int)std::min<int64_t>(128, std::max<int64_t>(16, w->n_walkers / 128));
     if (h->part_cap < n_p * nsplit) {
         if (h->d_part) (void)hipFree(h->d_part);
         h->d_part = nullptr;
