@@ -111,6 +111,8 @@ def parse():
                          "(40/80/160 orbitals in one launch)")
     ap.add_argument("--threads", type=int, default=0, help="workgroup size of the sweep kernel (0 = autotuned)")
     ap.add_argument("--eps", type=float, default=None, help="screening threshold (default: the workload's own)")
+    ap.add_argument("--orbitals", choices=("ghf", "uhf"), default="ghf",
+                    help="general or spin-blocked (unrestricted) orbitals of the same workload")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the E_L check against the oracle")
@@ -232,7 +234,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    wl = make_config(args.config, n_walkers=args.walkers, eps=args.eps)
+    wl = make_config(args.config, n_walkers=args.walkers, eps=args.eps, orbitals=args.orbitals)
+    uhf = args.orbitals == "uhf"
     W, S = args.walkers, args.sweep
     head_prec = vmc.VMC_MIXED if args.precision == "mixed" else vmc.VMC_FP64
 
@@ -376,17 +379,28 @@ def main():
     # (1.5 = mean electrons moved: the single/double pick mix is not tracked,
     # the midpoint is used); Jastrow sums 3 n_so; refresh amortised over the
     # sweep: GJ 2 Ne^3 + R 2 n_so Ne^2.
-    flops = (10.0 * K_d + (ne + 7.0) * K_s + ne * (ne - 1) / 2 + ne + 2 * 1.5 * (n_so * ne + ne * ne) + 3 * n_so
+    # Spin-blocked orbitals: the update touches one spin's blocks, R n x N_s
+    # and B N_s x N_s (N_s = N_e / 2 on average).
+    upd = (sysm.n_orb * ne / 2 + ne * ne / 4) if uhf else (n_so * ne + ne * ne)
+    flops = (10.0 * K_d + (ne + 7.0) * K_s + ne * (ne - 1) / 2 + ne + 2 * 1.5 * upd + 3 * n_so
              + (2.0 * ne ** 3 + 2.0 * n_so * ne * ne) / S)
     info = vmc.vmc_launch_info(sysm.handle)
     rbytes = 4 if args.precision == "mixed" else 8
     # HBM bytes per walker-step when the state stays in HBM: R and B read and
-    # written once per move
-    state_bytes = 2.0 * (n_so * ne * rbytes + ne * ne * 8)
+    # written once per move.  Spin-blocked: the moving spin's blocks, averaged
+    # over the two spins (exact for single moves and same-spin doubles; an
+    # opposite-spin double touches both spins' blocks)
+    if uhf:
+        na, nb, n = sysm.n_alpha, sysm.n_beta, sysm.n_orb
+        state_bytes = (n * na * rbytes + na * na * 8) + (n * nb * rbytes + nb * nb * 8)
+    else:
+        state_bytes = 2.0 * (n_so * ne * rbytes + ne * ne * 8)
     sweep_s = sweep_ms * 1e-3
     achieved_tflops = flops * W * S / sweep_s / 1e12
     # counted figures belong to the workload as defined, not to another screening threshold
     ckey = args.config if args.eps is None else f"{args.config}:eps={args.eps:g}"
+    if uhf:
+        ckey += ":uhf"
     traffic, traffic_split = counted_traffic(ckey, W, S, info["threads"], args.precision)
     common = {
         "kernel": ("k_sweep (persistent E_L + CTMC + Sherman-Morrison, walker state in LDS)" if info["state_in_lds"]
@@ -445,7 +459,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.config}: H-chain-like 20 orbitals, 10a+10b, eps=1e-6" if args.config ==
                    "hchain20" and args.eps is None else args.config, "walkers": W, "ctmc_moves_per_step": S,
-                   "refresh_period": S, "precision": args.precision, "eps": wl.eps},
+                   "refresh_period": S, "precision": args.precision, "eps": wl.eps, "orbitals": args.orbitals},
         "eloc_evals_per_s_in_sweep": W * S / (sweep_ms * 1e-3),
         "graph_replay_value": head["graph_value"],
         "el_max_abs_err_vs_oracle": el_err,

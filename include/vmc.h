@@ -67,6 +67,9 @@ typedef enum {
 
 enum { VMC_FP64 = 0, VMC_MIXED = 1 };
 
+/* Form of the determinant's orbitals (vmc_system_desc.orbitals). */
+enum { VMC_GHF = 0, VMC_UHF = 1 };
+
 /* per-walker status bits (device field `status`) */
 enum {
     VMC_ST_SINGULAR = 1u,   /* theta[N] singular at (re)inversion: psi(N) = 0 */
@@ -85,7 +88,18 @@ typedef struct {
                                re-inversion, the update denominators (recomputed as theta[a,:] B in FP64),
                                E_L, T and all accumulations stay FP64 */
     int32_t refresh_period; /* re-invert theta[N] from scratch every this many CTMC steps (>= 1) */
-    int32_t reserved;       /* must be 0 */
+    int32_t orbitals;       /* VMC_GHF: general orbitals, every entry of theta[:, 0:Ne] is used.
+                               VMC_UHF: spin-blocked (unrestricted) orbitals, the determinant form of the
+                               sections "Performance of the optimizer" and "2-D Hubbard Model Benchmark":
+                               theta[a][x] enters only where orbital a and occupied column x have the same
+                               spin (columns [0, n_alpha) alpha, [n_alpha, Ne) beta); vmc_set_params sets
+                               the other entries of its copy to zero.  The determinant then factors into
+                               an alpha and a beta determinant, slot p < n_alpha holds an alpha electron,
+                               B is block diagonal, R keeps each slot's own spin only ([W][Ne][n]), and a
+                               move updates the blocks of the spin it moves.  Needs Ne <= 128 and
+                               spin-conserving integrals (VMC_E_ARG otherwise); the walker state lives in
+                               HBM; no batches.  Walkers with a wrong alpha count are flagged
+                               VMC_ST_SINGULAR at initialisation. */
     uint64_t seed;          /* Philox key word 0 for CTMC draws */
 } vmc_system_desc;
 
@@ -101,7 +115,8 @@ enum {
     VMC_F_SLOT_ORB,  /* int32  [W][Ne]     orbital held by each slot */
     VMC_F_ORB_SLOT,  /* int32  [W][n_so]   slot of each orbital, -1 when empty */
     VMC_F_AINV,      /* double [W][Ne][Ne] B = theta[N]^-1, column by slot */
-    VMC_F_R,         /* double (VMC_FP64) or float (VMC_MIXED) [W][Ne][n_so] R, column by slot */
+    VMC_F_R,         /* double (VMC_FP64) or float (VMC_MIXED) [W][Ne][n_so] R, column by slot;
+                        VMC_UHF: [W][Ne][n], slot p's own spin only (orbital a at a - n for beta) */
     VMC_F_JSUM,      /* double [W][n_so]   s_p = sum_{q != p} J_pq n_q */
     VMC_F_HNN,       /* double [W]         H_NN */
     VMC_F_ELOC,      /* double [W]         last local energy */

@@ -14,6 +14,9 @@ constexpr int kQueue = 128;  // per-wave survivor queue (<= 63 left over + 64 ne
 // ------------------------------------------------------------------ views
 struct Tab {
     int n_so, ne, nw, G;
+    int n, na;                // spatial orbitals, alpha electrons
+    int uhf;                  // spin-blocked orbitals: slots [0, na) alpha, [na, ne) beta
+    int rrow;                 // length of one slot's row of R: n_so, or n when uhf (own spin only)
     int has_doubles;          // the table holds at least one doubles entry
     int has_sV;               // some singles entry has a nonzero Coulomb-exchange vector
     double eps;

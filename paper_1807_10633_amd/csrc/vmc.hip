@@ -145,12 +145,41 @@ __device__ __forceinline__ Group group_of(const Tab& T, int g, const int* occl, 
     return G;
 }
 
+// Position of R[a][p] in a walker's R: row p (one per slot) holds every
+// orbital, or with spin-blocked orbitals only the n orbitals of the slot's own
+// spin (slots [0, na) alpha, [na, Ne) beta; a must have that spin).
+__device__ __forceinline__ int r_index_uhf(const Tab& T, int p, int a) {
+    return p * T.n + a - ((p >= T.na) ? T.n : 0);
+}
+__device__ __forceinline__ int r_index(const Tab& T, int p, int a) {
+    return T.uhf ? r_index_uhf(T, p, a) : p * T.n_so + a;
+}
+// 2x2 minor R[a][p] R[b][q] - R[b][p] R[a][q] of a double (section "Local
+// energy and Gradient ratios", Eq. eq:R).  Spin-blocked orbitals: a pair of
+// the same spin is the full minor within that spin's rows; a pair of opposite
+// spins (i alpha, j beta, hence a alpha, b beta) has no cross term, so the
+// ratio is the product of the two spins' single ratios.
+template <typename RT>
+__device__ __forceinline__ RT pair_minor_uhf(const Tab& T, const RT* R, int p, int q, int a, int b) {
+    const int op = (p >= T.na) ? T.n : 0, oq = (q >= T.na) ? T.n : 0;
+    const int rp = p * T.n - op, rq = q * T.n - oq;
+    if (op != oq) return R[rp + a] * R[rq + b];
+    return R[rp + a] * R[rq + b] - R[rp + b] * R[rq + a];
+}
+template <typename RT>
+__device__ __forceinline__ RT pair_minor(const Tab& T, const RT* R, int p, int q, int a, int b) {
+    if (T.uhf) return pair_minor_uhf(T, R, p, q, a, b);
+    const RT* Rp = R + p * T.n_so;
+    const RT* Rq = R + q * T.n_so;
+    return Rp[a] * Rq[b] - Rp[b] * Rq[a];
+}
+
 // Ratio and matrix element of candidate e of group Gr (slot convention).
 template <typename RT>
 __device__ __forceinline__ double single_ratio(const Tab& T, const Group& Gr, uint32_t e, const RT* R,
                                                const double* es, int& a) {
     a = (int)T.sa[Gr.base + e];
-    return (double)R[Gr.p * T.n_so + a] * es[a] * Gr.fac * T.sK[Gr.base + e];
+    return (double)R[r_index(T, Gr.p, a)] * es[a] * Gr.fac * T.sK[Gr.base + e];
 }
 __device__ __forceinline__ double single_h(const Tab& T, const Group& Gr, uint32_t e, const int* occl) {
     const double* V = T.sV + (size_t)Gr.base * T.n_so + e;
@@ -164,9 +193,7 @@ __device__ __forceinline__ double double_ratio(const Tab& T, const Group& Gr, ui
     const uint32_t ab = T.dab[Gr.base + e];
     a = (int)(ab & 0xFFFFu);
     b = (int)(ab >> 16);
-    const RT* Rp = R + Gr.p * T.n_so;
-    const RT* Rq = R + Gr.q * T.n_so;
-    const RT det = Rp[a] * Rq[b] - Rp[b] * Rq[a];
+    const RT det = pair_minor(T, R, Gr.p, Gr.q, a, b);
     return (double)det * es[a] * es[b] * T.dvK[2 * (size_t)(Gr.base + e) + 1] * Gr.fac;
 }
 
@@ -307,7 +334,7 @@ __device__ __forceinline__ void r_gemm(const Tab& T, const double* B, RT* R, con
 // The same product with each wave holding a 16-orbital tile of theta in
 // registers (KS k-steps, Ne <= 4 KS) across all slot tiles, so that theta is
 // read once per walker instead of once per output tile; B in LDS.
-template <typename RT, int KS>
+template <typename RT, int KS, bool UHF>
 __device__ __forceinline__ void r_gemm_theta_regs(const Tab& T, const double* B, RT* R, const double* th, int ths) {
     const int ne = T.ne, n_so = T.n_so, l = lane_id();
     const int wv = (int)__builtin_amdgcn_readfirstlane((uint32_t)(threadIdx.x >> 6)), nwv = blockDim.x >> 6;
@@ -334,7 +361,11 @@ __device__ __forceinline__ void r_gemm_theta_regs(const Tab& T, const double* B,
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int pr = pt * 16 + Mma<RT>::row(kq, j);
-                if (pr < ne && a < n_so) R[pr * n_so + a] = acc[j];
+                if (pr < ne && a < n_so) {
+                    // spin-blocked orbitals: only the slot's own spin is kept
+                    if (!UHF) R[pr * n_so + a] = acc[j];
+                    else if ((a >= T.n) == (pr >= T.na)) R[r_index_uhf(T, pr, a)] = acc[j];
+                }
             }
         }
     }
@@ -385,6 +416,38 @@ __device__ __forceinline__ void rank_update(E* M, int rows, int cols, const doub
             double d = c1[c] * r1[r];
             if (TWO) d += c2[c] * r2[r];
             M[idx] = (E)((double)M[idx] - d);
+        }
+    }
+}
+
+// The same on a sub-block whose rows lie ld elements apart (one spin's block
+// of B with spin-blocked orbitals).
+template <bool TWO>
+__device__ __forceinline__ void rank_update_ld(double* M, int rows, int cols, int ld, const double* c1,
+                                               const double* r1, const double* c2, const double* r2) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    if ((cols & 1) == 0 && (ld & 1) == 0 && (((uintptr_t)M) & 15) == 0) {
+        const int cv = cols >> 1, nv = rows * cv;
+        for (int vi = tid; vi < nv; vi += nt) {
+            const int r = vi / cv, c = (vi - r * cv) * 2;
+            double2* q = (double2*)(M + (size_t)r * ld + c);
+            double2 v = *q;
+            const double a1 = r1[r], a2 = TWO ? r2[r] : 0.0;
+            double d0 = c1[c] * a1, d1 = c1[c + 1] * a1;
+            if (TWO) {
+                d0 += c2[c] * a2;
+                d1 += c2[c + 1] * a2;
+            }
+            v.x -= d0;
+            v.y -= d1;
+            *q = v;
+        }
+    } else {
+        for (int idx = tid; idx < rows * cols; idx += nt) {
+            const int r = idx / cols, c = idx - r * cols;
+            double d = c1[c] * r1[r];
+            if (TWO) d += c2[c] * r2[r];
+            M[(size_t)r * ld + c] -= d;
         }
     }
 }
@@ -615,7 +678,7 @@ struct StepView {
 // Unscaled without MASK (group descriptors in HBM), the high word of `ab`
 // carries the group's slots p | q << 16 / p, so the R loads need no
 // descriptor load first.
-template <bool DOUBLES, bool WANT_H, bool MASK, bool SCALED, typename RT>
+template <bool DOUBLES, bool WANT_H, bool MASK, bool SCALED, bool UHF, typename RT>
 __device__ __forceinline__ double cand_eval(const Tab& T, const StepView<RT>& V, uint32_t off, uint32_t g, uint64_t ab,
                                             double2 vk, double& term, int& cp, int& cq, int& ca, int& cb) {
     constexpr bool QPQ = !SCALED && !MASK;
@@ -631,9 +694,14 @@ __device__ __forceinline__ double cand_eval(const Tab& T, const StepView<RT>& V,
             a = (int)(ab & 0xFFFFu);
             b = (int)((ab >> 16) & 0xFFFFu);
         }
-        const RT* Rp = V.R + p * n_so;
-        const RT* Rq = V.R + q * n_so;
-        const double det = (double)(Rp[a] * Rq[b] - Rp[b] * Rq[a]);
+        double det;
+        if (UHF) {
+            det = (double)pair_minor_uhf(T, V.R, p, q, a, b);
+        } else {
+            const RT* Rp = V.R + p * n_so;
+            const RT* Rq = V.R + q * n_so;
+            det = (double)(Rp[a] * Rq[b] - Rp[b] * Rq[a]);
+        }
         const double ratio = SCALED ? det * vk.y : det * V.es[a] * V.es[b] * vk.y * V.dfac[g];
         if (WANT_H) term = vk.x * ratio;
         cp = p; cq = q; ca = a; cb = b;
@@ -641,7 +709,7 @@ __device__ __forceinline__ double cand_eval(const Tab& T, const StepView<RT>& V,
     } else {
         const int p = QPQ ? (int)(ab >> 32) : (int)V.spq[g];
         const int a = (int)(uint32_t)ab;
-        const double r1 = (double)V.R[p * n_so + a];
+        const double r1 = (double)V.R[UHF ? r_index_uhf(T, p, a) : p * n_so + a];
         const double ratio = SCALED ? r1 * T.sK[off] : r1 * V.es[a] * V.sfac[g] * T.sK[off];
         if (WANT_H) {
             double h = T.sh[off];
@@ -708,7 +776,7 @@ struct BatchLog {
 // the last positive-rate candidate); pick = {type, p, q, a, b}; returns true
 // if found.
 // The table loads of kUnroll chunks are issued together before they are consumed.
-template <bool DOUBLES, bool PICK, bool NW1, bool SCALED, typename RT>
+template <bool DOUBLES, bool PICK, bool NW1, bool SCALED, bool UHF, typename RT>
 __device__ __forceinline__ bool stream_pass(const Tab& T, const StepView<RT>& V, uint64_t occ0, const uint64_t* occw, uint32_t c0,
                             uint32_t c1, uint32_t g0, uint32_t ng, uint32_t first, uint64_t* q64, uint64_t* qab,
                             double& el, double* log_sum, uint32_t* log_off, uint32_t* log_grp, int log_cap, int& log_n,
@@ -820,7 +888,7 @@ __device__ __forceinline__ bool stream_pass(const Tab& T, const StepView<RT>& V,
         if (DOUBLES && act) vk = *(const double2*)(T.dvK + 2 * (size_t)off);
         double term = 0.0, r = 0.0;
         int cp = 0, cq = 0, ca = 0, cb = 0;
-        if (act) r = fabs(cand_eval<DOUBLES, !PICK, MASK, SCALED>(T, V, off, g, ab, vk, term, cp, cq, ca, cb));
+        if (act) r = fabs(cand_eval<DOUBLES, !PICK, MASK, SCALED, UHF>(T, V, off, g, ab, vk, term, cp, cq, ca, cb));
         if (!PICK) {
             el += term;
             log->add_batch(r, uni((uint32_t)og), uni((uint32_t)(og >> 32)));
@@ -890,7 +958,7 @@ __device__ __forceinline__ bool stream_pass(const Tab& T, const StepView<RT>& V,
             double term;
             int cp, cq, ca, cb;
             const double2 vk = DOUBLES ? *(const double2*)(T.dvK + 2 * (size_t)last_off) : make_double2(0.0, 0.0);
-            cand_eval<DOUBLES, false, MASK, SCALED>(T, V, last_off, last_g, last_ab, vk, term, cp, cq, ca, cb);
+            cand_eval<DOUBLES, false, MASK, SCALED, UHF>(T, V, last_off, last_g, last_ab, vk, term, cp, cq, ca, cb);
             pick[0] = DOUBLES ? 2 : 1; pick[1] = cp; pick[2] = cq; pick[3] = ca; pick[4] = cb;
         }
         found = true;
@@ -935,10 +1003,11 @@ constexpr int sweep_waves_target(int nso_t, bool small) {
 // update denominators and every accumulation stay FP64).
 // sweep_body runs walker w of the walker set S (W walkers) on the calling
 // workgroup.
-template <int NSO_T, int NE_T, int NT_T, bool NW1, bool SMALL, typename RT>
+template <int NSO_T, int NE_T, int NT_T, bool NW1, bool SMALL, typename RT, bool UHF = false>
 __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t W, int64_t w, int mode, int n_steps,
                                            uint64_t step0, uint64_t seed, int refresh_period, double* eloc_hist,
                                            double* t_hist, int64_t* pick_hist) {
+    static_assert(!(UHF && SMALL), "spin-blocked orbitals keep the walker state in HBM");
     extern __shared__ __align__(16) unsigned char smem[];
     Tab T = Targ;
     if (NSO_T) {
@@ -1006,7 +1075,7 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
         dpq = (uint32_t*)(smem + L.dpq);
         dfac = nullptr;
     } else {
-        R = (RT*)S.R + (size_t)w * n_so * ne;
+        R = (RT*)S.R + (size_t)w * T.rrow * ne;
         B = S.B + (size_t)w * ne * ne;
         Rh = R;
         uint8_t* sc = S.scratch + (size_t)w * S.scratch_stride;
@@ -1032,12 +1101,23 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
         // bits beyond n_so are ignored; a wrong electron count marks the walker
         if (tid == 0) {
             if ((n_so & 63) != 0) occw[nw - 1] &= (1ull << (n_so & 63)) - 1ull;
-            int pop = 0;
-            for (int k = 0; k < nw; ++k) pop += __popcll(occw[k]);
-            if (pop != ne) {
+            int pop = 0, popa = 0;
+            for (int k = 0; k < nw; ++k) {
+                pop += __popcll(occw[k]);
+                // alpha electrons: orbitals below n
+                const int lo = 64 * k;
+                if (lo < T.n) popa += __popcll(occw[k] & ((T.n - lo >= 64) ? ~0ull : ((1ull << (T.n - lo)) - 1ull)));
+            }
+            // spin-blocked orbitals also need na alpha electrons (slots [0, na)
+            // alpha); a flagged walker is parked on a valid determinant
+            const bool uhf = UHF;
+            if (pop != ne || (uhf && popa != T.na)) {
                 mi[MI_ST] = (int)VMC_ST_SINGULAR;
                 for (int k = 0; k < nw; ++k) occw[k] = 0ull;
-                for (int k = 0; k < ne; ++k) occw[k >> 6] |= 1ull << (k & 63);
+                for (int k = 0; k < ne; ++k) {
+                    const int o = (uhf && k >= T.na) ? T.n + k - T.na : k;
+                    occw[o >> 6] |= 1ull << (o & 63);
+                }
             }
         }
         __syncthreads();
@@ -1051,7 +1131,8 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
         }
         __syncthreads();
         // refresh_period 0: the caller runs the separate refresh kernel next
-        if (refresh_period > 0) refresh_state(T, slot, B, R, s, fcol, ipiv, mi, red, th, ths);
+        // (always, with spin-blocked orbitals)
+        if (refresh_period > 0 && !UHF) refresh_state(T, slot, B, R, s, fcol, ipiv, mi, red, th, ths);
     } else {
         for (int k = tid; k < ne; k += nt) slot[k] = S.slot_orb[(size_t)w * ne + k];
         for (int pp = tid; pp < n_so; pp += nt) {
@@ -1196,11 +1277,11 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
             const uint64_t occ0 = occw[0];
             if (r0s < r1s) {
                 const uint32_t g0 = find_group(sgend, (uint32_t)ne, r0s);
-                stream_pass<false, false, NW1, SMALL>(T, V, occ0, occw, r0s, r1s, g0, (uint32_t)ne, r0s, q64, qab, el_lane, lsum + lb, loff + lb, lg + lb, kLogS, ns, 0.0, 0.0, false, nullptr);
+                stream_pass<false, false, NW1, SMALL, UHF>(T, V, occ0, occw, r0s, r1s, g0, (uint32_t)ne, r0s, q64, qab, el_lane, lsum + lb, loff + lb, lg + lb, kLogS, ns, 0.0, 0.0, false, nullptr);
             }
             if (r0d < r1d) {
                 const uint32_t g0 = find_group(dgend, (uint32_t)gd, r0d);
-                stream_pass<true, false, NW1, SMALL>(T, V, occ0, occw, r0d, r1d, g0, (uint32_t)gd, r0d, q64, qab, el_lane, lsum + lb + kLogS, loff + lb + kLogS, lg + lb + kLogS, kLogD, nd, 0.0, 0.0, false, nullptr);
+                stream_pass<true, false, NW1, SMALL, UHF>(T, V, occ0, occw, r0d, r1d, g0, (uint32_t)gd, r0d, q64, qab, el_lane, lsum + lb + kLogS, loff + lb + kLogS, lg + lb + kLogS, kLogD, nd, 0.0, 0.0, false, nullptr);
             }
             // per-wave inclusive prefix sums of the two logs and their totals
             const double ts = log_prefix(lsum + lb, ns), td = log_prefix(lsum + lb + kLogS, nd);
@@ -1298,9 +1379,9 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
                 double dummy = 0.0;
                 int dn = 0;
                 if (fs == 0)
-                    stream_pass<false, true, NW1, SMALL>(T, V, occw[0], occw, c0, r1, g0, (uint32_t)ne, p0, q64, qab, dummy, nullptr, nullptr, nullptr, 0, dn, base, target, fb, mi + MI_PTYPE);
+                    stream_pass<false, true, NW1, SMALL, UHF>(T, V, occw[0], occw, c0, r1, g0, (uint32_t)ne, p0, q64, qab, dummy, nullptr, nullptr, nullptr, 0, dn, base, target, fb, mi + MI_PTYPE);
                 else
-                    stream_pass<true, true, NW1, SMALL>(T, V, occw[0], occw, c0, r1, g0, (uint32_t)gd, p0, q64, qab, dummy, nullptr, nullptr, nullptr, 0, dn, base, target, fb, mi + MI_PTYPE);
+                    stream_pass<true, true, NW1, SMALL, UHF>(T, V, occw[0], occw, c0, r1, g0, (uint32_t)gd, p0, q64, qab, dummy, nullptr, nullptr, nullptr, 0, dn, base, target, fb, mi + MI_PTYPE);
             }
             __syncthreads();
         }
@@ -1326,6 +1407,11 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
                         const double* thb = th + (size_t)b * ths;
                         for (int c = 0; c < ne; ++c) rb += thb[c] * Bx[c];
                     }
+                } else if (UHF) {
+                    // spin-blocked: a slot of the other spin holds zero
+                    const bool xb = x >= T.na;
+                    ra = (xb == (a >= T.n)) ? (double)R[r_index_uhf(T, x, a)] : 0.0;
+                    if (ptype == 2) rb = (xb == (b >= T.n)) ? (double)R[r_index_uhf(T, x, b)] : 0.0;
                 } else {
                     ra = (double)R[x * n_so + a];
                     if (ptype == 2) rb = (double)R[x * n_so + b];
@@ -1335,10 +1421,12 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
             }
             // old columns p (and q) of R over the orbitals (not needed in the
             // small mixed form, where R is re-formed after the move)
-            const RT* Rp = R + p * n_so;
-            const RT* Rq = R + q * n_so;
+            // (spin-blocked: the slot's row over its own spin's n orbitals)
+            const int rrow = UHF ? T.n : n_so;
+            const RT* Rp = R + p * rrow;
+            const RT* Rq = R + q * rrow;
             if (!(MIXED && SMALL))
-                for (int a2 = tid; a2 < n_so; a2 += nt) {
+                for (int a2 = tid; a2 < rrow; a2 += nt) {
                     cRp[a2] = (double)Rp[a2];
                     if (ptype == 2) cRq[a2] = (double)Rq[a2];
                 }
@@ -1385,8 +1473,15 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
                 for (int x = tid; x < ne; x += nt) w1[x] = (w1[x] - (x == p ? 1.0 : 0.0)) / rho;
                 __syncthreads();
                 // R[x][a'] -= R[a'][p] w_x;  B[x'][x] -= B[x][p] w_x'  (B column by slot)
-                if (!(MIXED && SMALL)) rank_update<RT, false>(R, ne, n_so, cRp, w1, nullptr, nullptr);
-                rank_update<double, false>(B, ne, ne, cBp, w1, nullptr, nullptr);
+                if (UHF) {
+                    // one spin's block of R (its slots' rows) and of B
+                    const int lo = (p >= T.na) ? T.na : 0, cnt = (p >= T.na) ? ne - T.na : T.na;
+                    rank_update<RT, false>(R + (size_t)lo * T.n, cnt, T.n, cRp, w1 + lo, nullptr, nullptr);
+                    rank_update_ld<false>(B + (size_t)lo * ne + lo, cnt, cnt, ne, cBp + lo, w1 + lo, nullptr, nullptr);
+                } else {
+                    if (!(MIXED && SMALL)) rank_update<RT, false>(R, ne, n_so, cRp, w1, nullptr, nullptr);
+                    rank_update<double, false>(B, ne, ne, cBp, w1, nullptr, nullptr);
+                }
                 if (tid == 0) md[MD_HNN] += dh + T.hdiag[a] - T.hdiag[i];
             } else {
                 const double c00 = w1[p], c01 = w1[q], c10 = w2[p], c11 = w2[q];
@@ -1400,8 +1495,28 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
                     w2[x] = (-c10 * ra + c00 * rb) / det;
                 }
                 __syncthreads();
-                if (!(MIXED && SMALL)) rank_update<RT, true>(R, ne, n_so, cRp, w1, cRq, w2);
-                rank_update<double, true>(B, ne, ne, cBp, w1, cBq, w2);
+                if (UHF) {
+                    const int na = T.na, nb = ne - T.na, n = T.n;
+                    if ((p >= na) == (q >= na)) {
+                        // same spin: rank 2 on that spin's blocks
+                        const int lo = (p >= na) ? na : 0, cnt = (p >= na) ? nb : na;
+                        rank_update<RT, true>(R + (size_t)lo * n, cnt, n, cRp, w1 + lo, cRq, w2 + lo);
+                        rank_update_ld<true>(B + (size_t)lo * ne + lo, cnt, cnt, ne, cBp + lo, w1 + lo, cBq + lo,
+                                             w2 + lo);
+                    } else {
+                        // opposite spins (p alpha, q beta): w1 vanishes on the
+                        // beta slots and w2 on the alpha ones, so each spin's
+                        // blocks take one rank-1 update
+                        rank_update<RT, false>(R, na, n, cRp, w1, nullptr, nullptr);
+                        rank_update<RT, false>(R + (size_t)na * n, nb, n, cRq, w2 + na, nullptr, nullptr);
+                        rank_update_ld<false>(B, na, na, ne, cBp, w1, nullptr, nullptr);
+                        rank_update_ld<false>(B + (size_t)na * ne + na, nb, nb, ne, cBq + na, w2 + na, nullptr,
+                                              nullptr);
+                    }
+                } else {
+                    if (!(MIXED && SMALL)) rank_update<RT, true>(R, ne, n_so, cRp, w1, cRq, w2);
+                    rank_update<double, true>(B, ne, ne, cBp, w1, cBq, w2);
+                }
                 if (tid == 0)
                     md[MD_HNN] += dh + T.hdiag[a] + T.hdiag[b] - T.hdiag[i] - T.hdiag[j] +
                                   T.D[(size_t)a * n_so + b] - T.D[(size_t)i * n_so + j];
@@ -1449,7 +1564,7 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
             if (pick_hist) pick_hist[(size_t)k * W + w] = code_last;
         }
         // ------------------------------------------------------- refresh
-        if (refresh_period > 0 && ((gstep + 1) % (uint64_t)refresh_period) == 0) {
+        if (refresh_period > 0 && !UHF && ((gstep + 1) % (uint64_t)refresh_period) == 0) {
             refresh_state(T, slot, B, R, s, fcol, ipiv, mi, red, th, ths);
             hnn_full();
         }
@@ -1484,7 +1599,7 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
 }
 
 // One workgroup per walker of one system.
-template <int NSO_T, int NE_T, int NT_T, bool NW1, bool SMALL, typename RT>
+template <int NSO_T, int NE_T, int NT_T, bool NW1, bool SMALL, typename RT, bool UHF = false>
 __global__ void __launch_bounds__(NT_T ? NT_T : 512) __attribute__((amdgpu_waves_per_eu(sweep_waves_target(NSO_T, SMALL))))
 k_sweep(Tab T, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, const uint64_t* step_dev, uint64_t seed,
         int refresh_period, double* eloc_hist, double* t_hist, int64_t* pick_hist) {
@@ -1493,7 +1608,7 @@ k_sweep(Tab T, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, const uin
     // global step of the first move: step0, plus a device-resident counter
     // when the caller keeps one (graph replays advance it)
     const uint64_t s0 = step_dev ? step0 + *step_dev : step0;
-    sweep_body<NSO_T, NE_T, NT_T, NW1, SMALL, RT>(T, S, W, w, mode, n_steps, s0, seed, refresh_period, eloc_hist,
+    sweep_body<NSO_T, NE_T, NT_T, NW1, SMALL, RT, UHF>(T, S, W, w, mode, n_steps, s0, seed, refresh_period, eloc_hist,
                                                   t_hist, pick_hist);
 }
 
@@ -1618,7 +1733,7 @@ __host__ __device__ inline size_t refresh_gj_lds_bytes(int ne) {
            16;
 }
 
-template <typename RT, int H, int JC>
+template <typename RT, int H, int JC, bool UHF>
 __global__ void __launch_bounds__(kRefreshThreads) __attribute__((amdgpu_waves_per_eu(4))) k_refresh_gj(Tab T, Wk S,
                                                                                                       int64_t W) {
     constexpr int NW = kRefreshThreads / 64;
@@ -1755,8 +1870,8 @@ __global__ void __launch_bounds__(kRefreshThreads) __attribute__((amdgpu_waves_p
     __syncthreads();
     double* Bg = S.B + (size_t)w * ne * ne;
     for (int k = tid; k < ne * ne; k += kRefreshThreads) Bg[k] = Bs[k];
-    RT* R = (RT*)S.R + (size_t)w * n_so * ne;
-    r_gemm_theta_regs<RT, 16 * H>(T, Bs, R, T.theta, n_so);
+    RT* R = (RT*)S.R + (size_t)w * T.rrow * ne;
+    r_gemm_theta_regs<RT, 16 * H, UHF>(T, Bs, R, T.theta, n_so);
     double* sv = S.s + (size_t)w * n_so;
     for (int pp = tid; pp < n_so; pp += kRefreshThreads) {
         const double* Jr = T.J + (size_t)pp * n_so;
@@ -1809,7 +1924,7 @@ __global__ void __launch_bounds__(64) k_excitations(Tab T, Wk S, int64_t w, int3
             occl[rank] = pp;
         }
     __syncthreads();
-    const RT* R = (const RT*)S.R + (size_t)w * n_so * ne;
+    const RT* R = (const RT*)S.R + (size_t)w * T.rrow * ne;
     int64_t off = 0;
     for (int g = 0; g < T.G; ++g) {
         const Group Gr = group_of(T, g, occl, oslot, ies);
@@ -1845,6 +1960,16 @@ __global__ void __launch_bounds__(64) k_excitations(Tab T, Wk S, int64_t w, int3
 }
 
 // ------------------------------------------------------------ parameters
+// Spin-blocked orbitals: theta[a][x] for the occupied columns x < Ne is kept
+// where orbital a and column x have the same spin (columns [0, na) alpha,
+// [na, Ne) beta) and set to zero elsewhere; one block per orbital row.
+__global__ void k_theta_spin_blocks(double* th, int n, int na, int ne) {
+    const int a = blockIdx.x, n_so = 2 * n;
+    const bool ab = a >= n;
+    for (int x = threadIdx.x; x < ne; x += blockDim.x)
+        if ((x >= na) != ab) th[(size_t)a * n_so + x] = 0.0;
+}
+
 __global__ void k_dense_J(const double* Jp, double* J, int n_so) {
     const int p = blockIdx.x;
     const int64_t start = (int64_t)p * n_so - (int64_t)p * (p - 1) / 2;
@@ -2030,6 +2155,7 @@ __global__ void __launch_bounds__(1024) k_estimate(const double* eloc, const dou
 // =============================================================================
 struct vmc_ctx {
     int n = 0, n_so = 0, na = 0, nb = 0, ne = 0, nw = 0, G = 0, precision = 0, refresh = 50;
+    bool uhf = false;  // spin-blocked orbitals (VMC_UHF)
     uint64_t seed = 0;
     double eps = 0.0;
     int device = 0;
@@ -2076,6 +2202,10 @@ Tab make_tab(const vmc_ctx* h) {
     T.ne = h->ne;
     T.nw = h->nw;
     T.G = h->G;
+    T.n = h->n;
+    T.na = h->na;
+    T.uhf = h->uhf ? 1 : 0;
+    T.rrow = h->uhf ? h->n : h->n_so;
     T.eps = h->eps;
     T.row_off = h->d_row_off;
     T.dab = h->d_dab;
@@ -2148,10 +2278,10 @@ struct SweepArgs {
     const uint64_t* step_dev;
 };
 
-template <int NSO, int NE, int NT, bool NW1, bool SM, typename RT>
+template <int NSO, int NE, int NT, bool NW1, bool SM, typename RT, bool UHF = false>
 void launch_one(dim3 grid, dim3 block, size_t lds, hipStream_t st, const Tab& T, const Wk& S, const vmc_walkers* w,
                 const SweepArgs& a, const vmc_ctx* h) {
-    hipLaunchKernelGGL((k_sweep<NSO, NE, NT, NW1, SM, RT>), grid, block, lds, st, T, S, w->n_walkers, a.mode,
+    hipLaunchKernelGGL((k_sweep<NSO, NE, NT, NW1, SM, RT, UHF>), grid, block, lds, st, T, S, w->n_walkers, a.mode,
                        a.n_steps, a.step0, a.step_dev, h->seed, a.refresh, a.eh, a.th, a.ph);
 }
 
@@ -2159,7 +2289,10 @@ template <typename RT>
 void launch_prec(bool small, bool nw1, int nt, dim3 grid, dim3 block, size_t lds, hipStream_t st, const Tab& T,
                  const Wk& S, const vmc_walkers* w, const SweepArgs& a, const vmc_ctx* h) {
     auto spec = [&](int n_so, int ne, int c) { return small && h->n_so == n_so && h->ne == ne && nt == c; };
-    if (spec(16, 8, 64)) launch_one<16, 8, 64, true, true, RT>(grid, block, lds, st, T, S, w, a, h);
+    // spin-blocked orbitals: walker state in HBM (never the small layout)
+    if (h->uhf && nw1) launch_one<0, 0, 0, true, false, RT, true>(grid, block, lds, st, T, S, w, a, h);
+    else if (h->uhf) launch_one<0, 0, 0, false, false, RT, true>(grid, block, lds, st, T, S, w, a, h);
+    else if (spec(16, 8, 64)) launch_one<16, 8, 64, true, true, RT>(grid, block, lds, st, T, S, w, a, h);
     else if (spec(16, 8, 128)) launch_one<16, 8, 128, true, true, RT>(grid, block, lds, st, T, S, w, a, h);
     else if (spec(16, 8, 256)) launch_one<16, 8, 256, true, true, RT>(grid, block, lds, st, T, S, w, a, h);
     else if (spec(40, 20, 128)) launch_one<40, 20, 128, true, true, RT>(grid, block, lds, st, T, S, w, a, h);
@@ -2181,7 +2314,8 @@ SweepGeom sweep_geom(const vmc_ctx* h) {
     SweepGeom g;
     g.nt = h->block_threads > 0 ? h->block_threads : 256;
     const int rb = (int)r_bytes(h);
-    g.small = lds_layout(h->n_so, h->ne, h->nw, g.nt, true, rb).total <= kMaxLds;
+    // spin-blocked orbitals: always the layout with the walker state in HBM
+    g.small = !h->uhf && lds_layout(h->n_so, h->ne, h->nw, g.nt, true, rb).total <= kMaxLds;
     g.lds = lds_layout(h->n_so, h->ne, h->nw, g.nt, g.small, rb).total;
     return g;
 }
@@ -2197,6 +2331,17 @@ bool use_refresh_kernel(const vmc_ctx* h) {
 // 0 where Ne is larger (B in LDS instead).
 int refresh_gj_rows(int ne) { return ne <= 64 ? 1 : ne <= 128 ? 2 : 0; }
 
+// The register Gauss-Jordan kernel for a shape (rows 1 or 2), precision and
+// orbital form.
+const void* refresh_gj_kernel(int rows, bool mixed, bool uhf) {
+    if (rows == 1) {
+        if (mixed) return uhf ? (const void*)k_refresh_gj<float, 1, 8, true> : (const void*)k_refresh_gj<float, 1, 8, false>;
+        return uhf ? (const void*)k_refresh_gj<double, 1, 8, true> : (const void*)k_refresh_gj<double, 1, 8, false>;
+    }
+    if (mixed) return uhf ? (const void*)k_refresh_gj<float, 2, 16, true> : (const void*)k_refresh_gj<float, 2, 16, false>;
+    return uhf ? (const void*)k_refresh_gj<double, 2, 16, true> : (const void*)k_refresh_gj<double, 2, 16, false>;
+}
+
 vmc_status launch_refresh(vmc_ctx* h, vmc_walkers* w, hipStream_t st) {
     const size_t lds = refresh_lds_bytes(h->ne, kRefreshThreads);
     const Tab T = make_tab(h);
@@ -2206,13 +2351,11 @@ vmc_status launch_refresh(vmc_ctx* h, vmc_walkers* w, hipStream_t st) {
     if (rows != 0) {
         const bool mixed = h->precision == VMC_MIXED;
         const size_t b = refresh_gj_lds_bytes(h->ne);
-        if (rows == 1) {
-            if (mixed) hipLaunchKernelGGL((k_refresh_gj<float, 1, 8>), grid, block, b, st, T, S, w->n_walkers);
-            else hipLaunchKernelGGL((k_refresh_gj<double, 1, 8>), grid, block, b, st, T, S, w->n_walkers);
-        } else {
-            if (mixed) hipLaunchKernelGGL((k_refresh_gj<float, 2, 16>), grid, block, b, st, T, S, w->n_walkers);
-            else hipLaunchKernelGGL((k_refresh_gj<double, 2, 16>), grid, block, b, st, T, S, w->n_walkers);
-        }
+        Tab Ta = T;
+        Wk Sa = S;
+        int64_t Wa = w->n_walkers;
+        void* args[] = {&Ta, &Sa, &Wa};
+        HIP_OR_FAIL(h, hipLaunchKernel(refresh_gj_kernel(rows, mixed, h->uhf), grid, block, args, b, st));
         HIP_OR_FAIL(h, hipGetLastError());
         return VMC_OK;
     }
@@ -2268,7 +2411,8 @@ vmc_status validate_desc(const vmc_system_desc* d) {
     if (d->precision != VMC_FP64 && d->precision != VMC_MIXED)
         return fail(nullptr, VMC_E_ARG, "precision must be VMC_FP64 or VMC_MIXED");
     if (d->refresh_period < 1) return fail(nullptr, VMC_E_ARG, "refresh_period must be >= 1");
-    if (d->reserved != 0) return fail(nullptr, VMC_E_ARG, "reserved must be 0");
+    if (d->orbitals != VMC_GHF && d->orbitals != VMC_UHF)
+        return fail(nullptr, VMC_E_ARG, "orbitals must be VMC_GHF or VMC_UHF");
     return VMC_OK;
 }
 
@@ -2347,6 +2491,23 @@ vmc_status vmc_init(const vmc_system_desc* desc, const double* h1, const vmc_eri
     if (!e.empty()) return fail(nullptr, VMC_E_ARG, e);
     if (T.dv.size() >= (size_t)UINT32_MAX || T.sa.size() >= (size_t)UINT32_MAX)
         return fail(nullptr, VMC_E_UNSUPPORTED, "table larger than 2^32 entries");
+    if (desc->orbitals == VMC_UHF) {
+        // the spin-blocked layout keeps one spin per slot: every kept
+        // excitation must move each electron within its own spin
+        if (refresh_gj_rows(desc->n_alpha + desc->n_beta) == 0)
+            return fail(nullptr, VMC_E_UNSUPPORTED, "VMC_UHF supports at most 128 electrons");
+        const int n = desc->n_orb, n_so = 2 * n;
+        auto beta = [n](int o) { return o >= n; };
+        for (int i = 0; i < n_so; ++i)
+            for (int64_t k = T.s_off[i]; k < T.s_off[i + 1]; ++k)
+                if (beta((int)T.sa[k]) != beta(i))
+                    return fail(nullptr, VMC_E_ARG, "VMC_UHF needs spin-conserving singles");
+        for (int i = 0; i < n_so; ++i)
+            for (int j = i + 1; j < n_so; ++j)
+                for (int64_t k = T.row_off[(size_t)i * n_so + j]; k < T.row_off[(size_t)i * n_so + j + 1]; ++k)
+                    if (beta((int)T.dab[2 * k]) != beta(i) || beta((int)T.dab[2 * k + 1]) != beta(j))
+                        return fail(nullptr, VMC_E_ARG, "VMC_UHF needs spin-conserving doubles");
+    }
     vmc_ctx* h = new vmc_ctx;
     h->n = desc->n_orb;
     h->n_so = 2 * h->n;
@@ -2356,6 +2517,7 @@ vmc_status vmc_init(const vmc_system_desc* desc, const double* h1, const vmc_eri
     h->nw = (h->n_so + 63) / 64;
     h->G = h->ne + h->ne * (h->ne - 1) / 2;
     h->precision = desc->precision;
+    h->uhf = desc->orbitals == VMC_UHF;
     h->refresh = desc->refresh_period;
     h->seed = desc->seed;
     h->eps = eps;
@@ -2412,6 +2574,10 @@ vmc_status vmc_init(const vmc_system_desc* desc, const double* h1, const vmc_eri
                              (const void*)k_sweep<0, 0, 0, true, false, double>,
                              (const void*)k_sweep<0, 0, 0, false, false, float>,
                              (const void*)k_sweep<0, 0, 0, true, false, float>,
+                             (const void*)k_sweep<0, 0, 0, false, false, double, true>,
+                             (const void*)k_sweep<0, 0, 0, true, false, double, true>,
+                             (const void*)k_sweep<0, 0, 0, false, false, float, true>,
+                             (const void*)k_sweep<0, 0, 0, true, false, float, true>,
                              (const void*)k_sweep_batch<double>, (const void*)k_sweep_batch<float>};
         for (const void* f : big) {
             const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLdsHbm);
@@ -2428,13 +2594,8 @@ vmc_status vmc_init(const vmc_system_desc* desc, const double* h1, const vmc_eri
                                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         const bool mixed = h->precision == VMC_MIXED;
         const int gj = (int)refresh_gj_lds_bytes(h->ne);
-        if (e == hipSuccess && refresh_gj_rows(h->ne) == 1)
-            e = hipFuncSetAttribute(mixed ? (const void*)k_refresh_gj<float, 1, 8>
-                                          : (const void*)k_refresh_gj<double, 1, 8>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, gj);
-        if (e == hipSuccess && refresh_gj_rows(h->ne) == 2)
-            e = hipFuncSetAttribute(mixed ? (const void*)k_refresh_gj<float, 2, 16>
-                                          : (const void*)k_refresh_gj<double, 2, 16>,
+        if (e == hipSuccess && refresh_gj_rows(h->ne) != 0)
+            e = hipFuncSetAttribute(refresh_gj_kernel(refresh_gj_rows(h->ne), mixed, h->uhf),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, gj);
         if (e != hipSuccess) {
             free_ctx(h);
@@ -2450,6 +2611,10 @@ vmc_status vmc_set_params(vmc_handle h, const double* J_dev, const double* theta
     if (!J_dev || !theta_dev) return fail(h, VMC_E_ARG, "parameter pointer is NULL");
     const int n_so = h->n_so;
     HIP_OR_FAIL(h, hipMemcpyAsync(h->d_theta, theta_dev, sizeof(double) * n_so * n_so, hipMemcpyDeviceToDevice, st));
+    if (h->uhf) {
+        hipLaunchKernelGGL(k_theta_spin_blocks, dim3(n_so), dim3(64), 0, st, h->d_theta, h->n, h->na, h->ne);
+        HIP_OR_FAIL(h, hipGetLastError());
+    }
     hipLaunchKernelGGL(k_dense_J, dim3(n_so), dim3(256), 0, st, J_dev, h->d_J, n_so);
     HIP_OR_FAIL(h, hipGetLastError());
     if (h->n_dent > 0) {
@@ -2473,7 +2638,7 @@ vmc_status vmc_walker_bytes(vmc_handle h, int64_t W, size_t fb[VMC_NFIELDS]) {
     fb[VMC_F_SLOT_ORB] = w * h->ne * 4;
     fb[VMC_F_ORB_SLOT] = w * h->n_so * 4;
     fb[VMC_F_AINV] = w * h->ne * h->ne * 8;
-    fb[VMC_F_R] = w * h->ne * h->n_so * r_bytes(h);
+    fb[VMC_F_R] = w * h->ne * (h->uhf ? h->n : h->n_so) * r_bytes(h);
     fb[VMC_F_JSUM] = w * h->n_so * 8;
     fb[VMC_F_HNN] = w * 8;
     fb[VMC_F_ELOC] = w * 8;
@@ -2786,6 +2951,7 @@ vmc_status vmc_batch_create(const vmc_handle* systems, int32_t n, vmc_batch* out
         if (systems[e]->precision != systems[0]->precision)
             return fail(nullptr, VMC_E_ARG, "all systems of a batch must have the same precision");
         if (!systems[e]->params_set) return fail(nullptr, VMC_E_ARG, "vmc_set_params has not been called");
+        if (systems[e]->uhf) return fail(nullptr, VMC_E_UNSUPPORTED, "batches hold VMC_GHF systems only");
     }
     vmc_batch_ctx* b = new vmc_batch_ctx;
     b->sys.assign(systems, systems + n);

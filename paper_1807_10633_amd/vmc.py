@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(_PKG, "libvmc.so")
 VMC_OK = 0
 VMC_FP64 = 0
 VMC_MIXED = 1
+VMC_GHF = 0
+VMC_UHF = 1
 ST_SINGULAR, ST_EMPTY, ST_NONFINITE, ST_SMALLDEN = 1, 2, 4, 8
 
 FIELDS = ("occ_bits", "slot_orb", "orb_slot", "ainv", "r", "jsum", "hnn", "eloc", "tres", "pick", "status", "scratch")
@@ -39,7 +41,7 @@ class VmcError(RuntimeError):
 
 class SystemDesc(C.Structure):
     _fields_ = [("n_orb", C.c_int32), ("n_alpha", C.c_int32), ("n_beta", C.c_int32), ("precision", C.c_int32),
-                ("refresh_period", C.c_int32), ("reserved", C.c_int32), ("seed", C.c_uint64)]
+                ("refresh_period", C.c_int32), ("orbitals", C.c_int32), ("seed", C.c_uint64)]
 
 
 class EriList(C.Structure):
@@ -131,9 +133,10 @@ def _dev_ptr(t) -> Optional[int]:
 # Thin wrappers, same names as the C ABI
 # ----------------------------------------------------------------------------
 def vmc_init(n_orb: int, n_alpha: int, n_beta: int, h1: np.ndarray, eri_idx: np.ndarray, eri_val: np.ndarray,
-             eps: float, *, precision: int = VMC_FP64, refresh_period: int = 50, seed: int = 0, stream=None):
+             eps: float, *, precision: int = VMC_FP64, refresh_period: int = 50, seed: int = 0,
+             orbitals: int = VMC_GHF, stream=None):
     lib = load_library()
-    desc = SystemDesc(n_orb, n_alpha, n_beta, precision, refresh_period, 0, seed)
+    desc = SystemDesc(n_orb, n_alpha, n_beta, precision, refresh_period, orbitals, seed)
     h = np.ascontiguousarray(h1, dtype=np.float64)
     ei = np.ascontiguousarray(eri_idx, dtype=np.int32).reshape(-1, 4)
     ev = np.ascontiguousarray(eri_val, dtype=np.float64)
@@ -354,7 +357,7 @@ class System:
     """One Hamiltonian on the device: tables (library-owned) and parameters."""
 
     def __init__(self, n_orb, n_alpha, n_beta, h1, eri_idx, eri_val, eps, *, refresh_period=50, seed=0,
-                 precision=VMC_FP64, device="cuda"):
+                 precision=VMC_FP64, orbitals=VMC_GHF, device="cuda"):
         self.n_orb, self.n_alpha, self.n_beta = int(n_orb), int(n_alpha), int(n_beta)
         self.n_so = 2 * self.n_orb
         self.ne = self.n_alpha + self.n_beta
@@ -362,13 +365,18 @@ class System:
         self.n_params = self.n_so * (self.n_so + 1) // 2 + self.n_so * self.n_so
         self.device = device
         self.precision = int(precision)
+        self.orbitals = int(orbitals)
+        # length of one slot's row of R: every orbital, or the slot's own spin
+        self.r_row = self.n_orb if self.orbitals == VMC_UHF else self.n_so
         self.handle = vmc_init(n_orb, n_alpha, n_beta, h1, eri_idx, eri_val, eps, precision=precision,
-                               refresh_period=refresh_period, seed=seed)
+                               refresh_period=refresh_period, seed=seed, orbitals=orbitals)
 
     @classmethod
     def from_workload(cls, wl, **kw):
         import torch
 
+        if getattr(wl, "orbitals", "ghf") == "uhf":
+            kw.setdefault("orbitals", VMC_UHF)
         s = cls(wl.n_orb, wl.n_alpha, wl.n_beta, wl.h1, wl.eri_idx, wl.eri_val, wl.eps, seed=wl.ctmc_seed, **kw)
         s.set_params(torch.as_tensor(wl.jastrow, device=s.device), torch.as_tensor(wl.theta, device=s.device))
         return s

@@ -8,9 +8,9 @@ import pytest
 from paper_1807_10633_amd import vmc
 
 
-def _init(n, na, nb, precision=0, refresh=50, reserved=0, eps=1e-6, h1=None):
+def _init(n, na, nb, precision=0, refresh=50, orbitals=0, eps=1e-6, h1=None):
     lib = vmc.load_library()
-    desc = vmc.SystemDesc(n, na, nb, precision, refresh, reserved, 0)
+    desc = vmc.SystemDesc(n, na, nb, precision, refresh, orbitals, 0)
     h = np.zeros((max(n, 1), max(n, 1))) if h1 is None else h1
     idx = np.zeros((0, 4), dtype=np.int32)
     val = np.zeros(0)
@@ -28,11 +28,17 @@ def _init(n, na, nb, precision=0, refresh=50, reserved=0, eps=1e-6, h1=None):
     ((2, 2, 2), -1, "empty spin-orbital"),
     ((4, 1, 1, 7), -1, "precision"),
     ((4, 1, 1, 0, 0), -1, "refresh_period"),
-    ((4, 1, 1, 0, 50, 3), -1, "reserved"),
+    ((4, 1, 1, 0, 50, 3), -1, "orbitals"),
 ])
 def test_init_rejects_bad_descriptions(args, code, msg):
     rc, err = _init(*args)
     assert rc == code and msg in err, (rc, err)
+
+
+def test_init_rejects_unsupported_spin_blocked_systems():
+    # spin-blocked orbitals need at most 128 electrons
+    rc, err = _init(100, 65, 64, orbitals=1)
+    assert rc == -6 and "128" in err, (rc, err)
 
 
 def test_init_rejects_bad_threshold_and_hamiltonian():

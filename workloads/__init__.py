@@ -33,6 +33,7 @@ from .generators import (  # noqa: F401
     hchain_like,
     splitmix64_uniform,
     init_theta,
+    spin_blocked,
     init_jastrow,
     init_walkers,
     eri_dense_spatial,

@@ -76,6 +76,7 @@ class Workload:
     occ: np.ndarray  # (W, n_words) uint64 occupation bitstrings
     ctmc_seed: int
     notes: str = ""
+    orbitals: str = "ghf"  # "ghf" general, "uhf" spin-blocked theta
 
     @property
     def n_so(self) -> int:
@@ -222,6 +223,21 @@ def init_theta(h1: np.ndarray, n_alpha: int, n_beta: int, noise: float, seed: in
     return np.ascontiguousarray(theta)
 
 
+def spin_blocked(theta: np.ndarray, n: int, n_alpha: int, n_beta: int) -> np.ndarray:
+    """Unrestricted (spin-blocked) form of an init_theta matrix: entries whose
+    orbital row and column have different spins set to zero.  Column spins
+    follow init_theta's layout: [0, na) alpha, [na, Ne) beta, then n - na alpha
+    and n - nb beta virtual columns."""
+    ne = n_alpha + n_beta
+    col_beta = np.zeros(2 * n, dtype=bool)
+    col_beta[n_alpha:ne] = True
+    col_beta[ne + n - n_alpha:] = True
+    row_beta = np.arange(2 * n) >= n
+    out = np.array(theta, dtype=np.float64, copy=True)
+    out[row_beta[:, None] != col_beta[None, :]] = 0.0
+    return np.ascontiguousarray(out)
+
+
 def init_jastrow(n_so: int, std: float, seed: int) -> np.ndarray:
     """Packed upper-triangular J (p<=q, row by row), entries N(0, std)."""
     m = n_so * (n_so + 1) // 2
@@ -254,7 +270,7 @@ CONFIG_NAMES = ("hubbard8", "hchain20", "hubbard10x10", "hchain160", "hchain40",
 
 def make_config(name: str, n_walkers: Optional[int] = None, *, theta_noise: float = 0.01,
                 jastrow_std: float = 0.05, U: Optional[float] = None, eps: Optional[float] = None,
-                seed_offset: int = 0) -> Workload:
+                seed_offset: int = 0, orbitals: str = "ghf") -> Workload:
     """Build one of the named workloads.
 
     hubbard8      8-site ring, t=1, U=4, 4+4 electrons, eps=0, 64 walkers
@@ -263,8 +279,11 @@ def make_config(name: str, n_walkers: Optional[int] = None, *, theta_noise: floa
     hchain160     H-chain-like, 160 orbitals, 80+80, eps=1e-5, 8192 walkers
     hchain40/80   members of the uneven batch (half filled, eps=1e-5, 2048 walkers)
     Seeds for configuration k: integrals 1000+k, psi 2000+k, walkers 3000+k,
-    CTMC 4000+k.
+    CTMC 4000+k.  orbitals="uhf" gives the spin-blocked (unrestricted) form of
+    the same theta (spin_blocked).
     """
+    if orbitals not in ("ghf", "uhf"):
+        raise ValueError(f"orbitals must be 'ghf' or 'uhf', not {orbitals!r}")
     table = {
         "hubbard8": (1, 64),
         "hchain20": (2, 4096),
@@ -297,7 +316,9 @@ def make_config(name: str, n_walkers: Optional[int] = None, *, theta_noise: floa
         e = eps
     n_so = 2 * n
     theta = init_theta(h1, na, nb, theta_noise, 2000 + k)
+    if orbitals == "uhf":
+        theta = spin_blocked(theta, n, na, nb)
     jas = init_jastrow(n_so, jastrow_std, 2000 + k)
     occ = init_walkers(n, na, nb, W, 3000 + k)
     return Workload(name=name, n_orb=n, n_alpha=na, n_beta=nb, h1=h1, eri_idx=ei, eri_val=ev,
-                    eps=e, theta=theta, jastrow=jas, occ=occ, ctmc_seed=4000 + k)
+                    eps=e, theta=theta, jastrow=jas, occ=occ, ctmc_seed=4000 + k, orbitals=orbitals)
