@@ -96,7 +96,7 @@ typedef struct {
                                the other entries of its copy to zero.  The determinant then factors into
                                an alpha and a beta determinant, slot p < n_alpha holds an alpha electron,
                                B is block diagonal, R keeps each slot's own spin only ([W][Ne][n]), and a
-                               move updates the blocks of the spin it moves.  Needs Ne <= 128 and
+                               move updates the blocks of the spin it moves.  Needs at most 128 electrons of each spin and
                                spin-conserving integrals (VMC_E_ARG otherwise); the walker state lives in
                                HBM; no batches.  Walkers with a wrong alpha count are flagged
                                VMC_ST_SINGULAR at initialisation. */

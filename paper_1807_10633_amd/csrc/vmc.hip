@@ -334,7 +334,7 @@ __device__ __forceinline__ void r_gemm(const Tab& T, const double* B, RT* R, con
 // The same product with each wave holding a 16-orbital tile of theta in
 // registers (KS k-steps, Ne <= 4 KS) across all slot tiles, so that theta is
 // read once per walker instead of once per output tile; B in LDS.
-template <typename RT, int KS, bool UHF>
+template <typename RT, int KS>
 __device__ __forceinline__ void r_gemm_theta_regs(const Tab& T, const double* B, RT* R, const double* th, int ths) {
     const int ne = T.ne, n_so = T.n_so, l = lane_id();
     const int wv = (int)__builtin_amdgcn_readfirstlane((uint32_t)(threadIdx.x >> 6)), nwv = blockDim.x >> 6;
@@ -361,11 +361,7 @@ __device__ __forceinline__ void r_gemm_theta_regs(const Tab& T, const double* B,
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int pr = pt * 16 + Mma<RT>::row(kq, j);
-                if (pr < ne && a < n_so) {
-                    // spin-blocked orbitals: only the slot's own spin is kept
-                    if (!UHF) R[pr * n_so + a] = acc[j];
-                    else if ((a >= T.n) == (pr >= T.na)) R[r_index_uhf(T, pr, a)] = acc[j];
-                }
+                if (pr < ne && a < n_so) R[pr * n_so + a] = acc[j];
             }
         }
     }
@@ -425,22 +421,37 @@ __device__ __forceinline__ void rank_update(E* M, int rows, int cols, const doub
 template <bool TWO>
 __device__ __forceinline__ void rank_update_ld(double* M, int rows, int cols, int ld, const double* c1,
                                                const double* r1, const double* c2, const double* r2) {
+    constexpr int U = 4;
     const int tid = threadIdx.x, nt = blockDim.x;
     if ((cols & 1) == 0 && (ld & 1) == 0 && (((uintptr_t)M) & 15) == 0) {
+        // 16-byte vectors, four loads in flight per thread as in rank_update
         const int cv = cols >> 1, nv = rows * cv;
-        for (int vi = tid; vi < nv; vi += nt) {
-            const int r = vi / cv, c = (vi - r * cv) * 2;
-            double2* q = (double2*)(M + (size_t)r * ld + c);
-            double2 v = *q;
-            const double a1 = r1[r], a2 = TWO ? r2[r] : 0.0;
-            double d0 = c1[c] * a1, d1 = c1[c + 1] * a1;
-            if (TWO) {
-                d0 += c2[c] * a2;
-                d1 += c2[c + 1] * a2;
+        for (int v0 = tid; v0 < nv; v0 += nt * U) {
+            double2 val[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int vi = v0 + u * nt;
+                if (vi < nv) {
+                    const int r = vi / cv, c = (vi - r * cv) * 2;
+                    val[u] = *(const double2*)(M + (size_t)r * ld + c);
+                }
             }
-            v.x -= d0;
-            v.y -= d1;
-            *q = v;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int vi = v0 + u * nt;
+                if (vi < nv) {
+                    const int r = vi / cv, c = (vi - r * cv) * 2;
+                    const double a1 = r1[r], a2 = TWO ? r2[r] : 0.0;
+                    double d0 = c1[c] * a1, d1 = c1[c + 1] * a1;
+                    if (TWO) {
+                        d0 += c2[c] * a2;
+                        d1 += c2[c + 1] * a2;
+                    }
+                    val[u].x -= d0;
+                    val[u].y -= d1;
+                    *(double2*)(M + (size_t)r * ld + c) = val[u];
+                }
+            }
         }
     } else {
         for (int idx = tid; idx < rows * cols; idx += nt) {
@@ -992,8 +1003,12 @@ enum { MODE_ELOC = 0, MODE_CTMC = 1, MODE_INIT = 2 };
 // Walker state in LDS: four waves per SIMD (measured faster than the
 // compiler's own choice of three up to 40 spin-orbitals, a few spills
 // included); the 64-spin-orbital specialisation is left to the compiler (1).
-constexpr int sweep_waves_target(int nso_t, bool small) {
-    return small ? ((nso_t <= 40) ? 4 : 1) : VMC_SWEEP_HBM_WAVES;
+// Spin-blocked orbitals (walker state in HBM, smaller update): its own target.
+#ifndef VMC_SWEEP_UHF_WAVES
+#define VMC_SWEEP_UHF_WAVES 3
+#endif
+constexpr int sweep_waves_target(int nso_t, bool small, bool uhf = false) {
+    return small ? ((nso_t <= 40) ? 4 : 1) : uhf ? VMC_SWEEP_UHF_WAVES : VMC_SWEEP_HBM_WAVES;
 }
 
 // NSO_T, NE_T, NT_T: compile-time n_so, Ne and workgroup size of a size
@@ -1600,7 +1615,7 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
 
 // One workgroup per walker of one system.
 template <int NSO_T, int NE_T, int NT_T, bool NW1, bool SMALL, typename RT, bool UHF = false>
-__global__ void __launch_bounds__(NT_T ? NT_T : 512) __attribute__((amdgpu_waves_per_eu(sweep_waves_target(NSO_T, SMALL))))
+__global__ void __launch_bounds__(NT_T ? NT_T : 512) __attribute__((amdgpu_waves_per_eu(sweep_waves_target(NSO_T, SMALL, UHF))))
 k_sweep(Tab T, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, const uint64_t* step_dev, uint64_t seed,
         int refresh_period, double* eloc_hist, double* t_hist, int64_t* pick_hist) {
     const int64_t w = blockIdx.x;
@@ -1727,23 +1742,34 @@ __device__ __forceinline__ double readlane_d(double x, int lane) {
     return __hiloint2double(hi, lo);
 }
 
-__host__ __device__ inline size_t refresh_gj_lds_bytes(int ne) {
-    const size_t mat = (size_t)ne * ne * 8, bufs = (2 * 128 + 4 + 2) * 8;
+// LDS of the register Gauss-Jordan kernel: the inverse of an nm x nm matrix
+// (theta[N], or the larger spin block) and slot lists of all Ne electrons.
+__host__ __device__ inline size_t refresh_gj_lds_bytes(int nm, int ne) {
+    const size_t mat = (size_t)nm * nm * 8, bufs = (2 * 128 + 4 + 2) * 8;
     return al16(mat > bufs ? mat : bufs) + 3 * al16((size_t)ne * 4) + al16((size_t)(kRefreshThreads / 64 + 2) * 8) +
            16;
 }
 
+// UHF (spin-blocked orbitals): one launch per spin (spin 0 alpha, 1 beta),
+// each inverting that spin's diagonal block of theta[N] (slots and occupied
+// columns [lo, lo + N_s)) and writing its rows of B (zero outside the block)
+// and of R (own spin only); the beta launch, which runs second, also forms
+// s and H_NN.  General orbitals: one launch, spin unused.
 template <typename RT, int H, int JC, bool UHF>
 __global__ void __launch_bounds__(kRefreshThreads) __attribute__((amdgpu_waves_per_eu(4))) k_refresh_gj(Tab T, Wk S,
-                                                                                                      int64_t W) {
+                                                                                                      int64_t W,
+                                                                                                      int spin) {
     constexpr int NW = kRefreshThreads / 64;
     static_assert(H * 64 <= 128 && NW * JC <= 128, "at most 128 rows and columns");
     extern __shared__ __align__(16) unsigned char smem[];
     const int64_t w = blockIdx.x;
     if (w >= W) return;
-    const int tid = threadIdx.x, ne = T.ne, n_so = T.n_so, l = lane_id();
+    const int ne_all = T.ne;
+    const int lo = (UHF && spin) ? T.na : 0;
+    const int tid = threadIdx.x, ne = UHF ? (spin ? ne_all - T.na : T.na) : ne_all, n_so = T.n_so, l = lane_id();
     const int wv = (int)uni((uint32_t)(tid >> 6));
-    const size_t mat = (size_t)ne * ne * 8, bufs = (2 * 128 + 4 + 2) * 8;
+    const int nm = UHF ? max(T.na, ne_all - T.na) : ne_all;  // the largest matrix of this system
+    const size_t mat = (size_t)nm * nm * 8, bufs = (2 * 128 + 4 + 2) * 8;
     size_t o = 0;
     double* Bs = (double*)smem;     // B (slot layout) once the elimination is done
     double* col = Bs;               // during it: the pivot column, two buffers
@@ -1751,15 +1777,15 @@ __global__ void __launch_bounds__(kRefreshThreads) __attribute__((amdgpu_waves_p
     int* pivb = (int*)(pvb + 4);    // pivot row, two buffers
     o += al16(mat > bufs ? mat : bufs);
     int* slot = (int*)(smem + o);
-    o += al16((size_t)ne * 4);
+    o += al16((size_t)ne_all * 4);
     int* pk = (int*)(smem + o);  // pivot row of step k
-    o += al16((size_t)ne * 4);
+    o += al16((size_t)ne_all * 4);
     int* qr = (int*)(smem + o);  // step at which row r was the pivot
-    o += al16((size_t)ne * 4);
+    o += al16((size_t)ne_all * 4);
     double* red = (double*)(smem + o);
     o += al16((size_t)(kRefreshThreads / 64 + 2) * 8);
     int* flag = (int*)(smem + o);
-    for (int k = tid; k < ne; k += kRefreshThreads) slot[k] = S.slot_orb[(size_t)w * ne + k];
+    for (int k = tid; k < ne; k += kRefreshThreads) slot[k] = S.slot_orb[(size_t)w * ne_all + lo + k];
     if (tid == 0) flag[0] = (int)S.status[w];
     __syncthreads();
     double g[H][JC];
@@ -1767,7 +1793,7 @@ __global__ void __launch_bounds__(kRefreshThreads) __attribute__((amdgpu_waves_p
 #pragma unroll
     for (int j = 0; j < JC; ++j) {
         const int c = wv + NW * j;
-        const double* tc = T.theta + (size_t)(c < ne ? slot[c] : 0) * n_so;
+        const double* tc = T.theta + (size_t)(c < ne ? slot[c] : 0) * n_so + lo;
 #pragma unroll
         for (int h = 0; h < H; ++h) {
             const int r = l + 64 * h;
@@ -1868,26 +1894,49 @@ __global__ void __launch_bounds__(kRefreshThreads) __attribute__((amdgpu_waves_p
         }
     }
     __syncthreads();
-    double* Bg = S.B + (size_t)w * ne * ne;
-    for (int k = tid; k < ne * ne; k += kRefreshThreads) Bg[k] = Bs[k];
-    RT* R = (RT*)S.R + (size_t)w * T.rrow * ne;
-    r_gemm_theta_regs<RT, 16 * H, UHF>(T, Bs, R, T.theta, n_so);
+    double* Bg = S.B + (size_t)w * ne_all * ne_all;
+    RT* R = (RT*)S.R + (size_t)w * T.rrow * ne_all;
+    if (!UHF) {
+        for (int k = tid; k < ne * ne; k += kRefreshThreads) Bg[k] = Bs[k];
+        r_gemm_theta_regs<RT, 16 * H>(T, Bs, R, T.theta, n_so);
+    } else {
+        // this spin's rows of B, zero outside the block
+        for (int k = tid; k < ne * ne_all; k += kRefreshThreads) {
+            const int p = k / ne_all, x = k - p * ne_all;
+            Bg[(size_t)(lo + p) * ne_all + x] = (x >= lo && x < lo + ne) ? Bs[p * ne + x - lo] : 0.0;
+        }
+        // R rows of this spin's slots over its n orbitals: theta[own spin
+        // rows][lo, lo + N_s) times the block inverse
+        Tab Tb = T;
+        Tb.ne = ne;
+        Tb.n_so = T.n;
+        r_gemm_theta_regs<RT, 16 * H>(Tb, Bs, R + (size_t)lo * T.n, T.theta + (size_t)(spin ? T.n : 0) * n_so + lo,
+                                      n_so);
+        if (spin == 0) {
+            if (tid == 0) S.status[w] = (uint32_t)flag[0];
+            return;
+        }
+        // the beta launch: s and H_NN over every slot
+        __syncthreads();
+        for (int k = tid; k < ne_all; k += kRefreshThreads) slot[k] = S.slot_orb[(size_t)w * ne_all + k];
+        __syncthreads();
+    }
     double* sv = S.s + (size_t)w * n_so;
     for (int pp = tid; pp < n_so; pp += kRefreshThreads) {
         const double* Jr = T.J + (size_t)pp * n_so;
         double acc = 0.0;
-        for (int k = 0; k < ne; ++k) {
+        for (int k = 0; k < ne_all; ++k) {
             const int q = slot[k];
             if (q != pp) acc += Jr[q];
         }
         sv[pp] = acc;
     }
     double hp = 0.0;
-    for (int x = tid; x < ne; x += kRefreshThreads) {
+    for (int x = tid; x < ne_all; x += kRefreshThreads) {
         const int i = slot[x];
         const double* Di = T.D + (size_t)i * n_so;
         hp += T.hdiag[i];
-        for (int y = x + 1; y < ne; ++y) hp += Di[slot[y]];
+        for (int y = x + 1; y < ne_all; ++y) hp += Di[slot[y]];
     }
     const double hnn = block_total(hp, red);
     if (tid == 0) {
@@ -2324,12 +2373,17 @@ SweepGeom sweep_geom(const vmc_ctx* h) {
 // kernel when B fits its LDS budget.
 constexpr size_t kMaxRefreshLds = 160 * 1024;
 bool use_refresh_kernel(const vmc_ctx* h) {
+    if (h->uhf) return true;  // always the register kernel, one spin block at a time
     return !sweep_geom(h).small && refresh_lds_bytes(h->ne, kRefreshThreads) <= kMaxRefreshLds;
 }
 
 // Register Gauss-Jordan shape: 1 (Ne <= 64) or 2 (Ne <= 128) rows per lane,
 // 0 where Ne is larger (B in LDS instead).
 int refresh_gj_rows(int ne) { return ne <= 64 ? 1 : ne <= 128 ? 2 : 0; }
+
+// Size of the matrices the register Gauss-Jordan kernel inverts: theta[N], or
+// with spin-blocked orbitals the larger of its two spin blocks.
+int gj_size(const vmc_ctx* h) { return h->uhf ? std::max(h->na, h->nb) : h->ne; }
 
 // The register Gauss-Jordan kernel for a shape (rows 1 or 2), precision and
 // orbital form.
@@ -2347,16 +2401,19 @@ vmc_status launch_refresh(vmc_ctx* h, vmc_walkers* w, hipStream_t st) {
     const Tab T = make_tab(h);
     const Wk S = make_wk(h, w);
     const dim3 grid((unsigned)w->n_walkers), block(kRefreshThreads);
-    const int rows = refresh_gj_rows(h->ne);
+    const int rows = refresh_gj_rows(gj_size(h));
     if (rows != 0) {
         const bool mixed = h->precision == VMC_MIXED;
-        const size_t b = refresh_gj_lds_bytes(h->ne);
+        const size_t b = refresh_gj_lds_bytes(gj_size(h), h->ne);
         Tab Ta = T;
         Wk Sa = S;
         int64_t Wa = w->n_walkers;
-        void* args[] = {&Ta, &Sa, &Wa};
-        HIP_OR_FAIL(h, hipLaunchKernel(refresh_gj_kernel(rows, mixed, h->uhf), grid, block, args, b, st));
-        HIP_OR_FAIL(h, hipGetLastError());
+        // spin-blocked: the alpha block, then the beta block (stream order)
+        for (int spin = 0; spin < (h->uhf ? 2 : 1); ++spin) {
+            int sp = spin;
+            void* args[] = {&Ta, &Sa, &Wa, &sp};
+            HIP_OR_FAIL(h, hipLaunchKernel(refresh_gj_kernel(rows, mixed, h->uhf), grid, block, args, b, st));
+        }
         return VMC_OK;
     }
     if (h->precision == VMC_MIXED) {
@@ -2494,8 +2551,8 @@ vmc_status vmc_init(const vmc_system_desc* desc, const double* h1, const vmc_eri
     if (desc->orbitals == VMC_UHF) {
         // the spin-blocked layout keeps one spin per slot: every kept
         // excitation must move each electron within its own spin
-        if (refresh_gj_rows(desc->n_alpha + desc->n_beta) == 0)
-            return fail(nullptr, VMC_E_UNSUPPORTED, "VMC_UHF supports at most 128 electrons");
+        if (refresh_gj_rows(std::max(desc->n_alpha, desc->n_beta)) == 0)
+            return fail(nullptr, VMC_E_UNSUPPORTED, "VMC_UHF supports at most 128 electrons of each spin");
         const int n = desc->n_orb, n_so = 2 * n;
         auto beta = [n](int o) { return o >= n; };
         for (int i = 0; i < n_so; ++i)
@@ -2587,16 +2644,17 @@ vmc_status vmc_init(const vmc_system_desc* desc, const double* h1, const vmc_eri
             }
         }
     }
-    if (refresh_lds_bytes(h->ne, kRefreshThreads) <= kMaxRefreshLds) {
-        const int lds = (int)refresh_lds_bytes(h->ne, kRefreshThreads);
-        hipError_t e = hipFuncSetAttribute((h->precision == VMC_MIXED) ? (const void*)k_refresh<float>
-                                                                       : (const void*)k_refresh<double>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    {
+        hipError_t e = hipSuccess;
         const bool mixed = h->precision == VMC_MIXED;
-        const int gj = (int)refresh_gj_lds_bytes(h->ne);
-        if (e == hipSuccess && refresh_gj_rows(h->ne) != 0)
-            e = hipFuncSetAttribute(refresh_gj_kernel(refresh_gj_rows(h->ne), mixed, h->uhf),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, gj);
+        if (refresh_lds_bytes(h->ne, kRefreshThreads) <= kMaxRefreshLds)
+            e = hipFuncSetAttribute(mixed ? (const void*)k_refresh<float> : (const void*)k_refresh<double>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)refresh_lds_bytes(h->ne, kRefreshThreads));
+        const size_t gj = refresh_gj_lds_bytes(gj_size(h), h->ne);
+        if (e == hipSuccess && refresh_gj_rows(gj_size(h)) != 0 && gj <= kMaxRefreshLds)
+            e = hipFuncSetAttribute(refresh_gj_kernel(refresh_gj_rows(gj_size(h)), mixed, h->uhf),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)gj);
         if (e != hipSuccess) {
             free_ctx(h);
             return fail(nullptr, VMC_E_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));

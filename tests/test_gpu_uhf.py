@@ -68,6 +68,31 @@ def test_uhf_ctmc_teacher_forced(torch, name, W, burn, steps, sample):
     assert res["picks_compared"] > 0.99 * len(idx) * steps
 
 
+@pytest.mark.parametrize("na,nb", [(5, 2), (3, 0), (0, 4)])
+def test_uhf_uneven_spins(torch, na, nb):
+    """Spin blocks of different sizes, one of them possibly empty (10-site
+    ring, U = 4): E_L, t and picks against the oracle over 70 moves (one
+    re-inversion of each block on the way)."""
+    from workloads import Workload, hubbard_ring, init_jastrow, init_theta, init_walkers, spin_blocked
+
+    L, W = 10, 48
+    h1, ei, ev = hubbard_ring(L, 1.0, 4.0)
+    wl = Workload(name=f"ring{L}_{na}_{nb}", n_orb=L, n_alpha=na, n_beta=nb, h1=h1, eri_idx=ei, eri_val=ev, eps=0.0,
+                  theta=spin_blocked(init_theta(h1, na, nb, 0.05, 5), L, na, nb), jastrow=init_jastrow(2 * L, 0.05, 5),
+                  occ=init_walkers(L, na, nb, W, 6), ctmc_seed=7, orbitals="uhf")
+    _say(f"[uhf uneven] ring10 {na}+{nb}")
+    sysm = gpu_system(wl)
+    walkers = sysm.walkers(wl.occ)
+    occ0 = occ_of(sysm, walkers)
+    eh, th, ph = run_sweep(sysm, walkers, 70)
+    st = field(sysm, walkers, "status", torch.int32, 1)[:, 0]
+    assert np.all((st & 1) == 0)
+    orc = OracleSystem.from_workload(wl)
+    res = teacher_forced_check(orc, wl.ctmc_seed, occ0, 0, eh, th, ph, range(0, W, 6))
+    scaled = res["dE_all"] / (EL_TOL * np.maximum(1.0, res["T_all"] / 100.0))
+    assert scaled.max() <= 1.0 and not res["mismatches"], res["mismatches"][:3]
+
+
 def test_uhf_state_after_updates(torch):
     """After 37 moves without re-inversion: B equals a fresh inverse of
     theta[N] in slot order and is exactly block diagonal, slots [0, na) hold
@@ -240,3 +265,31 @@ def test_uhf_optimizer_keeps_the_spin_blocks(torch):
     for w in (0, 100, 255):
         r = orc.local_energy(occ[w], ORC_LEMMA, with_candidates=False)
         assert abs(el[w] - r["eloc"]) <= EL_TOL * max(1.0, r["T"] / 100.0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_uhf_hchain160_full_size_sampled(torch, prec):
+    """160 orbitals, 80+80 electrons (above the 128 a general-orbital inverse
+    fits in registers; each spin block has 80), eps = 1e-5, 8192 walkers: E_L of
+    sampled walkers, fresh and after a short sweep, against the oracle."""
+    from paper_1807_10633_amd.vmc import VMC_FP64, VMC_MIXED, vmc_local_energy
+
+    wl = _uhf("hchain160", 8192)
+    _say(f"[uhf hchain160 {prec}] W=8192")
+    sysm = gpu_system(wl, precision=VMC_MIXED if prec == "mixed" else VMC_FP64)
+    walkers = sysm.walkers(wl.occ)
+    tol = MIXED_TOL * wl.n_elec if prec == "mixed" else EL_TOL
+    orc = OracleSystem.from_workload(wl)
+    idx = [0, 4095, 8191]
+    for sweep in (0, 3):
+        if sweep:
+            run_sweep(sysm, walkers, sweep)
+        vmc_local_energy(sysm.handle, walkers)
+        torch.cuda.synchronize()
+        st = field(sysm, walkers, "status", torch.int32, 1)[:, 0]
+        assert np.all((st & 1) == 0)
+        el = field(sysm, walkers, "eloc", torch.float64, 1)[:, 0]
+        occ = occ_of(sysm, walkers)
+        for w in idx[: 3 if sweep == 0 else 2]:
+            r = orc.local_energy(occ[w], ORC_LEMMA, with_candidates=False)
+            assert abs(el[w] - r["eloc"]) <= tol * max(1.0, r["T"] / 100.0), (w, el[w], r["eloc"], r["T"])

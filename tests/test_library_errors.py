@@ -36,8 +36,8 @@ def test_init_rejects_bad_descriptions(args, code, msg):
 
 
 def test_init_rejects_unsupported_spin_blocked_systems():
-    # spin-blocked orbitals need at most 128 electrons
-    rc, err = _init(100, 65, 64, orbitals=1)
+    # spin-blocked orbitals need at most 128 electrons of each spin
+    rc, err = _init(130, 129, 1, orbitals=1)
     assert rc == -6 and "128" in err, (rc, err)
 
 
