@@ -44,32 +44,36 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("paper_1807_10633_amd/csrc/vmc.hip", "paper_1807_10633_amd/csrc/device.hpp",
                   "paper_1807_10633_amd/csrc/tables.cpp")
 COUNTED_TRAFFIC = {
-    ("2dd0bbf23395396a50ce6507379f252bebba5d30cf02c27cd7f1a16012edf940",
-     "769edbfb386e269240a511822f4a97b0c1092caec56fbcb07664cf0d53b24099",
+    ("a727e8764237ca891ab5cdffac78fe46f27d464e8f727f77424ec546d519b97f",
+     "e42321a173f348e60cbd4a8c9a6c2ece6e89405d4e145e8681061726bb564736",
      "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d", "hchain20", 4096, 50, 256, "fp64"):
-        {"fetch_kib": 58840.8, "fetch_factor": 2.0, "write_kib": 62363.25, "write_factor": 1.0},
-    ("2dd0bbf23395396a50ce6507379f252bebba5d30cf02c27cd7f1a16012edf940",
-     "769edbfb386e269240a511822f4a97b0c1092caec56fbcb07664cf0d53b24099",
+        {"fetch_kib": 57137.1, "fetch_factor": 2.0, "write_kib": 62356.2, "write_factor": 1.0},
+    ("a727e8764237ca891ab5cdffac78fe46f27d464e8f727f77424ec546d519b97f",
+     "e42321a173f348e60cbd4a8c9a6c2ece6e89405d4e145e8681061726bb564736",
      "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d", "hubbard10x10", 16384, 50, 256, "fp64"):
-        {"fetch_kib": 112214545.8, "fetch_factor": 2.0, "write_kib": 191987012.75, "write_factor": 1.0},
-    ("2dd0bbf23395396a50ce6507379f252bebba5d30cf02c27cd7f1a16012edf940",
-     "769edbfb386e269240a511822f4a97b0c1092caec56fbcb07664cf0d53b24099",
-     "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d", "hubbard10x10", 16384, 50, 256, "mixed"):
-        {"fetch_kib": 80064124.8, "fetch_factor": 2.0, "write_kib": 128007679.25, "write_factor": 1.0},
+        {"fetch_kib": 112315848.4, "fetch_factor": 2.0, "write_kib": 191990021.0, "write_factor": 1.0},
+    ("a727e8764237ca891ab5cdffac78fe46f27d464e8f727f77424ec546d519b97f",
+     "e42321a173f348e60cbd4a8c9a6c2ece6e89405d4e145e8681061726bb564736",
+     "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d", "hubbard10x10", 16384, 50, 128, "mixed"):
+        {"fetch_kib": 80026261.6, "fetch_factor": 2.0, "write_kib": 128005788.4, "write_factor": 1.0},
+    ("a727e8764237ca891ab5cdffac78fe46f27d464e8f727f77424ec546d519b97f",
+     "e42321a173f348e60cbd4a8c9a6c2ece6e89405d4e145e8681061726bb564736",
+     "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d", "hubbard10x10:uhf", 16384, 50, 128, "fp64"):
+        {"fetch_kib": 37645934.5, "fetch_factor": 2.0, "write_kib": 48661708.7, "write_factor": 1.0},
 }
 
 
-# VALU wave-instructions per sweep launch (rocprofv3 --pmc SQ_INSTS_VALU ...
-# SQ_ACTIVE_INST_VALU GRBM_GUI_ACTIVE on the same bench command as the HBM
+# Instruction counts per sweep launch (rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_SALU
+# SQ_INSTS_LDS SQ_INSTS_VMEM_RD, and VALUBusy in a run of its own, on the same bench command as the HBM
 # counters), keyed like COUNTED_TRAFFIC.  The issue peak is one wave64 VALU
 # instruction per SIMD every 4 cycles (16 lanes): 256 CUs x 4 SIMDs x 2.4 GHz / 4.
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 COUNTED_ISSUE = {
-    ("2dd0bbf23395396a50ce6507379f252bebba5d30cf02c27cd7f1a16012edf940",
-     "769edbfb386e269240a511822f4a97b0c1092caec56fbcb07664cf0d53b24099",
+    ("a727e8764237ca891ab5cdffac78fe46f27d464e8f727f77424ec546d519b97f",
+     "e42321a173f348e60cbd4a8c9a6c2ece6e89405d4e145e8681061726bb564736",
      "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d", "hchain20", 4096, 50, 256, "fp64"):
         {"valu_insts": 4890615390.0, "salu_insts": 2665121788.0, "lds_insts": 548790633.5,
-         "vmem_rd_insts": 168605103.5, "valu_busy_pct": 64.45},
+         "vmem_rd_insts": 168605103.5, "valu_busy_pct": 64.70},
 }
 
 
