@@ -665,7 +665,8 @@ __device__ __forceinline__ double block_total(double v, double* red) {
 // One walker's per-step data.  The candidate stream of each kind is the
 // concatenation of its groups' table rows (singles: one group per occupied
 // orbital; doubles: one per occupied pair), each padded to a multiple of 64
-// positions so that a 64-lane chunk lies within one group.
+// positions so that a 64-lane chunk lies within one group.  With the walker
+// state in HBM the singles rows are not padded (see stream_pass).
 template <typename RT>
 struct StepView {
     const int* occl;
@@ -809,6 +810,11 @@ __device__ __forceinline__ bool stream_pass(const Tab& T, const StepView<RT>& V,
     // held one per lane, the chunk's group found by a ballot, so that empty
     // groups cost nothing and descriptor loads are coalesced.
     constexpr bool REG_CURSOR = !SCALED;
+    // Singles with their descriptors in LDS and the walker state in HBM: the
+    // groups are not padded (a Hubbard electron has only a few targets), so a
+    // chunk may span several groups and each lane finds its own by a binary
+    // search over the group ends, from a lower bound carried chunk to chunk.
+    constexpr bool DENSE = !DOUBLES && REG_CURSOR;
     // queue entries carry the group's slots (see cand_eval)
     constexpr bool QPQ = REG_CURSOR && !MASK;
     const uint32_t* gpq = DOUBLES ? V.dpq : V.spq;
@@ -824,7 +830,9 @@ __device__ __forceinline__ bool stream_pass(const Tab& T, const StepView<RT>& V,
         b_delta = in ? delta[gg] : 0u;
         if (QPQ) b_pq = in ? gpq[gg] : 0u;
     };
-    if (REG_CURSOR) {
+    if (DENSE) {
+        // gc: a lower bound of the group of every position still to come
+    } else if (REG_CURSOR) {
         blk = gc & ~63u;
         load_block();
     } else {
@@ -846,6 +854,7 @@ __device__ __forceinline__ bool stream_pass(const Tab& T, const StepView<RT>& V,
     // compute the chunks' groups and offsets (advancing the uniform group
     // cursor) and issue their table loads
     auto fetch = [&](uint32_t c, Stage& st) __attribute__((always_inline)) {
+        uint32_t gnext = gc;  // dense singles: the searches of one fetch share gc as their lower bound
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             const uint32_t cu = c + (uint32_t)(u * kWave);
@@ -853,7 +862,20 @@ __device__ __forceinline__ bool stream_pass(const Tab& T, const StepView<RT>& V,
             st.g[u] = gc;
             st.off[u] = 0;
             st.pq[u] = 0;
-            if (cu < c1) {
+            if (DENSE && cu < c1) {
+                const uint32_t pos = cu + (uint32_t)l;
+                uint32_t lo = gc, hi = ng - 1;
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (gend[mid] > pos) hi = mid;
+                    else lo = mid + 1;
+                }
+                st.g[u] = lo;
+                st.pq[u] = gpq[lo];
+                st.ok[u] = pos < vend[lo] && pos >= first;
+                st.off[u] = st.ok[u] ? pos + delta[lo] : 0u;  // entry 0 stands in for lanes without a candidate
+                gnext = (uint32_t)__builtin_amdgcn_readlane((int)lo, kWave - 1);
+            } else if (cu < c1) {
                 if (REG_CURSOR) {
                     uint64_t m = __ballot(b_end > cu);
                     while (m == 0ull) {
@@ -881,6 +903,7 @@ __device__ __forceinline__ bool stream_pass(const Tab& T, const StepView<RT>& V,
                 st.off[u] = st.ok[u] ? pos + e_delta : 0u;  // entry 0 stands in for lanes without a candidate
             }
         }
+        if (DENSE) gc = gnext;
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             if (MASK) st.ab[u] = T.dmask[st.off[u]];
@@ -1211,7 +1234,7 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
             const uint32_t b0 = T.s_off[i], len = T.s_off[i + 1] - b0;
             sdelta[x] = b0;
             svend[x] = len;
-            sgend[x] = (len + 63u) & ~63u;
+            sgend[x] = SMALL ? ((len + 63u) & ~63u) : len;  // unpadded in HBM layout (dense stream)
             spq[x] = (uint32_t)oslot[i];
             sfac[x] = ies[i];
         }
@@ -1283,8 +1306,9 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
         // ------------------------------------------------- local energy
         double el_lane = 0.0;
         if (!singular) {
-            // contiguous, chunk-aligned ranges of each padded stream per wave
-            const uint32_t cs = LS >> 6, cd = LD >> 6;
+            // contiguous, chunk-aligned ranges of each stream per wave (the
+            // singles stream of the HBM layout ends anywhere in its last chunk)
+            const uint32_t cs = (LS + 63u) >> 6, cd = LD >> 6;
             const uint32_t r0s = (uint32_t)(((uint64_t)cs * wv / nwv) << 6), r1s = (uint32_t)(((uint64_t)cs * (wv + 1) / nwv) << 6);
             const uint32_t r0d = (uint32_t)(((uint64_t)cd * wv / nwv) << 6), r1d = (uint32_t)(((uint64_t)cd * (wv + 1) / nwv) << 6);
             const int lb = wv * (kLogS + kLogD);
@@ -1754,7 +1778,8 @@ __host__ __device__ inline size_t refresh_gj_lds_bytes(int nm, int ne) {
 // each inverting that spin's diagonal block of theta[N] (slots and occupied
 // columns [lo, lo + N_s)) and writing its rows of B (zero outside the block)
 // and of R (own spin only); the beta launch, which runs second, also forms
-// s and H_NN.  General orbitals: one launch, spin unused.
+// s and H_NN.  (Both spins in one launch of 2W workgroups measured slower.)
+// General orbitals: one launch, spin unused.
 template <typename RT, int H, int JC, bool UHF>
 __global__ void __launch_bounds__(kRefreshThreads) __attribute__((amdgpu_waves_per_eu(4))) k_refresh_gj(Tab T, Wk S,
                                                                                                       int64_t W,
