@@ -44,22 +44,22 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("paper_1807_10633_amd/csrc/vmc.hip", "paper_1807_10633_amd/csrc/device.hpp",
                   "paper_1807_10633_amd/csrc/tables.cpp")
 COUNTED_TRAFFIC = {
-    ("a727e8764237ca891ab5cdffac78fe46f27d464e8f727f77424ec546d519b97f",
+    ("a13badd7014ec437e4c804f31cb4dd36a43b9170bd436089374af0cb771910ae",
      "e42321a173f348e60cbd4a8c9a6c2ece6e89405d4e145e8681061726bb564736",
      "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d", "hchain20", 4096, 50, 256, "fp64"):
-        {"fetch_kib": 57137.1, "fetch_factor": 2.0, "write_kib": 62356.2, "write_factor": 1.0},
-    ("a727e8764237ca891ab5cdffac78fe46f27d464e8f727f77424ec546d519b97f",
+        {"fetch_kib": 59750.9, "fetch_factor": 2.0, "write_kib": 62352.2, "write_factor": 1.0},
+    ("a13badd7014ec437e4c804f31cb4dd36a43b9170bd436089374af0cb771910ae",
      "e42321a173f348e60cbd4a8c9a6c2ece6e89405d4e145e8681061726bb564736",
      "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d", "hubbard10x10", 16384, 50, 256, "fp64"):
-        {"fetch_kib": 112315848.4, "fetch_factor": 2.0, "write_kib": 191990021.0, "write_factor": 1.0},
-    ("a727e8764237ca891ab5cdffac78fe46f27d464e8f727f77424ec546d519b97f",
+        {"fetch_kib": 112944173.5, "fetch_factor": 2.0, "write_kib": 192000465.6, "write_factor": 1.0},
+    ("a13badd7014ec437e4c804f31cb4dd36a43b9170bd436089374af0cb771910ae",
      "e42321a173f348e60cbd4a8c9a6c2ece6e89405d4e145e8681061726bb564736",
      "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d", "hubbard10x10", 16384, 50, 128, "mixed"):
-        {"fetch_kib": 80026261.6, "fetch_factor": 2.0, "write_kib": 128005788.4, "write_factor": 1.0},
-    ("a727e8764237ca891ab5cdffac78fe46f27d464e8f727f77424ec546d519b97f",
+        {"fetch_kib": 80336727.1, "fetch_factor": 2.0, "write_kib": 128003526.8, "write_factor": 1.0},
+    ("a13badd7014ec437e4c804f31cb4dd36a43b9170bd436089374af0cb771910ae",
      "e42321a173f348e60cbd4a8c9a6c2ece6e89405d4e145e8681061726bb564736",
      "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d", "hubbard10x10:uhf", 16384, 50, 128, "fp64"):
-        {"fetch_kib": 37645934.5, "fetch_factor": 2.0, "write_kib": 48661708.7, "write_factor": 1.0},
+        {"fetch_kib": 39075371.0, "fetch_factor": 2.0, "write_kib": 48679839.5, "write_factor": 1.0},
 }
 
 
@@ -69,11 +69,11 @@ COUNTED_TRAFFIC = {
 # instruction per SIMD every 4 cycles (16 lanes): 256 CUs x 4 SIMDs x 2.4 GHz / 4.
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 COUNTED_ISSUE = {
-    ("a727e8764237ca891ab5cdffac78fe46f27d464e8f727f77424ec546d519b97f",
+    ("a13badd7014ec437e4c804f31cb4dd36a43b9170bd436089374af0cb771910ae",
      "e42321a173f348e60cbd4a8c9a6c2ece6e89405d4e145e8681061726bb564736",
      "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d", "hchain20", 4096, 50, 256, "fp64"):
-        {"valu_insts": 4890615390.0, "salu_insts": 2665121788.0, "lds_insts": 548790633.5,
-         "vmem_rd_insts": 168605103.5, "valu_busy_pct": 64.70},
+        {"valu_insts": 4890615390.0, "salu_insts": 2665940988.0, "lds_insts": 548790633.5,
+         "vmem_rd_insts": 168605103.5, "valu_busy_pct": 64.69},
 }
 
 
