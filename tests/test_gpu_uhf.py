@@ -293,3 +293,43 @@ def test_uhf_hchain160_full_size_sampled(torch, prec):
         for w in idx[: 3 if sweep == 0 else 2]:
             r = orc.local_energy(occ[w], ORC_LEMMA, with_candidates=False)
             assert abs(el[w] - r["eloc"]) <= tol * max(1.0, r["T"] / 100.0), (w, el[w], r["eloc"], r["T"])
+
+
+@pytest.mark.parametrize("name,nw", [("hubbard8", 4), ("hchain20", 4)])
+def test_uhf_excitation_lists(torch, name, nw):
+    """The diagnostic candidate list reads the spin-blocked R: candidates
+    bit-exact, H * ratio and |ratio| against the oracle, after some moves."""
+    from paper_1807_10633_amd.vmc import vmc_excitations
+
+    wl = _uhf(name, nw)
+    sysm = gpu_system(wl)
+    walkers = sysm.walkers(wl.occ)
+    run_sweep(sysm, walkers, 7)
+    occ = occ_of(sysm, walkers)
+    orc = OracleSystem.from_workload(wl)
+    cap = 200000
+    ijab = torch.zeros((cap, 5), dtype=torch.int32, device="cuda")
+    hv = torch.zeros(cap, dtype=torch.float64, device="cuda")
+    rv = torch.zeros(cap, dtype=torch.float64, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    for w in range(nw):
+        vmc_excitations(sysm.handle, walkers, w, ijab, hv, rv, cap, cnt)
+        torch.cuda.synchronize()
+        n = int(cnt.item())
+        ref = orc.local_energy(occ[w], ORC_LEMMA)["cand"]
+        assert n == ref.size
+        exp = np.stack([ref["type"], ref["i"], ref["j"], ref["a"], ref["b"]], axis=1)
+        assert np.array_equal(ijab[:n].cpu().numpy(), exp)
+        h, r = hv[:n].cpu().numpy(), rv[:n].cpu().numpy()
+        scale = np.abs(ref["ratio"]).sum() + 1.0
+        assert np.max(np.abs(h * r - ref["h"] * ref["ratio"])) <= 1e-12 * scale
+        assert np.allclose(np.abs(r), np.abs(ref["ratio"]), rtol=1e-10, atol=1e-13 * scale)
+
+
+def test_uhf_systems_are_not_batched(torch):
+    from paper_1807_10633_amd.vmc import VmcError, vmc_batch_create
+
+    wl = _uhf("hubbard8", 8)
+    sysm = gpu_system(wl)
+    with pytest.raises(VmcError):
+        vmc_batch_create([sysm.handle])
