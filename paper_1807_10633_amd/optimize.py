@@ -20,12 +20,18 @@ alpha = 0.001 for the first 5 iterations, then 0.01.  beta1 = 0.9 and beta2 =
 
     python -m paper_1807_10633_amd.optimize --config hubbard8 --iters 40
 prints one JSON line per iteration.
+
+`evaluate` gives the energy of fixed parameters at another screening
+threshold: the paper optimises with a loose eps and computes the final energy
+in one shot with a tighter one (section "Accuracy and scaling"); `--eval-eps`
+runs that after the iterations.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import sys
+import time
 from typing import Callable, List, Optional
 
 import torch
@@ -99,6 +105,36 @@ class Optimizer:
         return [float(self.step().item()) for _ in range(n_iter)]
 
 
+def evaluate(wl, J, theta, occ, *, eps: float, rounds: int = 10, moves: int = 50, burn: int = 100,
+             precision: int = _vmc.VMC_FP64, orbitals: int = _vmc.VMC_GHF, stream=None) -> dict:
+    """Energy of fixed parameters (device tensors J, theta) on the Hamiltonian of
+    workload wl screened at eps, from walkers starting at occupations occ.
+
+    After `burn` CTMC moves, each of `rounds` rounds makes `moves` moves and
+    estimates E from the residence-time weighted local energies of the final
+    states (vmc_estimate).  Returns the mean over rounds, its standard error
+    (rounds taken as independent) and the per-round values.
+    """
+    system = _vmc.System(wl.n_orb, wl.n_alpha, wl.n_beta, wl.h1, wl.eri_idx, wl.eri_val, eps, seed=wl.ctmc_seed + 1,
+                         refresh_period=moves, precision=precision, orbitals=orbitals)
+    system.set_params(J, theta)
+    walkers = system.walkers(occ)
+    est = torch.zeros(4, dtype=torch.float64, device=J.device)
+    g = torch.zeros(walkers.n_walkers, dtype=torch.float64, device=J.device)
+    if burn:
+        _vmc.vmc_ctmc_step(system.handle, walkers, burn, stream=stream)
+    energies = []
+    for _ in range(rounds):
+        _vmc.vmc_ctmc_step(system.handle, walkers, moves, stream=stream)
+        _vmc.vmc_local_energy(system.handle, walkers, stream=stream)
+        _vmc.vmc_estimate(system.handle, walkers, est, g, stream=stream)
+        energies.append(float(est[2].item()))
+    e = torch.tensor(energies, dtype=torch.float64)
+    err = float(e.std(unbiased=True).item() / len(energies) ** 0.5) if len(energies) > 1 else float("nan")
+    return {"energy": float(e.mean().item()), "stderr": err, "rounds": energies, "eps": eps,
+            "system": system, "walkers": walkers}
+
+
 def _main(argv: Optional[List[str]] = None) -> int:
     from workloads import make_config
 
@@ -109,20 +145,33 @@ def _main(argv: Optional[List[str]] = None) -> int:
     ap.add_argument("--moves", type=int, default=50)
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
     ap.add_argument("--paper-literal", action="store_true")
+    ap.add_argument("--eps", type=float, default=None, help="screening threshold of the optimisation "
+                    "(default: the configuration's own)")
+    ap.add_argument("--eval-eps", type=float, default=None,
+                    help="after the iterations, evaluate the final parameters at this threshold")
+    ap.add_argument("--eval-rounds", type=int, default=20)
     args = ap.parse_args(argv)
     if not torch.cuda.is_available():
         print(json.dumps({"error": "needs a GPU"}))
         return 2
-    wl = make_config(args.config, n_walkers=args.walkers or None)
+    wl = make_config(args.config, n_walkers=args.walkers or None, eps=args.eps)
     prec = _vmc.VMC_MIXED if args.precision == "mixed" else _vmc.VMC_FP64
     system = _vmc.System.from_workload(wl, precision=prec, refresh_period=args.moves)
     walkers = system.walkers(wl.occ)
     opt = Optimizer(system, walkers, torch.as_tensor(wl.jastrow, device="cuda"),
                     torch.as_tensor(wl.theta, device="cuda"), moves=args.moves, paper_literal=args.paper_literal)
     for i in range(args.iters):
-        E = float(opt.step().item())
+        t0 = time.perf_counter()
+        E = float(opt.step().item())  # .item() waits for the iteration
         print(json.dumps({"iteration": i, "alpha": paper_schedule(i), "energy": E,
-                          "energy_per_electron": E / wl.n_elec}), flush=True)
+                          "energy_per_electron": E / wl.n_elec, "ms": (time.perf_counter() - t0) * 1e3}), flush=True)
+    if args.eval_eps is not None:
+        occ = walkers.view("occ_bits", torch.int64)[: walkers.n_walkers * system.n_words].cpu().numpy()
+        ev = evaluate(wl, opt.J.clone(), opt.theta.clone(), occ.view("uint64").reshape(walkers.n_walkers, -1),
+                      eps=args.eval_eps, rounds=args.eval_rounds, moves=args.moves, precision=prec,
+                      orbitals=system.orbitals)
+        print(json.dumps({"eval_eps": args.eval_eps, "energy": ev["energy"], "stderr": ev["stderr"],
+                          "energy_per_electron": ev["energy"] / wl.n_elec}), flush=True)
     return 0
 
 

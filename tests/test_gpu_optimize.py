@@ -10,6 +10,9 @@
 * The loop lowers the exact variational energy of the 8-site ring: <psi|H|psi>
   from the brute-force Hamiltonian goes from -1.16 to -4.31 in 40 iterations
   (ground state -4.60), and never below the ground state.
+* Optimise at a loose eps, evaluate at a tight one (section "Accuracy and
+  scaling"): the evaluation at the tight eps matches the oracle built at that
+  eps with the optimised parameters.
 """
 import numpy as np
 import pytest
@@ -111,3 +114,34 @@ def test_loop_lowers_exact_energy_of_the_ring(torch):
     assert e_end >= e0 - 1e-9
     # 40 iterations recover most of the gap to the ground state (91 % here)
     assert e_end < e_start - 0.8 * (e_start - e0)
+
+
+def test_loose_eps_optimisation_tight_eps_evaluation(torch):
+    from paper_1807_10633_amd.optimize import Optimizer, evaluate
+
+    wl = make_config("hchain20", n_walkers=256, eps=1e-4)
+    sysm = gpu_system(wl)
+    walkers = sysm.walkers(wl.occ)
+    opt = Optimizer(sysm, walkers, torch.as_tensor(wl.jastrow, device="cuda"), torch.as_tensor(wl.theta, device="cuda"),
+                    moves=20)
+    opt.run(6)
+    torch.cuda.synchronize()
+    occ = occ_of(sysm, walkers)
+    ev = evaluate(wl, opt.J.clone(), opt.theta.clone(), occ, eps=1e-7, rounds=2, moves=20, burn=20)
+    es, ew = ev["system"], ev["walkers"]
+    p = opt.params.cpu().numpy()
+    orc = OracleSystem(wl.n_orb, wl.n_alpha, wl.n_beta, wl.h1, wl.eri_idx, wl.eri_val, 1e-7)
+    orc.set_params(p[: opt.nj], p[opt.nj:].reshape(sysm.n_so, sysm.n_so))
+    occ2 = occ_of(es, ew)
+    el = field(es, ew, "eloc", torch.float64, 1)[:, 0]
+    st = field(es, ew, "status", torch.int32, 1)[:, 0]
+    assert np.all((st & 1) == 0)
+    el_o, T_o, _, st_o = orc.local_energy_batch(occ2, ORC_LEMMA)
+    assert np.all(st_o == 0)
+    tol = 1e-10 * np.maximum(1.0, T_o / 100.0)
+    assert np.all(np.abs(el - el_o) <= tol), float(np.max(np.abs(el - el_o) / tol))
+    # the last round's energy is the residence-time weighted mean of these E_L
+    E_ref = weighted_energy(el_o, 1.0 / T_o)
+    assert abs(ev["rounds"][-1] - E_ref) <= 1e-10 * max(1.0, abs(E_ref))
+    _say(f"    optimised at eps 1e-4 (last sampled E {opt.est[2].item():.5f}); "
+         f"at eps 1e-7: E {ev['energy']:.5f} +- {ev['stderr']:.5f}")
