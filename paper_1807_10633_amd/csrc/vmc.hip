@@ -1017,21 +1017,16 @@ __device__ __forceinline__ double log_prefix(double* a, int n) {
 
 enum { MODE_ELOC = 0, MODE_CTMC = 1, MODE_INIT = 2 };
 
-// Occupancy target of the sweep kernel when the walker state lives in HBM:
-// at least this many waves per SIMD, so that enough walkers stream their
-// updates concurrently (the LDS layout of that variant allows four, the registers three).
-#ifndef VMC_SWEEP_HBM_WAVES
-#define VMC_SWEEP_HBM_WAVES 3
-#endif
+// Occupancy target of the sweep kernel when the walker state lives in HBM,
+// HW waves per SIMD, compiled for two values: 3 for systems without doubles
+// (the Hubbard update stream is HBM-bound and runs faster with the registers
+// of three waves), 4 for systems with doubles (their candidate gathers wait on
+// L2 and MALL and gain from a fourth wave per SIMD, a few spills included).
 // Walker state in LDS: four waves per SIMD (measured faster than the
 // compiler's own choice of three up to 40 spin-orbitals, a few spills
 // included); the 64-spin-orbital specialisation is left to the compiler (1).
-// Spin-blocked orbitals (walker state in HBM, smaller update): its own target.
-#ifndef VMC_SWEEP_UHF_WAVES
-#define VMC_SWEEP_UHF_WAVES 3
-#endif
-constexpr int sweep_waves_target(int nso_t, bool small, bool uhf = false) {
-    return small ? ((nso_t <= 40) ? 4 : 1) : uhf ? VMC_SWEEP_UHF_WAVES : VMC_SWEEP_HBM_WAVES;
+constexpr int sweep_waves_target(int nso_t, bool small, int hw) {
+    return small ? ((nso_t <= 40) ? 4 : 1) : hw;
 }
 
 // NSO_T, NE_T, NT_T: compile-time n_so, Ne and workgroup size of a size
@@ -1638,8 +1633,8 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
 }
 
 // One workgroup per walker of one system.
-template <int NSO_T, int NE_T, int NT_T, bool NW1, bool SMALL, typename RT, bool UHF = false>
-__global__ void __launch_bounds__(NT_T ? NT_T : 512) __attribute__((amdgpu_waves_per_eu(sweep_waves_target(NSO_T, SMALL, UHF))))
+template <int NSO_T, int NE_T, int NT_T, bool NW1, bool SMALL, typename RT, bool UHF = false, int HW = 3>
+__global__ void __launch_bounds__(NT_T ? NT_T : 512) __attribute__((amdgpu_waves_per_eu(sweep_waves_target(NSO_T, SMALL, HW))))
 k_sweep(Tab T, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, const uint64_t* step_dev, uint64_t seed,
         int refresh_period, double* eloc_hist, double* t_hist, int64_t* pick_hist) {
     const int64_t w = blockIdx.x;
@@ -1675,7 +1670,7 @@ struct BatchArgs {
 };
 
 template <typename RT>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(VMC_SWEEP_HBM_WAVES)))
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
 k_sweep_batch(BatchArgs A, int mode, int n_steps) {
     const int64_t b = blockIdx.x;
     int e = 0;
@@ -2352,30 +2347,41 @@ struct SweepArgs {
     const uint64_t* step_dev;
 };
 
-template <int NSO, int NE, int NT, bool NW1, bool SM, typename RT, bool UHF = false>
+template <int NSO, int NE, int NT, bool NW1, bool SM, typename RT, bool UHF = false, int HW = 3>
 void launch_one(dim3 grid, dim3 block, size_t lds, hipStream_t st, const Tab& T, const Wk& S, const vmc_walkers* w,
                 const SweepArgs& a, const vmc_ctx* h) {
-    hipLaunchKernelGGL((k_sweep<NSO, NE, NT, NW1, SM, RT, UHF>), grid, block, lds, st, T, S, w->n_walkers, a.mode,
+    hipLaunchKernelGGL((k_sweep<NSO, NE, NT, NW1, SM, RT, UHF, HW>), grid, block, lds, st, T, S, w->n_walkers, a.mode,
                        a.n_steps, a.step0, a.step_dev, h->seed, a.refresh, a.eh, a.th, a.ph);
+}
+
+// Waves per SIMD of the HBM variant for this system: 4 with doubles, else 3.
+int hbm_waves(const vmc_ctx* h) { return h->n_dent > 0 ? 4 : 3; }
+
+template <bool NW1, bool UHF, typename RT>
+void launch_hbm(dim3 grid, dim3 block, size_t lds, hipStream_t st, const Tab& T, const Wk& S, const vmc_walkers* w,
+                const SweepArgs& a, const vmc_ctx* h) {
+    if (hbm_waves(h) == 4) launch_one<0, 0, 0, NW1, false, RT, UHF, 4>(grid, block, lds, st, T, S, w, a, h);
+    else launch_one<0, 0, 0, NW1, false, RT, UHF, 3>(grid, block, lds, st, T, S, w, a, h);
 }
 
 template <typename RT>
 void launch_prec(bool small, bool nw1, int nt, dim3 grid, dim3 block, size_t lds, hipStream_t st, const Tab& T,
                  const Wk& S, const vmc_walkers* w, const SweepArgs& a, const vmc_ctx* h) {
     auto spec = [&](int n_so, int ne, int c) { return small && h->n_so == n_so && h->ne == ne && nt == c; };
-    // spin-blocked orbitals: walker state in HBM (never the small layout)
-    if (h->uhf && nw1) launch_one<0, 0, 0, true, false, RT, true>(grid, block, lds, st, T, S, w, a, h);
-    else if (h->uhf) launch_one<0, 0, 0, false, false, RT, true>(grid, block, lds, st, T, S, w, a, h);
-    else if (spec(16, 8, 64)) launch_one<16, 8, 64, true, true, RT>(grid, block, lds, st, T, S, w, a, h);
+    // walker state in HBM (always, with spin-blocked orbitals)
+    if (!small) {
+        if (h->uhf && nw1) launch_hbm<true, true, RT>(grid, block, lds, st, T, S, w, a, h);
+        else if (h->uhf) launch_hbm<false, true, RT>(grid, block, lds, st, T, S, w, a, h);
+        else if (nw1) launch_hbm<true, false, RT>(grid, block, lds, st, T, S, w, a, h);
+        else launch_hbm<false, false, RT>(grid, block, lds, st, T, S, w, a, h);
+    } else if (spec(16, 8, 64)) launch_one<16, 8, 64, true, true, RT>(grid, block, lds, st, T, S, w, a, h);
     else if (spec(16, 8, 128)) launch_one<16, 8, 128, true, true, RT>(grid, block, lds, st, T, S, w, a, h);
     else if (spec(16, 8, 256)) launch_one<16, 8, 256, true, true, RT>(grid, block, lds, st, T, S, w, a, h);
     else if (spec(40, 20, 128)) launch_one<40, 20, 128, true, true, RT>(grid, block, lds, st, T, S, w, a, h);
     else if (spec(40, 20, 256)) launch_one<40, 20, 256, true, true, RT>(grid, block, lds, st, T, S, w, a, h);
     else if (spec(64, 32, 256)) launch_one<64, 32, 256, true, true, RT>(grid, block, lds, st, T, S, w, a, h);
-    else if (nw1 && small) launch_one<0, 0, 0, true, true, RT>(grid, block, lds, st, T, S, w, a, h);
-    else if (nw1) launch_one<0, 0, 0, true, false, RT>(grid, block, lds, st, T, S, w, a, h);
-    else if (small) launch_one<0, 0, 0, false, true, RT>(grid, block, lds, st, T, S, w, a, h);
-    else launch_one<0, 0, 0, false, false, RT>(grid, block, lds, st, T, S, w, a, h);
+    else if (nw1) launch_one<0, 0, 0, true, true, RT>(grid, block, lds, st, T, S, w, a, h);
+    else launch_one<0, 0, 0, false, true, RT>(grid, block, lds, st, T, S, w, a, h);
 }
 
 // Geometry of the sweep launch for this system.
@@ -2652,14 +2658,22 @@ vmc_status vmc_init(const vmc_system_desc* desc, const double* h1, const vmc_eri
     // dynamic LDS beyond 64 KB for the kernels that may need it, set here once
     // so that later calls (possibly under graph capture) only launch
     {
-        const void* big[] = {(const void*)k_sweep<0, 0, 0, false, false, double>,
-                             (const void*)k_sweep<0, 0, 0, true, false, double>,
-                             (const void*)k_sweep<0, 0, 0, false, false, float>,
-                             (const void*)k_sweep<0, 0, 0, true, false, float>,
-                             (const void*)k_sweep<0, 0, 0, false, false, double, true>,
-                             (const void*)k_sweep<0, 0, 0, true, false, double, true>,
-                             (const void*)k_sweep<0, 0, 0, false, false, float, true>,
-                             (const void*)k_sweep<0, 0, 0, true, false, float, true>,
+        const void* big[] = {(const void*)k_sweep<0, 0, 0, false, false, double, false, 3>,
+                             (const void*)k_sweep<0, 0, 0, true, false, double, false, 3>,
+                             (const void*)k_sweep<0, 0, 0, false, false, float, false, 3>,
+                             (const void*)k_sweep<0, 0, 0, true, false, float, false, 3>,
+                             (const void*)k_sweep<0, 0, 0, false, false, double, true, 3>,
+                             (const void*)k_sweep<0, 0, 0, true, false, double, true, 3>,
+                             (const void*)k_sweep<0, 0, 0, false, false, float, true, 3>,
+                             (const void*)k_sweep<0, 0, 0, true, false, float, true, 3>,
+                             (const void*)k_sweep<0, 0, 0, false, false, double, false, 4>,
+                             (const void*)k_sweep<0, 0, 0, true, false, double, false, 4>,
+                             (const void*)k_sweep<0, 0, 0, false, false, float, false, 4>,
+                             (const void*)k_sweep<0, 0, 0, true, false, float, false, 4>,
+                             (const void*)k_sweep<0, 0, 0, false, false, double, true, 4>,
+                             (const void*)k_sweep<0, 0, 0, true, false, double, true, 4>,
+                             (const void*)k_sweep<0, 0, 0, false, false, float, true, 4>,
+                             (const void*)k_sweep<0, 0, 0, true, false, float, true, 4>,
                              (const void*)k_sweep_batch<double>, (const void*)k_sweep_batch<float>};
         for (const void* f : big) {
             const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLdsHbm);
