@@ -44,22 +44,22 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("paper_1807_10633_amd/csrc/vmc.hip", "paper_1807_10633_amd/csrc/device.hpp",
                   "paper_1807_10633_amd/csrc/tables.cpp")
 COUNTED_TRAFFIC = {
-    ("a13badd7014ec437e4c804f31cb4dd36a43b9170bd436089374af0cb771910ae",
+    ("5af7e828dc7bc47fb823d8a564888dedd12b92e4d5c47e6577002d4f097a2631",
      "e42321a173f348e60cbd4a8c9a6c2ece6e89405d4e145e8681061726bb564736",
      "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d", "hchain20", 4096, 50, 256, "fp64"):
-        {"fetch_kib": 59750.9, "fetch_factor": 2.0, "write_kib": 62352.2, "write_factor": 1.0},
-    ("a13badd7014ec437e4c804f31cb4dd36a43b9170bd436089374af0cb771910ae",
+        {"fetch_kib": 59086.56, "fetch_factor": 2.0, "write_kib": 62350.08, "write_factor": 1.0},
+    ("5af7e828dc7bc47fb823d8a564888dedd12b92e4d5c47e6577002d4f097a2631",
      "e42321a173f348e60cbd4a8c9a6c2ece6e89405d4e145e8681061726bb564736",
      "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d", "hubbard10x10", 16384, 50, 256, "fp64"):
-        {"fetch_kib": 112944173.5, "fetch_factor": 2.0, "write_kib": 192000465.6, "write_factor": 1.0},
-    ("a13badd7014ec437e4c804f31cb4dd36a43b9170bd436089374af0cb771910ae",
+        {"fetch_kib": 112855937.47, "fetch_factor": 2.0, "write_kib": 191992325.92, "write_factor": 1.0},
+    ("5af7e828dc7bc47fb823d8a564888dedd12b92e4d5c47e6577002d4f097a2631",
      "e42321a173f348e60cbd4a8c9a6c2ece6e89405d4e145e8681061726bb564736",
      "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d", "hubbard10x10", 16384, 50, 128, "mixed"):
-        {"fetch_kib": 80336727.1, "fetch_factor": 2.0, "write_kib": 128003526.8, "write_factor": 1.0},
-    ("a13badd7014ec437e4c804f31cb4dd36a43b9170bd436089374af0cb771910ae",
+        {"fetch_kib": 80298374.16, "fetch_factor": 2.0, "write_kib": 127996267.33, "write_factor": 1.0},
+    ("5af7e828dc7bc47fb823d8a564888dedd12b92e4d5c47e6577002d4f097a2631",
      "e42321a173f348e60cbd4a8c9a6c2ece6e89405d4e145e8681061726bb564736",
      "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d", "hubbard10x10:uhf", 16384, 50, 128, "fp64"):
-        {"fetch_kib": 39075371.0, "fetch_factor": 2.0, "write_kib": 48679839.5, "write_factor": 1.0},
+        {"fetch_kib": 39086717.72, "fetch_factor": 2.0, "write_kib": 48678339.64, "write_factor": 1.0},
 }
 
 
@@ -69,11 +69,11 @@ COUNTED_TRAFFIC = {
 # instruction per SIMD every 4 cycles (16 lanes): 256 CUs x 4 SIMDs x 2.4 GHz / 4.
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 COUNTED_ISSUE = {
-    ("a13badd7014ec437e4c804f31cb4dd36a43b9170bd436089374af0cb771910ae",
+    ("5af7e828dc7bc47fb823d8a564888dedd12b92e4d5c47e6577002d4f097a2631",
      "e42321a173f348e60cbd4a8c9a6c2ece6e89405d4e145e8681061726bb564736",
      "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d", "hchain20", 4096, 50, 256, "fp64"):
         {"valu_insts": 4890615390.0, "salu_insts": 2665940988.0, "lds_insts": 548790633.5,
-         "vmem_rd_insts": 168605103.5, "valu_busy_pct": 64.69},
+         "vmem_rd_insts": 168605103.5, "valu_busy_pct": 64.72},
 }
 
 
