@@ -96,10 +96,12 @@ typedef struct {
                                the other entries of its copy to zero.  The determinant then factors into
                                an alpha and a beta determinant, slot p < n_alpha holds an alpha electron,
                                B is block diagonal, R keeps each slot's own spin only ([W][Ne][n]), and a
-                               move updates the blocks of the spin it moves.  Needs at most 128 electrons of each spin and
-                               spin-conserving integrals (VMC_E_ARG otherwise); the walker state lives in
-                               HBM; no batches.  Walkers with a wrong alpha count are flagged
-                               VMC_ST_SINGULAR at initialisation. */
+                               move updates the blocks of the spin it moves.  At most 128 electrons of
+                               each spin (VMC_E_UNSUPPORTED beyond); the screened singles and doubles must
+                               keep every electron in its spin (VMC_E_ARG otherwise; integrals over
+                               spatial orbitals always do); the walker state lives in HBM; a batch refuses
+                               such a system (VMC_E_UNSUPPORTED).  Walkers with a wrong alpha count are
+                               flagged VMC_ST_SINGULAR at initialisation. */
     uint64_t seed;          /* Philox key word 0 for CTMC draws */
 } vmc_system_desc;
 
