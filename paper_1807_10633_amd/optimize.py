@@ -144,6 +144,8 @@ def _main(argv: Optional[List[str]] = None) -> int:
     ap.add_argument("--iters", type=int, default=40)
     ap.add_argument("--moves", type=int, default=50)
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
+    ap.add_argument("--orbitals", choices=("ghf", "uhf"), default="ghf",
+                    help="general or spin-blocked (unrestricted) orbitals")
     ap.add_argument("--paper-literal", action="store_true")
     ap.add_argument("--eps", type=float, default=None, help="screening threshold of the optimisation "
                     "(default: the configuration's own)")
@@ -154,7 +156,7 @@ def _main(argv: Optional[List[str]] = None) -> int:
     if not torch.cuda.is_available():
         print(json.dumps({"error": "needs a GPU"}))
         return 2
-    wl = make_config(args.config, n_walkers=args.walkers or None, eps=args.eps)
+    wl = make_config(args.config, n_walkers=args.walkers or None, eps=args.eps, orbitals=args.orbitals)
     prec = _vmc.VMC_MIXED if args.precision == "mixed" else _vmc.VMC_FP64
     system = _vmc.System.from_workload(wl, precision=prec, refresh_period=args.moves)
     walkers = system.walkers(wl.occ)
