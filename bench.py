@@ -60,6 +60,10 @@ COUNTED_TRAFFIC = {
      "e42321a173f348e60cbd4a8c9a6c2ece6e89405d4e145e8681061726bb564736",
      "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d", "hubbard10x10:uhf", 16384, 50, 128, "fp64"):
         {"fetch_kib": 39086717.72, "fetch_factor": 2.0, "write_kib": 48678339.64, "write_factor": 1.0},
+    ("5af7e828dc7bc47fb823d8a564888dedd12b92e4d5c47e6577002d4f097a2631",
+     "e42321a173f348e60cbd4a8c9a6c2ece6e89405d4e145e8681061726bb564736",
+     "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d", "hubbard10x10:uhf", 16384, 50, 128, "mixed"):
+        {"fetch_kib": 26732429.3, "fetch_factor": 2.0, "write_kib": 32659113.0, "write_factor": 1.0},
 }
 
 
