@@ -227,6 +227,11 @@ vmc_status vmc_ctmc_step_dev(vmc_handle h, vmc_walkers* w, int32_t n_steps, uint
  * else 0.  If g_dev (device, W doubles) is NULL, out_dev receives the dense
  * [W][N_p] matrix; otherwise out_dev receives G = sum_w g_w O_w (N_p doubles),
  * the contracted backward used for Eq. eq:grad with g_w = 2 t_w (E_L,w - E)/sum t.
+ * The contracted form sums over ranges of about 128 walkers (16 to 128 ranges)
+ * into partials the handle owns: the first such call for a walker count needing
+ * more ranges than any before allocates them (N_p x ranges doubles, VMC_E_OOM
+ * if that fails); later calls allocate nothing, so a caller that captures this
+ * call in a hipGraph issues it once eagerly first.  Deterministic.
  */
 vmc_status vmc_logderiv(vmc_handle h, const vmc_walkers* w, const double* g_dev, double* out_dev,
                         hipStream_t stream);
