@@ -14,8 +14,12 @@ sector (Jordan-Wigner signs counted on the bitstring).  From it:
   Eq. eloc:hci's parent expression),
 * E = <psi|H|psi>/<psi|psi> = sum_N rho_N E_L(N)  (Eq. eq:vmc),
 * the exact ground-state energy by diagonalisation,
-* psi(N) = exp(sum_{p<=q} J_pq n_p n_q) det(theta[occ(N), 0:Ne]) with numpy's
-  determinant.
+* psi(N) = C[N] exp(sum_{p<=q} J_pq n_p n_q) det(theta[occ(N), 0:Ne]) with
+  numpy's determinant, C[N] the correlator product: for each correlator (a
+  list of sites, i.e. spatial orbitals) the coefficient of the site
+  occupations it sees, read off the bitstring site by site (alpha and beta
+  occupation of site s_m giving digit n_alpha + 2 n_beta in place m of a base-4
+  number).
 """
 from __future__ import annotations
 
@@ -110,7 +114,25 @@ def jastrow_dense(J_packed: np.ndarray, n_so: int) -> np.ndarray:
     return J
 
 
-def psi_vector(theta: np.ndarray, J_packed: np.ndarray, dets: List[int], n_so: int, ne: int) -> np.ndarray:
+def correlator_product(d: int, n: int, sites, coeffs) -> float:
+    """C[N] for the bitstring d: sites is a list of site lists, coeffs a list
+    of coefficient arrays (4^len(sites[l]) each)."""
+    c = 1.0
+    for lam, vals in zip(sites, coeffs):
+        digits = []
+        for s in lam:
+            up = (d >> s) & 1
+            dn = (d >> (n + s)) & 1
+            digits.append(up + 2 * dn)
+        state = 0
+        for m in reversed(range(len(digits))):
+            state = 4 * state + digits[m]
+        c *= float(vals[state])
+    return c
+
+
+def psi_vector(theta: np.ndarray, J_packed: np.ndarray, dets: List[int], n_so: int, ne: int, cps=None) -> np.ndarray:
+    """cps: None, or (sites, coeffs) as for correlator_product."""
     J = jastrow_dense(J_packed, n_so)
     out = np.zeros(len(dets))
     for k, d in enumerate(dets):
@@ -120,6 +142,8 @@ def psi_vector(theta: np.ndarray, J_packed: np.ndarray, dets: List[int], n_so: i
             for y in range(x, len(occ)):
                 logj += J[occ[x], occ[y]]
         out[k] = np.exp(logj) * np.linalg.det(theta[np.array(occ)][:, :ne])
+        if cps is not None:
+            out[k] *= correlator_product(d, n_so // 2, cps[0], cps[1])
     return out
 
 
@@ -133,8 +157,8 @@ class BruteSystem:
         self.dets, self.index = sector_basis(n, na, nb)
         self.H = hamiltonian_matrix(h1, g, self.dets, self.index)
 
-    def psi(self, theta: np.ndarray, J_packed: np.ndarray) -> np.ndarray:
-        return psi_vector(theta, J_packed, self.dets, self.n_so, self.ne)
+    def psi(self, theta: np.ndarray, J_packed: np.ndarray, cps=None) -> np.ndarray:
+        return psi_vector(theta, J_packed, self.dets, self.n_so, self.ne, cps)
 
     def local_energies(self, psi: np.ndarray) -> np.ndarray:
         return (self.H @ psi) / psi

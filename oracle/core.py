@@ -73,6 +73,11 @@ def _load():
     lib.orc_logderiv.restype = C.c_int
     lib.orc_logderiv.argtypes = [P, P, P]
     lib.orc_ctmc_batch.argtypes = [P, C.c_int64, P, C.c_int, C.c_uint64, C.c_uint64, C.c_int, P, P, P, C.c_int]
+    lib.orc_eval_states.argtypes = [P, C.c_int64, P, C.c_int, C.c_uint64, P, P, P, P, P, P, P, C.c_int]
+    lib.orc_set_cps.restype = C.c_int64
+    lib.orc_set_cps.argtypes = [P, C.c_int, P, P]
+    lib.orc_num_cps_params.restype = C.c_int64
+    lib.orc_num_cps_params.argtypes = [P]
     _lib = lib
     return lib
 
@@ -119,6 +124,8 @@ class OracleSystem:
     def from_workload(cls, wl, eps: Optional[float] = None) -> "OracleSystem":
         s = cls(wl.n_orb, wl.n_alpha, wl.n_beta, wl.h1, wl.eri_idx, wl.eri_val, wl.eps if eps is None else eps)
         s.set_params(wl.jastrow, wl.theta)
+        if getattr(wl, "cps_sites", None) is not None and len(wl.cps_sites):
+            s.set_cps(wl.cps_sites, wl.cps_coeffs)
         return s
 
     def __del__(self):
@@ -134,6 +141,27 @@ class OracleSystem:
         assert self._J.size == self.n_so * (self.n_so + 1) // 2
         assert self._theta.shape == (self.n_so, self.n_so)
         self._lib.orc_set_params(self._h, _ptr(self._J), _ptr(self._theta))
+
+    def set_cps(self, sites, coeffs) -> int:
+        """Correlators: sites (n_corr, 5) int, spatial orbitals padded with -1;
+        coeffs: the 4^k coefficients of each correlator, concatenated.  An
+        empty site list removes the correlator factor."""
+        sites = np.ascontiguousarray(sites, dtype=np.int32).reshape(-1, 5)
+        self._cps_sites = sites
+        self._cps_coeffs = np.ascontiguousarray(coeffs, dtype=np.float64).reshape(-1)
+        n = int(self._lib.orc_set_cps(self._h, sites.shape[0], _ptr(sites), _ptr(self._cps_coeffs)))
+        if n < 0:
+            raise ValueError("malformed correlator site list")
+        if n != self._cps_coeffs.size:
+            raise ValueError(f"expected {n} correlator coefficients, got {self._cps_coeffs.size}")
+        return n
+
+    def num_cps_params(self) -> int:
+        return int(self._lib.orc_num_cps_params(self._h))
+
+    @property
+    def n_params(self) -> int:
+        return self.n_so * (self.n_so + 1) // 2 + self.n_so * self.n_so + self.num_cps_params()
 
     def num_double_entries(self) -> int:
         return int(self._lib.orc_num_double_entries(self._h))
@@ -223,8 +251,25 @@ class OracleSystem:
                                  int(threads))
         return occ, el, t, st
 
+    def eval_states(self, occ: np.ndarray, seed: int, walker, step, mode: int = ORC_LEMMA, threads: int = 0):
+        """Teacher-forced evaluation of independent states (OpenMP over states):
+        state k is occ[k] of walker walker[k] at step step[k].  Returns
+        (eloc, t, picks (n, 5), margin, rc) as orc_ctmc_step would, no move applied."""
+        occ = np.ascontiguousarray(occ, dtype=np.uint64).reshape(-1, self.nw)
+        n = occ.shape[0]
+        wk = np.ascontiguousarray(np.broadcast_to(np.asarray(walker, dtype=np.int64), (n,)))
+        sk = np.ascontiguousarray(np.broadcast_to(np.asarray(step, dtype=np.int64), (n,)))
+        el = np.zeros(n)
+        t = np.zeros(n)
+        pick = np.zeros((n, 5), dtype=np.int32)
+        margin = np.zeros(n)
+        rc = np.zeros(n, dtype=np.int32)
+        self._lib.orc_eval_states(self._h, n, _ptr(occ), mode, seed, _ptr(wk), _ptr(sk), _ptr(el), _ptr(t),
+                                  _ptr(pick), _ptr(margin), _ptr(rc), int(threads))
+        return el, t, pick, margin, rc
+
     def logderiv(self, occ) -> np.ndarray:
-        n_p = self.n_so * (self.n_so + 1) // 2 + self.n_so * self.n_so
+        n_p = self.n_params
         out = np.zeros(n_p)
         rc = self._lib.orc_logderiv(self._h, _ptr(self._bits(occ)), _ptr(out))
         if rc != 0:

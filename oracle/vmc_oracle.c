@@ -8,9 +8,13 @@
  * What it computes, each from its plain definition (Sabzevari & Sharma,
  * "Improved speed and scaling in orbital space variational Monte Carlo"):
  *
- *  - psi(N) = exp(sum_{p<=q} J_pq n_p n_q) * det(theta[occ(N), 0:Ne])
- *    (Jastrow reading of the correlator factor times the Slater determinant of
- *    the section "Correlator product states and Slater determinant").
+ *  - psi(N) = C[N] * exp(sum_{p<=q} J_pq n_p n_q) * det(theta[occ(N), 0:Ne])
+ *    (section "Correlator product states and Slater determinant"): C[N] is the
+ *    product over correlators l of the coefficient c_l[n_l(N)] of the local
+ *    Fock state n_l(N) of the correlator's sites (spatial orbitals s_0..s_{k-1},
+ *    k <= 5, n_l = sum_m (n_{s_m alpha} + 2 n_{s_m beta}) 4^m); no correlators
+ *    means C = 1.  The Jastrow factor is the two-site correlator written on
+ *    spin-orbitals (c_11 = e^J).
  *  - E_L[N, eps] = sum over M with |H_NM| above the screening threshold of
  *    H_NM psi(M)/psi(N), with the diagonal M = N always included (Eq. eloc:hci).
  *      singles: kept when S_ia = |h_ia| + sum_j |(ia|jj) - (ij|ja)| > eps
@@ -25,12 +29,17 @@
  *                  single is R_ai = sum_x theta_ax (theta[N]^-1)_xi and of a double
  *                  the 2x2 minor R_ai R_bj - R_bi R_aj (Eq. R and the text after
  *                  it), with the sign of the permutation that sorts M.
- *    The Jastrow factor ratio is recomputed from scratch in both modes.
+ *    The correlator ratio C[M]/C[N] is the ratio of the two products, each
+ *    taken over every correlator, in both modes.  The Jastrow ratio is
+ *    recomputed from scratch in ORC_DET; in ORC_LEMMA it is the change of the
+ *    quadratic form sum_{p<=q} J_pq n_p n_q written out with the occupation
+ *    change D = n(M) - n(N):  D.(J n) + (D.J D)/2 + sum_p J_pp D_p / 2.
  *  - CTMC (section "Continuous time Monte Carlo"): rates r = |psi(M)/psi(N)|
  *    over the same screened set, residence time t = 1/sum r, pick the smallest k
  *    whose running sum exceeds u*T, u from Philox4x64-10.
  *  - Gradient ratios (section "Local energy and Gradient ratios"):
- *    O_{J_pq} = n_p n_q and O_{theta_kx} = (theta[N]^-1)_{x, pos(k)}.
+ *    O_{J_pq} = n_p n_q, O_{theta_kx} = (theta[N]^-1)_{x, pos(k)} and
+ *    O_{c_l[n]} = [n_l(N) = n] / c_l[n].
  *
  * Canonical candidate order: singles first (occupied i ascending, then a by
  * descending S_ia, ties by a), then doubles (occupied pairs i<j ascending
@@ -75,6 +84,13 @@ typedef struct {
     orc_dentry* d_ent;
     double* J;       /* n_so*n_so symmetric */
     double* theta;   /* n_so*n_so row-major */
+    /* correlator product state: n_corr correlators of ck[l] <= 5 sites
+     * csite[5 l + m] (spatial orbitals), coefficients cc[coff[l] + n] */
+    int n_corr;
+    int* ck;
+    int* csite;
+    int64_t* coff;
+    double* cc;
 } orc_sys;
 
 /* ---------------------------------------------------------------- indices */
@@ -212,6 +228,32 @@ static double log_jastrow(const orc_sys* s, const int* occ, int m) {
     return acc;
 }
 
+/* local Fock state of correlator l in the determinant occ_bits */
+static int64_t cps_state(const orc_sys* s, int l, const uint64_t* occ_bits) {
+    int64_t idx = 0, w = 1;
+    for (int m = 0; m < s->ck[l]; ++m) {
+        int site = s->csite[5 * l + m];
+        idx += w * (occ_test(occ_bits, site) + 2 * occ_test(occ_bits, s->n + site));
+        w *= 4;
+    }
+    return idx;
+}
+
+/* log|C[N]| over every correlator; *sign receives the sign (0 if a
+ * coefficient is zero) */
+static double log_cps(const orc_sys* s, const uint64_t* occ_bits, int* sign) {
+    double acc = 0.0;
+    int sg = 1;
+    for (int l = 0; l < s->n_corr; ++l) {
+        double c = s->cc[s->coff[l] + cps_state(s, l, occ_bits)];
+        if (c == 0.0) { *sign = 0; return -INFINITY; }
+        if (c < 0.0) sg = -sg;
+        acc += log(fabs(c));
+    }
+    *sign = sg;
+    return acc;
+}
+
 /* ------------------------------------------------------------------ create */
 orc_sys* orc_create(int n, int na, int nb, const double* h1, int64_t n_eri, const int32_t* eri_idx,
                     const double* eri_val, double eps) {
@@ -299,6 +341,7 @@ orc_sys* orc_create(int n, int na, int nb, const double* h1, int64_t n_eri, cons
 void orc_destroy(orc_sys* s) {
     if (!s) return;
     free(s->h1); free(s->eri); free(s->S); free(s->d_off); free(s->d_ent); free(s->J); free(s->theta);
+    free(s->ck); free(s->csite); free(s->coff); free(s->cc);
     free(s);
 }
 
@@ -316,6 +359,40 @@ void orc_set_params(orc_sys* s, const double* J_packed, const double* theta) {
         }
     memcpy(s->theta, theta, sizeof(double) * nso * nso);
 }
+
+/* Correlators: n_corr of them, correlator l on the sites[5 l + m] (m < k,
+ * k = number of entries >= 0 before the first -1, at most 5, distinct spatial
+ * orbitals), with 4^k coefficients each, concatenated in coeffs.  n_corr = 0
+ * removes the correlator factor.  Returns the number of coefficients, or -1
+ * on a malformed site list. */
+int64_t orc_set_cps(orc_sys* s, int n_corr, const int32_t* sites, const double* coeffs) {
+    free(s->ck); free(s->csite); free(s->coff); free(s->cc);
+    s->ck = NULL; s->csite = NULL; s->coff = NULL; s->cc = NULL;
+    s->n_corr = 0;
+    if (n_corr <= 0) return 0;
+    s->ck = (int*)calloc((size_t)n_corr, sizeof(int));
+    s->csite = (int*)malloc(sizeof(int) * 5 * (size_t)n_corr);
+    s->coff = (int64_t*)calloc((size_t)n_corr + 1, sizeof(int64_t));
+    for (int l = 0; l < n_corr; ++l) {
+        int k = 0;
+        while (k < 5 && sites[5 * l + k] >= 0) ++k;
+        if (k == 0) return -1;
+        for (int m = 0; m < 5; ++m) s->csite[5 * l + m] = (m < k) ? sites[5 * l + m] : -1;
+        for (int m = 0; m < k; ++m) {
+            if (sites[5 * l + m] >= s->n) return -1;
+            for (int m2 = 0; m2 < m; ++m2)
+                if (sites[5 * l + m2] == sites[5 * l + m]) return -1;
+        }
+        s->ck[l] = k;
+        s->coff[l + 1] = s->coff[l] + ((int64_t)1 << (2 * k));
+    }
+    s->cc = (double*)malloc(sizeof(double) * (size_t)s->coff[n_corr]);
+    memcpy(s->cc, coeffs, sizeof(double) * (size_t)s->coff[n_corr]);
+    s->n_corr = n_corr;
+    return s->coff[n_corr];
+}
+
+int64_t orc_num_cps_params(const orc_sys* s) { return s->n_corr ? s->coff[s->n_corr] : 0; }
 
 /* singles bound table, for inspection: out[n_so*n_so] */
 void orc_singles_bound(const orc_sys* s, double* out) {
@@ -375,9 +452,11 @@ double orc_log_psi(const orc_sys* s, const uint64_t* occ_bits, int* sign_out) {
     int sg = 0;
     double ld = (m == s->ne) ? slater_logdet(s, occ, &sg, work, perm) : -INFINITY;
     double lj = log_jastrow(s, occ, m);
+    int sc = 1;
+    double lc = log_cps(s, occ_bits, &sc);
     free(occ); free(work); free(perm);
-    *sign_out = sg;
-    return ld + lj;
+    *sign_out = sg * sc;
+    return ld + lj + lc;
 }
 
 /* ----------------------------------------------------------- local energy */
@@ -397,13 +476,17 @@ typedef struct {
     /* scratch for one walker */
     int* occ;
     int* occ_m;
+    int* iwork;     /* 2 ne ints for the parity count */
     double* work;
     double* work2;
     int* perm;
     double* Binv;   /* ne x ne inverse of theta[N] (lemma mode) */
     double* R;      /* n_so x ne */
+    double* v;      /* n_so: (J n)_p = sum_{q occupied} J_pq (lemma mode) */
     orc_sentry* sl;
     orc_dentry* dl;
+    orc_cand* cand; /* candidates of the last evaluation, when stored */
+    int64_t cand_cap;
 } orc_ws;
 
 static orc_ws* ws_alloc(const orc_sys* s) {
@@ -411,11 +494,13 @@ static orc_ws* ws_alloc(const orc_sys* s) {
     int ne = s->ne, nso = s->n_so;
     w->occ = (int*)malloc(sizeof(int) * nso);
     w->occ_m = (int*)malloc(sizeof(int) * nso);
+    w->iwork = (int*)malloc(sizeof(int) * 2 * ne + 8);
     w->work = (double*)malloc(sizeof(double) * ne * ne + 8);
     w->work2 = (double*)malloc(sizeof(double) * ne + 8);
     w->perm = (int*)malloc(sizeof(int) * ne + 8);
     w->Binv = (double*)malloc(sizeof(double) * ne * ne + 8);
     w->R = (double*)malloc(sizeof(double) * nso * ne + 8);
+    w->v = (double*)malloc(sizeof(double) * nso + 8);
     w->sl = (orc_sentry*)malloc(sizeof(orc_sentry) * nso + 8);
     int64_t maxrow = 0;
     for (int64_t k = 0; k < (int64_t)nso * nso; ++k) {
@@ -426,23 +511,49 @@ static orc_ws* ws_alloc(const orc_sys* s) {
     return w;
 }
 static void ws_free(orc_ws* w) {
-    free(w->occ); free(w->occ_m); free(w->work); free(w->work2); free(w->perm); free(w->Binv);
-    free(w->R); free(w->sl); free(w->dl); free(w);
+    free(w->occ); free(w->occ_m); free(w->iwork); free(w->work); free(w->work2); free(w->perm); free(w->Binv);
+    free(w->R); free(w->v); free(w->sl); free(w->dl); free(w->cand); free(w);
 }
 
-/* parity (+1/-1) of the permutation that sorts rows[0..m-1] ascending */
-static int sort_parity(const int* rows, int m) {
-    int inv = 0;
-    for (int x = 0; x < m; ++x)
-        for (int y = x + 1; y < m; ++y)
-            if (rows[x] > rows[y]) ++inv;
-    return (inv & 1) ? -1 : 1;
+/* number of inversions of a[0..m-1] (pairs x < y with a[x] > a[y]), counted
+ * while merge-sorting it in place; tmp holds m ints */
+static int64_t count_inversions(int* a, int* tmp, int m) {
+    if (m < 2) return 0;
+    int h = m / 2;
+    int64_t inv = count_inversions(a, tmp, h) + count_inversions(a + h, tmp, m - h);
+    int x = 0, y = h, k = 0;
+    while (x < h && y < m) {
+        if (a[y] < a[x]) { inv += h - x; tmp[k++] = a[y++]; }
+        else tmp[k++] = a[x++];
+    }
+    while (x < h) tmp[k++] = a[x++];
+    while (y < m) tmp[k++] = a[y++];
+    memcpy(a, tmp, sizeof(int) * (size_t)m);
+    return inv;
 }
 
-/* psi(M)/psi(N) where M is described by its unsorted row list occ_m (N's list
- * with replaced entries), in the sorted-determinant convention. */
-static double ratio_det(const orc_sys* s, orc_ws* w, const int* occ_m_unsorted, double logdetN, int signN,
-                        double logjN) {
+/* parity (+1/-1) of the permutation that sorts rows[0..m-1] ascending: the
+ * parity of its inversion count; work holds 2m ints */
+static int sort_parity(const int* rows, int m, int* work) {
+    memcpy(work, rows, sizeof(int) * (size_t)m);
+    return (count_inversions(work, work + m, m) & 1) ? -1 : 1;
+}
+
+static void store_cand(orc_ws* w, int64_t k, int type, int i, int j, int a, int b, double h, double ratio) {
+    if (k >= w->cand_cap) {
+        int64_t cap = w->cand_cap ? 2 * w->cand_cap : 4096;
+        while (cap <= k) cap *= 2;
+        w->cand = (orc_cand*)realloc(w->cand, sizeof(orc_cand) * (size_t)cap);
+        w->cand_cap = cap;
+    }
+    orc_cand* c = w->cand + k;
+    c->type = type; c->i = i; c->j = j; c->a = a; c->b = b; c->h = h; c->ratio = ratio;
+}
+
+/* psi(M)/psi(N) from scratch: M given by its unsorted row list (N's list with
+ * replaced entries) and its occupation bits; sorted-determinant convention. */
+static double ratio_det(const orc_sys* s, orc_ws* w, const int* occ_m_unsorted, const uint64_t* bits_m,
+                        double logN, int signN) {
     int m = s->ne;
     int* sorted = w->occ_m;
     memcpy(sorted, occ_m_unsorted, sizeof(int) * m);
@@ -452,28 +563,48 @@ static double ratio_det(const orc_sys* s, orc_ws* w, const int* occ_m_unsorted, 
         while (y >= 0 && sorted[y] > v) { sorted[y + 1] = sorted[y]; --y; }
         sorted[y + 1] = v;
     }
-    int sg;
+    int sg, sc;
     double ld = slater_logdet(s, sorted, &sg, w->work, w->perm);
     if (sg == 0) return 0.0;
+    double lc = log_cps(s, bits_m, &sc);
+    if (sc == 0) return 0.0;
     double lj = log_jastrow(s, sorted, m);
-    return (double)(sg * signN) * exp(ld - logdetN + lj - logjN);
+    return (double)(sg * sc * signN) * exp(ld + lj + lc - logN);
+}
+
+/* Change of the Jastrow exponent sum_{p<=q} J_pq n_p n_q when the occupation
+ * changes by D (entries d[k] = +-1 at orbitals o[k], k < nd): with n the
+ * occupation of N and v = J n, the quadratic form changes by
+ * D.v + (D.J D)/2 + sum_p J_pp D_p / 2 (symmetric J, n_p^2 = n_p). */
+static double jastrow_change(const orc_sys* s, const double* v, const int* o, const int* d, int nd) {
+    int nso = s->n_so;
+    double lin = 0.0, quad = 0.0, diag = 0.0;
+    for (int k = 0; k < nd; ++k) {
+        lin += d[k] * v[o[k]];
+        diag += d[k] * s->J[o[k] * nso + o[k]];
+        for (int l = 0; l < nd; ++l) quad += d[k] * d[l] * s->J[o[k] * nso + o[l]];
+    }
+    return lin + 0.5 * quad + 0.5 * diag;
 }
 
 /*
- * Local energy of one walker.  Writes E_L, T = sum of rates, the number of
- * candidates, and (if cand != NULL) up to cap candidates in canonical order.
- * Returns 0 on success, -1 if psi(N) = 0.
+ * Local energy of one walker.  Writes E_L, T = sum of rates and the number of
+ * candidates; with `store` the candidates are kept in w->cand in canonical
+ * order.  Returns 0 on success, -1 if psi(N) = 0, -2 for a wrong electron count.
  */
 static int eloc_one(const orc_sys* s, orc_ws* w, const uint64_t* occ_bits, int mode, double* eloc_out,
-                    double* T_out, int64_t* ncand_out, orc_cand* cand, int64_t cap, double* hnn_out) {
+                    double* T_out, int64_t* ncand_out, int store, double* hnn_out) {
     int nso = s->n_so, ne = s->ne;
     int m = occ_list(s, occ_bits, w->occ);
     if (m != ne) return -2;
     int* occ = w->occ;
-    int signN;
+    int signN, signC;
     double logdetN = slater_logdet(s, occ, &signN, w->work, w->perm);
     if (signN == 0) return -1;
+    double logcN = log_cps(s, occ_bits, &signC);
+    if (signC == 0) return -1;
     double logjN = log_jastrow(s, occ, ne);
+    double logN = logdetN + logjN + logcN;
     if (mode == ORC_LEMMA) {
         /* fresh inverse of theta[N] and R = theta[:, 0:ne] theta[N]^-1 */
         for (int r = 0; r < ne; ++r)
@@ -487,6 +618,12 @@ static int eloc_one(const orc_sys* s, orc_ws* w, const uint64_t* occ_bits, int m
                 for (int x = 0; x < ne; ++x) acc += s->theta[a * nso + x] * w->Binv[x * ne + p];
                 w->R[a * ne + p] = acc;
             }
+        /* v = J n(N) for the Jastrow change */
+        for (int p = 0; p < nso; ++p) {
+            double acc = 0.0;
+            for (int y = 0; y < ne; ++y) acc += s->J[p * nso + occ[y]];
+            w->v[p] = acc;
+        }
     }
     double hnn = h_diag(s, occ, ne);
     double el = hnn, T = 0.0;
@@ -505,7 +642,7 @@ static int eloc_one(const orc_sys* s, orc_ws* w, const uint64_t* occ_bits, int m
         qsort(w->sl, (size_t)ns, sizeof(orc_sentry), cmp_sentry);
         for (int k = 0; k < ns; ++k) {
             int a = w->sl[k].a;
-            /* sign of a_a^dagger a_i applied to |N> */
+            /* sign of a_a^dagger a_i applied to |N>; bits becomes M */
             memcpy(bits, occ_bits, sizeof(uint64_t) * s->nw);
             int g = apply_annihilate(bits, i);
             g *= apply_create(bits, a);
@@ -520,24 +657,18 @@ static int eloc_one(const orc_sys* s, orc_ws* w, const uint64_t* occ_bits, int m
             memcpy(rows, occ, sizeof(int) * ne);
             rows[x] = a;
             if (mode == ORC_DET) {
-                ratio = ratio_det(s, w, rows, logdetN, signN, logjN);
+                ratio = ratio_det(s, w, rows, bits, logN, signN * signC);
             } else {
-                double detr = w->R[a * ne + x] * (double)sort_parity(rows, ne);
-                /* Jastrow ratio from scratch */
-                memcpy(w->occ_m, rows, sizeof(int) * ne);
-                for (int u = 1; u < ne; ++u) {
-                    int v = w->occ_m[u], z = u - 1;
-                    while (z >= 0 && w->occ_m[z] > v) { w->occ_m[z + 1] = w->occ_m[z]; --z; }
-                    w->occ_m[z + 1] = v;
-                }
-                ratio = detr * exp(log_jastrow(s, w->occ_m, ne) - logjN);
+                double detr = w->R[a * ne + x] * (double)sort_parity(rows, ne, w->iwork);
+                int o[2] = {a, i}, d[2] = {1, -1};
+                int sc;
+                double lc = log_cps(s, bits, &sc);
+                double cr = (sc == 0) ? 0.0 : (double)(sc * signC) * exp(lc - logcN);
+                ratio = detr * cr * exp(jastrow_change(s, w->v, o, d, 2));
             }
             el += hel * ratio;
             T += fabs(ratio);
-            if (cand && nc < cap) {
-                orc_cand* c = cand + nc;
-                c->type = 1; c->i = i; c->j = -1; c->a = a; c->b = -1; c->h = hel; c->ratio = ratio;
-            }
+            if (store) store_cand(w, nc, 1, i, -1, a, -1, hel, ratio);
             ++nc;
         }
     }
@@ -545,12 +676,12 @@ static int eloc_one(const orc_sys* s, orc_ws* w, const uint64_t* occ_bits, int m
     for (int x = 0; x < ne; ++x)
         for (int y = x + 1; y < ne; ++y) {
             int i = occ[x], j = occ[y];
-            int64_t o = s->d_off[i * nso + j], e = s->d_off[i * nso + j + 1];
+            int64_t o0 = s->d_off[i * nso + j], e = s->d_off[i * nso + j + 1];
             int nd = 0;
-            for (int64_t k = o; k < e; ++k) {
-                const orc_dentry* d = s->d_ent + k;
-                if (occ_test(occ_bits, d->a) || occ_test(occ_bits, d->b)) continue;
-                w->dl[nd++] = *d;
+            for (int64_t k = o0; k < e; ++k) {
+                const orc_dentry* dd = s->d_ent + k;
+                if (occ_test(occ_bits, dd->a) || occ_test(occ_bits, dd->b)) continue;
+                w->dl[nd++] = *dd;
             }
             qsort(w->dl, (size_t)nd, sizeof(orc_dentry), cmp_dentry);
             for (int k = 0; k < nd; ++k) {
@@ -567,24 +698,19 @@ static int eloc_one(const orc_sys* s, orc_ws* w, const uint64_t* occ_bits, int m
                 rows[x] = a;
                 rows[y] = b;
                 if (mode == ORC_DET) {
-                    ratio = ratio_det(s, w, rows, logdetN, signN, logjN);
+                    ratio = ratio_det(s, w, rows, bits, logN, signN * signC);
                 } else {
                     double minor = w->R[a * ne + x] * w->R[b * ne + y] - w->R[b * ne + x] * w->R[a * ne + y];
-                    double detr = minor * (double)sort_parity(rows, ne);
-                    memcpy(w->occ_m, rows, sizeof(int) * ne);
-                    for (int u = 1; u < ne; ++u) {
-                        int v = w->occ_m[u], z = u - 1;
-                        while (z >= 0 && w->occ_m[z] > v) { w->occ_m[z + 1] = w->occ_m[z]; --z; }
-                        w->occ_m[z + 1] = v;
-                    }
-                    ratio = detr * exp(log_jastrow(s, w->occ_m, ne) - logjN);
+                    double detr = minor * (double)sort_parity(rows, ne, w->iwork);
+                    int o[4] = {a, b, i, j}, d[4] = {1, 1, -1, -1};
+                    int sc;
+                    double lc = log_cps(s, bits, &sc);
+                    double cr = (sc == 0) ? 0.0 : (double)(sc * signC) * exp(lc - logcN);
+                    ratio = detr * cr * exp(jastrow_change(s, w->v, o, d, 4));
                 }
                 el += hel * ratio;
                 T += fabs(ratio);
-                if (cand && nc < cap) {
-                    orc_cand* c = cand + nc;
-                    c->type = 2; c->i = i; c->j = j; c->a = a; c->b = b; c->h = hel; c->ratio = ratio;
-                }
+                if (store) store_cand(w, nc, 2, i, j, a, b, hel, ratio);
                 ++nc;
             }
         }
@@ -599,7 +725,9 @@ static int eloc_one(const orc_sys* s, orc_ws* w, const uint64_t* occ_bits, int m
 int orc_local_energy(const orc_sys* s, const uint64_t* occ_bits, int mode, double* eloc, double* T,
                      int64_t* ncand, orc_cand* cand, int64_t cap, double* hnn) {
     orc_ws* w = ws_alloc(s);
-    int rc = eloc_one(s, w, occ_bits, mode, eloc, T, ncand, cand, cap, hnn);
+    int rc = eloc_one(s, w, occ_bits, mode, eloc, T, ncand, cand != NULL, hnn);
+    if (rc == 0 && cand)
+        for (int64_t k = 0; k < *ncand && k < cap; ++k) cand[k] = w->cand[k];
     ws_free(w);
     return rc;
 }
@@ -616,7 +744,7 @@ void orc_local_energy_batch(const orc_sys* s, int64_t nwalk, const uint64_t* occ
 #pragma omp for schedule(dynamic)
         for (int64_t k = 0; k < nwalk; ++k) {
             int64_t nc = 0;
-            status[k] = eloc_one(s, w, occ_bits + k * s->nw, mode, eloc + k, T + k, &nc, NULL, 0, NULL);
+            status[k] = eloc_one(s, w, occ_bits + k * s->nw, mode, eloc + k, T + k, &nc, 0, NULL);
             ncand[k] = nc;
         }
         ws_free(w);
@@ -658,42 +786,31 @@ double orc_uniform(uint64_t seed, uint64_t walker, uint64_t step) {
 }
 
 /* -------------------------------------------------------------------- CTMC */
-/*
- * One CTMC move of walker `walker` at step `step`: computes E_L and the rates
- * over the screened connected set, t = 1/T, draws u and picks the smallest
- * candidate index k whose running sum exceeds u*T.  occ_bits is updated in
- * place.  pick_out = {type, i, j, a, b} (type 0 = no move), margin_out = the
- * smallest |u*T - C_k| / T over all running sums C_k.
- * Returns 0, or a negative code when psi(N) = 0 or the set is empty.
- */
-int orc_ctmc_step(const orc_sys* s, uint64_t* occ_bits, int mode, uint64_t seed, uint64_t walker, uint64_t step,
-                  double* eloc, double* tres, int32_t* pick_out, double* margin_out) {
-    orc_ws* w = ws_alloc(s);
-    int64_t cap = 0;
-    /* first pass counts the candidates */
+/* The CTMC move of one state (section "Continuous time Monte Carlo"): E_L and
+ * the rates r = |psi(M)/psi(N)| over the screened connected set, t = 1/T,
+ * u from Philox, the smallest candidate index k whose running sum exceeds u*T
+ * (the last positive-rate candidate if rounding leaves none).  Nothing is
+ * changed; pick_out = {type, i, j, a, b} (type 0 = no move), *margin_out = the
+ * smallest |u*T - C_k| / T over the running sums C_k. */
+static int ctmc_eval(const orc_sys* s, orc_ws* w, const uint64_t* occ_bits, int mode, uint64_t seed,
+                     uint64_t walker, uint64_t step, double* eloc, double* tres, int32_t* pick_out,
+                     double* margin_out) {
     double el, T;
     int64_t nc;
-    int rc = eloc_one(s, w, occ_bits, mode, &el, &T, &nc, NULL, 0, NULL);
-    if (rc != 0) { ws_free(w); return rc; }
-    cap = nc;
-    orc_cand* cand = (orc_cand*)malloc(sizeof(orc_cand) * (size_t)(cap + 1));
-    eloc_one(s, w, occ_bits, mode, &el, &T, &nc, cand, cap, NULL);
-    *eloc = el;
     pick_out[0] = 0; pick_out[1] = pick_out[2] = pick_out[3] = pick_out[4] = -1;
-    if (!(T > 0.0)) {
-        *tres = 0.0;
-        *margin_out = 0.0;
-        free(cand);
-        ws_free(w);
-        return -3;
-    }
+    *tres = 0.0;
+    *margin_out = 0.0;
+    int rc = eloc_one(s, w, occ_bits, mode, &el, &T, &nc, 1, NULL);
+    if (rc != 0) return rc;
+    *eloc = el;
+    if (!(T > 0.0)) return -3;
     *tres = 1.0 / T;
     double u = orc_uniform(seed, walker, step);
     double target = u * T;
     double run = 0.0, margin = INFINITY;
     int64_t pick = -1, last_pos = -1;
     for (int64_t k = 0; k < nc; ++k) {
-        double r = fabs(cand[k].ratio);
+        double r = fabs(w->cand[k].ratio);
         if (r > 0.0) last_pos = k;
         run += r;
         double d = fabs(target - run);
@@ -702,22 +819,61 @@ int orc_ctmc_step(const orc_sys* s, uint64_t* occ_bits, int mode, uint64_t seed,
     }
     if (pick < 0) pick = last_pos;
     *margin_out = margin / T;
-    orc_cand* c = cand + pick;
+    const orc_cand* c = w->cand + pick;
     pick_out[0] = c->type; pick_out[1] = c->i; pick_out[2] = c->j; pick_out[3] = c->a; pick_out[4] = c->b;
-    occ_clr(occ_bits, c->i);
-    occ_set(occ_bits, c->a);
-    if (c->type == 2) { occ_clr(occ_bits, c->j); occ_set(occ_bits, c->b); }
-    free(cand);
-    ws_free(w);
     return 0;
+}
+
+/*
+ * One CTMC move of walker `walker` at step `step` (ctmc_eval), applied to
+ * occ_bits in place.  Returns 0, or a negative code when psi(N) = 0 or the
+ * set is empty.
+ */
+int orc_ctmc_step(const orc_sys* s, uint64_t* occ_bits, int mode, uint64_t seed, uint64_t walker, uint64_t step,
+                  double* eloc, double* tres, int32_t* pick_out, double* margin_out) {
+    orc_ws* w = ws_alloc(s);
+    int rc = ctmc_eval(s, w, occ_bits, mode, seed, walker, step, eloc, tres, pick_out, margin_out);
+    if (rc == 0) {
+        occ_clr(occ_bits, pick_out[1]);
+        occ_set(occ_bits, pick_out[3]);
+        if (pick_out[0] == 2) { occ_clr(occ_bits, pick_out[2]); occ_set(occ_bits, pick_out[4]); }
+    }
+    ws_free(w);
+    return rc;
+}
+
+/* Teacher-forced evaluation of n independent states (OpenMP over states):
+ * state k is the determinant occ_bits[k] of walker walker[k] at step step[k];
+ * each gets its E_L, t, pick and margin as from orc_ctmc_step, without any
+ * move being applied.  rc[k] = the return code. */
+void orc_eval_states(const orc_sys* s, int64_t n, const uint64_t* occ_bits, int mode, uint64_t seed,
+                     const int64_t* walker, const int64_t* step, double* eloc, double* tres, int32_t* pick,
+                     double* margin, int32_t* rc, int nthreads) {
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel
+    {
+        orc_ws* w = ws_alloc(s);
+#pragma omp for schedule(dynamic)
+        for (int64_t k = 0; k < n; ++k) {
+            eloc[k] = NAN;
+            rc[k] = ctmc_eval(s, w, occ_bits + k * s->nw, mode, seed, (uint64_t)walker[k], (uint64_t)step[k],
+                              eloc + k, tres + k, pick + 5 * k, margin + k);
+        }
+        ws_free(w);
+    }
 }
 
 /* ---------------------------------------------------------- gradient ratios */
 /*
- * O_k for one walker, length n_so(n_so+1)/2 + n_so*n_so:
+ * O_k for one walker, length n_so(n_so+1)/2 + n_so*n_so (+ the correlator
+ * coefficients when correlators are set):
  *   Jastrow part (packed p<=q): n_p n_q;
  *   orbital part theta_kx (row-major): (theta[N]^-1)_{x, pos(k)} for occupied k
- *   and x < Ne, zero otherwise; pos(k) = row of k in the sorted theta[N].
+ *   and x < Ne, zero otherwise; pos(k) = row of k in the sorted theta[N];
+ *   correlator part c_l[n]: 1/c_l[n] where n is the correlator's local Fock
+ *   state in N, zero elsewhere.
  */
 int orc_logderiv(const orc_sys* s, const uint64_t* occ_bits, double* out) {
     int nso = s->n_so, ne = s->ne;
@@ -743,6 +899,14 @@ int orc_logderiv(const orc_sys* s, const uint64_t* occ_bits, double* out) {
         for (int r = 0; r < ne; ++r)
             for (int x = 0; x < ne; ++x) th[occ[r] * nso + x] = Ainv[x * ne + r];
     }
+    if (s->n_corr) {
+        double* oc = th + (int64_t)nso * nso;
+        memset(oc, 0, sizeof(double) * (size_t)s->coff[s->n_corr]);
+        for (int l = 0; l < s->n_corr; ++l) {
+            int64_t e = s->coff[l] + cps_state(s, l, occ_bits);
+            oc[e] = 1.0 / s->cc[e];
+        }
+    }
     free(occ); free(A); free(Ainv); free(col); free(perm);
     return sg == 0 ? -1 : 0;
 }
@@ -754,15 +918,24 @@ void orc_ctmc_batch(const orc_sys* s, int64_t nwalk, uint64_t* occ_bits, int mod
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #endif
-#pragma omp parallel for schedule(dynamic)
-    for (int64_t k = 0; k < nwalk; ++k) {
-        int32_t pick[5];
-        double margin;
-        status[k] = 0;
-        for (int st = 0; st < n_steps; ++st) {
-            int rc = orc_ctmc_step(s, occ_bits + k * s->nw, mode, seed, (uint64_t)k, step0 + (uint64_t)st,
-                                   eloc + k * n_steps + st, tres + k * n_steps + st, pick, &margin);
-            if (rc != 0) { status[k] = rc; break; }
+#pragma omp parallel
+    {
+        orc_ws* w = ws_alloc(s);
+#pragma omp for schedule(dynamic)
+        for (int64_t k = 0; k < nwalk; ++k) {
+            int32_t pick[5];
+            double margin;
+            uint64_t* bits = occ_bits + k * s->nw;
+            status[k] = 0;
+            for (int st = 0; st < n_steps; ++st) {
+                int rc = ctmc_eval(s, w, bits, mode, seed, (uint64_t)k, step0 + (uint64_t)st, eloc + k * n_steps + st,
+                                   tres + k * n_steps + st, pick, &margin);
+                if (rc != 0) { status[k] = rc; break; }
+                occ_clr(bits, pick[1]);
+                occ_set(bits, pick[3]);
+                if (pick[0] == 2) { occ_clr(bits, pick[2]); occ_set(bits, pick[4]); }
+            }
         }
+        ws_free(w);
     }
 }

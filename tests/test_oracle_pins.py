@@ -381,6 +381,51 @@ def test_amsgrad_closed_form_constant_gradient():
         p = p_new
 
 
+def test_amsgrad_paper_literal_closed_form_constant_gradient():
+    """Paper-literal second moment n <- max(n, b2 n + (1-b2) g^2) (Eq. eq:m2
+    with the paper's beta' = 1 - beta): for a constant gradient the moving
+    average never falls below n, so n_t = g^2 (1 - b2^t), m_t = g (1 - b1^t)."""
+    g = np.array([0.3, -2.0, 1e-3, 7.5])
+    b1, b2, lr = 0.9, 0.99, 1e-2
+    opt = AMSGrad(4, lr=lr, beta1=b1, beta2=b2, paper_literal=True)
+    p = np.zeros(4)
+    for t in range(1, 12):
+        p_new = opt.step(p, g)
+        m = g * (1 - b1 ** t)
+        n = g * g * (1 - b2 ** t)
+        assert np.allclose(opt.m, m, rtol=1e-14)
+        assert np.allclose(opt.vhat, n, rtol=1e-14)
+        assert np.allclose(p_new - p, -lr * m / (np.sqrt(n) + 1e-8), rtol=1e-13)
+        p = p_new
+
+
+def test_amsgrad_forms_differ_where_the_max_sits():
+    """A gradient G at step 1, zero for k steps, then H.  Written out by hand:
+    paper-literal (EMA of the maxed n): n = (1-b2) G^2 through the zeros, then
+    max(n, b2 n + (1-b2) H^2).  Reddi form (EMA v kept apart, vhat = max):
+    v = b2^k (1-b2) G^2 after the zeros, then b2 v + (1-b2) H^2, vhat the
+    larger of that and (1-b2) G^2.  The two differ, which pins where each
+    branch takes the maximum."""
+    b1, b2, G, H, k = 0.9, 0.99, 1.0, 1.0, 200
+    seq = [G] + [0.0] * k + [H]
+    lit = AMSGrad(1, beta1=b1, beta2=b2, paper_literal=True)
+    red = AMSGrad(1, beta1=b1, beta2=b2, paper_literal=False)
+    p = np.zeros(1)
+    for x in seq:
+        lit.step(p, np.array([x]))
+        red.step(p, np.array([x]))
+    n1 = (1 - b2) * G * G
+    lit_ref = max(n1, b2 * n1 + (1 - b2) * H * H)
+    v_ref = b2 ** (k + 1) * (1 - b2) * G * G + (1 - b2) * H * H
+    red_ref = max(n1, v_ref)
+    assert lit.vhat[0] == pytest.approx(lit_ref, rel=1e-13)
+    assert red.vhat[0] == pytest.approx(red_ref, rel=1e-13)
+    assert red.v[0] == pytest.approx(v_ref, rel=1e-13)
+    assert abs(lit_ref - red_ref) > 1e-3  # the sequence separates the forms
+    m_ref = b1 ** (k + 1) * (1 - b1) * G + (1 - b1) * H
+    assert lit.m[0] == pytest.approx(m_ref, rel=1e-13) and red.m[0] == pytest.approx(m_ref, rel=1e-13)
+
+
 def test_amsgrad_second_moment_is_monotone():
     rng = np.random.default_rng(0)
     for literal in (False, True):

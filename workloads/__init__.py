@@ -19,6 +19,9 @@ Conventions shared by every consumer of these inputs
   column = molecular orbital); the determinant uses columns 0..N_e-1.
 * Occupations are little-endian bitstrings in 64-bit words, ceil(n_so/64) words
   per walker.
+* Correlators (optional): each is a list of at most five sites (spatial
+  orbitals), passed as an (n_corr, 5) int32 array padded with -1, with the 4^k
+  coefficients of each correlator concatenated in correlator order.
 
 The Hubbard and H-chain-like models stand in for the paper's benchmark systems
 (2-D Hubbard lattices and sto-6g hydrogen chains), whose integrals cannot be
@@ -39,4 +42,8 @@ from .generators import (  # noqa: F401
     eri_dense_spatial,
     make_config,
     CONFIG_NAMES,
+    cps_chain_windows,
+    cps_square_plus,
+    cps_pack,
+    init_cps,
 )

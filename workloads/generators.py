@@ -77,6 +77,10 @@ class Workload:
     ctmc_seed: int
     notes: str = ""
     orbitals: str = "ghf"  # "ghf" general, "uhf" spin-blocked theta
+    # correlator product state: sites (n_corr, 5) int32 padded with -1, and the
+    # 4^k coefficients of each correlator concatenated; empty = no correlators
+    cps_sites: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 5), dtype=np.int32))
+    cps_coeffs: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros(0))
 
     @property
     def n_so(self) -> int:
@@ -263,6 +267,49 @@ def init_walkers(n: int, n_alpha: int, n_beta: int, n_walkers: int, seed: int) -
 
 
 # ---------------------------------------------------------------------------
+# Correlator layouts (sites are spatial orbitals) and coefficients
+# ---------------------------------------------------------------------------
+def cps_chain_windows(n: int, k: int, periodic: bool = False):
+    """k consecutive sites starting at every site of a chain (n - k + 1
+    correlators) or of a ring (n correlators, wrapping round)."""
+    starts = range(n) if periodic else range(n - k + 1)
+    return [[(s0 + m) % n for m in range(k)] for s0 in starts]
+
+
+def cps_square_plus(Lx: int, Ly: int):
+    """One five-site correlator centred on each site of a periodic Lx x Ly
+    square lattice (site index x*Ly + y): the site and its four neighbours."""
+    out = []
+    for x in range(Lx):
+        for y in range(Ly):
+            c = x * Ly + y
+            nb = [((x + 1) % Lx) * Ly + y, ((x - 1) % Lx) * Ly + y, x * Ly + (y + 1) % Ly, x * Ly + (y - 1) % Ly]
+            sites = [c]
+            for t in nb:
+                if t not in sites:
+                    sites.append(t)
+            out.append(sites)
+    return out
+
+
+def cps_pack(site_lists) -> np.ndarray:
+    """(n_corr, 5) int32 site array, -1 after the last site of each correlator."""
+    out = np.full((len(site_lists), 5), -1, dtype=np.int32)
+    for l, st in enumerate(site_lists):
+        if not 1 <= len(st) <= 5:
+            raise ValueError("a correlator has 1 to 5 sites")
+        out[l, : len(st)] = st
+    return out
+
+
+def init_cps(site_lists, noise: float, seed: int) -> np.ndarray:
+    """Coefficients 1 + N(0, noise), 4^k per correlator, concatenated."""
+    n = sum(4 ** len(st) for st in site_lists)
+    rng = np.random.default_rng(seed + 104729)
+    return 1.0 + rng.normal(0.0, noise, size=n) if noise > 0.0 else np.ones(n)
+
+
+# ---------------------------------------------------------------------------
 # Named configurations
 # ---------------------------------------------------------------------------
 CONFIG_NAMES = ("hubbard8", "hchain20", "hubbard10x10", "hchain160", "hchain40", "hchain80")
@@ -270,7 +317,8 @@ CONFIG_NAMES = ("hubbard8", "hchain20", "hubbard10x10", "hchain160", "hchain40",
 
 def make_config(name: str, n_walkers: Optional[int] = None, *, theta_noise: float = 0.01,
                 jastrow_std: float = 0.05, U: Optional[float] = None, eps: Optional[float] = None,
-                seed_offset: int = 0, orbitals: str = "ghf") -> Workload:
+                seed_offset: int = 0, orbitals: str = "ghf", cps: Optional[str] = None,
+                cps_noise: float = 0.1) -> Workload:
     """Build one of the named workloads.
 
     hubbard8      8-site ring, t=1, U=4, 4+4 electrons, eps=0, 64 walkers
@@ -280,7 +328,10 @@ def make_config(name: str, n_walkers: Optional[int] = None, *, theta_noise: floa
     hchain40/80   members of the uneven batch (half filled, eps=1e-5, 2048 walkers)
     Seeds for configuration k: integrals 1000+k, psi 2000+k, walkers 3000+k,
     CTMC 4000+k.  orbitals="uhf" gives the spin-blocked (unrestricted) form of
-    the same theta (spin_blocked).
+    the same theta (spin_blocked).  cps adds correlators with coefficients
+    1 + N(0, cps_noise): "chainK" (K consecutive sites from every site; a ring
+    for hubbard8), or "plus5" (five-site crosses centred on every site of the
+    10x10 lattice).
     """
     if orbitals not in ("ghf", "uhf"):
         raise ValueError(f"orbitals must be 'ghf' or 'uhf', not {orbitals!r}")
@@ -320,5 +371,16 @@ def make_config(name: str, n_walkers: Optional[int] = None, *, theta_noise: floa
         theta = spin_blocked(theta, n, na, nb)
     jas = init_jastrow(n_so, jastrow_std, 2000 + k)
     occ = init_walkers(n, na, nb, W, 3000 + k)
-    return Workload(name=name, n_orb=n, n_alpha=na, n_beta=nb, h1=h1, eri_idx=ei, eri_val=ev,
-                    eps=e, theta=theta, jastrow=jas, occ=occ, ctmc_seed=4000 + k, orbitals=orbitals)
+    wl = Workload(name=name, n_orb=n, n_alpha=na, n_beta=nb, h1=h1, eri_idx=ei, eri_val=ev,
+                  eps=e, theta=theta, jastrow=jas, occ=occ, ctmc_seed=4000 + k, orbitals=orbitals)
+    if cps:
+        if cps.startswith("chain"):
+            sites = cps_chain_windows(n, int(cps[5:]), periodic=(name == "hubbard8"))
+        elif cps == "plus5" and name == "hubbard10x10":
+            sites = cps_square_plus(10, 10)
+        else:
+            raise ValueError(f"unknown correlator layout {cps!r} for {name}")
+        wl.cps_sites = cps_pack(sites)
+        wl.cps_coeffs = init_cps(sites, cps_noise, 2000 + k)
+        wl.notes = f"correlators {cps}"
+    return wl
