@@ -75,7 +75,10 @@ enum {
     VMC_ST_SINGULAR = 1u,   /* theta[N] singular at (re)inversion: psi(N) = 0 */
     VMC_ST_EMPTY = 2u,      /* no connected determinant with a positive rate: no move */
     VMC_ST_NONFINITE = 4u,  /* E_L or T not finite */
-    VMC_ST_SMALLDEN = 8u    /* a Sherman-Morrison denominator below 1e-8 in magnitude */
+    VMC_ST_SMALLDEN = 8u,   /* a Sherman-Morrison denominator below 1e-8 in magnitude */
+    VMC_ST_STALE = 16u      /* walkers re-inverted by the separate refresh kernel (state in HBM): B and R
+                               carry updates made since their last inversion; set by a sweep that moved
+                               the walker, cleared by every (re-)inversion.  Not an error. */
 };
 
 typedef struct {
@@ -119,6 +122,11 @@ enum {
     VMC_F_AINV,      /* double [W][Ne][Ne] B = theta[N]^-1, column by slot */
     VMC_F_R,         /* double (VMC_FP64) or float (VMC_MIXED) [W][Ne][n_so] R, column by slot;
                         VMC_UHF: [W][Ne][n], slot p's own spin only (orbital a at a - n for beta) */
+    VMC_F_RLO,       /* uint16 [W][Ne][n_so] (VMC_UHF: [W][Ne][n]), VMC_MIXED only (0 bytes in
+                        VMC_FP64): the bfloat16 remainder of each R entry, R = r + rlo to about
+                        2^-33 relative.  With the walker state in HBM the re-inversion writes it
+                        and every move carries it, so the FP32 r read by the ratios never drifts
+                        from the FP64 R; where the state fits on chip it is written as zero */
     VMC_F_JSUM,      /* double [W][n_so]   s_p = sum_{q != p} J_pq n_q */
     VMC_F_HNN,       /* double [W]         H_NN */
     VMC_F_ELOC,      /* double [W]         last local energy */
@@ -136,6 +144,7 @@ typedef struct {
     void* orb_slot;
     void* ainv;
     void* r;
+    void* rlo;              /* VMC_MIXED: required; VMC_FP64: ignored, may be NULL */
     void* jsum;
     void* hnn;
     void* eloc;
@@ -159,11 +168,49 @@ typedef struct {
 vmc_status vmc_init(const vmc_system_desc* desc, const double* h1, const vmc_eri_list* eri_screened, double eps,
                     hipStream_t stream, vmc_handle* out);
 
-/* Copy wavefunction parameters (device pointers, caller-owned): J packed
+/* Wavefunction parameters of the section "Correlator product states and
+ * Slater determinant": the correlator factor in its two-site (Jastrow) form
+ * exp(sum_{p<=q} J_pq n_p n_q) and the Slater determinant's orbital matrix
+ * theta.  Copies them (device pointers, caller-owned, read on `stream` during
+ * the call's kernels; they may be freed once that work has completed): J packed
  * upper triangle, n_so(n_so+1)/2 doubles; theta n_so x n_so row-major.
  * Rebuilds the Jastrow factors folded into the tables.  Walkers must be
- * re-initialised (vmc_walkers_init) afterwards. */
+ * re-initialised (vmc_walkers_init) or re-inverted (vmc_walkers_refresh)
+ * afterwards.  Errors: VMC_E_ARG for a NULL handle or pointer, VMC_E_HIP on a
+ * failed copy or launch.  Values are not checked: a NaN or infinity in theta
+ * reaches the walkers as VMC_ST_SINGULAR | VMC_ST_NONFINITE at re-inversion. */
 vmc_status vmc_set_params(vmc_handle h, const double* J_dev, const double* theta_dev, hipStream_t stream);
+
+/*
+ * Correlator product state, the wavefunction factor C of the section
+ * "Correlator product states and Slater determinant": psi(N) = C[N] x the
+ * Jastrow factor x det(theta[N]), C[N] = prod_l c_l[n_l(N)].  Correlator l
+ * covers k_l <= 5 distinct sites (spatial orbitals) sites[5 l + m], m < k_l,
+ * -1 after the last; its local Fock state in N is
+ * n_l(N) = sum_m (n_{s_m alpha} + 2 n_{s_m beta}) 4^m and it has 4^k_l
+ * coefficients, stored in correlator order (offset of l = sum_{l' < l} 4^k_l').
+ * The ratio C[M]/C[N] takes only the correlators holding a site whose
+ * occupation the move changes, found through per-site correlator lists
+ * (section "Local energy and Gradient ratios").
+ *
+ * vmc_cps_init: a setup call, made once per handle (VMC_E_ARG if repeated),
+ * before or after walkers exist: validates the site lists (VMC_E_ARG: no
+ * site, a repeated site or a site >= n_orb; VMC_E_UNSUPPORTED beyond 2^31
+ * coefficients), builds the per-site lists and allocates the coefficient
+ * buffer (it allocates and synchronises the device; VMC_E_OOM on failure).
+ * sites: host, 5 * n_corr int32, read during the call only.
+ * vmc_set_cps: copies the coefficients (device, caller-owned, read on
+ * `stream`; nothing allocated); required before any walker call once
+ * correlators exist.  Walker state holds nothing of C, so walkers need no
+ * re-initialisation.  A zero coefficient met by a walker makes its ratios
+ * non-finite (VMC_ST_NONFINITE).
+ * vmc_cps_info: out[0] = correlators, out[1] = coefficients (0, 0 without).
+ * With correlators, vmc_logderiv appends their gradient ratios
+ * O_{c_l[n]} = [n_l(N) = n] / c_l[n] after the orbital part.
+ */
+vmc_status vmc_cps_init(vmc_handle h, int32_t n_corr, const int32_t* sites);
+vmc_status vmc_set_cps(vmc_handle h, const double* coeffs_dev, hipStream_t stream);
+vmc_status vmc_cps_info(vmc_handle h, int64_t out[2]);
 
 /* Bytes of each walker field for n_walkers walkers (host-only call). */
 vmc_status vmc_walker_bytes(vmc_handle h, int64_t n_walkers, size_t field_bytes[VMC_NFIELDS]);
@@ -183,11 +230,27 @@ vmc_status vmc_walkers_init(vmc_handle h, vmc_walkers* w, hipStream_t stream);
  * must not be in use by work on another stream. */
 vmc_status vmc_walkers_refresh(vmc_handle h, vmc_walkers* w, hipStream_t stream);
 
-/* E_L and t = 1/T for every walker from its current state; no state change. */
+/* E_L[N, eps] = H_NN + sum over the screened singles and doubles M of
+ * H_NM psi(M)/psi(N) (Eq. eloc:hci; screening of the section "Reduced scaling
+ * evaluation of the local energy"), and t = 1/T with T = sum_M |psi(M)/psi(N)|
+ * over the same set (Eq. eq:rate), for every walker from its current state,
+ * into the walkers' eloc and tres fields; no state change.  A walker whose
+ * state is flagged VMC_ST_SINGULAR gets E_L = NaN and t = 0; a non-finite E_L
+ * or T sets VMC_ST_NONFINITE, T = 0 sets VMC_ST_EMPTY (t = 0).  Errors:
+ * VMC_E_ARG for a NULL handle or walker field, or before vmc_set_params;
+ * VMC_E_UNSUPPORTED when the system exceeds the per-walker LDS budget;
+ * launch failures as VMC_E_HIP. */
 vmc_status vmc_local_energy(vmc_handle h, vmc_walkers* w, hipStream_t stream);
 
 /*
- * n_steps CTMC moves of every walker in one persistent launch.  Step k of
+ * n_steps continuous-time Monte Carlo moves (section "Continuous time Monte
+ * Carlo for sampling determinants": rates r_M = |psi(M)/psi(N)| of Eq.
+ * eq:rate over the screened set, residence time t = 1/sum r, M drawn with
+ * probability r_M / sum r) of every walker in one persistent launch, each
+ * followed by the Sherman-Morrison update of the section "Local energy and
+ * Gradient ratios".  Errors: VMC_E_ARG for a NULL handle or walker field,
+ * n_steps < 0, or before vmc_set_params; VMC_E_UNSUPPORTED when the system
+ * exceeds the per-walker LDS budget; launch failures as VMC_E_HIP.  Step k of
  * walker i draws u from Philox4x64-10 with counter (w->step + k, 0, 0, 0) and
  * key (seed, i) (first output word, 53 high bits), picks the smallest
  * candidate index whose running rate sum exceeds u*T, and updates B, R, s and
@@ -212,26 +275,34 @@ vmc_status vmc_ctmc_step(vmc_handle h, vmc_walkers* w, int32_t n_steps, double* 
  * captured in a hipGraph and replayed: every replay draws the next uniforms.
  * w->step is not used or changed; no histories.  Refresh: as vmc_ctmc_step
  * when the walker state fits LDS (by the global step); for walkers whose state
- * lives in HBM, n_steps must be a multiple of refresh_period, and the separate
- * refresh kernel runs after every refresh_period moves of the call, whatever
- * w->since_inv holds (a replayed graph repeats the same launches), then sets it
- * to 0.
+ * lives in HBM, n_steps must be a multiple of refresh_period (VMC_E_ARG
+ * otherwise), and before every refresh_period moves of the call the separate
+ * refresh kernel re-inverts exactly the walkers marked VMC_ST_STALE (moved
+ * since their last inversion; fresh walkers, e.g. just re-inverted for new
+ * parameters, are skipped), so no walker makes more than refresh_period moves
+ * on one inverse whatever state a replay finds.  w->since_inv is set to
+ * refresh_period (an eager vmc_ctmc_step that follows re-inverts first).
  * step_dev: device, 8 bytes, caller-owned.
  */
 vmc_status vmc_ctmc_step_dev(vmc_handle h, vmc_walkers* w, int32_t n_steps, uint64_t* step_dev, hipStream_t stream);
 
 /*
  * Gradient ratios O_k of each walker's current state, N_p = n_so(n_so+1)/2 +
- * n_so^2 (Jastrow part packed like J, then theta row-major):
+ * n_so^2 (+ the correlator coefficients, see vmc_cps_init) (Jastrow part
+ * packed like J, then theta row-major, then the correlators):
  * O_{J_pq} = n_p n_q, O_{theta_kx} = B[x][slot(k)] for occupied k and x < Ne,
- * else 0.  If g_dev (device, W doubles) is NULL, out_dev receives the dense
+ * else 0, O_{c_l[n]} = [n_l(N) = n] / c_l[n].  If g_dev (device, W doubles) is NULL, out_dev receives the dense
  * [W][N_p] matrix; otherwise out_dev receives G = sum_w g_w O_w (N_p doubles),
  * the contracted backward used for Eq. eq:grad with g_w = 2 t_w (E_L,w - E)/sum t.
- * The contracted form sums over ranges of about 128 walkers (16 to 128 ranges)
- * into partials the handle owns: the first such call for a walker count needing
- * more ranges than any before allocates them (N_p x ranges doubles, VMC_E_OOM
- * if that fails); later calls allocate nothing, so a caller that captures this
- * call in a hipGraph issues it once eagerly first.  Deterministic.
+ * The contracted form computes the Jastrow part as Occ^T diag(g) Occ (Occ the
+ * W x n_so occupation matrix) on the FP64 matrix cores and the orbital part
+ * row by row over the walkers holding each orbital; every sum runs over the
+ * walkers in a fixed order, so the result is deterministic, and walkers with
+ * g_w = 0 contribute nothing (their B is not read).  Nothing is allocated:
+ * the call can be captured in a hipGraph as it is.  Errors: VMC_E_ARG for a
+ * NULL handle, walkers or out_dev; launch failures as VMC_E_HIP.
+ * Defined in the section "Local energy and Gradient ratios" (gradient ratios
+ * of the Jastrow and orbital parameters) and Eq. eq:grad.
  */
 vmc_status vmc_logderiv(vmc_handle h, const vmc_walkers* w, const double* g_dev, double* out_dev,
                         hipStream_t stream);

@@ -40,8 +40,9 @@ class _VMCEnergy(torch.autograd.Function):
         G = torch.empty(system.n_params, dtype=torch.float64, device=g.device)
         _vmc.vmc_logderiv(system.handle, walkers, g, G)
         nj = system.n_so * (system.n_so + 1) // 2
+        nt = system.n_so * system.n_so
         gJ = (grad_out * G[:nj]).reshape(ctx.shapes[0])
-        gT = (grad_out * G[nj:]).reshape(ctx.shapes[1])
+        gT = (grad_out * G[nj:nj + nt]).reshape(ctx.shapes[1])
         return gJ, gT, None, None
 
 

@@ -19,6 +19,7 @@ struct Tab {
     int rrow;                 // length of one slot's row of R: n_so, or n when uhf (own spin only)
     int has_doubles;          // the table holds at least one doubles entry
     int has_sV;               // some singles entry has a nonzero Coulomb-exchange vector
+    int fock;                 // keep the walker's singles elements in its scratch (state in HBM, has_sV)
     double eps;
     const uint32_t* row_off;  // n_so*n_so + 1
     const uint32_t* dab;      // a | b << 16
@@ -33,6 +34,13 @@ struct Tab {
     const double* hdiag;      // n_so
     const double* J;          // dense n_so*n_so
     const double* theta;      // n_so*n_so row-major
+    // correlator product state (ncorr = 0: none)
+    int ncorr;
+    const int32_t* csite;     // 5 per correlator: its sites (spatial orbitals), -1 after the last
+    const int32_t* coff;      // ncorr + 1: offsets of each correlator's 4^k coefficients
+    const double* cc;         // the coefficients
+    const int32_t* sc_off;    // n + 1: the correlators holding each site are sc_list[sc_off[s] ..)
+    const uint32_t* sc_list;  // correlator index (low 24 bits) | position of the site in it << 24
 };
 
 struct Wk {
@@ -41,6 +49,7 @@ struct Wk {
     int32_t* orb_slot;
     double* B;
     void* R;  // double (FP64 form) or float (mixed form)
+    uint16_t* Rlo;  // mixed form: bfloat16 remainder of each R entry (R = hi + lo), R's layout
     double* s;
     double* hnn;
     double* eloc;

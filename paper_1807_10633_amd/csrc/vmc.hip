@@ -22,11 +22,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "device.hpp"
@@ -158,28 +160,34 @@ __device__ __forceinline__ int r_index(const Tab& T, int p, int a) {
 // energy and Gradient ratios", Eq. eq:R).  Spin-blocked orbitals: a pair of
 // the same spin is the full minor within that spin's rows; a pair of opposite
 // spins (i alpha, j beta, hence a alpha, b beta) has no cross term, so the
-// ratio is the product of the two spins' single ratios.
+// ratio is the product of the two spins' single ratios.  Products and the
+// difference are formed in FP64 whatever the storage of R, so that the
+// cancellation of a minor near a node adds no rounding of the storage type.
 template <typename RT>
-__device__ __forceinline__ RT pair_minor_uhf(const Tab& T, const RT* R, int p, int q, int a, int b) {
+__device__ __forceinline__ double pair_minor_uhf(const Tab& T, const RT* R, int p, int q, int a, int b) {
     const int op = (p >= T.na) ? T.n : 0, oq = (q >= T.na) ? T.n : 0;
     const int rp = p * T.n - op, rq = q * T.n - oq;
-    if (op != oq) return R[rp + a] * R[rq + b];
-    return R[rp + a] * R[rq + b] - R[rp + b] * R[rq + a];
+    if (op != oq) return (double)R[rp + a] * (double)R[rq + b];
+    return (double)R[rp + a] * (double)R[rq + b] - (double)R[rp + b] * (double)R[rq + a];
 }
 template <typename RT>
-__device__ __forceinline__ RT pair_minor(const Tab& T, const RT* R, int p, int q, int a, int b) {
+__device__ __forceinline__ double pair_minor(const Tab& T, const RT* R, int p, int q, int a, int b) {
     if (T.uhf) return pair_minor_uhf(T, R, p, q, a, b);
     const RT* Rp = R + p * T.n_so;
     const RT* Rq = R + q * T.n_so;
-    return Rp[a] * Rq[b] - Rp[b] * Rq[a];
+    return (double)Rp[a] * (double)Rq[b] - (double)Rp[b] * (double)Rq[a];
 }
 
 // Ratio and matrix element of candidate e of group Gr (slot convention).
+__device__ __forceinline__ double cps_ratio(const Tab& T, const uint32_t* cidx, const double* cinv, int nk, int o0,
+                                            int o1, int o2, int o3);
 template <typename RT>
 __device__ __forceinline__ double single_ratio(const Tab& T, const Group& Gr, uint32_t e, const RT* R,
-                                               const double* es, int& a) {
+                                               const double* es, const uint32_t* cidx, const double* cinv, int& a) {
     a = (int)T.sa[Gr.base + e];
-    return (double)R[r_index(T, Gr.p, a)] * es[a] * Gr.fac * T.sK[Gr.base + e];
+    double r = (double)R[r_index(T, Gr.p, a)] * es[a] * Gr.fac * T.sK[Gr.base + e];
+    if (T.ncorr) r *= cps_ratio(T, cidx, cinv, 2, Gr.i, a, 0, 0);
+    return r;
 }
 __device__ __forceinline__ double single_h(const Tab& T, const Group& Gr, uint32_t e, const int* occl) {
     const double* V = T.sV + (size_t)Gr.base * T.n_so + e;
@@ -189,12 +197,15 @@ __device__ __forceinline__ double single_h(const Tab& T, const Group& Gr, uint32
 }
 template <typename RT>
 __device__ __forceinline__ double double_ratio(const Tab& T, const Group& Gr, uint32_t e, const RT* R,
-                                               const double* es, int& a, int& b) {
+                                               const double* es, const uint32_t* cidx, const double* cinv, int& a,
+                                               int& b) {
     const uint32_t ab = T.dab[Gr.base + e];
     a = (int)(ab & 0xFFFFu);
     b = (int)(ab >> 16);
-    const RT det = pair_minor(T, R, Gr.p, Gr.q, a, b);
-    return (double)det * es[a] * es[b] * T.dvK[2 * (size_t)(Gr.base + e) + 1] * Gr.fac;
+    const double det = pair_minor(T, R, Gr.p, Gr.q, a, b);
+    double r = det * es[a] * es[b] * T.dvK[2 * (size_t)(Gr.base + e) + 1] * Gr.fac;
+    if (T.ncorr) r *= cps_ratio(T, cidx, cinv, 4, Gr.i, Gr.j, a, b);
+    return r;
 }
 
 // --------------------------------------------------------------- LDS layout
@@ -205,7 +216,8 @@ constexpr int kUnroll = 6;  // 64-entry chunks whose table loads are issued toge
 
 struct Lds {
     uint32_t occw, occl, slot, oslot, s, es, ies, red, stmp, mi, md, wst, wtot, q64, qab, lsum, loff, lg, sgend, sdelta,
-        svend, spq, sfac, dgend, ddelta, dvend, dpq, dfac, w1, w2, cRp, cRq, cBp, cBq, ipiv, dblk, fcol, R, B, Rh, thl, total;
+        svend, spq, sfac, dgend, ddelta, dvend, dpq, dfac, w1, w2, cRp, cRq, cBp, cBq, ipiv, dblk, fcol, cidx, cinv, R, B, Rh,
+        thl, total;
 };
 __host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~(size_t)15; }
 // bytes of the doubles group descriptors (padded stream end, offset delta,
@@ -214,8 +226,9 @@ __host__ __device__ inline size_t desc_bytes(int ne) {
     const size_t gd = (size_t)ne * (ne - 1) / 2;
     return al16(gd * 4) * 4 + al16(gd * 8);
 }
-// rb: bytes per R element (8 for the FP64 form, 4 for the mixed form)
-__host__ __device__ __forceinline__ Lds lds_layout(int n_so, int ne, int nw, int nt, bool small, int rb) {
+// rb: bytes per R element (8 for the FP64 form, 4 for the mixed form);
+// ncorr: correlators (their current states and inverse coefficients)
+__host__ __device__ __forceinline__ Lds lds_layout(int n_so, int ne, int nw, int nt, bool small, int rb, int ncorr) {
     Lds L;
     size_t o = 0;
     const int nwv = nt / 64;
@@ -253,6 +266,8 @@ __host__ __device__ __forceinline__ Lds lds_layout(int n_so, int ne, int nw, int
     L.ipiv = take((size_t)ne * 4);
     L.dblk = take(((gd + 63) / 64 + 1) * 4);
     L.fcol = take((size_t)ne * 8);
+    L.cidx = take((size_t)ncorr * 4);
+    L.cinv = take((size_t)ncorr * 8);
     if (small) {
         L.dgend = take(gd * 4);
         L.ddelta = take(gd * 4);
@@ -271,7 +286,12 @@ __host__ __device__ __forceinline__ Lds lds_layout(int n_so, int ne, int nw, int
     return L;
 }
 // per-walker global scratch: the doubles group descriptors when they do not fit in LDS
-__host__ __device__ inline size_t scratch_layout_bytes(int ne) { return desc_bytes(ne) + 16; }
+// followed, when the singles carry Coulomb-exchange vectors, by the walker's
+// Fock-like singles elements (one double per singles-table entry)
+__host__ __device__ inline size_t scratch_fock_offset(int ne) { return al16(desc_bytes(ne) + 16); }
+__host__ __device__ inline size_t scratch_layout_bytes(int ne, int64_t n_fock) {
+    return scratch_fock_offset(ne) + (size_t)n_fock * 8;
+}
 
 // misc int slots
 enum { MI_ST = 0, MI_PIV, MI_PTYPE, MI_PP, MI_PQ, MI_PA, MI_PB, MI_FS, MI_FW, MI_FK, MI_FFB, MI_WAVE = 32 };
@@ -302,12 +322,33 @@ struct Mma<double> {
     static __device__ __forceinline__ int row(int kq, int j) { return kq + 4 * j; }
 };
 
+// Split storage of the mixed form with the walker state in HBM: an R entry is
+// hi + lo, hi its FP32 rounding and lo the bfloat16 rounding of the remainder
+// (about 2^-33 relative in all).  The ratios read hi only; the re-inversion
+// and every update carry both, so hi stays the rounding of the FP64 R instead
+// of accumulating one FP32 rounding per move.
+__device__ __forceinline__ uint16_t bf16_rn(float x) {
+    uint32_t b = __float_as_uint(x);
+    b += 0x7FFFu + ((b >> 16) & 1u);  // round to nearest, ties to even
+    return (uint16_t)(b >> 16);
+}
+__device__ __forceinline__ float bf16_val(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ void store_split(float* hi, uint16_t* lo, size_t i, double v) {
+    const float h = (float)v;
+    hi[i] = h;
+    lo[i] = (fabsf(h) <= FLT_MAX) ? bf16_rn((float)(v - (double)h)) : (uint16_t)0;
+}
+
 // R[p][a] = sum_x B[p][x] theta[a][x] (p < Ne slots, a < n_so orbitals, x < Ne)
-// on the matrix cores: 16x16 output tiles dealt round-robin to the waves,
-// operands rounded to the precision of R, accumulation in that precision.
+// on the matrix cores: 16x16 output tiles dealt round-robin to the waves.
+// Without SPLIT the operands are rounded to the precision of R and accumulated
+// in it; with SPLIT (FP32 R with its bfloat16 remainder in Rlo) the product is
+// formed in FP64 and stored split.
 // th: theta[:, 0:Ne] with row stride ths (the table, or a copy in LDS).
-template <typename RT>
-__device__ __forceinline__ void r_gemm(const Tab& T, const double* B, RT* R, const double* th, int ths) {
+template <typename RT, bool SPLIT = false>
+__device__ __forceinline__ void r_gemm(const Tab& T, const double* B, RT* R, const double* th, int ths,
+                                       uint16_t* Rlo = nullptr) {
+    typedef typename std::conditional<SPLIT, double, RT>::type CT;
     const int ne = T.ne, n_so = T.n_so, l = lane_id();
     const int wv = (int)__builtin_amdgcn_readfirstlane((uint32_t)(threadIdx.x >> 6)), nwv = blockDim.x >> 6;
     const int mt = (ne + 15) >> 4, nt16 = (n_so + 15) >> 4;
@@ -315,18 +356,21 @@ __device__ __forceinline__ void r_gemm(const Tab& T, const double* B, RT* R, con
     for (int t = wv; t < mt * nt16; t += nwv) {
         const int pt = t / nt16, at = t - pt * nt16;
         const int p = pt * 16 + m, a = at * 16 + m;
-        typename Mma<RT>::acc_t acc = {0, 0, 0, 0};
+        typename Mma<CT>::acc_t acc = {0, 0, 0, 0};
 #pragma unroll 4
         for (int k0 = 0; k0 < ne; k0 += 4) {
             const int x = k0 + kq;
-            const RT av = (p < ne && x < ne) ? (RT)B[p * ne + x] : (RT)0;
-            const RT bv = (a < n_so && x < ne) ? (RT)th[(size_t)a * ths + x] : (RT)0;
-            acc = Mma<RT>::step(av, bv, acc);
+            const CT av = (p < ne && x < ne) ? (CT)B[p * ne + x] : (CT)0;
+            const CT bv = (a < n_so && x < ne) ? (CT)th[(size_t)a * ths + x] : (CT)0;
+            acc = Mma<CT>::step(av, bv, acc);
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int pr = pt * 16 + Mma<RT>::row(kq, j);
-            if (pr < ne && a < n_so) R[pr * n_so + a] = acc[j];
+            const int pr = pt * 16 + Mma<CT>::row(kq, j);
+            if (pr < ne && a < n_so) {
+                if constexpr (SPLIT) store_split(R, Rlo, (size_t)pr * n_so + a, acc[j]);
+                else R[pr * n_so + a] = acc[j];
+            }
         }
     }
 }
@@ -334,34 +378,39 @@ __device__ __forceinline__ void r_gemm(const Tab& T, const double* B, RT* R, con
 // The same product with each wave holding a 16-orbital tile of theta in
 // registers (KS k-steps, Ne <= 4 KS) across all slot tiles, so that theta is
 // read once per walker instead of once per output tile; B in LDS.
-template <typename RT, int KS>
-__device__ __forceinline__ void r_gemm_theta_regs(const Tab& T, const double* B, RT* R, const double* th, int ths) {
+template <typename RT, int KS, bool SPLIT = false>
+__device__ __forceinline__ void r_gemm_theta_regs(const Tab& T, const double* B, RT* R, const double* th, int ths,
+                                                  uint16_t* Rlo = nullptr) {
+    typedef typename std::conditional<SPLIT, double, RT>::type CT;
     const int ne = T.ne, n_so = T.n_so, l = lane_id();
     const int wv = (int)__builtin_amdgcn_readfirstlane((uint32_t)(threadIdx.x >> 6)), nwv = blockDim.x >> 6;
     const int mt = (ne + 15) >> 4, nt16 = (n_so + 15) >> 4;
     const int m = l & 15, kq = l >> 4;
     for (int at = wv; at < nt16; at += nwv) {
         const int a = at * 16 + m;
-        RT tr[KS];
+        CT tr[KS];
 #pragma unroll
         for (int st = 0; st < KS; ++st) {
             const int x = 4 * st + kq;
-            tr[st] = (a < n_so && x < ne) ? (RT)th[(size_t)a * ths + x] : (RT)0;
+            tr[st] = (a < n_so && x < ne) ? (CT)th[(size_t)a * ths + x] : (CT)0;
         }
         for (int pt = 0; pt < mt; ++pt) {
             const int p = pt * 16 + m;
-            typename Mma<RT>::acc_t acc = {0, 0, 0, 0};
+            typename Mma<CT>::acc_t acc = {0, 0, 0, 0};
 #pragma unroll
             for (int st = 0; st < KS; ++st)
                 if (4 * st < ne) {
                     const int x = 4 * st + kq;
-                    const RT av = (p < ne && x < ne) ? (RT)B[p * ne + x] : (RT)0;
-                    acc = Mma<RT>::step(av, tr[st], acc);
+                    const CT av = (p < ne && x < ne) ? (CT)B[p * ne + x] : (CT)0;
+                    acc = Mma<CT>::step(av, tr[st], acc);
                 }
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const int pr = pt * 16 + Mma<RT>::row(kq, j);
-                if (pr < ne && a < n_so) R[pr * n_so + a] = acc[j];
+                const int pr = pt * 16 + Mma<CT>::row(kq, j);
+                if (pr < ne && a < n_so) {
+                    if constexpr (SPLIT) store_split(R, Rlo, (size_t)pr * n_so + a, acc[j]);
+                    else R[pr * n_so + a] = acc[j];
+                }
             }
         }
     }
@@ -416,6 +465,73 @@ __device__ __forceinline__ void rank_update(E* M, int rows, int cols, const doub
     }
 }
 
+// The same on split storage (FP32 hi, bfloat16 lo): each entry is read as
+// hi + lo, updated in FP64 and stored split again.  Vectors of four entries
+// (16 bytes of hi, 8 of lo), four in flight per thread.
+template <bool TWO>
+__device__ __forceinline__ void rank_update_split(float* M, uint16_t* L, int rows, int cols, const double* c1,
+                                                  const double* r1, const double* c2, const double* r2) {
+    constexpr int U = 2;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    struct alignas(16) V4 {
+        float v[4];
+    };
+    struct alignas(8) L4 {
+        uint16_t v[4];
+    };
+    if ((cols & 3) == 0 && (((uintptr_t)M) & 15) == 0 && (((uintptr_t)L) & 7) == 0) {
+        const int cv = cols >> 2, nv = rows * cv;
+        V4* Mv = (V4*)M;
+        L4* Lv = (L4*)L;
+        for (int v0 = tid; v0 < nv; v0 += nt * U) {
+            V4 hv[U];
+            L4 lv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int vi = v0 + u * nt;
+                if (vi < nv) {
+                    hv[u] = Mv[vi];
+                    lv[u] = Lv[vi];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int vi = v0 + u * nt;
+                if (vi < nv) {
+                    const int r = vi / cv, c = (vi - r * cv) * 4;
+                    const double a1 = r1[r], a2 = TWO ? r2[r] : 0.0;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        double d = c1[c + j] * a1;
+                        if (TWO) d += c2[c + j] * a2;
+                        const double v = ((double)hv[u].v[j] + (double)bf16_val(lv[u].v[j])) - d;
+                        const float h = (float)v;
+                        hv[u].v[j] = h;
+                        lv[u].v[j] = (fabsf(h) <= FLT_MAX) ? bf16_rn((float)(v - (double)h)) : (uint16_t)0;
+                    }
+                    Mv[vi] = hv[u];
+                    Lv[vi] = lv[u];
+                }
+            }
+        }
+    } else {
+        for (int idx = tid; idx < rows * cols; idx += nt) {
+            const int r = idx / cols, c = idx - r * cols;
+            double d = c1[c] * r1[r];
+            if (TWO) d += c2[c] * r2[r];
+            store_split(M, L, idx, ((double)M[idx] + (double)bf16_val(L[idx])) - d);
+        }
+    }
+}
+
+// Rank-1/2 update of R in its storage: split (mixed form, state in HBM) or plain.
+template <typename RT, bool TWO, bool SPLIT>
+__device__ __forceinline__ void r_update(RT* R, uint16_t* Rlo, int rows, int cols, const double* c1, const double* r1,
+                                         const double* c2, const double* r2) {
+    if constexpr (SPLIT) rank_update_split<TWO>(R, Rlo, rows, cols, c1, r1, c2, r2);
+    else rank_update<RT, TWO>(R, rows, cols, c1, r1, c2, r2);
+}
+
 // The same on a sub-block whose rows lie ld elements apart (one spin's block
 // of B with spin-blocked orbitals).
 template <bool TWO>
@@ -466,9 +582,9 @@ __device__ __forceinline__ void rank_update_ld(double* M, int rows, int cols, in
 // Rebuild B = theta[N]^-1 (Gauss-Jordan, partial pivoting, FP64), R and s from
 // the slot list.  B is stored column by slot (B[x][p] at B[p*ne + x]): the
 // elimination works on A^T, whose inverse laid out row-major is exactly that.
-template <typename RT>
+template <typename RT, bool SPLIT = false>
 __device__ __forceinline__ void refresh_state(const Tab& T, const int* slot, double* B, RT* R, double* s, double* fcol, int* ipiv,
-                              int* mi, double* red, const double* th, int ths) {
+                              int* mi, double* red, const double* th, int ths, uint16_t* Rlo = nullptr) {
     const int tid = threadIdx.x, nt = blockDim.x, ne = T.ne, n_so = T.n_so;
     const int wv = tid >> 6, nwv = nt >> 6;
     for (int idx = tid; idx < ne * ne; idx += nt) {
@@ -477,10 +593,14 @@ __device__ __forceinline__ void refresh_state(const Tab& T, const int* slot, dou
     }
     __syncthreads();
     for (int k = 0; k < ne; ++k) {
+        // every candidate starts at a valid row (k), and a NaN or infinite
+        // entry ranks as the largest, so the pivot is always an unused row
+        // below ne whatever the matrix holds; such a walker is flagged below
         double bv = -1.0;
-        int bi = INT_MAX;
+        int bi = k;
         for (int r = k + tid; r < ne; r += nt) {
-            const double v = fabs(B[r * ne + k]);
+            double v = fabs(B[r * ne + k]);
+            if (!(v <= DBL_MAX)) v = INFINITY;
             if (v > bv) { bv = v; bi = r; }
         }
 #pragma unroll
@@ -499,6 +619,7 @@ __device__ __forceinline__ void refresh_state(const Tab& T, const int* slot, dou
             mi[MI_PIV] = bidx;
             ipiv[k] = bidx;
             if (!(best > 0.0)) mi[MI_ST] |= (int)VMC_ST_SINGULAR;
+            if (!(best <= DBL_MAX)) mi[MI_ST] |= (int)(VMC_ST_SINGULAR | VMC_ST_NONFINITE);
         }
         __syncthreads();
         const int piv = mi[MI_PIV];
@@ -532,7 +653,7 @@ __device__ __forceinline__ void refresh_state(const Tab& T, const int* slot, dou
             }
         __syncthreads();
     }
-    r_gemm<RT>(T, B, R, th, ths);
+    r_gemm<RT, SPLIT>(T, B, R, th, ths, Rlo);
     for (int pp = tid; pp < n_so; pp += nt) {
         const double* Jr = T.J + (size_t)pp * n_so;
         double acc = 0.0;
@@ -682,7 +803,123 @@ struct StepView {
     const uint32_t* dvend;
     const uint32_t* dpq;    //          slots p | q << 16
     const double* dfac;     //          exp(-s_i - s_j) (unscaled path)
+    const int* slot;        // orbital held by each slot
+    const uint32_t* cidx;   // correlators: current local Fock state of each
+    const double* cinv;     //              and 1 / its coefficient
+    const double* F;        // singles elements h_ia + sum_{j occupied} V_ia[j] per table entry (state in
+                            // HBM with Coulomb-exchange vectors), else null
 };
+
+// Fock-like singles elements F[e] = h_ia + sum_{j occupied} V_e[j] (the
+// element of the section "Reduced scaling evaluation of the local energy"
+// before its phase) for every entry e of the rows of the orbitals rows[0..nr),
+// from scratch over the occupied orbitals occ[0..ne): one wave per row, lanes
+// over its entries (the j-major vectors make them contiguous for each j).
+__device__ __forceinline__ void fock_rows(const Tab& T, double* F, const int* rows, int nr, const int* occ, int ne) {
+    const int l = lane_id(), wv = (int)uni((uint32_t)(threadIdx.x >> 6)), nwv = blockDim.x >> 6;
+    for (int x = wv; x < nr; x += nwv) {
+        const int r = rows[x];
+        const uint32_t b0 = T.s_off[r], len = T.s_off[r + 1] - b0;
+        for (uint32_t e = l; e < len; e += kWave) {
+            const double* Vr = T.sV + (size_t)b0 * T.n_so + e;
+            double h = T.sh[b0 + e];
+#pragma unroll 8
+            for (int y = 0; y < ne; ++y) h += Vr[(size_t)occ[y] * len];
+            F[b0 + e] = h;
+        }
+    }
+}
+
+// After a move that empties i (j) and fills a (b): the rows of the orbitals
+// occupied before and after change by V_e[a] - V_e[i] (+ V_e[b] - V_e[j]);
+// the rows of a (b) are built from scratch over the new occupation slot[0..ne).
+__device__ __forceinline__ void fock_move(const Tab& T, double* F, const int* slot, int ne, int i, int j, int a, int b) {
+    const int l = lane_id(), wv = (int)uni((uint32_t)(threadIdx.x >> 6)), nwv = blockDim.x >> 6;
+    for (int x = wv; x < ne; x += nwv) {
+        const int r = slot[x];
+        const uint32_t b0 = T.s_off[r], len = T.s_off[r + 1] - b0;
+        const bool fresh = (r == a) || (b >= 0 && r == b);
+        for (uint32_t e = l; e < len; e += kWave) {
+            const double* Vr = T.sV + (size_t)b0 * T.n_so + e;
+            if (fresh) {
+                double h = T.sh[b0 + e];
+#pragma unroll 8
+                for (int y = 0; y < ne; ++y) h += Vr[(size_t)slot[y] * len];
+                F[b0 + e] = h;
+            } else {
+                double d = Vr[(size_t)a * len] - Vr[(size_t)i * len];
+                if (b >= 0) d += Vr[(size_t)b * len] - Vr[(size_t)j * len];
+                F[b0 + e] += d;
+            }
+        }
+    }
+}
+
+// Correlator ratio C[M]/C[N] (section "Local energy and Gradient ratios": only
+// the correlators holding a site whose occupation changes enter, each once).
+// The move empties the first nk/2 orbitals o0 (o1) and fills the other nk/2
+// (nk = 2: i -> a; nk = 4: i, j -> a, b).  For each correlator holding the
+// site of some changed orbital, its state in M is its state in N plus, for
+// every changed orbital on its sites, -1 (emptied) or +1 (filled) times the
+// orbital's digit weight (1 alpha, 2 beta) times 4^(position of the site);
+// the ratio multiplies c[state in M] / c[state in N].  Inlined: a call would
+// make the sweep kernels, whose register budget is fixed by their occupancy
+// target, save their live registers to scratch around it.
+__device__ __forceinline__ double cps_ratio(const Tab& T, const uint32_t* cidx, const double* cinv, int nk, int o0,
+                                            int o1, int o2, int o3) {
+    const int n = T.n;
+    int st[4], wt[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int o = k == 0 ? o0 : k == 1 ? o1 : k == 2 ? o2 : o3;
+        st[k] = (k < nk) ? ((o >= n) ? o - n : o) : -2;
+        wt[k] = ((k < nk / 2) ? -1 : 1) * ((o >= n) ? 2 : 1);
+    }
+    double r = 1.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (k >= nk) break;
+        const int e1 = T.sc_off[st[k] + 1];
+        for (int e = T.sc_off[st[k]]; e < e1; ++e) {
+            const int lam = (int)(T.sc_list[e] & 0xFFFFFFu);
+            const int* cs = T.csite + 5 * lam;
+            const int c0 = cs[0], c1 = cs[1], c2 = cs[2], c3 = cs[3], c4 = cs[4];
+            auto pos = [&](int x) {
+                return x == c0 ? 0 : x == c1 ? 1 : x == c2 ? 2 : x == c3 ? 3 : x == c4 ? 4 : -1;
+            };
+            bool seen = false;
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2)
+                if (k2 < k) seen = seen || pos(st[k2]) >= 0;
+            if (seen) continue;  // handled with the earlier orbital's correlators
+            int delta = 0;
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) {
+                const int m = (k2 < nk) ? pos(st[k2]) : -1;
+                if (m >= 0) delta += wt[k2] * (1 << (2 * m));
+            }
+            r *= T.cc[T.coff[lam] + (int)cidx[lam] + delta] * cinv[lam];
+        }
+    }
+    return r;
+}
+
+// Local Fock state of every correlator in the occupation occw, and the inverse
+// of its coefficient, by the whole block (LDS outputs).
+__device__ __forceinline__ void cps_states(const Tab& T, const uint64_t* occw, uint32_t* cidx, double* cinv) {
+    for (int lam = threadIdx.x; lam < T.ncorr; lam += blockDim.x) {
+        uint32_t idx = 0, w = 1;
+        for (int m = 0; m < 5; ++m) {
+            const int site = T.csite[5 * lam + m];
+            if (site < 0) break;
+            const int b = site + T.n;
+            idx += w * (uint32_t)(((occw[site >> 6] >> (site & 63)) & 1ull) + 2 * ((occw[b >> 6] >> (b & 63)) & 1ull));
+            w *= 4;
+        }
+        cidx[lam] = idx;
+        cinv[lam] = 1.0 / T.cc[T.coff[lam] + (int)idx];
+    }
+}
 
 // Ratio psi(M)/psi(N) (and, when WANT_H, the local-energy term H_NM * ratio)
 // of a queued candidate: table offset `off`, group g, targets in `ab` (a
@@ -708,13 +945,14 @@ __device__ __forceinline__ double cand_eval(const Tab& T, const StepView<RT>& V,
         }
         double det;
         if (UHF) {
-            det = (double)pair_minor_uhf(T, V.R, p, q, a, b);
+            det = pair_minor_uhf(T, V.R, p, q, a, b);
         } else {
             const RT* Rp = V.R + p * n_so;
             const RT* Rq = V.R + q * n_so;
-            det = (double)(Rp[a] * Rq[b] - Rp[b] * Rq[a]);
+            det = (double)Rp[a] * (double)Rq[b] - (double)Rp[b] * (double)Rq[a];
         }
-        const double ratio = SCALED ? det * vk.y : det * V.es[a] * V.es[b] * vk.y * V.dfac[g];
+        double ratio = SCALED ? det * vk.y : det * V.es[a] * V.es[b] * vk.y * V.dfac[g];
+        if (T.ncorr) ratio *= cps_ratio(T, V.cidx, V.cinv, 4, V.slot[p], V.slot[q], a, b);
         if (WANT_H) term = vk.x * ratio;
         cp = p; cq = q; ca = a; cb = b;
         return ratio;
@@ -722,8 +960,11 @@ __device__ __forceinline__ double cand_eval(const Tab& T, const StepView<RT>& V,
         const int p = QPQ ? (int)(ab >> 32) : (int)V.spq[g];
         const int a = (int)(uint32_t)ab;
         const double r1 = (double)V.R[UHF ? r_index_uhf(T, p, a) : p * n_so + a];
-        const double ratio = SCALED ? r1 * T.sK[off] : r1 * V.es[a] * V.sfac[g] * T.sK[off];
-        if (WANT_H) {
+        double ratio = SCALED ? r1 * T.sK[off] : r1 * V.es[a] * V.sfac[g] * T.sK[off];
+        if (T.ncorr) ratio *= cps_ratio(T, V.cidx, V.cinv, 2, V.slot[p], a, 0, 0);
+        if (WANT_H && V.F) {
+            term = V.F[off] * ratio;
+        } else if (WANT_H) {
             double h = T.sh[off];
             if (T.has_sV) {
                 // the row of orbital i stores V[j] of its entries contiguously
@@ -1056,8 +1297,10 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
     // pairs of occupied slots; none when the table holds no doubles (Hubbard)
     const int gd = T.has_doubles ? ne * (ne - 1) / 2 : 0;
     T.G = ne + gd;
-    const Lds L = lds_layout(n_so, ne, nw, nt, SMALL, (int)sizeof(RT));
+    const Lds L = lds_layout(n_so, ne, nw, nt, SMALL, (int)sizeof(RT), T.ncorr);
     constexpr bool MIXED = sizeof(RT) < sizeof(double);
+    // mixed form with the state in HBM: R stored split (FP32 + bfloat16 remainder)
+    constexpr bool SPLIT = MIXED && !SMALL;
     uint64_t* occw = (uint64_t*)(smem + L.occw);
     int* occl = (int*)(smem + L.occl);
     int* slot = (int*)(smem + L.slot);
@@ -1095,8 +1338,12 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
     int* ipiv = (int*)(smem + L.ipiv);
     uint32_t* dblk = (uint32_t*)(smem + L.dblk);
     double* fcol = (double*)(smem + L.fcol);
+    uint32_t* cidx = (uint32_t*)(smem + L.cidx);
+    double* cinv = (double*)(smem + L.cinv);
     RT *R, *Rh;
+    uint16_t* Rlo = nullptr;
     double *B, *dfac;
+    double* Fk = nullptr;  // the walker's Fock-like singles elements (state in HBM, Coulomb-exchange vectors)
     uint32_t *dgend, *ddelta, *dvend, *dpq;
     if (SMALL) {
         R = (RT*)(smem + L.R);
@@ -1109,9 +1356,11 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
         dfac = nullptr;
     } else {
         R = (RT*)S.R + (size_t)w * T.rrow * ne;
+        if (SPLIT) Rlo = S.Rlo + (size_t)w * T.rrow * ne;
         B = S.B + (size_t)w * ne * ne;
         Rh = R;
         uint8_t* sc = S.scratch + (size_t)w * S.scratch_stride;
+        if (T.has_sV && T.fock) Fk = (double*)(sc + scratch_fock_offset(ne));
         const size_t st4 = al16((size_t)gd * 4);
         dgend = (uint32_t*)sc;
         ddelta = (uint32_t*)(sc + st4);
@@ -1119,7 +1368,8 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
         dpq = (uint32_t*)(sc + 3 * st4);
         dfac = (double*)(sc + 4 * st4);
     }
-    const StepView<RT> V{occl, es, SMALL ? Rh : R, sgend, sdelta, svend, spq, sfac, dgend, ddelta, dvend, dpq, dfac};
+    const StepView<RT> V{occl, es,   SMALL ? Rh : R, sgend, sdelta, svend, spq, sfac, dgend, ddelta, dvend, dpq, dfac,
+                         slot, cidx, cinv, Fk};
 
     // ---------------------------------------------------------------- load
     if (th_lds)
@@ -1165,7 +1415,7 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
         __syncthreads();
         // refresh_period 0: the caller runs the separate refresh kernel next
         // (always, with spin-blocked orbitals)
-        if (refresh_period > 0 && !UHF) refresh_state(T, slot, B, R, s, fcol, ipiv, mi, red, th, ths);
+        if (refresh_period > 0 && !UHF) refresh_state<RT, SPLIT>(T, slot, B, R, s, fcol, ipiv, mi, red, th, ths, Rlo);
     } else {
         for (int k = tid; k < ne; k += nt) slot[k] = S.slot_orb[(size_t)w * ne + k];
         for (int pp = tid; pp < n_so; pp += nt) {
@@ -1198,6 +1448,7 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
     const int steps = (mode == MODE_CTMC) ? n_steps : 1;
     double el_last = 0.0, t_last = 0.0;
     int64_t code_last = 0;
+    bool moved = false;  // block-uniform: some move changed the state
     for (int k = 0; k < steps && mode != MODE_INIT; ++k) {
         const uint64_t gstep = step0 + (uint64_t)k;
         const bool singular = (mi[MI_ST] & (int)VMC_ST_SINGULAR) != 0;
@@ -1211,6 +1462,7 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
             rank += __popcll(occw[pp >> 6] & ((1ull << (pp & 63)) - 1ull));
             occl[rank] = pp;
         }
+        if (T.ncorr) cps_states(T, occw, cidx, cinv);
         __syncthreads();
         if (SMALL) {
             // Rh[p][a] = R[a][p] exp(s_a) exp(-s_i), i = slot[p]: the Jastrow
@@ -1298,6 +1550,12 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
         }
         __syncthreads();
 
+        // Fock-like singles elements of the occupied rows, from scratch at the
+        // first move of the launch, updated after every move below
+        if (Fk && k == 0 && !singular) {
+            fock_rows(T, Fk, occl, ne, occl, ne);
+            __syncthreads();
+        }
         // ------------------------------------------------- local energy
         double el_lane = 0.0;
         if (!singular) {
@@ -1425,11 +1683,14 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
         if (ptype != 0) {
             const int p = mi[MI_PP], q = mi[MI_PQ], a = mi[MI_PA], b = mi[MI_PB];
             const int i = slot[p], j = (ptype == 2) ? slot[q] : -1;
-            // rows a (and b) of R over the slots, in FP64.  FP64 form: read
-            // from R.  Small mixed form: recomputed as theta[a, 0:Ne] B from
-            // theta in LDS, so that B stays FP64-exact.  Large mixed form: read
-            // from the FP32 R, with the pivot entries (the denominators)
-            // recomputed in FP64 below.
+            // rows a (and b) of R over the slots, w, in FP64: read from R (the
+            // split storage of the mixed form with the state in HBM gives them
+            // to about 2^-33), or in the small mixed form recomputed as
+            // theta[a, 0:Ne] B from theta in LDS, one thread per slot
+            const int rrow = UHF ? T.n : n_so;
+            auto rval = [&](size_t idx) __attribute__((always_inline)) -> double {
+                return SPLIT ? (double)R[idx] + (double)bf16_val(Rlo[idx]) : (double)R[idx];
+            };
             for (int x = tid; x < ne; x += nt) {
                 double ra, rb = 0.0;
                 if (MIXED && SMALL) {
@@ -1444,29 +1705,47 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
                 } else if (UHF) {
                     // spin-blocked: a slot of the other spin holds zero
                     const bool xb = x >= T.na;
-                    ra = (xb == (a >= T.n)) ? (double)R[r_index_uhf(T, x, a)] : 0.0;
-                    if (ptype == 2) rb = (xb == (b >= T.n)) ? (double)R[r_index_uhf(T, x, b)] : 0.0;
+                    ra = (xb == (a >= T.n)) ? rval(r_index_uhf(T, x, a)) : 0.0;
+                    if (ptype == 2) rb = (xb == (b >= T.n)) ? rval(r_index_uhf(T, x, b)) : 0.0;
                 } else {
-                    ra = (double)R[x * n_so + a];
-                    if (ptype == 2) rb = (double)R[x * n_so + b];
+                    ra = rval((size_t)x * n_so + a);
+                    if (ptype == 2) rb = rval((size_t)x * n_so + b);
                 }
                 w1[x] = ra;
                 w2[x] = rb;
             }
-            // old columns p (and q) of R over the orbitals (not needed in the
-            // small mixed form, where R is re-formed after the move)
-            // (spin-blocked: the slot's row over its own spin's n orbitals)
-            const int rrow = UHF ? T.n : n_so;
-            const RT* Rp = R + p * rrow;
-            const RT* Rq = R + q * rrow;
-            if (!(MIXED && SMALL))
-                for (int a2 = tid; a2 < rrow; a2 += nt) {
-                    cRp[a2] = (double)Rp[a2];
-                    if (ptype == 2) cRq[a2] = (double)Rq[a2];
-                }
             for (int x = tid; x < ne; x += nt) {
                 cBp[x] = B[p * ne + x];
                 if (ptype == 2) cBq[x] = B[q * ne + x];
+            }
+            // old rows p (and q) of R over the orbitals (spin-blocked: over the
+            // slot's own spin's n orbitals); not needed in the small mixed
+            // form, where R is re-formed after the move
+            if (!(MIXED && SMALL)) {
+                for (int a2 = tid; a2 < rrow; a2 += nt) {
+                    cRp[a2] = rval((size_t)p * rrow + a2);
+                    if (ptype == 2) cRq[a2] = rval((size_t)q * rrow + a2);
+                }
+            }
+            if (SPLIT) {
+                // the Sherman-Morrison denominators in FP64 from B: entry (a', x)
+                // of R is theta[a', 0:Ne] B[x, :] (spin-blocked: zero across the
+                // spins, the dot over x's own block), one wave per entry
+                __syncthreads();  // the rows above read w before it is overwritten
+                const int nden = ptype == 2 ? 4 : 1;
+                for (int e = wv; e < nden; e += nwv) {
+                    const int ao = (e & 2) ? b : a, x = (e & 1) ? q : p;
+                    const bool xb = UHF && x >= T.na;
+                    double acc = 0.0;
+                    if (!UHF || (xb == (ao >= T.n))) {
+                        const int c0 = xb ? T.na : 0, c1 = (UHF && !xb) ? T.na : ne;
+                        const double* ta = th + (size_t)ao * ths;
+                        const double* Bx = B + x * ne;
+                        for (int c = c0 + l; c < c1; c += kWave) acc += ta[c] * Bx[c];
+                        acc = wave_total(acc);
+                    }
+                    if (l == 0) ((e & 2) ? w2 : w1)[x] = acc;
+                }
             }
             // change of H_NN (sum over the unchanged occupied orbitals)
             double dh = 0.0;
@@ -1477,29 +1756,6 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
                 if (ptype == 2) dh += T.D[(size_t)b * n_so + kk] - T.D[(size_t)j * n_so + kk];
             }
             dh = block_total(dh, red);  // its barriers also publish the rows and copies above
-            if (MIXED && !SMALL) {
-                // FP64 denominators: the pivot entries R[a][p] (R[a][q], R[b][p],
-                // R[b][q]) as theta[a, 0:Ne] B[:, p], one wave per entry
-                const int nk = (ptype == 2) ? 4 : 1;
-                for (int k = wv; k < nk; k += nwv) {
-                    const double* tr = th + (size_t)((k & 2) ? b : a) * ths;
-                    const double* Bc = B + ((k & 1) ? q : p) * ne;
-                    double acc = 0.0;
-                    for (int c = l; c < ne; c += kWave) acc += tr[c] * Bc[c];
-                    acc = wave_total(acc);
-                    if (l == 0) md[MD_C00 + k] = acc;
-                }
-                __syncthreads();
-                if (tid == 0) {
-                    w1[p] = md[MD_C00];
-                    if (ptype == 2) {
-                        w1[q] = md[MD_C01];
-                        w2[p] = md[MD_C10];
-                        w2[q] = md[MD_C11];
-                    }
-                }
-                __syncthreads();
-            }
             if (ptype == 1) {
                 const double rho = w1[p];
                 if (tid == 0 && fabs(rho) < 1e-8) mi[MI_ST] |= (int)VMC_ST_SMALLDEN;
@@ -1510,10 +1766,11 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
                 if (UHF) {
                     // one spin's block of R (its slots' rows) and of B
                     const int lo = (p >= T.na) ? T.na : 0, cnt = (p >= T.na) ? ne - T.na : T.na;
-                    rank_update<RT, false>(R + (size_t)lo * T.n, cnt, T.n, cRp, w1 + lo, nullptr, nullptr);
+                    r_update<RT, false, SPLIT>(R + (size_t)lo * T.n, Rlo + (SPLIT ? (size_t)lo * T.n : 0), cnt, T.n,
+                                               cRp, w1 + lo, nullptr, nullptr);
                     rank_update_ld<false>(B + (size_t)lo * ne + lo, cnt, cnt, ne, cBp + lo, w1 + lo, nullptr, nullptr);
                 } else {
-                    if (!(MIXED && SMALL)) rank_update<RT, false>(R, ne, n_so, cRp, w1, nullptr, nullptr);
+                    if (!(MIXED && SMALL)) r_update<RT, false, SPLIT>(R, Rlo, ne, n_so, cRp, w1, nullptr, nullptr);
                     rank_update<double, false>(B, ne, ne, cBp, w1, nullptr, nullptr);
                 }
                 if (tid == 0) md[MD_HNN] += dh + T.hdiag[a] - T.hdiag[i];
@@ -1534,21 +1791,23 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
                     if ((p >= na) == (q >= na)) {
                         // same spin: rank 2 on that spin's blocks
                         const int lo = (p >= na) ? na : 0, cnt = (p >= na) ? nb : na;
-                        rank_update<RT, true>(R + (size_t)lo * n, cnt, n, cRp, w1 + lo, cRq, w2 + lo);
+                        r_update<RT, true, SPLIT>(R + (size_t)lo * n, Rlo + (SPLIT ? (size_t)lo * n : 0), cnt, n,
+                                                  cRp, w1 + lo, cRq, w2 + lo);
                         rank_update_ld<true>(B + (size_t)lo * ne + lo, cnt, cnt, ne, cBp + lo, w1 + lo, cBq + lo,
                                              w2 + lo);
                     } else {
                         // opposite spins (p alpha, q beta): w1 vanishes on the
                         // beta slots and w2 on the alpha ones, so each spin's
                         // blocks take one rank-1 update
-                        rank_update<RT, false>(R, na, n, cRp, w1, nullptr, nullptr);
-                        rank_update<RT, false>(R + (size_t)na * n, nb, n, cRq, w2 + na, nullptr, nullptr);
+                        r_update<RT, false, SPLIT>(R, Rlo, na, n, cRp, w1, nullptr, nullptr);
+                        r_update<RT, false, SPLIT>(R + (size_t)na * n, Rlo + (SPLIT ? (size_t)na * n : 0), nb, n,
+                                                   cRq, w2 + na, nullptr, nullptr);
                         rank_update_ld<false>(B, na, na, ne, cBp, w1, nullptr, nullptr);
                         rank_update_ld<false>(B + (size_t)na * ne + na, nb, nb, ne, cBq + na, w2 + na, nullptr,
                                               nullptr);
                     }
                 } else {
-                    if (!(MIXED && SMALL)) rank_update<RT, true>(R, ne, n_so, cRp, w1, cRq, w2);
+                    if (!(MIXED && SMALL)) r_update<RT, true, SPLIT>(R, Rlo, ne, n_so, cRp, w1, cRq, w2);
                     rank_update<double, true>(B, ne, ne, cBp, w1, cBq, w2);
                 }
                 if (tid == 0)
@@ -1590,7 +1849,9 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
                 }
             }
             code_last = pack_pick(ptype, i, j, a, b);
+            moved = true;
             __syncthreads();
+            if (Fk) fock_move(T, Fk, slot, ne, i, ptype == 2 ? j : -1, a, ptype == 2 ? b : -1);
         }
         if (tid == 0) {
             if (eloc_hist) eloc_hist[(size_t)k * W + w] = el;
@@ -1599,7 +1860,7 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
         }
         // ------------------------------------------------------- refresh
         if (refresh_period > 0 && !UHF && ((gstep + 1) % (uint64_t)refresh_period) == 0) {
-            refresh_state(T, slot, B, R, s, fcol, ipiv, mi, red, th, ths);
+            refresh_state<RT, SPLIT>(T, slot, B, R, s, fcol, ipiv, mi, red, th, ths, Rlo);
             hnn_full();
         }
     }
@@ -1618,10 +1879,19 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
             double* Bg = S.B + (size_t)w * ne * ne;
             for (int k = tid; k < n_so * ne; k += nt) Rg[k] = R[k];
             for (int k = tid; k < ne * ne; k += nt) Bg[k] = B[k];
+            // the split remainder starts at zero should the walkers later run
+            // with their state in HBM (a batch)
+            if (MIXED) {
+                uint16_t* Lg = S.Rlo + (size_t)w * n_so * ne;
+                for (int k = tid; k < n_so * ne; k += nt) Lg[k] = 0;
+            }
         }
     }
     if (tid == 0) {
         S.hnn[w] = md[MD_HNN];
+        // walkers re-inverted by the separate refresh kernel carry updates
+        // since their last inversion once they have moved
+        if (mode == MODE_CTMC && !SMALL && refresh_period == 0 && moved) mi[MI_ST] |= (int)VMC_ST_STALE;
         S.status[w] = (uint32_t)mi[MI_ST];
         if (mode != MODE_INIT) {
             S.eloc[w] = el_last;
@@ -1695,10 +1965,12 @@ __host__ __device__ inline size_t refresh_lds_bytes(int ne, int nt) {
 // workgroup), then R = theta B on the matrix cores, s and H_NN.
 constexpr int kRefreshThreads = 512;
 template <typename RT>
-__global__ void __launch_bounds__(kRefreshThreads) k_refresh(Tab T, Wk S, int64_t W) {
+__global__ void __launch_bounds__(kRefreshThreads) k_refresh(Tab T, Wk S, int64_t W, int lazy) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int64_t w = blockIdx.x;
     if (w >= W) return;
+    // lazy: walkers that have not moved since their last inversion are skipped
+    if (lazy && !(S.status[w] & VMC_ST_STALE)) return;
     const int tid = threadIdx.x, nt = blockDim.x, nwv = nt >> 6;
     const int ne = T.ne, n_so = T.n_so;
     size_t o = 0;
@@ -1717,9 +1989,11 @@ __global__ void __launch_bounds__(kRefreshThreads) k_refresh(Tab T, Wk S, int64_
     if (tid == 0) mi[MI_ST] = (int)S.status[w];
     __syncthreads();
     RT* R = (RT*)S.R + (size_t)w * n_so * ne;
+    constexpr bool SPLIT = sizeof(RT) < sizeof(double);
+    uint16_t* Rlo = SPLIT ? S.Rlo + (size_t)w * n_so * ne : nullptr;
     double* s = S.s + (size_t)w * n_so;
     double* Bg = S.B + (size_t)w * ne * ne;
-    refresh_state(T, slot, B, R, s, fcol, ipiv, mi, red, T.theta, n_so);
+    refresh_state<RT, SPLIT>(T, slot, B, R, s, fcol, ipiv, mi, red, T.theta, n_so, Rlo);
     for (int k = tid; k < ne * ne; k += nt) Bg[k] = B[k];
     double hp = 0.0;
     for (int x = tid; x < ne; x += nt) {
@@ -1731,7 +2005,7 @@ __global__ void __launch_bounds__(kRefreshThreads) k_refresh(Tab T, Wk S, int64_
     const double hnn = block_total(hp, red);
     if (tid == 0) {
         S.hnn[w] = hnn;
-        S.status[w] = (uint32_t)mi[MI_ST];
+        S.status[w] = (uint32_t)mi[MI_ST] & ~(uint32_t)VMC_ST_STALE;
     }
 }
 
@@ -1778,12 +2052,17 @@ __host__ __device__ inline size_t refresh_gj_lds_bytes(int nm, int ne) {
 template <typename RT, int H, int JC, bool UHF>
 __global__ void __launch_bounds__(kRefreshThreads) __attribute__((amdgpu_waves_per_eu(4))) k_refresh_gj(Tab T, Wk S,
                                                                                                       int64_t W,
-                                                                                                      int spin) {
+                                                                                                      int spin,
+                                                                                                      int lazy) {
     constexpr int NW = kRefreshThreads / 64;
     static_assert(H * 64 <= 128 && NW * JC <= 128, "at most 128 rows and columns");
     extern __shared__ __align__(16) unsigned char smem[];
     const int64_t w = blockIdx.x;
     if (w >= W) return;
+    // lazy: walkers that have not moved since their last inversion are
+    // skipped (with spin-blocked orbitals the beta launch, which runs last,
+    // clears the mark, so both launches see it)
+    if (lazy && !(S.status[w] & VMC_ST_STALE)) return;
     const int ne_all = T.ne;
     const int lo = (UHF && spin) ? T.na : 0;
     const int tid = threadIdx.x, ne = UHF ? (spin ? ne_all - T.na : T.na) : ne_all, n_so = T.n_so, l = lane_id();
@@ -1866,7 +2145,7 @@ __global__ void __launch_bounds__(kRefreshThreads) __attribute__((amdgpu_waves_p
         const double pv = pvb[2 * b], ipv = pvb[2 * b + 1];
         if (piv < 64) used0 |= 1ull << piv;
         else used1 |= 1ull << (piv - 64);
-        singular |= !(fabs(pv) > 0.0);
+        singular |= !(fabs(pv) > 0.0) || !(fabs(pv) <= DBL_MAX);
         // every row: G[r][c] -= (G[r][k] / pv) G[p][c]; the pivot row reads
         // pv + 1 for G[p][k] and so becomes -G[p][c] / pv
         double t[H];
@@ -1916,9 +2195,11 @@ __global__ void __launch_bounds__(kRefreshThreads) __attribute__((amdgpu_waves_p
     __syncthreads();
     double* Bg = S.B + (size_t)w * ne_all * ne_all;
     RT* R = (RT*)S.R + (size_t)w * T.rrow * ne_all;
+    constexpr bool SPLIT = sizeof(RT) < sizeof(double);
+    uint16_t* Rlo = SPLIT ? S.Rlo + (size_t)w * T.rrow * ne_all : nullptr;
     if (!UHF) {
         for (int k = tid; k < ne * ne; k += kRefreshThreads) Bg[k] = Bs[k];
-        r_gemm_theta_regs<RT, 16 * H>(T, Bs, R, T.theta, n_so);
+        r_gemm_theta_regs<RT, 16 * H, SPLIT>(T, Bs, R, T.theta, n_so, Rlo);
     } else {
         // this spin's rows of B, zero outside the block
         for (int k = tid; k < ne * ne_all; k += kRefreshThreads) {
@@ -1930,8 +2211,9 @@ __global__ void __launch_bounds__(kRefreshThreads) __attribute__((amdgpu_waves_p
         Tab Tb = T;
         Tb.ne = ne;
         Tb.n_so = T.n;
-        r_gemm_theta_regs<RT, 16 * H>(Tb, Bs, R + (size_t)lo * T.n, T.theta + (size_t)(spin ? T.n : 0) * n_so + lo,
-                                      n_so);
+        r_gemm_theta_regs<RT, 16 * H, SPLIT>(Tb, Bs, R + (size_t)lo * T.n,
+                                             T.theta + (size_t)(spin ? T.n : 0) * n_so + lo, n_so,
+                                             SPLIT ? Rlo + (size_t)lo * T.n : nullptr);
         if (spin == 0) {
             if (tid == 0) S.status[w] = (uint32_t)flag[0];
             return;
@@ -1961,7 +2243,7 @@ __global__ void __launch_bounds__(kRefreshThreads) __attribute__((amdgpu_waves_p
     const double hnn = block_total(hp, red);
     if (tid == 0) {
         S.hnn[w] = hnn;
-        S.status[w] = (uint32_t)flag[0];
+        S.status[w] = (uint32_t)flag[0] & ~(uint32_t)VMC_ST_STALE;
     }
 }
 
@@ -1977,6 +2259,8 @@ __global__ void __launch_bounds__(64) k_excitations(Tab T, Wk S, int64_t w, int3
     double* es = (double*)(smem + al16((size_t)nw * 8) + al16((size_t)ne * 4) + al16((size_t)n_so * 4));
     double* ies = es + n_so;
     uint32_t* queue = (uint32_t*)(ies + n_so);
+    double* cinv = (double*)(queue + kQueue);
+    uint32_t* cidx = (uint32_t*)(cinv + T.ncorr);
     for (int k = l; k < nw; k += 64) occw[k] = S.occ[(size_t)w * nw + k];
     for (int pp = l; pp < n_so; pp += 64) {
         oslot[pp] = S.orb_slot[(size_t)w * n_so + pp];
@@ -1992,6 +2276,7 @@ __global__ void __launch_bounds__(64) k_excitations(Tab T, Wk S, int64_t w, int3
             rank += __popcll(occw[pp >> 6] & ((1ull << (pp & 63)) - 1ull));
             occl[rank] = pp;
         }
+    if (T.ncorr) cps_states(T, occw, cidx, cinv);
     __syncthreads();
     const RT* R = (const RT*)S.R + (size_t)w * T.rrow * ne;
     int64_t off = 0;
@@ -2003,10 +2288,10 @@ __global__ void __launch_bounds__(64) k_excitations(Tab T, Wk S, int64_t w, int3
                 int a, b = -1;
                 double r, h;
                 if (Gr.type == 1) {
-                    r = single_ratio(T, Gr, e, R, es, a);
+                    r = single_ratio(T, Gr, e, R, es, cidx, cinv, a);
                     h = single_h(T, Gr, e, occl);
                 } else {
-                    r = double_ratio(T, Gr, e, R, es, a, b);
+                    r = double_ratio(T, Gr, e, R, es, cidx, cinv, a, b);
                     h = T.dvK[2 * (size_t)(Gr.base + e)];
                 }
                 if (pos < cap) {
@@ -2104,50 +2389,218 @@ __global__ void k_logderiv_dense(Tab T, Wk S, double* out, int64_t n_p) {
         const int sl = oslot[k];
         o[nj + idx] = (sl >= 0 && x < ne) ? B[(size_t)sl * ne + x] : 0.0;
     }
-}
-
-// Jastrow part of G = sum_w g_w O_w: G[p<=q] = sum_w g_w n_p n_q, split over
-// nsplit walker ranges (partials combined in a fixed order afterwards).
-__global__ void k_grad_J(Tab T, Wk S, int64_t W, const double* g, double* part, int64_t n_p, int nsplit) {
-    const int p = blockIdx.x, sp = blockIdx.y;
-    const int n_so = T.n_so, nw = T.nw;
-    const int64_t w0 = W * sp / nsplit, w1 = W * (sp + 1) / nsplit;
-    const int64_t start = (int64_t)p * n_so - (int64_t)p * (p - 1) / 2;
-    for (int q = p + threadIdx.x; q < n_so; q += blockDim.x) {
-        double acc = 0.0;
-#pragma unroll 4
-        for (int64_t w = w0; w < w1; ++w) {
-            const uint64_t* occ = S.occ + (size_t)w * nw;
-            if (((occ[p >> 6] >> (p & 63)) & 1ull) && ((occ[q >> 6] >> (q & 63)) & 1ull)) acc += g[w];
-        }
-        part[(size_t)sp * n_p + start + (q - p)] = acc;
-    }
-}
-
-// Orbital part: G[k][x] = sum_w g_w B_w[x][slot_w(k)] for occupied k, x < Ne.
-__global__ void k_grad_theta(Tab T, Wk S, int64_t W, const double* g, double* part, int64_t n_p, int nsplit) {
-    const int k = blockIdx.x, sp = blockIdx.y;
-    const int n_so = T.n_so, ne = T.ne;
-    const int64_t w0 = W * sp / nsplit, w1 = W * (sp + 1) / nsplit;
-    const int64_t nj = (int64_t)n_so * (n_so + 1) / 2;
-    for (int x = threadIdx.x; x < n_so; x += blockDim.x) {
-        double acc = 0.0;
-        if (x < ne)
-#pragma unroll 4
-            for (int64_t w = w0; w < w1; ++w) {
-                const int sl = S.orb_slot[(size_t)w * n_so + k];
-                if (sl >= 0) acc += g[w] * S.B[(size_t)w * ne * ne + (size_t)sl * ne + x];
+    if (T.ncorr) {
+        // correlators: 1/c at the state each correlator sees, 0 elsewhere
+        double* oc = o + nj + (int64_t)n_so * n_so;
+        const int ncoef = T.coff[T.ncorr];
+        for (int e = threadIdx.x; e < ncoef; e += blockDim.x) oc[e] = 0.0;
+        __syncthreads();
+        for (int lam = threadIdx.x; lam < T.ncorr; lam += blockDim.x) {
+            int idx = 0, wt = 1;
+            for (int m = 0; m < 5; ++m) {
+                const int site = T.csite[5 * lam + m];
+                if (site < 0) break;
+                const int b = site + T.n;
+                idx += wt * (int)(((occ[site >> 6] >> (site & 63)) & 1ull) + 2 * ((occ[b >> 6] >> (b & 63)) & 1ull));
+                wt *= 4;
             }
-        part[(size_t)sp * n_p + nj + (size_t)k * n_so + x] = acc;
+            oc[T.coff[lam] + idx] = 1.0 / T.cc[T.coff[lam] + idx];
+        }
     }
 }
 
-__global__ void k_combine(const double* part, double* out, int64_t n_p, int nsplit) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n_p) return;
-    double acc = 0.0;
-    for (int sp = 0; sp < nsplit; ++sp) acc += part[(size_t)sp * n_p + k];
-    out[k] = acc;
+// Jastrow part of G = sum_w g_w O_w: G_J[p][q] = sum_w g_w n_p(w) n_q(w) for
+// p <= q, i.e. Occ^T diag(g) Occ with Occ the W x n_so occupation matrix, a
+// symmetric rank-W update on the FP64 matrix cores.  One workgroup per 16 x 16
+// tile (pt <= qt) of G_J, four waves over contiguous walker ranges.  A wave
+// loads 64 walkers at a time (lane = walker: the occupation words of the
+// tile's rows and columns, and g_w) and feeds them to 16 mfma_f64_16x16x4
+// steps, A[m][k] = g_w n_p and B[k][m] = n_q for walker k of the step; the
+// four partial tiles are added in wave order, so the result is deterministic.
+constexpr int kSyrkWaves = 4;
+__global__ void __launch_bounds__(64 * kSyrkWaves) k_grad_J_syrk(Tab T, Wk S, int64_t W, const double* g,
+                                                                 double* out) {
+    __shared__ double part[kSyrkWaves][16][16];
+    const int n_so = T.n_so, nw = T.nw, nt16 = (n_so + 15) >> 4;
+    int t = blockIdx.x, pt = 0;
+    while (t >= nt16 - pt) {
+        t -= nt16 - pt;
+        ++pt;
+    }
+    const int qt = pt + t;
+    const int l = lane_id(), m = l & 15, kq = l >> 4;
+    const int wv = (int)uni((uint32_t)(threadIdx.x >> 6));
+    // a 16-aligned tile lies within one 64-bit occupation word
+    const int wp = (pt * 16) >> 6, wq = (qt * 16) >> 6;
+    const int bp = (pt * 16 + m) & 63, bq = (qt * 16 + m) & 63;
+    const int64_t w0 = W * wv / kSyrkWaves, w1 = W * (wv + 1) / kSyrkWaves;
+    Mma<double>::acc_t acc = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t c = w0; c < w1; c += kWave) {
+        const int64_t wl = c + l;
+        uint64_t op = 0, oq = 0;
+        double gv = 0.0;
+        if (wl < w1) {
+            op = S.occ[(size_t)wl * nw + wp];
+            oq = S.occ[(size_t)wl * nw + wq];
+            gv = g[wl];
+        }
+#pragma unroll
+        for (int st = 0; st < 16; ++st) {
+            const int src = 4 * st + kq;
+            const uint64_t sp = ((uint64_t)(uint32_t)__shfl((int)(op >> 32), src, kWave) << 32) |
+                                (uint32_t)__shfl((int)(uint32_t)op, src, kWave);
+            const uint64_t sq = ((uint64_t)(uint32_t)__shfl((int)(oq >> 32), src, kWave) << 32) |
+                                (uint32_t)__shfl((int)(uint32_t)oq, src, kWave);
+            const double sg = __shfl(gv, src, kWave);
+            const double a = ((sp >> bp) & 1ull) ? sg : 0.0;
+            const double b = ((sq >> bq) & 1ull) ? 1.0 : 0.0;
+            acc = Mma<double>::step(a, b, acc);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) part[wv][Mma<double>::row(kq, j)][m] = acc[j];
+    __syncthreads();
+    for (int e = threadIdx.x; e < 256; e += blockDim.x) {
+        const int r = e >> 4, cc = e & 15;
+        const int p = pt * 16 + r, q = qt * 16 + cc;
+        if (p >= n_so || q >= n_so || q < p) continue;
+        double v = 0.0;
+        for (int k = 0; k < kSyrkWaves; ++k) v += part[k][r][cc];
+        out[(int64_t)p * n_so - (int64_t)p * (p - 1) / 2 + (q - p)] = v;
+    }
+}
+
+// Orbital part: G[k][x] = sum_w g_w B_w[slot_w(k)][x] over the walkers that
+// hold orbital k (B column by slot: the row of slot s is contiguous over x),
+// x < Ne; zero for x >= Ne.  One workgroup per orbital k, 16 waves over
+// contiguous walker ranges, lanes over x (NR values each, Ne <= 64 NR).  A
+// wave loads the slots and weights of 64 walkers at once (lane = walker),
+// then accumulates the rows of those that hold k, several rows in flight
+// (four, or fewer for long rows so that they stay in registers);
+// walkers with g_w = 0 (flagged ones among them) are skipped, so a
+// non-finite B of a flagged walker cannot reach G.  The 16 partial rows are
+// added in wave order: deterministic.
+constexpr int kGradWaves = 16;
+template <int NR>
+__global__ void __launch_bounds__(64 * kGradWaves) k_grad_theta_rows(Tab T, Wk S, int64_t W, const double* g,
+                                                                     double* out, int64_t nj) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    double* buf = (double*)smem;  // Ne doubles
+    const int k = blockIdx.x, n_so = T.n_so, ne = T.ne, l = lane_id();
+    const int wv = (int)uni((uint32_t)(threadIdx.x >> 6));
+    const int64_t w0 = W * wv / kGradWaves, w1 = W * (wv + 1) / kGradWaves;
+    constexpr int UF = NR <= 4 ? 4 : NR <= 8 ? 2 : 1;  // rows in flight
+    double acc[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[r] = 0.0;
+    for (int64_t c = w0; c < w1; c += kWave) {
+        const int64_t wl = c + l;
+        int sl = -1;
+        double gv = 0.0;
+        if (wl < w1) {
+            sl = S.orb_slot[(size_t)wl * n_so + k];
+            gv = g[wl];
+        }
+        uint64_t m = __ballot(sl >= 0 && gv != 0.0);
+        while (m) {
+            // up to UF walkers of this chunk at a time, their rows loaded together
+            int jl[UF];
+            int cnt = 0;
+#pragma unroll
+            for (int u = 0; u < UF; ++u) {
+                jl[u] = 0;
+                if (m) {
+                    jl[u] = __ffsll((unsigned long long)m) - 1;
+                    m &= m - 1;
+                    ++cnt;
+                }
+            }
+            double v[UF][NR];
+            double gw[UF];
+#pragma unroll
+            for (int u = 0; u < UF; ++u) {
+                gw[u] = 0.0;
+                if (u < cnt) {
+                    const int j = (int)uni((uint32_t)jl[u]);
+                    const int slot = __builtin_amdgcn_readlane(sl, j);
+                    gw[u] = readlane_d(gv, j);
+                    const double* row = S.B + ((size_t)(c + j) * ne + slot) * ne;
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) {
+                        const int x = l + 64 * r;
+                        v[u][r] = (x < ne) ? row[x] : 0.0;
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < UF; ++u)
+                if (u < cnt)
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) acc[r] = fma(gw[u], v[u][r], acc[r]);
+        }
+    }
+    for (int q = 0; q < kGradWaves; ++q) {
+        if (wv == q)
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const int x = l + 64 * r;
+                if (x < ne) buf[x] = (q ? buf[x] : 0.0) + acc[r];
+            }
+        __syncthreads();
+    }
+    double* o = out + nj + (size_t)k * n_so;
+    for (int x = threadIdx.x; x < n_so; x += blockDim.x) o[x] = (x < ne) ? buf[x] : 0.0;
+}
+
+// Correlator part of G = sum_w g_w O_w: G[l][n] = (sum of g_w over the walkers
+// whose correlator l is in state n) / c_l[n].  One workgroup per correlator,
+// four waves over contiguous walker ranges; a wave reads the states and
+// weights of 64 walkers at once (lane = walker) and adds them into its own LDS
+// histogram in walker order (lane 0, one walker at a time); the four
+// histograms are added in wave order.  Deterministic; walkers with g_w = 0
+// add nothing.
+constexpr int kCpsWaves = 4;
+__global__ void __launch_bounds__(64 * kCpsWaves) k_grad_cps(Tab T, Wk S, int64_t W, const double* g, double* out,
+                                                             int64_t off0) {
+    __shared__ double hist[kCpsWaves][1024];
+    const int lam = blockIdx.x, l = lane_id(), nw = T.nw;
+    const int wv = (int)uni((uint32_t)(threadIdx.x >> 6));
+    const int c0 = T.coff[lam], ns = T.coff[lam + 1] - c0;
+    int st[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) st[m] = T.csite[5 * lam + m];
+    for (int e = threadIdx.x; e < kCpsWaves * 1024; e += blockDim.x) (&hist[0][0])[e] = 0.0;
+    __syncthreads();
+    const int64_t w0 = W * wv / kCpsWaves, w1 = W * (wv + 1) / kCpsWaves;
+    for (int64_t c = w0; c < w1; c += kWave) {
+        const int64_t wl = c + l;
+        int idx = 0;
+        double gv = 0.0;
+        if (wl < w1) {
+            const uint64_t* occ = S.occ + (size_t)wl * nw;
+            int wt = 1;
+#pragma unroll
+            for (int m = 0; m < 5; ++m)
+                if (st[m] >= 0) {
+                    const int a = st[m], b = st[m] + T.n;
+                    idx += wt * (int)(((occ[a >> 6] >> (a & 63)) & 1ull) + 2 * ((occ[b >> 6] >> (b & 63)) & 1ull));
+                    wt *= 4;
+                }
+            gv = g[wl];
+        }
+        const int cnt = (int)min<int64_t>(kWave, w1 - c);
+        for (int j = 0; j < cnt; ++j) {
+            const double gj = readlane_d(gv, j);
+            const int ij = __builtin_amdgcn_readlane(idx, j);
+            if (gj != 0.0 && l == 0) hist[wv][ij] += gj;
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < ns; e += blockDim.x) {
+        double v = 0.0;
+        for (int q = 0; q < kCpsWaves; ++q) v += hist[q][e];
+        out[off0 + c0 + e] = v / T.cc[c0 + e];
+    }
 }
 
 __global__ void k_amsgrad(int64_t n, double* p, double* m, double* v, double* vh, const double* g, double lr, double b1,
@@ -2231,12 +2684,19 @@ struct vmc_ctx {
     int block_threads = 0;  // 0 = automatic
     int64_t n_dent = 0, n_sent = 0;
     bool has_sV = true;
+    bool fock = false;  // singles elements kept per walker (see Tab::fock)
     uint32_t *d_row_off = nullptr, *d_dab = nullptr, *d_s_off = nullptr, *d_sa = nullptr;
     uint64_t* d_dmask = nullptr;
     double *d_dvK = nullptr, *d_sh = nullptr, *d_sV = nullptr, *d_sK = nullptr, *d_D = nullptr,
-           *d_hdiag = nullptr, *d_J = nullptr, *d_theta = nullptr, *d_part = nullptr;
-    int64_t part_cap = 0;
+           *d_hdiag = nullptr, *d_J = nullptr, *d_theta = nullptr;
     bool params_set = false;
+    // correlators (vmc_cps_init, vmc_set_cps)
+    int ncorr = 0;
+    int64_t n_coef = 0;
+    int32_t *d_csite = nullptr, *d_coff = nullptr, *d_sc_off = nullptr;
+    uint32_t* d_sc_list = nullptr;
+    double* d_cc = nullptr;
+    bool cps_set = false;
     std::string err;
 };
 
@@ -2286,15 +2746,24 @@ Tab make_tab(const vmc_ctx* h) {
     T.sV = h->d_sV;
     T.has_doubles = h->n_dent > 0 ? 1 : 0;
     T.has_sV = h->has_sV ? 1 : 0;
+    T.fock = (h->has_sV && h->fock) ? 1 : 0;
     T.sK = h->d_sK;
     T.D = h->d_D;
     T.hdiag = h->d_hdiag;
     T.J = h->d_J;
     T.theta = h->d_theta;
+    T.ncorr = h->ncorr;
+    T.csite = h->d_csite;
+    T.coff = h->d_coff;
+    T.cc = h->d_cc;
+    T.sc_off = h->d_sc_off;
+    T.sc_list = h->d_sc_list;
     return T;
 }
 
-int64_t scratch_bytes(const vmc_ctx* h) { return (int64_t)scratch_layout_bytes(h->ne); }
+// the Fock-like elements are sized whatever the launch shape, so that a later
+// vmc_set_launch cannot outgrow walkers allocated before it
+int64_t scratch_bytes(const vmc_ctx* h) { return (int64_t)scratch_layout_bytes(h->ne, h->has_sV ? h->n_sent : 0); }
 
 // bytes per element of R: FP64 form 8, mixed form 4
 size_t r_bytes(const vmc_ctx* h) { return h->precision == VMC_MIXED ? 4 : 8; }
@@ -2305,7 +2774,9 @@ vmc_status check_walkers(vmc_ctx* h, const vmc_walkers* w) {
     if (!w->occ_bits || !w->slot_orb || !w->orb_slot || !w->ainv || !w->r || !w->jsum || !w->hnn || !w->eloc ||
         !w->tres || !w->pick || !w->status || !w->scratch)
         return fail(h, VMC_E_ARG, "a walker field pointer is NULL");
+    if (h->precision == VMC_MIXED && !w->rlo) return fail(h, VMC_E_ARG, "the mixed form needs the rlo field");
     if (!h->params_set) return fail(h, VMC_E_ARG, "vmc_set_params has not been called");
+    if (h->ncorr > 0 && !h->cps_set) return fail(h, VMC_E_ARG, "vmc_set_cps has not been called");
     return VMC_OK;
 }
 
@@ -2316,6 +2787,7 @@ Wk make_wk(const vmc_ctx* h, const vmc_walkers* w) {
     S.orb_slot = (int32_t*)w->orb_slot;
     S.B = (double*)w->ainv;
     S.R = w->r;
+    S.Rlo = (uint16_t*)w->rlo;
     S.s = (double*)w->jsum;
     S.hnn = (double*)w->hnn;
     S.eloc = (double*)w->eloc;
@@ -2395,8 +2867,8 @@ SweepGeom sweep_geom(const vmc_ctx* h) {
     g.nt = h->block_threads > 0 ? h->block_threads : 256;
     const int rb = (int)r_bytes(h);
     // spin-blocked orbitals: always the layout with the walker state in HBM
-    g.small = !h->uhf && lds_layout(h->n_so, h->ne, h->nw, g.nt, true, rb).total <= kMaxLds;
-    g.lds = lds_layout(h->n_so, h->ne, h->nw, g.nt, g.small, rb).total;
+    g.small = !h->uhf && lds_layout(h->n_so, h->ne, h->nw, g.nt, true, rb, h->ncorr).total <= kMaxLds;
+    g.lds = lds_layout(h->n_so, h->ne, h->nw, g.nt, g.small, rb, h->ncorr).total;
     return g;
 }
 
@@ -2427,7 +2899,7 @@ const void* refresh_gj_kernel(int rows, bool mixed, bool uhf) {
     return uhf ? (const void*)k_refresh_gj<double, 2, 16, true> : (const void*)k_refresh_gj<double, 2, 16, false>;
 }
 
-vmc_status launch_refresh(vmc_ctx* h, vmc_walkers* w, hipStream_t st) {
+vmc_status launch_refresh(vmc_ctx* h, vmc_walkers* w, hipStream_t st, bool lazy = false) {
     const size_t lds = refresh_lds_bytes(h->ne, kRefreshThreads);
     const Tab T = make_tab(h);
     const Wk S = make_wk(h, w);
@@ -2440,17 +2912,18 @@ vmc_status launch_refresh(vmc_ctx* h, vmc_walkers* w, hipStream_t st) {
         Wk Sa = S;
         int64_t Wa = w->n_walkers;
         // spin-blocked: the alpha block, then the beta block (stream order)
+        int lz = lazy ? 1 : 0;
         for (int spin = 0; spin < (h->uhf ? 2 : 1); ++spin) {
             int sp = spin;
-            void* args[] = {&Ta, &Sa, &Wa, &sp};
+            void* args[] = {&Ta, &Sa, &Wa, &sp, &lz};
             HIP_OR_FAIL(h, hipLaunchKernel(refresh_gj_kernel(rows, mixed, h->uhf), grid, block, args, b, st));
         }
         return VMC_OK;
     }
     if (h->precision == VMC_MIXED) {
-        hipLaunchKernelGGL((k_refresh<float>), grid, block, lds, st, T, S, w->n_walkers);
+        hipLaunchKernelGGL((k_refresh<float>), grid, block, lds, st, T, S, w->n_walkers, lazy ? 1 : 0);
     } else {
-        hipLaunchKernelGGL((k_refresh<double>), grid, block, lds, st, T, S, w->n_walkers);
+        hipLaunchKernelGGL((k_refresh<double>), grid, block, lds, st, T, S, w->n_walkers, lazy ? 1 : 0);
     }
     HIP_OR_FAIL(h, hipGetLastError());
     return VMC_OK;
@@ -2481,8 +2954,9 @@ vmc_status upload(vmc_ctx* h, T** dst, const std::vector<T>& src, hipStream_t st
 
 void free_ctx(vmc_ctx* h) {
     if (!h) return;
-    void* ptrs[] = {h->d_row_off, h->d_dab, h->d_dmask, h->d_s_off, h->d_sa, h->d_dvK, h->d_sh, h->d_sV,
-                    h->d_sK,      h->d_D,   h->d_hdiag, h->d_J,  h->d_theta, h->d_part};
+    void* ptrs[] = {h->d_row_off, h->d_dab,   h->d_dmask, h->d_s_off, h->d_sa,   h->d_dvK,    h->d_sh,
+                    h->d_sV,      h->d_sK,    h->d_D,     h->d_hdiag, h->d_J,    h->d_theta,  h->d_csite,
+                    h->d_coff,    h->d_sc_off, h->d_sc_list, h->d_cc};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete h;
@@ -2727,6 +3201,66 @@ vmc_status vmc_set_params(vmc_handle h, const double* J_dev, const double* theta
     return VMC_OK;
 }
 
+vmc_status vmc_cps_init(vmc_handle h, int32_t n_corr, const int32_t* sites) {
+    if (!h) return fail(nullptr, VMC_E_ARG, "handle is NULL");
+    if (h->ncorr > 0) return fail(h, VMC_E_ARG, "correlators are already set for this handle");
+    if (n_corr < 1 || n_corr >= (1 << 24) || !sites) return fail(h, VMC_E_ARG, "n_corr must be in 1..2^24-1 with sites");
+    const int n = h->n;
+    std::vector<int32_t> csite((size_t)5 * n_corr), coff((size_t)n_corr + 1, 0), sc_off((size_t)n + 1, 0);
+    std::vector<std::vector<uint32_t>> per_site((size_t)n);
+    int64_t total = 0;
+    for (int l = 0; l < n_corr; ++l) {
+        int k = 0;
+        while (k < 5 && sites[5 * l + k] >= 0) ++k;
+        if (k == 0) return fail(h, VMC_E_ARG, "correlator " + std::to_string(l) + " has no site");
+        for (int m = 0; m < 5; ++m) {
+            const int st = (m < k) ? sites[5 * l + m] : -1;
+            if (m < k && st >= n) return fail(h, VMC_E_ARG, "correlator " + std::to_string(l) + ": site out of range");
+            for (int m2 = 0; m2 < m && m < k; ++m2)
+                if (csite[5 * l + m2] == st) return fail(h, VMC_E_ARG, "correlator " + std::to_string(l) + ": repeated site");
+            csite[5 * (size_t)l + m] = st;
+            if (m < k) per_site[st].push_back((uint32_t)l | ((uint32_t)m << 24));
+        }
+        total += (int64_t)1 << (2 * k);
+        if (total >= INT_MAX) return fail(h, VMC_E_UNSUPPORTED, "too many correlator coefficients");
+        coff[l + 1] = (int32_t)total;
+    }
+    std::vector<uint32_t> sc_list;
+    for (int st = 0; st < n; ++st) {
+        sc_off[st] = (int32_t)sc_list.size();
+        sc_list.insert(sc_list.end(), per_site[st].begin(), per_site[st].end());
+    }
+    sc_off[n] = (int32_t)sc_list.size();
+    vmc_status u = VMC_OK;
+    if ((u = upload(h, &h->d_csite, csite, nullptr)) != VMC_OK || (u = upload(h, &h->d_coff, coff, nullptr)) != VMC_OK ||
+        (u = upload(h, &h->d_sc_off, sc_off, nullptr)) != VMC_OK ||
+        (u = upload(h, &h->d_sc_list, sc_list, nullptr)) != VMC_OK)
+        return u;
+    if (hipMalloc((void**)&h->d_cc, sizeof(double) * (size_t)total) != hipSuccess)
+        return fail(h, VMC_E_OOM, "hipMalloc failed for correlator coefficients");
+    HIP_OR_FAIL(h, hipStreamSynchronize(nullptr));
+    h->ncorr = n_corr;
+    h->n_coef = total;
+    h->cps_set = false;
+    return VMC_OK;
+}
+
+vmc_status vmc_set_cps(vmc_handle h, const double* coeffs_dev, hipStream_t st) {
+    if (!h) return fail(nullptr, VMC_E_ARG, "handle is NULL");
+    if (h->ncorr == 0) return fail(h, VMC_E_ARG, "vmc_cps_init has not been called");
+    if (!coeffs_dev) return fail(h, VMC_E_ARG, "coefficient pointer is NULL");
+    HIP_OR_FAIL(h, hipMemcpyAsync(h->d_cc, coeffs_dev, sizeof(double) * (size_t)h->n_coef, hipMemcpyDeviceToDevice, st));
+    h->cps_set = true;
+    return VMC_OK;
+}
+
+vmc_status vmc_cps_info(vmc_handle h, int64_t out[2]) {
+    if (!h || !out) return fail(h, VMC_E_ARG, "NULL argument");
+    out[0] = h->ncorr;
+    out[1] = h->n_coef;
+    return VMC_OK;
+}
+
 vmc_status vmc_walker_bytes(vmc_handle h, int64_t W, size_t fb[VMC_NFIELDS]) {
     if (!h) return fail(nullptr, VMC_E_ARG, "handle is NULL");
     if (!fb || W <= 0) return fail(h, VMC_E_ARG, "bad arguments");
@@ -2736,6 +3270,7 @@ vmc_status vmc_walker_bytes(vmc_handle h, int64_t W, size_t fb[VMC_NFIELDS]) {
     fb[VMC_F_ORB_SLOT] = w * h->n_so * 4;
     fb[VMC_F_AINV] = w * h->ne * h->ne * 8;
     fb[VMC_F_R] = w * h->ne * (h->uhf ? h->n : h->n_so) * r_bytes(h);
+    fb[VMC_F_RLO] = h->precision == VMC_MIXED ? w * h->ne * (h->uhf ? h->n : h->n_so) * 2 : 0;
     fb[VMC_F_JSUM] = w * h->n_so * 8;
     fb[VMC_F_HNN] = w * 8;
     fb[VMC_F_ELOC] = w * 8;
@@ -2823,12 +3358,16 @@ vmc_status vmc_ctmc_step_dev(vmc_handle h, vmc_walkers* w, int32_t n_steps, uint
     } else {
         if (n_steps % h->refresh != 0)
             return fail(h, VMC_E_ARG, "with the separate refresh kernel, n_steps must be a multiple of refresh_period");
+        // before every segment of refresh_period moves, a lazy re-inversion:
+        // walkers marked STALE (moved since their last inversion) are
+        // re-inverted, fresh ones skip it, whatever state a replay finds
         for (int k = 0; k < n_steps && s == VMC_OK; k += h->refresh) {
-            s = launch_sweep(h, w, SweepArgs{MODE_CTMC, h->refresh, 0, (uint64_t)k, nullptr, nullptr, nullptr, step_dev},
-                             st);
-            if (s == VMC_OK) s = launch_refresh(h, w, st);
+            s = launch_refresh(h, w, st, true);
+            if (s == VMC_OK)
+                s = launch_sweep(h, w, SweepArgs{MODE_CTMC, h->refresh, 0, (uint64_t)k, nullptr, nullptr, nullptr,
+                                                 step_dev}, st);
         }
-        w->since_inv = 0;
+        w->since_inv = (uint64_t)h->refresh;
     }
     if (s != VMC_OK) return s;
     hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(64), 0, st, step_dev, (uint64_t)n_steps);
@@ -2844,7 +3383,7 @@ vmc_status vmc_excitations(vmc_handle h, const vmc_walkers* w, int64_t walker, i
     if (walker < 0 || walker >= w->n_walkers) return fail(h, VMC_E_ARG, "walker index out of range");
     if (!count || cap < 0 || (cap > 0 && (!ijab || !hval || !ratio))) return fail(h, VMC_E_ARG, "bad output buffers");
     const size_t lds = al16((size_t)h->nw * 8) + al16((size_t)h->ne * 4) + al16((size_t)h->n_so * 4) +
-                       2 * (size_t)h->n_so * 8 + (size_t)kQueue * 4;
+                       2 * (size_t)h->n_so * 8 + (size_t)kQueue * 4 + (size_t)h->ncorr * 12;
     if (h->precision == VMC_MIXED)
         hipLaunchKernelGGL(k_excitations<float>, dim3(1), dim3(64), lds, st, make_tab(h), make_wk(h, w), walker, ijab,
                            hval, ratio, cap, count);
@@ -2868,7 +3407,7 @@ vmc_status vmc_logderiv(vmc_handle h, const vmc_walkers* w, const double* g, dou
     vmc_status s = check_walkers(h, w);
     if (s != VMC_OK) return s;
     if (!out) return fail(h, VMC_E_ARG, "out is NULL");
-    const int64_t n_p = (int64_t)h->n_so * (h->n_so + 1) / 2 + (int64_t)h->n_so * h->n_so;
+    const int64_t n_p = (int64_t)h->n_so * (h->n_so + 1) / 2 + (int64_t)h->n_so * h->n_so + h->n_coef;
     const Tab T = make_tab(h);
     const Wk S = make_wk(h, w);
     if (!g) {
@@ -2876,24 +3415,28 @@ vmc_status vmc_logderiv(vmc_handle h, const vmc_walkers* w, const double* g, dou
         HIP_OR_FAIL(h, hipGetLastError());
         return VMC_OK;
     }
-    // walker ranges of about 128 walkers (16 to 128 of them), enough blocks to
-    // keep the serial loads of each range overlapped across the chip
-    const int nsplit = (int)std::min<int64_t>(128, std::max<int64_t>(16, w->n_walkers / 128));
-    if (h->part_cap < n_p * nsplit) {
-        if (h->d_part) (void)hipFree(h->d_part);
-        h->d_part = nullptr;
-        h->part_cap = 0;
-        if (hipMalloc((void**)&h->d_part, sizeof(double) * n_p * nsplit) != hipSuccess)
-            return fail(h, VMC_E_OOM, "hipMalloc failed for gradient partials");
-        h->part_cap = n_p * nsplit;
+    // Jastrow part: one SYRK tile per workgroup; orbital part: one workgroup
+    // per orbital, rows of Ne/64 doubles per lane (the smallest instantiation
+    // that holds them).  Nothing is allocated.
+    const int nt16 = (h->n_so + 15) / 16;
+    hipLaunchKernelGGL(k_grad_J_syrk, dim3((unsigned)(nt16 * (nt16 + 1) / 2)), dim3(64 * kSyrkWaves), 0, st, T, S,
+                       w->n_walkers, g, out);
+    HIP_OR_FAIL(h, hipGetLastError());
+    const int nr = (h->ne + 63) / 64;
+    const int64_t nj = (int64_t)h->n_so * (h->n_so + 1) / 2;
+    const dim3 grid((unsigned)h->n_so), block(64 * kGradWaves);
+    const size_t lds = (size_t)h->ne * 8;
+    if (nr <= 1) hipLaunchKernelGGL(k_grad_theta_rows<1>, grid, block, lds, st, T, S, w->n_walkers, g, out, nj);
+    else if (nr <= 2) hipLaunchKernelGGL(k_grad_theta_rows<2>, grid, block, lds, st, T, S, w->n_walkers, g, out, nj);
+    else if (nr <= 4) hipLaunchKernelGGL(k_grad_theta_rows<4>, grid, block, lds, st, T, S, w->n_walkers, g, out, nj);
+    else if (nr <= 8) hipLaunchKernelGGL(k_grad_theta_rows<8>, grid, block, lds, st, T, S, w->n_walkers, g, out, nj);
+    else hipLaunchKernelGGL(k_grad_theta_rows<16>, grid, block, lds, st, T, S, w->n_walkers, g, out, nj);
+    HIP_OR_FAIL(h, hipGetLastError());
+    if (h->ncorr > 0) {
+        hipLaunchKernelGGL(k_grad_cps, dim3((unsigned)h->ncorr), dim3(64 * kCpsWaves), 0, st, T, S, w->n_walkers, g,
+                           out, nj + (int64_t)h->n_so * h->n_so);
+        HIP_OR_FAIL(h, hipGetLastError());
     }
-    hipLaunchKernelGGL(k_grad_J, dim3(h->n_so, nsplit), dim3(64), 0, st, T, S, w->n_walkers, g, h->d_part, n_p, nsplit);
-    HIP_OR_FAIL(h, hipGetLastError());
-    hipLaunchKernelGGL(k_grad_theta, dim3(h->n_so, nsplit), dim3(64), 0, st, T, S, w->n_walkers, g, h->d_part, n_p,
-                       nsplit);
-    HIP_OR_FAIL(h, hipGetLastError());
-    hipLaunchKernelGGL(k_combine, dim3((unsigned)((n_p + 255) / 256)), dim3(256), 0, st, h->d_part, out, n_p, nsplit);
-    HIP_OR_FAIL(h, hipGetLastError());
     return VMC_OK;
 }
 
@@ -2996,7 +3539,7 @@ vmc_status vmc_batch_autotune(vmc_batch b, vmc_walkers* const* walkers, int32_t 
     for (int nt : kTuneThreads) {
         size_t lds = 0;
         for (vmc_ctx* h : b->sys)
-            lds = std::max(lds, (size_t)lds_layout(h->n_so, h->ne, h->nw, nt, false, (int)r_bytes(h)).total);
+            lds = std::max(lds, (size_t)lds_layout(h->n_so, h->ne, h->nw, nt, false, (int)r_bytes(h), h->ncorr).total);
         if (lds > kMaxLdsHbm) continue;
         b->nt = nt;
         float ms = 0.0f;
@@ -3086,7 +3629,7 @@ static vmc_status launch_batch(vmc_batch b, vmc_walkers* const* ws, int mode, in
         E.step0 = ws[e]->step;
         E.refresh = h->refresh;
         blocks += E.W;
-        lds = std::max(lds, (size_t)lds_layout(h->n_so, h->ne, h->nw, b->nt, false, (int)r_bytes(h)).total);
+        lds = std::max(lds, (size_t)lds_layout(h->n_so, h->ne, h->nw, b->nt, false, (int)r_bytes(h), h->ncorr).total);
     }
     if (lds > kMaxLdsHbm) return fail(nullptr, VMC_E_UNSUPPORTED, "a batched system exceeds the per-walker LDS budget");
     if (blocks > (int64_t)INT_MAX) return fail(nullptr, VMC_E_ARG, "too many walkers in the batch");

@@ -1,15 +1,23 @@
 """The energy-minimisation loop: sample, estimate, backward, AMSGrad, repeat.
 
 Each iteration (section "AMSGrad algorithm for optimizing the energy") is
-  1. `moves` CTMC moves of every walker (vmc_ctmc_step);
-  2. E_L and t of the final states (vmc_local_energy) and the weighted energy
-     E = sum t E_L / sum t with the gradient weights g_w (vmc_estimate,
-     Eq. eq:vmc with residence-time weights);
-  3. the gradient G = sum_w g_w O_w (vmc_logderiv, Eq. eq:grad);
-  4. one AMSGrad step (vmc_amsgrad, Eqs. eq:m1, eq:m2) with the step size of
+  1. `moves` CTMC moves of every walker (vmc_ctmc_step), keeping E_L and t of
+     every visited state;
+  2. the energy estimate over every visited state, E = sum t E_L / sum t
+     (vmc_estimate over the W x moves histories, Eq. eq:vmc with
+     residence-time weights);
+  3. E_L and t of the final states (vmc_local_energy), their weighted mean and
+     the gradient weights g_w (vmc_estimate);
+  4. the gradient G = sum_w g_w O_w over the final states (vmc_logderiv,
+     Eq. eq:grad);
+  5. one AMSGrad step (vmc_amsgrad, Eqs. eq:m1, eq:m2) with the step size of
      the schedule;
-  5. the new parameters into the tables (vmc_set_params) and the walkers'
-     inverses recomputed for them (vmc_walkers_refresh).
+  6. the new parameters into the tables (vmc_set_params, vmc_set_cps) and the
+     walkers' inverses recomputed for them (vmc_walkers_refresh).
+The gradient uses one state per walker, the last of the iteration: the O_k of
+a state need its inverse, which the sweep does not keep for the states it
+passes through, and the final states of `moves`-move walks are nearly
+independent samples; the energy uses all of them.
 
 Every step runs in the library's kernels; this module only sequences the calls
 on one stream and holds the device buffers.  The default schedule is the
@@ -45,14 +53,16 @@ def paper_schedule(i: int) -> float:
 
 
 class Optimizer:
-    """Energy minimisation of one system's Jastrow and orbital parameters.
+    """Energy minimisation of one system's Jastrow, orbital and (when the
+    system has them) correlator parameters.
 
-    system: a vmc.System; walkers: its vmc.Walkers (initialised); J, theta:
-    device float64 tensors (packed Jastrow upper triangle, n_so x n_so theta),
-    copied into one parameter vector that the optimiser owns.
+    system: a vmc.System; walkers: its vmc.Walkers (initialised); J, theta
+    (and cps): device float64 tensors (packed Jastrow upper triangle, n_so x
+    n_so theta, correlator coefficients), copied into one parameter vector,
+    in the order of vmc_logderiv, that the optimiser owns.
     """
 
-    def __init__(self, system, walkers, J, theta, *, moves: int = 50,
+    def __init__(self, system, walkers, J, theta, *, cps=None, moves: int = 50,
                  schedule: Callable[[int], float] = paper_schedule, beta1: float = 0.9, beta2: float = 0.99,
                  delta: float = 1e-8, paper_literal: bool = False, stream=None):
         if not J.is_cuda or not theta.is_cuda:
@@ -63,8 +73,16 @@ class Optimizer:
         self.stream = stream
         dev = J.device
         self.nj = system.n_so * (system.n_so + 1) // 2
-        self.params = torch.cat([J.reshape(-1).to(torch.float64), theta.reshape(-1).to(torch.float64)]).contiguous()
+        self.nt = system.n_so * system.n_so
+        parts = [J.reshape(-1).to(torch.float64), theta.reshape(-1).to(torch.float64)]
+        if system.n_cps:
+            parts.append((cps if cps is not None else system.cps).reshape(-1).to(torch.float64))
+        self.params = torch.cat(parts).contiguous()
         assert self.params.numel() == system.n_params
+        W = walkers.n_walkers
+        self.eh = torch.zeros((self.moves, W), dtype=torch.float64, device=dev)
+        self.th = torch.zeros((self.moves, W), dtype=torch.float64, device=dev)
+        self.est_all = torch.zeros(4, dtype=torch.float64, device=dev)
         self.m = torch.zeros_like(self.params)
         self.v = torch.zeros_like(self.params)
         self.vhat = torch.zeros_like(self.params)
@@ -80,18 +98,24 @@ class Optimizer:
 
     @property
     def theta(self):
-        return self.params[self.nj:].view(self.system.n_so, self.system.n_so)
+        return self.params[self.nj:self.nj + self.nt].view(self.system.n_so, self.system.n_so)
+
+    @property
+    def cps(self):
+        return self.params[self.nj + self.nt:]
 
     def _apply(self) -> None:
         h, st = self.system.handle, self.stream
-        _vmc.vmc_set_params(h, self.params[: self.nj], self.params[self.nj:], stream=st)
+        self.system.set_param_vector(self.params, stream=st)
         _vmc.vmc_walkers_refresh(h, self.walkers, stream=st)
 
     def step(self) -> torch.Tensor:
-        """One iteration; returns the device scalar E of the sampled states
-        (estimated before the parameter update)."""
+        """One iteration; returns the device scalar E of the final states
+        (estimated before the parameter update).  est_all then holds {sum t,
+        sum t E_L, E, count} over every state the iteration visited."""
         h, st, w = self.system.handle, self.stream, self.walkers
-        _vmc.vmc_ctmc_step(h, w, self.moves, stream=st)
+        _vmc.vmc_ctmc_step(h, w, self.moves, self.eh, self.th, stream=st)
+        _vmc.vmc_estimate_arrays(h, self.eh, self.th, self.eh.numel(), self.est_all, stream=st)
         _vmc.vmc_local_energy(h, w, stream=st)
         _vmc.vmc_estimate(h, w, self.est, self.g, stream=st)
         _vmc.vmc_logderiv(h, w, self.g, self.G, stream=st)
@@ -103,6 +127,14 @@ class Optimizer:
 
     def run(self, n_iter: int) -> List[float]:
         return [float(self.step().item()) for _ in range(n_iter)]
+
+    def run_all_states(self, n_iter: int) -> List[float]:
+        """As run, returning the energies over every visited state."""
+        out = []
+        for _ in range(n_iter):
+            self.step()
+            out.append(float(self.est_all[2].item()))
+        return out
 
 
 def evaluate(wl, J, theta, occ, *, eps: float, rounds: int = 10, moves: int = 50, burn: int = 100,
@@ -152,11 +184,13 @@ def _main(argv: Optional[List[str]] = None) -> int:
     ap.add_argument("--eval-eps", type=float, default=None,
                     help="after the iterations, evaluate the final parameters at this threshold")
     ap.add_argument("--eval-rounds", type=int, default=20)
+    ap.add_argument("--cps", default=None, help="correlators (chainK, plus5)")
     args = ap.parse_args(argv)
     if not torch.cuda.is_available():
         print(json.dumps({"error": "needs a GPU"}))
         return 2
-    wl = make_config(args.config, n_walkers=args.walkers or None, eps=args.eps, orbitals=args.orbitals)
+    wl = make_config(args.config, n_walkers=args.walkers or None, eps=args.eps, orbitals=args.orbitals,
+                     cps=args.cps)
     prec = _vmc.VMC_MIXED if args.precision == "mixed" else _vmc.VMC_FP64
     system = _vmc.System.from_workload(wl, precision=prec, refresh_period=args.moves)
     walkers = system.walkers(wl.occ)
@@ -165,8 +199,11 @@ def _main(argv: Optional[List[str]] = None) -> int:
     for i in range(args.iters):
         t0 = time.perf_counter()
         E = float(opt.step().item())  # .item() waits for the iteration
+        ea = opt.est_all.cpu().numpy()
         print(json.dumps({"iteration": i, "alpha": paper_schedule(i), "energy": E,
-                          "energy_per_electron": E / wl.n_elec, "ms": (time.perf_counter() - t0) * 1e3}), flush=True)
+                          "energy_all_states": float(ea[2]), "states": int(ea[3]),
+                          "energy_per_electron": float(ea[2]) / wl.n_elec, "ms": (time.perf_counter() - t0) * 1e3}),
+              flush=True)
     if args.eval_eps is not None:
         occ = walkers.view("occ_bits", torch.int64)[: walkers.n_walkers * system.n_words].cpu().numpy()
         ev = evaluate(wl, opt.J.clone(), opt.theta.clone(), occ.view("uint64").reshape(walkers.n_walkers, -1),

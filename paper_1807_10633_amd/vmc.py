@@ -22,7 +22,7 @@ VMC_GHF = 0
 VMC_UHF = 1
 ST_SINGULAR, ST_EMPTY, ST_NONFINITE, ST_SMALLDEN = 1, 2, 4, 8
 
-FIELDS = ("occ_bits", "slot_orb", "orb_slot", "ainv", "r", "jsum", "hnn", "eloc", "tres", "pick", "status", "scratch")
+FIELDS = ("occ_bits", "slot_orb", "orb_slot", "ainv", "r", "rlo", "jsum", "hnn", "eloc", "tres", "pick", "status", "scratch")
 NFIELDS = len(FIELDS)
 
 EXPORTED = (
@@ -31,7 +31,7 @@ EXPORTED = (
     "vmc_destroy", "vmc_last_error", "vmc_host_tables_build", "vmc_host_tables_sizes", "vmc_host_tables_get",
     "vmc_host_tables_free", "vmc_set_launch", "vmc_launch_info", "vmc_estimate", "vmc_batch_create",
     "vmc_batch_set_launch", "vmc_batch_local_energy", "vmc_batch_ctmc_step", "vmc_batch_destroy", "vmc_autotune",
-    "vmc_batch_autotune", "vmc_ctmc_step_dev", "vmc_walkers_refresh",
+    "vmc_batch_autotune", "vmc_ctmc_step_dev", "vmc_walkers_refresh", "vmc_cps_init", "vmc_set_cps", "vmc_cps_info",
 )
 
 
@@ -68,6 +68,9 @@ def load_library() -> C.CDLL:
     sig = {
         "vmc_init": ([P, P, P, d, P, P], i32),
         "vmc_set_params": ([P, P, P, P], i32),
+        "vmc_cps_init": ([P, i32, P], i32),
+        "vmc_set_cps": ([P, P, P], i32),
+        "vmc_cps_info": ([P, P], i32),
         "vmc_walker_bytes": ([P, i64, P], i32),
         "vmc_walkers_init": ([P, P, P], i32),
         "vmc_walkers_refresh": ([P, P, P], i32),
@@ -152,6 +155,22 @@ def vmc_set_params(handle, J_dev, theta_dev, stream=None) -> None:
            "vmc_set_params")
 
 
+def vmc_cps_init(handle, sites: np.ndarray) -> None:
+    """Correlators: sites (n_corr, 5) int32 spatial orbitals, -1 padded."""
+    st = np.ascontiguousarray(sites, dtype=np.int32).reshape(-1, 5)
+    _check(load_library().vmc_cps_init(handle, st.shape[0], _np_ptr(st)), handle, "vmc_cps_init")
+
+
+def vmc_set_cps(handle, coeffs_dev, stream=None) -> None:
+    _check(load_library().vmc_set_cps(handle, _dev_ptr(coeffs_dev), _stream_ptr(stream)), handle, "vmc_set_cps")
+
+
+def vmc_cps_info(handle):
+    out = (C.c_int64 * 2)()
+    _check(load_library().vmc_cps_info(handle, out), handle, "vmc_cps_info")
+    return {"correlators": int(out[0]), "coefficients": int(out[1])}
+
+
 def vmc_walker_bytes(handle, n_walkers: int) -> Dict[str, int]:
     arr = (C.c_size_t * NFIELDS)()
     _check(load_library().vmc_walker_bytes(handle, int(n_walkers), arr), handle, "vmc_walker_bytes")
@@ -194,6 +213,17 @@ def vmc_logderiv(handle, walkers: "Walkers", g_dev, out_dev, stream=None) -> Non
 def vmc_estimate(handle, walkers: "Walkers", out_dev, g_dev=None, stream=None) -> None:
     """out_dev (4 FP64, device) <- {sum t, sum t E_L, E, count}; g_dev (W FP64) <- gradient weights."""
     _check(load_library().vmc_estimate(handle, C.byref(walkers.cstruct), _dev_ptr(out_dev),
+                                       _dev_ptr(g_dev) if g_dev is not None else None, _stream_ptr(stream)),
+           handle, "vmc_estimate")
+
+
+def vmc_estimate_arrays(handle, eloc_dev, tres_dev, n: int, out_dev, g_dev=None, stream=None) -> None:
+    """vmc_estimate over n (E_L, t) pairs held in any device arrays (e.g. the
+    histories of a sweep): the walker record passed carries only those two."""
+    ws = WalkersStruct(int(n), *([None] * NFIELDS), 0, 0)
+    ws.eloc = _dev_ptr(eloc_dev)
+    ws.tres = _dev_ptr(tres_dev)
+    _check(load_library().vmc_estimate(handle, C.byref(ws), _dev_ptr(out_dev),
                                        _dev_ptr(g_dev) if g_dev is not None else None, _stream_ptr(stream)),
            handle, "vmc_estimate")
 
@@ -362,7 +392,10 @@ class System:
         self.n_so = 2 * self.n_orb
         self.ne = self.n_alpha + self.n_beta
         self.n_words = (self.n_so + 63) // 64
-        self.n_params = self.n_so * (self.n_so + 1) // 2 + self.n_so * self.n_so
+        self.n_base_params = self.n_so * (self.n_so + 1) // 2 + self.n_so * self.n_so
+        self.n_cps = 0
+        self.cps = None
+        self._pvec = None
         self.device = device
         self.precision = int(precision)
         self.orbitals = int(orbitals)
@@ -379,12 +412,59 @@ class System:
             kw.setdefault("orbitals", VMC_UHF)
         s = cls(wl.n_orb, wl.n_alpha, wl.n_beta, wl.h1, wl.eri_idx, wl.eri_val, wl.eps, seed=wl.ctmc_seed, **kw)
         s.set_params(torch.as_tensor(wl.jastrow, device=s.device), torch.as_tensor(wl.theta, device=s.device))
+        if getattr(wl, "cps_sites", None) is not None and len(wl.cps_sites):
+            s.set_cps(wl.cps_sites, torch.as_tensor(wl.cps_coeffs, device=s.device))
         return s
+
+    @property
+    def n_params(self) -> int:
+        return self.n_base_params + self.n_cps
 
     def set_params(self, J_packed, theta) -> None:
         self.J = J_packed.contiguous().to(dtype=__import__("torch").float64)
         self.theta = theta.contiguous().to(dtype=__import__("torch").float64)
         vmc_set_params(self.handle, self.J, self.theta)
+
+    def set_cps(self, sites, coeffs) -> None:
+        """Correlators (vmc_cps_init on first use) and their coefficients."""
+        if self.n_cps == 0:
+            vmc_cps_init(self.handle, sites)
+            self.n_cps = vmc_cps_info(self.handle)["coefficients"]
+            self.cps_sites = np.ascontiguousarray(sites, dtype=np.int32).reshape(-1, 5)
+        self.cps = coeffs.contiguous().to(dtype=__import__("torch").float64)
+        assert self.cps.numel() == self.n_cps
+        vmc_set_cps(self.handle, self.cps)
+
+    def param_vector(self):
+        """All parameters in the order of vmc_logderiv: J, theta, correlators."""
+        import torch
+
+        parts = [self.J, self.theta.reshape(-1)] + ([self.cps] if self.n_cps else [])
+        return torch.cat(parts)
+
+    def set_param_vector(self, p, stream=None) -> None:
+        """Hand a vector in param_vector's order to the library (views, no copy
+        here: the library copies on `stream`); keeps a reference for host_params."""
+        nj = self.n_so * (self.n_so + 1) // 2
+        nt = self.n_so * self.n_so
+        vmc_set_params(self.handle, p[:nj], p[nj:nj + nt], stream=stream)
+        if self.n_cps:
+            vmc_set_cps(self.handle, p[nj + nt:], stream=stream)
+        self._pvec = p
+
+    def host_params(self):
+        """(J packed, theta) of the parameters last handed over, as numpy."""
+        nj = self.n_so * (self.n_so + 1) // 2
+        if self._pvec is None:
+            return self.J.cpu().numpy(), self.theta.cpu().numpy()
+        p = self._pvec.cpu().numpy()
+        return p[:nj], p[nj:nj + self.n_so * self.n_so].reshape(self.n_so, self.n_so)
+
+    def host_cps(self):
+        nj = self.n_so * (self.n_so + 1) // 2
+        if self._pvec is None:
+            return self.cps.cpu().numpy()
+        return self._pvec.cpu().numpy()[nj + self.n_so * self.n_so:]
 
     def walkers(self, occ: np.ndarray) -> Walkers:
         import torch
