@@ -5,7 +5,81 @@ import numpy as np
 from oracle.core import ORC_LEMMA, OracleSystem
 
 EL_TOL = 1e-10  # |Delta E_L| bar for the FP64 path (Hartree, or units of t)
+MIXED_TOL = 1e-6  # per electron, the mixed form's bar
 PICK_MARGIN = 1e-12  # picks within this relative distance of a boundary are exempt
+ST_STALE = 16  # status bit: moved since the last inversion (not an error)
+
+
+def el_tol(T):
+    """FP64 bar near nodes: 1e-10 + 1e-13 T, T = sum |psi(M)/psi(N)| of the
+    state.  The fresh-LU and lemma ratios of oracle and GPU round at a level
+    that grows with the conditioning of theta[N], which T measures; for T below
+    about 1e3 this is the plain 1e-10."""
+    return EL_TOL + 1e-13 * np.asarray(T, dtype=np.float64)
+
+
+def mixed_tol(T, n_elec):
+    """Mixed-form bar: 1e-6 per electron, plus a T-scaled term 1e-8 T for
+    states near a node, where the FP32 storage of R (unit roundoff 6e-8)
+    enters every ratio relative to the walker's scale T."""
+    return MIXED_TOL * n_elec + 1e-8 * np.asarray(T, dtype=np.float64)
+
+
+def trajectory_states(occ0, ph, idx, k_range=None):
+    """The determinants a sweep visited: for each sampled walker w in idx, the
+    state before move k (k in k_range, default all) rebuilt from its start
+    occ0[w] and the packed picks ph[:, w].  Also returns the state after the
+    last move.  Returns (states, walker, k) arrays, with k = n_steps for the
+    final states."""
+    n_steps = ph.shape[0]
+    ks = set(range(n_steps)) if k_range is None else set(k_range)
+    states, wk, kk = [], [], []
+    for w in idx:
+        bits = occ0[w].copy()
+        for k in range(n_steps):
+            if k in ks:
+                states.append(bits.copy())
+                wk.append(int(w))
+                kk.append(k)
+            bits = apply_pick(bits, ph[k, w])
+        states.append(bits.copy())
+        wk.append(int(w))
+        kk.append(n_steps)
+    return np.stack(states), np.array(wk), np.array(kk)
+
+
+def teacher_forced_batch(orc, seed, occ0, step0, eh, th, ph, idx, k_range=None, el_final=None, threads=0):
+    """teacher_forced_check with every state evaluated in one parallel oracle
+    call (orc.eval_states).  The final states are compared with el_final (E_L
+    of vmc_local_energy after the sweep) when given.  Returns arrays per state
+    (dE, T, dt_rel, k) and the pick statistics."""
+    from paper_1807_10633_amd.vmc import vmc_decode_pick
+
+    states, wk, kk = trajectory_states(occ0, ph, idx, k_range)
+    n_steps = eh.shape[0]
+    e_o, t_o, pick, margin, rc = orc.eval_states(states, seed, wk, step0 + kk, ORC_LEMMA, threads)
+    sel = kk < n_steps if el_final is None else np.ones(kk.size, dtype=bool)
+    assert np.all(rc[sel] == 0), "oracle failed on a visited state"
+    gpu_el = np.where(kk < n_steps, eh[np.minimum(kk, n_steps - 1), wk], np.nan)
+    if el_final is not None:
+        gpu_el = np.where(kk == n_steps, el_final[wk], gpu_el)
+    gpu_t = np.where(kk < n_steps, th[np.minimum(kk, n_steps - 1), wk], np.nan)
+    dE = np.abs(e_o - gpu_el)[sel]
+    T = 1.0 / t_o[sel]
+    mv = kk < n_steps
+    dt_rel = np.abs(t_o[mv] - gpu_t[mv]) / t_o[mv]
+    n_pick = n_exempt = 0
+    mismatches = []
+    for s in np.flatnonzero(mv):
+        g = vmc_decode_pick(int(ph[kk[s], wk[s]]))
+        if margin[s] < PICK_MARGIN:
+            n_exempt += 1
+        else:
+            n_pick += 1
+            if tuple(g) != tuple(int(x) for x in pick[s]):
+                mismatches.append((int(wk[s]), int(kk[s]), tuple(pick[s]), g, float(margin[s])))
+    return {"dE": dE, "T": T, "k": kk[sel], "dt_rel": dt_rel, "picks_compared": n_pick, "picks_exempt": n_exempt,
+            "mismatches": mismatches, "states": int(sel.sum())}
 
 
 def torch_mod():

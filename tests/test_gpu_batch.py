@@ -16,7 +16,7 @@ from oracle.core import ORC_LEMMA, OracleSystem
 from oracle.optim import AMSGrad
 from workloads import make_config
 
-from gpu_common import EL_TOL, field, gpu_system, occ_of
+from gpu_common import EL_TOL, ST_STALE, el_tol, field, gpu_system, occ_of
 
 pytestmark = pytest.mark.gpu
 
@@ -79,6 +79,10 @@ def test_batch_equals_separate_launches(torch, batch_setup):
     for name, s, a, c in zip(NAMES, systems, sep, bat):
         assert a.step == c.step == 3
         sa, sc = _state(torch, s, a), _state(torch, s, c)
+        # the separate launches re-invert in their own kernel and mark moved
+        # walkers stale; the batch re-inverts in place: the mark is scheduling
+        sa["status"] = sa["status"] & ~ST_STALE
+        sc["status"] = sc["status"] & ~ST_STALE
         for k in sa:
             assert np.array_equal(sa[k], sc[k]), f"{name}: field {k} differs between batch and separate launches"
         assert np.all((sa["status"] & 1) == 0)
@@ -102,7 +106,7 @@ def test_batch_local_energy_matches_oracle(torch, batch_setup):
         worst = 0.0
         for w in (0, W // 2, W - 1):
             r = orc.local_energy(wl.occ[w], ORC_LEMMA, with_candidates=False)
-            tol = EL_TOL * max(1.0, r["T"] / 100.0)
+            tol = el_tol(r["T"])
             d = abs(el[w] - r["eloc"])
             worst = max(worst, d / tol)
             assert d <= tol, (wl.name, w, el[w], r["eloc"], r["T"])
@@ -195,5 +199,5 @@ def test_batch_autotune(torch):
         el = field(s, wk, "eloc", torch.float64, 1)[:, 0]
         orc = OracleSystem.from_workload(wl)
         r = orc.local_energy(occ_of(s, wk)[5], ORC_LEMMA, with_candidates=False)
-        assert abs(el[5] - r["eloc"]) <= EL_TOL * max(1.0, r["T"] / 100.0)
+        assert abs(el[5] - r["eloc"]) <= el_tol(r["T"])
     _say(f"    batch autotuned workgroup: {nt}")

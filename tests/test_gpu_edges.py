@@ -9,7 +9,7 @@ import pytest
 from oracle.core import ORC_LEMMA, OracleSystem, list_to_occ
 from workloads import Workload, hubbard_ring, init_jastrow, init_theta, init_walkers, make_config
 
-from gpu_common import EL_TOL, field, gpu_system, occ_of, run_sweep, teacher_forced_check
+from gpu_common import EL_TOL, el_tol, field, gpu_system, occ_of, run_sweep, teacher_forced_check
 
 pytestmark = pytest.mark.gpu
 
@@ -38,7 +38,7 @@ def test_one_electron_has_no_pair_groups(torch):
     eh, th, ph = run_sweep(sysm, walkers, 40)
     orc = OracleSystem.from_workload(wl)
     res = teacher_forced_check(orc, wl.ctmc_seed, occ0, 0, eh, th, ph, range(0, 64, 8))
-    scaled = res["dE_all"] / (EL_TOL * np.maximum(1.0, res["T_all"] / 100.0))
+    scaled = res["dE_all"] / (el_tol(res["T_all"]))
     assert scaled.max() <= 1.0 and not res["mismatches"], res["mismatches"][:3]
 
 
@@ -51,7 +51,7 @@ def test_single_walker(torch):
     orc = OracleSystem.from_workload(wl)
     res = teacher_forced_check(orc, wl.ctmc_seed, occ0, 0, eh, th, ph, [0])
     # the walker starts from a random determinant: the bar scales with T there
-    scaled = res["dE_all"] / (EL_TOL * np.maximum(1.0, res["T_all"] / 100.0))
+    scaled = res["dE_all"] / (el_tol(res["T_all"]))
     assert scaled.max() <= 1.0 and not res["mismatches"]
 
 
@@ -127,7 +127,7 @@ def test_flagged_walkers_never_move_and_carry_no_weight(torch):
     for w in good[:3]:
         r = orc.local_energy(after[w], ORC_LEMMA, with_candidates=False)
         e = field(sysm, walkers, "eloc", torch.float64, 1)[w, 0]
-        assert abs(e - r["eloc"]) <= EL_TOL * max(1.0, r["T"] / 100.0)
+        assert abs(e - r["eloc"]) <= el_tol(r["T"])
 
 
 def test_largest_space_512_orbitals(torch):

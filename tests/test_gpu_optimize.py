@@ -22,7 +22,7 @@ from oracle.core import ORC_LEMMA, OracleSystem
 from oracle.optim import AMSGrad, gradient, weighted_energy
 from workloads import eri_dense_spatial, make_config
 
-from gpu_common import field, gpu_system, occ_of
+from gpu_common import el_tol, field, gpu_system, mixed_tol, occ_of
 
 pytestmark = pytest.mark.gpu
 
@@ -92,7 +92,7 @@ def test_iterations_match_oracle_algebra(torch, paper_literal, mixed):
     occ = occ_of(sysm, walkers)
     for w in (0, 31, 63):
         r = orc.local_energy(occ[w], ORC_LEMMA, with_candidates=False)
-        assert abs(el[w] - r["eloc"]) <= e_tol * max(1.0, r["T"] / 100.0)
+        assert abs(el[w] - r["eloc"]) <= (mixed_tol(r["T"], wl.n_elec) if mixed else el_tol(r["T"]))
 
 
 def test_loop_lowers_exact_energy_of_the_ring(torch):
@@ -138,7 +138,7 @@ def test_loose_eps_optimisation_tight_eps_evaluation(torch):
     assert np.all((st & 1) == 0)
     el_o, T_o, _, st_o = orc.local_energy_batch(occ2, ORC_LEMMA)
     assert np.all(st_o == 0)
-    tol = 1e-10 * np.maximum(1.0, T_o / 100.0)
+    tol = el_tol(T_o)
     assert np.all(np.abs(el - el_o) <= tol), float(np.max(np.abs(el - el_o) / tol))
     # the last round's energy is the residence-time weighted mean of these E_L
     E_ref = weighted_energy(el_o, 1.0 / T_o)

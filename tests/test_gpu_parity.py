@@ -9,7 +9,7 @@ import pytest
 from oracle.core import ORC_DET, ORC_LEMMA, OracleSystem, uniform
 from workloads import hubbard_2d, hubbard_ring, init_jastrow, init_theta, init_walkers, make_config
 
-from gpu_common import EL_TOL, field, gpu_system, occ_of, run_sweep, teacher_forced_check
+from gpu_common import EL_TOL, el_tol, field, gpu_system, mixed_tol, occ_of, run_sweep, teacher_forced_check
 
 pytestmark = pytest.mark.gpu
 
@@ -105,7 +105,7 @@ def test_local_energy_matches_oracle(torch, name, W, sample):
         r = orc.local_energy(wl.occ[w], ORC_LEMMA, with_candidates=False)
         # random initial determinants sit near nodes (T up to ~1e5): the
         # rounding of both sides grows with T, so the bar is scaled by it
-        tol = EL_TOL * max(1.0, r["T"] / 100.0)
+        tol = el_tol(r["T"])
         d = abs(el[w] - r["eloc"])
         worst = max(worst, d / tol)
         assert d <= tol, f"walker {w}: gpu {el[w]!r} oracle {r['eloc']!r} T={r['T']}"
@@ -243,7 +243,7 @@ def test_refresh_kernel_state_and_energy(torch, prec):
     orc = OracleSystem.from_workload(wl)
     for w in (0, 21, 42, 63):
         r = orc.local_energy(occ[w], ORC_LEMMA, with_candidates=False)
-        tol = (1e-6 * ne if mixed else EL_TOL) * max(1.0, r["T"] / 100.0)
+        tol = mixed_tol(r["T"], ne) if mixed else el_tol(r["T"])
         assert abs(el[w] - r["eloc"]) <= tol, (w, el[w], r["eloc"], r["T"])
 
 
@@ -266,7 +266,7 @@ def test_autotune_picks_a_valid_shape_and_keeps_walkers_valid(torch):
     orc = OracleSystem.from_workload(wl)
     for w in (0, 255, 511):
         r = orc.local_energy(occ[w], ORC_LEMMA, with_candidates=False)
-        assert abs(el[w] - r["eloc"]) <= EL_TOL * max(1.0, r["T"] / 100.0)
+        assert abs(el[w] - r["eloc"]) <= el_tol(r["T"])
     _say(f"    autotuned workgroup: {nt} threads per walker")
 
 
@@ -314,7 +314,7 @@ def test_walkers_refresh_after_new_parameters(torch, name, scale):
     orc.set_params(J, theta)
     for w in (0, 21, 42, 63):
         r = orc.local_energy(occ[w], ORC_LEMMA, with_candidates=False)
-        assert abs(el[w] - r["eloc"]) <= EL_TOL * max(1.0, r["T"] / 100.0), (w, el[w], r["eloc"], r["T"])
+        assert abs(el[w] - r["eloc"]) <= el_tol(r["T"]), (w, el[w], r["eloc"], r["T"])
 
 
 def test_refresh_schedule_counts_moves_since_inversion(torch):
@@ -352,7 +352,7 @@ def test_refresh_schedule_counts_moves_since_inversion(torch):
     orc = OracleSystem.from_workload(wl)
     for w in (0, 63):
         r = orc.local_energy(occ[w], ORC_LEMMA, with_candidates=False)
-        assert abs(el[w] - r["eloc"]) <= EL_TOL * max(1.0, r["T"] / 100.0)
+        assert abs(el[w] - r["eloc"]) <= el_tol(r["T"])
 
 
 def test_refresh_kernel_lds_path_above_128_electrons(torch):
@@ -393,4 +393,4 @@ def test_refresh_kernel_lds_path_above_128_electrons(torch):
     orc.set_params(jas, theta)
     for w in (0, 13, 31):
         r = orc.local_energy(occ[w], ORC_LEMMA, with_candidates=False)
-        assert abs(el[w] - r["eloc"]) <= EL_TOL * max(1.0, r["T"] / 100.0), (w, el[w], r["eloc"], r["T"])
+        assert abs(el[w] - r["eloc"]) <= el_tol(r["T"]), (w, el[w], r["eloc"], r["T"])
