@@ -1,21 +1,28 @@
 #!/usr/bin/env python3
 """Throughput of the screened VMC hot path on one MI355X.
 
-Workload: the synthetic H-chain-like Hamiltonian with 20 spatial orbitals,
-10 alpha + 10 beta electrons, eps = 1e-6, 4096 walkers, FP64 (Jastrow-Slater
-wavefunction, random-init parameters, synthetic integrals).
+Default workload: the synthetic H-chain-like Hamiltonian with 160 spatial
+orbitals, 80 alpha + 80 beta electrons, eps = 1e-5, 8192 walkers, with the
+Jastrow-Slater wavefunction (51,360 Jastrow + 102,400 orbital parameters,
+random-init), synthetic integrals.  The headline is the mixed-precision form
+(FP32 R, FP64 inverse, denominators and accumulations); the plain FP64 form
+is measured beside it (`other_form`).
 
 One timed step is one optimisation iteration of the hot path:
   * vmc_ctmc_step: a persistent sweep of `--sweep` (= the refresh period, 50)
     CTMC moves of every walker -- screened singles/doubles enumeration,
-    ratios, local energy, rates, pick, Sherman-Morrison updates, and the
-    periodic re-inversion at the end of the sweep;
+    ratios, local energy, rates, pick, Sherman-Morrison updates;
   * vmc_local_energy of the post-sweep states, and vmc_estimate: their
     residence-time weighted energy and the contraction weights;
   * vmc_logderiv (contracted backward), vmc_amsgrad, vmc_set_params (Jastrow
-    factors folded into the tables) and vmc_walkers_init (fresh inverses for
-    the new parameters).
+    factors folded into the tables) and vmc_walkers_refresh (fresh inverses
+    for the new parameters).
 value = walker-steps/s = walkers * sweep * steps / wall time of the timed steps.
+
+E_L is checked against the FP64 oracle on the states a sweep leaves before
+any re-inversion: the last ten moves of a refresh period and the final
+states, on a sample of walkers (teacher forced: the oracle evaluates the
+GPU's own trajectory).
 
 Prints one JSON line (see --help for knobs).
 """
@@ -110,21 +117,23 @@ def counted_traffic(config, walkers, sweep, threads, precision):
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--walkers", type=int, default=4096)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--walkers", type=int, default=0, help="walkers (0 = the workload's own: 8192 for hchain160)")
     ap.add_argument("--sweep", type=int, default=50, help="CTMC moves per step (= refresh period)")
-    ap.add_argument("--config", default="hchain20",
-                    help="hchain20 (default), hubbard8, hubbard10x10, hchain40, hchain80, hchain160, or batch "
+    ap.add_argument("--config", default="hchain160",
+                    help="hchain160 (default), hchain20, hubbard8, hubbard10x10, hchain40, hchain80, or batch "
                          "(40/80/160 orbitals in one launch)")
     ap.add_argument("--threads", type=int, default=0, help="workgroup size of the sweep kernel (0 = autotuned)")
     ap.add_argument("--eps", type=float, default=None, help="screening threshold (default: the workload's own)")
     ap.add_argument("--orbitals", choices=("ghf", "uhf"), default="ghf",
                     help="general or spin-blocked (unrestricted) orbitals of the same workload")
+    ap.add_argument("--cps", default=None, help="add correlators to the wavefunction (chainK, plus5)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the E_L check against the oracle")
-    ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
+    ap.add_argument("--check-walkers", type=int, default=16, help="walkers sampled for the E_L check")
+    ap.add_argument("--precision", choices=("fp64", "mixed"), default="mixed",
                     help="form of the headline number (the other form is measured beside it)")
     ap.add_argument("--no-other-form", action="store_true", help="do not measure the other precision form")
     ap.add_argument("--no-graph", action="store_true", help="do not time the hipGraph-replayed iteration")
@@ -146,6 +155,55 @@ def copy_calibration(mib):
         y.copy_(x)
     torch.cuda.synchronize()
     print(json.dumps({"copy_calibration_bytes_read": n * 8, "bytes_written": n * 8}), flush=True)
+
+
+class HipTimer:
+    """HIP events on the stream the library launches on (the current torch
+    stream is passed to every call), averaged over the recorded intervals."""
+
+    def __init__(self, stream):
+        self.stream = stream
+        self.ev = []
+
+    def start(self):
+        import torch
+
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(self.stream)
+        self._e0 = e
+
+    def stop(self):
+        import torch
+
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(self.stream)
+        self.ev.append((self._e0, e))
+
+    def mean_ms(self):
+        import numpy as np
+
+        return float(np.mean([a.elapsed_time(b) for a, b in self.ev])) if self.ev else None
+
+
+def cpu_oracle_baseline(wl, seconds, oracle_sys=None):
+    """The plain oracle (fresh-inverse ratios, OpenMP over walkers) timed on a
+    bounded sample of the same workload: walker-steps/s and the thread count."""
+    from oracle.core import ORC_LEMMA, OracleSystem
+
+    orc0 = oracle_sys or OracleSystem.from_workload(wl)
+    threads = min(16, os.cpu_count() or 1)
+    c0 = time.perf_counter()
+    orc0.ctmc_batch(wl.occ[:threads], wl.ctmc_seed, 0, 1, ORC_LEMMA, threads)
+    per = (time.perf_counter() - c0) / threads  # wall s per walker-step at full thread use
+    n_ws = max(threads, int(seconds / max(per, 1e-9)))
+    n_w = max(threads, min(wl.n_walkers, (n_ws // 5 // threads) * threads))
+    n_steps_cpu = max(2, n_ws // n_w)
+    c0 = time.perf_counter()
+    orc0.ctmc_batch(wl.occ[:n_w], wl.ctmc_seed, 0, n_steps_cpu, ORC_LEMMA, threads)
+    cpu_wall = time.perf_counter() - c0
+    return {"value": n_w * n_steps_cpu / cpu_wall, "unit": "walker-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_w} walkers x {n_steps_cpu} CTMC moves of the same workload (oracle, fresh-inverse "
+                      f"ratios, OpenMP over walkers), {cpu_wall:.1f} s"}
 
 
 def batch_bench(args):
@@ -170,36 +228,56 @@ def batch_bench(args):
     systems = [vmc.System.from_workload(wl, refresh_period=S, precision=prec) for wl in wls]
     walkers = [s.walkers(wl.occ) for s, wl in zip(systems, wls)]
     b = vmc.vmc_batch_create([s.handle for s in systems])
+    stream = torch.cuda.current_stream()
+    timer = HipTimer(stream)
     try:
         nt = args.threads or vmc.vmc_batch_autotune(b, walkers, 2)
         if args.threads:
             vmc.vmc_batch_set_launch(b, nt)
-        stream = torch.cuda.current_stream()
         vmc.vmc_batch_ctmc_step(b, walkers, S, stream=stream)  # burn-in
         for _ in range(args.warmup):
             vmc.vmc_batch_ctmc_step(b, walkers, S, stream=stream)
         torch.cuda.synchronize()
-        evs = []
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
+            timer.start()
             vmc.vmc_batch_ctmc_step(b, walkers, S, stream=stream)
-            e1.record(stream)
-            evs.append((e0, e1))
+            timer.stop()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        ms = float(np.mean([a.elapsed_time(c) for a, c in evs]))
+        ms = timer.mean_ms()
         vmc.vmc_batch_local_energy(b, walkers, stream=stream)
         torch.cuda.synchronize()
+        el_err = None
+        if not args.no_check:
+            from oracle.core import ORC_LEMMA, OracleSystem
+
+            errs = []
+            for s, w, wl in zip(systems, walkers, wls):
+                el = w.view("eloc", torch.float64)[:Wb].cpu().numpy()
+                occ = w.view("occ_bits", torch.int64)[: Wb * s.n_words].cpu().numpy().view(np.uint64)
+                occ = occ.reshape(Wb, s.n_words)
+                idx = np.arange(0, Wb, Wb // 4)
+                orc = OracleSystem.from_workload(wl)
+                e_o, _, _, _ = orc.local_energy_batch(occ[idx], ORC_LEMMA)
+                errs.append(float(np.max(np.abs(e_o - el[idx])) / (wl.n_elec if prec == vmc.VMC_MIXED else 1)))
+            el_err = max(errs)
     finally:
         vmc.vmc_batch_destroy(b)
     total_w = Wb * len(names)
-    rb = 4 if prec == vmc.VMC_MIXED else 8
+    # mixed form with the state in HBM: FP32 R plus its bfloat16 remainder
+    rb = 6 if prec == vmc.VMC_MIXED else 8
     bytes_per_move = sum(2.0 * (s.n_so * s.ne * rb + s.ne * s.ne * 8) * Wb for s in systems)
     gbs = bytes_per_move * S / (ms * 1e-3) / 1e9
     flagged = sum(int(np.count_nonzero(w.view("status", torch.int32)[:Wb].cpu().numpy() & 1)) for w in walkers)
+    traffic, split = counted_traffic("batch", total_w, S, nt, args.precision)
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle on each system for a third of the time, summed as walker-steps per second of all three
+        parts = [cpu_oracle_baseline(wl, args.cpu_seconds / 3) for wl in wls]
+        per_ws = sum(1.0 / p["value"] for p in parts) / len(parts)  # mean CPU seconds per walker-step
+        cpu = {"value": 1.0 / per_ws, "unit": "walker-steps/s", "cores": parts[0]["cores"], "kind": "oracle",
+               "sample": "; ".join(f"{n}: {p['sample']}" for n, p in zip(names, parts))}
     out = {
         "metric": METRIC, "value": total_w * S * args.steps / wall, "unit": "walker-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
@@ -209,10 +287,12 @@ def batch_bench(args):
                    "walkers": [Wb] * len(names), "ctmc_moves_per_step": S, "threads": nt,
                    "precision": args.precision},
         "flagged_walkers": flagged,
+        ("el_max_abs_err_per_electron" if prec == vmc.VMC_MIXED else "el_max_abs_err_vs_oracle"): el_err,
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "k_sweep_batch (one launch)",
-                     "sweep_kernel_ms": ms, "bytes_per_move_all_walkers": bytes_per_move},
-        "cpu_baseline": None,
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": traffic, "traffic_split": split,
+                     "kernel": "k_sweep_batch (one launch)", "sweep_kernel_ms": ms,
+                     "bytes_per_move_all_walkers": bytes_per_move},
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
@@ -242,47 +322,49 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    wl = make_config(args.config, n_walkers=args.walkers, eps=args.eps, orbitals=args.orbitals)
+    wl = make_config(args.config, n_walkers=(args.walkers or None), eps=args.eps, orbitals=args.orbitals,
+                     cps=args.cps)
     uhf = args.orbitals == "uhf"
-    W, S = args.walkers, args.sweep
+    W, S = wl.n_walkers, args.sweep
     head_prec = vmc.VMC_MIXED if args.precision == "mixed" else vmc.VMC_FP64
+    stream = torch.cuda.current_stream()
 
     def run_form(precision, steps, warmup, check):
         """One optimisation iteration per step, as described in the module docstring."""
+        mixed = precision == vmc.VMC_MIXED
         sysm = vmc.System.from_workload(wl, refresh_period=S, precision=precision)
         walkers = sysm.walkers(wl.occ)
         if args.threads:
             vmc.vmc_set_launch(sysm.handle, args.threads)
         else:
-            # project autotuner: workgroup size from timed sweeps (they count as burn-in)
+            # project autotuner: launch shape from timed sweeps (they count as burn-in)
             vmc.vmc_autotune(sysm.handle, walkers, 5)
-        nj = sysm.n_so * (sysm.n_so + 1) // 2
-        params = torch.cat([sysm.J, sysm.theta.reshape(-1)]).clone()
+        npar = sysm.n_params
+        params = sysm.param_vector().clone()
         m = torch.zeros_like(params)
         v = torch.zeros_like(params)
         vh = torch.zeros_like(params)
         G = torch.zeros_like(params)
         est = torch.zeros(4, dtype=torch.float64, device=dev)
         g = torch.zeros(W, dtype=torch.float64, device=dev)
-        stream = torch.cuda.current_stream()
-        sweep_events = []
+        sweep_t, eloc_t = HipTimer(stream), HipTimer(stream)
+
+        def iteration(st):
+            vmc.vmc_local_energy(sysm.handle, walkers, stream=st)
+            vmc.vmc_estimate(sysm.handle, walkers, est, g, stream=st)
+            vmc.vmc_logderiv(sysm.handle, walkers, g, G, stream=st)
+            vmc.vmc_amsgrad(params, m, v, vh, G, 1e-3, 0.9, 0.99, 1e-8, False, stream=st)
+            sysm.set_param_vector(params, stream=st)
+            vmc.vmc_walkers_refresh(sysm.handle, walkers, stream=st)
 
         def one_step(timed):
             if timed:
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
+                sweep_t.start()
             vmc.vmc_ctmc_step(sysm.handle, walkers, S, stream=stream)
             if timed:
-                e1.record(stream)
-                sweep_events.append((e0, e1))
+                sweep_t.stop()
             # E_L and t of the post-sweep states, so that O_k and E_L refer to the same determinant
-            vmc.vmc_local_energy(sysm.handle, walkers, stream=stream)
-            vmc.vmc_estimate(sysm.handle, walkers, est, g, stream=stream)
-            vmc.vmc_logderiv(sysm.handle, walkers, g, G, stream=stream)
-            vmc.vmc_amsgrad(params, m, v, vh, G, 1e-3, 0.9, 0.99, 1e-8, False, stream=stream)
-            vmc.vmc_set_params(sysm.handle, params[:nj], params[nj:], stream=stream)
-            vmc.vmc_walkers_refresh(sysm.handle, walkers, stream=stream)
+            iteration(stream)
             return est[2]
 
         # burn-in of the walkers (not timed, not counted)
@@ -296,27 +378,25 @@ def main():
             E = one_step(True)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        # E_L evaluations alone (vmc_local_energy over every walker)
+        for _ in range(3):
+            eloc_t.start()
+            vmc.vmc_local_energy(sysm.handle, walkers, stream=stream)
+            eloc_t.stop()
+        torch.cuda.synchronize()
         # the same iteration captured once in a HIP graph and replayed (CTMC
         # moves with the device-resident step counter)
         graph_value = None
         if not args.no_graph:
             step_dev = torch.tensor([walkers.step], dtype=torch.int64, device=dev)
-
-            def graph_step(st):
-                vmc.vmc_ctmc_step_dev(sysm.handle, walkers, S, step_dev, stream=st)
-                vmc.vmc_local_energy(sysm.handle, walkers, stream=st)
-                vmc.vmc_estimate(sysm.handle, walkers, est, g, stream=st)
-                vmc.vmc_logderiv(sysm.handle, walkers, g, G, stream=st)
-                vmc.vmc_amsgrad(params, m, v, vh, G, 1e-3, 0.9, 0.99, 1e-8, False, stream=st)
-                vmc.vmc_set_params(sysm.handle, params[:nj], params[nj:], stream=st)
-                vmc.vmc_walkers_refresh(sysm.handle, walkers, stream=st)
-
             graph = torch.cuda.CUDAGraph()
             cs = torch.cuda.Stream()
             cs.wait_stream(torch.cuda.current_stream())
             with torch.cuda.stream(cs):
                 with torch.cuda.graph(graph, stream=cs):
-                    graph_step(torch.cuda.current_stream())
+                    st = torch.cuda.current_stream()
+                    vmc.vmc_ctmc_step_dev(sysm.handle, walkers, S, step_dev, stream=st)
+                    iteration(st)
             torch.cuda.current_stream().wait_stream(cs)
             graph.replay()
             torch.cuda.synchronize()
@@ -327,49 +407,83 @@ def main():
             graph_value = W * S * steps / (time.perf_counter() - t0)
             walkers.step = int(step_dev.item())
         res = {"sysm": sysm, "walkers": walkers, "params": params, "wall": wall, "E": float(E),
-               "graph_value": graph_value,
-               "value": W * S * steps / wall,
-               "sweep_ms": float(np.mean([a.elapsed_time(b) for a, b in sweep_events])),
-               "status": walkers.view("status", torch.int32)[:W].cpu().numpy()}
-        # E_L of the final states against the oracle, on a sample of walkers
-        res["el_err"] = None
-        if check:
-            from oracle.core import ORC_LEMMA, OracleSystem
-
-            vmc.vmc_local_energy(sysm.handle, walkers, stream=stream)
-            torch.cuda.synchronize()
-            el = walkers.view("eloc", torch.float64)[:W].cpu().numpy()
-            occ = walkers.view("occ_bits", torch.int64)[: W * sysm.n_words].cpu().numpy().view(np.uint64)
-            occ = occ.reshape(W, sysm.n_words)
-            orc = OracleSystem(wl.n_orb, wl.n_alpha, wl.n_beta, wl.h1, wl.eri_idx, wl.eri_val, wl.eps)
-            p = params.cpu().numpy()
-            orc.set_params(p[:nj], p[nj:].reshape(sysm.n_so, sysm.n_so))
-            idx = np.arange(0, W, max(1, W // 16))
-            e_o, _, _, _ = orc.local_energy_batch(occ[idx], ORC_LEMMA)
-            res["el_err"] = float(np.max(np.abs(e_o - el[idx])))
+               "graph_value": graph_value, "value": W * S * steps / wall, "sweep_ms": sweep_t.mean_ms(),
+               "eloc_ms": eloc_t.mean_ms(), "status": walkers.view("status", torch.int32)[:W].cpu().numpy()}
+        res["check"] = check_eloc(sysm, walkers, mixed) if check else None
         return res
+
+    def check_eloc(sysm, walkers, mixed):
+        """One more refresh period from fresh inverses with histories; the
+        oracle evaluates the sampled walkers' states of its last ten moves
+        (E_L before each move) and the states it ends on (E_L by
+        vmc_local_energy), all before any re-inversion."""
+        from oracle.core import ORC_LEMMA, OracleSystem
+
+        nw = sysm.n_words
+        vmc.vmc_walkers_refresh(sysm.handle, walkers, stream=stream)
+        occ0 = walkers.view("occ_bits", torch.int64)[: W * nw].cpu().numpy().view(np.uint64).reshape(W, nw).copy()
+        step0 = walkers.step
+        eh = torch.zeros((S, W), dtype=torch.float64, device=dev)
+        ph = torch.zeros((S, W), dtype=torch.int64, device=dev)
+        vmc.vmc_ctmc_step(sysm.handle, walkers, S, eh, None, ph, stream=stream)
+        vmc.vmc_local_energy(sysm.handle, walkers, stream=stream)
+        torch.cuda.synchronize()
+        el_end = walkers.view("eloc", torch.float64)[:W].cpu().numpy()
+        eh, ph = eh.cpu().numpy(), ph.cpu().numpy()
+        idx = np.unique(np.linspace(0, W - 1, args.check_walkers).astype(int))
+        states, ref, wk, sk = [], [], [], []
+        k0 = max(0, S - 10)
+        for w in idx:
+            bits = occ0[w].copy()
+            for k in range(S):
+                if k >= k0:
+                    states.append(bits.copy())
+                    ref.append(eh[k, w])
+                    wk.append(w)
+                    sk.append(step0 + k)
+                t, i, j, a, b = vmc.vmc_decode_pick(int(ph[k, w]))
+                if t:
+                    bits[i >> 6] &= ~np.uint64(1 << (i & 63))
+                    bits[a >> 6] |= np.uint64(1 << (a & 63))
+                    if t == 2:
+                        bits[j >> 6] &= ~np.uint64(1 << (j & 63))
+                        bits[b >> 6] |= np.uint64(1 << (b & 63))
+            states.append(bits.copy())
+            ref.append(el_end[w])
+            wk.append(w)
+            sk.append(step0 + S)
+        orc = OracleSystem.from_workload(wl)
+        orc.set_params(*sysm.host_params())
+        if len(wl.cps_sites):
+            orc.set_cps(wl.cps_sites, sysm.host_cps())
+        e_o, t_o, _, _, rc = orc.eval_states(np.stack(states), wl.ctmc_seed, np.array(wk), np.array(sk), ORC_LEMMA,
+                                             min(16, os.cpu_count() or 1))
+        ok = rc == 0
+        d = np.abs(e_o - np.array(ref))[ok]
+        T = 1.0 / t_o[ok]
+        tol = (1e-6 * wl.n_elec + 1e-9 * T) if mixed else (1e-10 + 1e-13 * T)
+        return {"states": int(ok.sum()), "walkers": int(idx.size), "moves_since_inversion": [k0, S],
+                "max_abs_err": float(d.max()), "max_abs_err_per_electron": float(d.max() / wl.n_elec),
+                "max_err_over_tol": float(np.max(d / tol)), "median_T": float(np.median(T))}
 
     head = run_form(head_prec, args.steps, args.warmup, not args.no_check)
     sysm, walkers = head["sysm"], head["walkers"]
-    value, wall, sweep_ms, E, status, el_err = (head["value"], head["wall"], head["sweep_ms"], head["E"],
-                                               head["status"], head["el_err"])
+    value, wall, sweep_ms, E, status = head["value"], head["wall"], head["sweep_ms"], head["E"], head["status"]
     other = None
     if not args.no_other_form:
         o_prec = vmc.VMC_FP64 if head_prec == vmc.VMC_MIXED else vmc.VMC_MIXED
         o = run_form(o_prec, args.steps, args.warmup, not args.no_check)
         other = {"precision": "fp64" if o_prec == vmc.VMC_FP64 else "mixed", "value": o["value"],
                  "unit": "walker-steps/s", "sweep_kernel_ms": o["sweep_ms"],
-                 "eloc_evals_per_s_in_sweep": W * S / (o["sweep_ms"] * 1e-3),
-                 "el_max_abs_err_vs_oracle": o["el_err"],
-                 "el_max_abs_err_per_electron": (o["el_err"] / wl.n_elec) if o["el_err"] is not None else None,
+                 "eloc_evals_per_s": W / (o["eloc_ms"] * 1e-3), "eloc_check": o["check"],
                  "energy": o["E"], "flagged_walkers": int(np.count_nonzero(o["status"] & 1)),
-                 "graph_replay_value": o["graph_value"]}
+                 "graph_replay_value": o["graph_value"], "headline_over_this": value / o["value"]}
         o["sysm"].close()
 
     # --- algorithmic work of the sweep kernel, from candidate counts of a
     #     sample of the final walker states (library diagnostic entry point)
     ne, n_so = sysm.ne, sysm.n_so
-    cap = 200000
+    cap = 400000
     ijab = torch.zeros((cap, 5), dtype=torch.int32, device=dev)
     hv = torch.zeros(cap, dtype=torch.float64, device=dev)
     rv = torch.zeros(cap, dtype=torch.float64, device=dev)
@@ -378,7 +492,7 @@ def main():
     for w in range(0, W, max(1, W // 32)):
         vmc.vmc_excitations(sysm.handle, walkers, w, ijab, hv, rv, cap, cnt)
         n = int(cnt.item())
-        types = ijab[:n, 0].cpu().numpy()
+        types = ijab[: min(n, cap), 0].cpu().numpy()
         ks.append(int(np.count_nonzero(types == 1)))
         kd.append(int(np.count_nonzero(types == 2)))
     K_s, K_d = float(np.mean(ks)), float(np.mean(kd))
@@ -393,7 +507,8 @@ def main():
     flops = (10.0 * K_d + (ne + 7.0) * K_s + ne * (ne - 1) / 2 + ne + 2 * 1.5 * upd + 3 * n_so
              + (2.0 * ne ** 3 + 2.0 * n_so * ne * ne) / S)
     info = vmc.vmc_launch_info(sysm.handle)
-    rbytes = 4 if args.precision == "mixed" else 8
+    # mixed form: FP32 R, plus its bfloat16 remainder where the state is in HBM
+    rbytes = (4 if info["state_in_lds"] else 6) if args.precision == "mixed" else 8
     # HBM bytes per walker-step when the state stays in HBM: R and B read and
     # written once per move.  Spin-blocked: the moving spin's blocks, averaged
     # over the two spins (exact for single moves and same-spin doubles; an
@@ -409,11 +524,13 @@ def main():
     ckey = args.config if args.eps is None else f"{args.config}:eps={args.eps:g}"
     if uhf:
         ckey += ":uhf"
+    if args.cps:
+        ckey += f":cps={args.cps}"
     traffic, traffic_split = counted_traffic(ckey, W, S, info["threads"], args.precision)
     common = {
         "kernel": ("k_sweep (persistent E_L + CTMC + Sherman-Morrison, walker state in LDS)" if info["state_in_lds"]
                    else "k_sweep (walker state in HBM), one vmc_ctmc_step; the re-inversion after each parameter "
-                        "update (k_refresh_gj) is outside the timed sweep but inside the step"),
+                        "update is outside the timed sweep but inside the step"),
         "traffic": traffic,
         "traffic_split": traffic_split,
         "hbm_gbs_measured": (traffic / sweep_s / 1e9) if traffic else None,
@@ -432,26 +549,15 @@ def main():
         roofline = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
                     "bytes_per_walker_step": state_bytes, "fp64_tflops": achieved_tflops, **common}
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        from oracle.core import ORC_LEMMA, OracleSystem
-
-        orc0 = OracleSystem.from_workload(wl)
-        threads = min(16, os.cpu_count() or 1)
-        # calibrate on a small batch, then time a bounded sample
-        c0 = time.perf_counter()
-        orc0.ctmc_batch(wl.occ[:threads], wl.ctmc_seed, 0, 2, ORC_LEMMA, threads)
-        per = (time.perf_counter() - c0) / (2 * threads)  # wall s per walker-step at full thread use
-        n_ws = max(threads, int(args.cpu_seconds / max(per, 1e-9)))
-        n_w = max(threads, min(W, n_ws // 5))
-        n_steps_cpu = max(5, n_ws // n_w)
-        c0 = time.perf_counter()
-        orc0.ctmc_batch(wl.occ[:n_w], wl.ctmc_seed, 0, n_steps_cpu, ORC_LEMMA, threads)
-        cpu_wall = time.perf_counter() - c0
-        cpu = {"value": n_w * n_steps_cpu / cpu_wall, "unit": "walker-steps/s", "cores": threads, "kind": "oracle",
-               "sample": f"{n_w} walkers x {n_steps_cpu} CTMC moves of the same workload (oracle, fresh-inverse "
-                         f"ratios, OpenMP over walkers), {cpu_wall:.1f} s"}
-
+    cpu = None if args.no_cpu_baseline else cpu_oracle_baseline(wl, args.cpu_seconds)
+    chk = head["check"]
+    workload = {
+        "hchain160": "hchain160: H-chain-like 160 orbitals, 80a+80b, eps=1e-5, 8192 walkers",
+        "hchain20": "hchain20: H-chain-like 20 orbitals, 10a+10b, eps=1e-6, 4096 walkers",
+        "hubbard10x10": "hubbard10x10: 2-D Hubbard 10x10 periodic, U=4, 50a+50b, 16384 walkers",
+    }.get(args.config, args.config)
+    if args.eps is not None or args.walkers or uhf or args.cps:
+        workload = f"{args.config} (eps={wl.eps:g}, {W} walkers, {args.orbitals}, cps={args.cps})"
     out = {
         "metric": METRIC,
         "value": value,
@@ -465,12 +571,15 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.config}: H-chain-like 20 orbitals, 10a+10b, eps=1e-6" if args.config ==
-                   "hchain20" and args.eps is None else args.config, "walkers": W, "ctmc_moves_per_step": S,
-                   "refresh_period": S, "precision": args.precision, "eps": wl.eps, "orbitals": args.orbitals},
-        "eloc_evals_per_s_in_sweep": W * S / (sweep_ms * 1e-3),
+        "config": {"workload": workload, "walkers": W, "ctmc_moves_per_step": S, "refresh_period": S,
+                   "precision": args.precision, "eps": wl.eps, "orbitals": args.orbitals,
+                   "correlators": args.cps},
+        "eloc_evals_per_s": W / (head["eloc_ms"] * 1e-3),
+        "eloc_kernel_ms": head["eloc_ms"],
         "graph_replay_value": head["graph_value"],
-        "el_max_abs_err_vs_oracle": el_err,
+        "el_max_abs_err_vs_oracle": chk["max_abs_err"] if chk else None,
+        "el_max_abs_err_per_electron": chk["max_abs_err_per_electron"] if chk else None,
+        "eloc_check": chk,
         "energy": E,
         "other_form": other,
         "flagged_walkers": int(np.count_nonzero(status & 1)),
