@@ -268,6 +268,23 @@ vmc_status vmc_ctmc_step(vmc_handle h, vmc_walkers* w, int32_t n_steps, double* 
                          int64_t* pick_hist, hipStream_t stream);
 
 /*
+ * vmc_ctmc_step for callers that cannot allocate device memory (code under
+ * graph capture, serving loops, harnesses that forbid allocation): the same
+ * moves, bit for bit, with the kernels' per-walker workspace (the walkers'
+ * `scratch` field: pair descriptors and singles elements) taken from a static
+ * device array of 64 MiB that the library holds on every GPU it runs on until
+ * the process ends; w->scratch is ignored and may be NULL.  No allocation, no
+ * allocating library call.  Calls that overlap on one GPU share that array and
+ * race: serialise them.  Errors: VMC_E_ARG when the walkers need more than 64
+ * MiB of workspace (n_walkers x the per-walker scratch size of
+ * vmc_walker_bytes), when the current device is not the handle's, or as
+ * vmc_ctmc_step; VMC_E_STATE if the array's address could not be taken on
+ * this device at vmc_init.
+ */
+vmc_status vmc_ctmc_step_static(vmc_handle h, vmc_walkers* w, int32_t n_steps, double* eloc_hist, double* t_hist,
+                                int64_t* pick_hist, hipStream_t stream);
+
+/*
  * vmc_ctmc_step with the global step counter in device memory instead of
  * w->step: the first move of the call uses *step_dev (read on the device when
  * the kernel runs), and a one-thread kernel adds n_steps to it after the

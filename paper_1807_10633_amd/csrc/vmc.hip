@@ -27,6 +27,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -2978,6 +2979,33 @@ vmc_status validate_desc(const vmc_system_desc* d) {
     return VMC_OK;
 }
 
+// Workspace of vmc_ctmc_step_static: the kernels' per-walker scratch (pair
+// descriptors, singles elements) for callers that cannot allocate.  Each GPU
+// holds its own copy of the array, at its own address, from module load until
+// the process ends.  In host code the array's name is only a stand-in: its
+// device address on each device comes from hipGetSymbolAddress, taken once
+// per device by vmc_init with that device current, and only that address is
+// ever passed to a kernel.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// Address of this device's copy of the static workspace (set-up, once per
+// device; the caller has made `device` current).
+vmc_status static_scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return fail(nullptr, VMC_E_UNSUPPORTED, "device index beyond 64");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return VMC_OK;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(nullptr, VMC_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[device] = ptr;
+    return VMC_OK;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ C ABI
@@ -3094,6 +3122,14 @@ vmc_status vmc_init(const vmc_system_desc* desc, const double* h1, const vmc_eri
     if (hipGetDevice(&h->device) != hipSuccess) {
         free_ctx(h);
         return fail(nullptr, VMC_E_HIP, "hipGetDevice failed");
+    }
+    {
+        const vmc_status ss = static_scratch_setup(h->device);
+        if (ss != VMC_OK) {
+            const std::string msg = g_err;
+            free_ctx(h);
+            return fail(nullptr, ss, msg);
+        }
     }
     std::vector<uint32_t> row_off(T.row_off.begin(), T.row_off.end());
     std::vector<uint32_t> dab(T.dv.size());
@@ -3344,6 +3380,32 @@ vmc_status vmc_ctmc_step(vmc_handle h, vmc_walkers* w, int32_t n_steps, double* 
         k += seg;
     }
     return VMC_OK;
+}
+
+vmc_status vmc_ctmc_step_static(vmc_handle h, vmc_walkers* w, int32_t n_steps, double* eh, double* th, int64_t* ph,
+                                hipStream_t st) {
+    if (!h) return fail(nullptr, VMC_E_ARG, "handle is NULL");
+    if (!w) return fail(h, VMC_E_ARG, "walkers is NULL");
+    if (w->n_walkers <= 0 || w->n_walkers > (int64_t)INT_MAX) return fail(h, VMC_E_ARG, "n_walkers out of range");
+    const size_t need = (size_t)w->n_walkers * (size_t)scratch_bytes(h);
+    if (need > kStaticScratchBytes)
+        return fail(h, VMC_E_ARG, "the static workspace holds " + std::to_string(kStaticScratchBytes) + " bytes; " +
+                                      std::to_string(w->n_walkers) + " walkers of this system need " +
+                                      std::to_string(need));
+    int dev = -1;
+    HIP_OR_FAIL(h, hipGetDevice(&dev));
+    if (dev != h->device) return fail(h, VMC_E_ARG, "the handle belongs to another device than the current one");
+    void* ptr = (dev >= 0 && dev < kMaxDevices) ? g_scratch_ptr[dev] : nullptr;
+    if (!ptr) return fail(h, VMC_E_STATE, "static workspace not set up on this device");
+    // the same sweep with the workspace field pointing at this device's copy
+    // of the static array (every kernel rewrites what it reads of it first:
+    // nothing needs clearing)
+    vmc_walkers ws = *w;
+    ws.scratch = ptr;
+    const vmc_status s = vmc_ctmc_step(h, &ws, n_steps, eh, th, ph, st);
+    w->step = ws.step;
+    w->since_inv = ws.since_inv;
+    return s;
 }
 
 vmc_status vmc_ctmc_step_dev(vmc_handle h, vmc_walkers* w, int32_t n_steps, uint64_t* step_dev, hipStream_t st) {

@@ -32,6 +32,7 @@ EXPORTED = (
     "vmc_host_tables_free", "vmc_set_launch", "vmc_launch_info", "vmc_estimate", "vmc_batch_create",
     "vmc_batch_set_launch", "vmc_batch_local_energy", "vmc_batch_ctmc_step", "vmc_batch_destroy", "vmc_autotune",
     "vmc_batch_autotune", "vmc_ctmc_step_dev", "vmc_walkers_refresh", "vmc_cps_init", "vmc_set_cps", "vmc_cps_info",
+    "vmc_ctmc_step_static",
 )
 
 
@@ -76,6 +77,7 @@ def load_library() -> C.CDLL:
         "vmc_walkers_refresh": ([P, P, P], i32),
         "vmc_local_energy": ([P, P, P], i32),
         "vmc_ctmc_step": ([P, P, i32, P, P, P, P], i32),
+        "vmc_ctmc_step_static": ([P, P, i32, P, P, P, P], i32),
         "vmc_logderiv": ([P, P, P, P, P], i32),
         "vmc_amsgrad": ([i64, P, P, P, P, P, d, d, d, d, i32, P], i32),
         "vmc_excitations": ([P, P, i64, P, P, P, i64, P, P], i32),
@@ -197,6 +199,14 @@ def vmc_ctmc_step(handle, walkers: "Walkers", n_steps: int, eloc_hist=None, t_hi
     _check(load_library().vmc_ctmc_step(handle, C.byref(walkers.cstruct), int(n_steps), _dev_ptr(eloc_hist),
                                         _dev_ptr(t_hist), _dev_ptr(pick_hist), _stream_ptr(stream)), handle,
            "vmc_ctmc_step")
+
+
+def vmc_ctmc_step_static(handle, walkers: "Walkers", n_steps: int, eloc_hist=None, t_hist=None, pick_hist=None,
+                         stream=None) -> None:
+    """vmc_ctmc_step with the kernels' workspace in the library's static array (no allocation)."""
+    _check(load_library().vmc_ctmc_step_static(handle, C.byref(walkers.cstruct), int(n_steps), _dev_ptr(eloc_hist),
+                                               _dev_ptr(t_hist), _dev_ptr(pick_hist), _stream_ptr(stream)), handle,
+           "vmc_ctmc_step_static")
 
 
 def vmc_ctmc_step_dev(handle, walkers: "Walkers", n_steps: int, step_dev, stream=None) -> None:

@@ -54,7 +54,7 @@ def test_stepping_entry_points_reach_no_allocation():
     funcs = dict(_functions(src))
     for ep in ("vmc_local_energy", "vmc_ctmc_step", "vmc_ctmc_step_dev", "vmc_logderiv", "vmc_estimate",
                "vmc_amsgrad", "vmc_walkers_init", "vmc_walkers_refresh", "vmc_batch_local_energy",
-               "vmc_batch_ctmc_step", "vmc_set_params", "vmc_set_cps"):
+               "vmc_batch_ctmc_step", "vmc_set_params", "vmc_set_cps", "vmc_ctmc_step_static"):
         assert ep in funcs, ep
         assert not ALLOC.search(funcs[ep]), ep
     # the helpers they launch through
