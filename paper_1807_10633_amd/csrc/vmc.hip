@@ -221,12 +221,10 @@ struct Lds {
         thl, total;
 };
 __host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~(size_t)15; }
-// bytes of the doubles group descriptors (padded stream end, offset delta,
-// valid end, slots, Jastrow factor) for one walker
-__host__ __device__ inline size_t desc_bytes(int ne) {
-    const size_t gd = (size_t)ne * (ne - 1) / 2;
-    return al16(gd * 4) * 4 + al16(gd * 8);
-}
+// Doubles of the layout with the walker state in HBM run over tiles of
+// kPairBlock x kPairBlock occupied pairs (pair_tiles).
+constexpr int kPairBlock = 16;
+__host__ __device__ inline int pair_blocks(int ne) { return (ne + kPairBlock - 1) / kPairBlock; }
 // rb: bytes per R element (8 for the FP64 form, 4 for the mixed form);
 // ncorr: correlators (their current states and inverse coefficients)
 __host__ __device__ __forceinline__ Lds lds_layout(int n_so, int ne, int nw, int nt, bool small, int rb, int ncorr) {
@@ -286,10 +284,11 @@ __host__ __device__ __forceinline__ Lds lds_layout(int n_so, int ne, int nw, int
     L.total = (uint32_t)o;
     return L;
 }
-// per-walker global scratch: the doubles group descriptors when they do not fit in LDS
-// followed, when the singles carry Coulomb-exchange vectors, by the walker's
-// Fock-like singles elements (one double per singles-table entry)
-__host__ __device__ inline size_t scratch_fock_offset(int ne) { return al16(desc_bytes(ne) + 16); }
+// per-walker global scratch (walker state in HBM): the rate sums of the
+// doubles' pair segments (Ne x pair_blocks(Ne)), followed, when the singles
+// carry Coulomb-exchange vectors, by the walker's Fock-like singles elements
+// (one double per singles-table entry)
+__host__ __device__ inline size_t scratch_fock_offset(int ne) { return al16((size_t)ne * pair_blocks(ne) * 8 + 16); }
 __host__ __device__ inline size_t scratch_layout_bytes(int ne, int64_t n_fock) {
     return scratch_fock_offset(ne) + (size_t)n_fock * 8;
 }
@@ -803,7 +802,7 @@ struct StepView {
     const uint32_t* ddelta;
     const uint32_t* dvend;
     const uint32_t* dpq;    //          slots p | q << 16
-    const double* dfac;     //          exp(-s_i - s_j) (unscaled path)
+    const double* ies;      // exp(-s_p)         (unscaled path)
     const int* slot;        // orbital held by each slot
     const uint32_t* cidx;   // correlators: current local Fock state of each
     const double* cinv;     //              and 1 / its coefficient
@@ -952,7 +951,7 @@ __device__ __forceinline__ double cand_eval(const Tab& T, const StepView<RT>& V,
             const RT* Rq = V.R + q * n_so;
             det = (double)Rp[a] * (double)Rq[b] - (double)Rp[b] * (double)Rq[a];
         }
-        double ratio = SCALED ? det * vk.y : det * V.es[a] * V.es[b] * vk.y * V.dfac[g];
+        double ratio = SCALED ? det * vk.y : det * V.es[a] * V.es[b] * vk.y * (V.ies[V.slot[p]] * V.ies[V.slot[q]]);
         if (T.ncorr) ratio *= cps_ratio(T, V.cidx, V.cinv, 4, V.slot[p], V.slot[q], a, b);
         if (WANT_H) term = vk.x * ratio;
         cp = p; cq = q; ca = a; cb = b;
@@ -1242,6 +1241,183 @@ __device__ __forceinline__ bool stream_pass(const Tab& T, const StepView<RT>& V,
     return found;
 }
 
+// Doubles of the layout with the walker state in HBM, over tiles of occupied
+// pairs.  The occupied orbitals (ascending, index x) are cut into blocks of
+// kPairBlock.  Segment (x, Y) is the run of pairs (x, y), y > x, y in block Y:
+// a contiguous piece of the canonical order (pairs by x, then by y), whose
+// rate sum goes to segsum[x * nb + Y].  Tiles (X, Y), X <= Y, are visited
+// Y-major by all waves of the workgroup together (segment x of tile k to wave
+// (x - X kPairBlock + k) mod nwv), so that the rows of R of the two blocks,
+// which the pairs' 2x2 minors gather, are reused from the caches across the
+// tile instead of fetched once per pair.  Per segment the lanes hold its
+// pairs' table rows, each padded to 64 positions so that a chunk lies in one
+// row; survivors queue and are evaluated 64 at a time as in stream_pass, and
+// since the queue keeps processing order each segment's survivors form one
+// run of lanes.  ELOC: E_L terms into `el`, rate sums per segment (segments
+// without survivors keep the zero written before).  PICK: segment (px, py)
+// only, running sum from `base`, pick as stream_pass.
+template <bool PICK, bool UHF, typename RT>
+__device__ __forceinline__ bool pair_tiles(const Tab& T, const StepView<RT>& V, const uint64_t* occw, const int* oslot,
+                                           uint64_t* q64, uint64_t* qab, double& el, double* segsum, int px, int py,
+                                           double base, double target, bool fallback, int* pick) {
+    const int l = lane_id();
+    const int wv = (int)uni((uint32_t)(threadIdx.x >> 6)), nwv = blockDim.x >> 6;
+    const int ne = T.ne, n_so = T.n_so, nb = pair_blocks(ne);
+    uint32_t qn = 0, qh = 0;
+    double run = base;
+    bool found = false;
+    int last_l = -1;
+    uint32_t last_off = 0;
+    uint64_t last_ab = 0;
+    int cur_s = -1;  // ELOC: the open segment and its rate sum so far (wave-uniform)
+    double cur_sum = 0.0;
+
+    auto batch = [&](int k) __attribute__((always_inline)) -> bool {
+        wave_lds_sync();
+        const bool act = l < k;
+        const uint32_t qi = (qh + (uint32_t)l) & (kQueue - 1);
+        const uint64_t og = act ? q64[qi] : 0ull;
+        const uint32_t off = (uint32_t)og, sg = (uint32_t)(og >> 32);
+        const uint64_t ab = act ? qab[qi] : 0ull;
+        double term = 0.0, r = 0.0;
+        int cp = 0, cq = 0, ca = 0, cb = 0;
+        if (act) {
+            const double2 vk = *(const double2*)(T.dvK + 2 * (size_t)off);
+            r = fabs(cand_eval<true, !PICK, false, false, UHF>(T, V, off, 0u, ab, vk, term, cp, cq, ca, cb));
+        }
+        if (!PICK) {
+            el += term;
+            uint64_t rem = __ballot(act);
+            while (rem) {
+                const int fl = __ffsll((unsigned long long)rem) - 1;
+                const int s0 = __builtin_amdgcn_readlane((int)sg, fl);
+                const uint64_t m = __ballot(act && (int)sg == s0);
+                const double part = wave_total(((m >> l) & 1ull) ? r : 0.0);
+                if (s0 != cur_s) {
+                    if (cur_s >= 0 && l == 0) segsum[cur_s] = cur_sum;
+                    cur_s = s0;
+                    cur_sum = 0.0;
+                }
+                cur_sum += part;
+                rem &= ~m;
+            }
+            return false;
+        }
+        const uint64_t mpos = __ballot(r > 0.0);
+        if (mpos) {
+            last_l = 63 - __clzll((long long)mpos);
+            last_off = __shfl(off, last_l, kWave);
+            last_ab = ((uint64_t)__shfl((uint32_t)(ab >> 32), last_l, kWave) << 32) |
+                      (uint64_t)__shfl((uint32_t)ab, last_l, kWave);
+        }
+        if (fallback) return false;
+        const double incl = wave_inclusive_scan(r);
+        const uint64_t mx = __ballot(act && r > 0.0 && run + incl > target);
+        if (mx) {
+            const int fl = __ffsll((unsigned long long)mx) - 1;
+            if (l == fl) { pick[0] = 2; pick[1] = cp; pick[2] = cq; pick[3] = ca; pick[4] = cb; }
+            return true;
+        }
+        run += __shfl(incl, kWave - 1, kWave);
+        return false;
+    };
+
+    auto segment = [&](int x, int yb) __attribute__((always_inline)) {
+        const int y0 = max(x + 1, yb * kPairBlock), y1 = min(ne, (yb + 1) * kPairBlock) - 1;
+        if (y0 > y1) return;
+        const int np = y1 - y0 + 1;
+        const uint32_t sid = (uint32_t)(x * nb + yb);
+        // lane l < np: pair (x, y0 + l), its table row and its slots
+        uint32_t b0 = 0, len = 0, plen = 0, pq = 0;
+        if (l < np) {
+            const int i = V.occl[x], j = V.occl[y0 + l];
+            const int row = i * n_so + j;
+            b0 = T.row_off[row];
+            len = T.row_off[row + 1] - b0;
+            plen = (len + 63u) & ~63u;
+            pq = (uint32_t)oslot[i] | ((uint32_t)oslot[j] << 16);
+        }
+        const uint32_t end = wave_scan_u32(plen), start = end - plen;
+        const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)end, np - 1);
+        for (uint32_t c = 0; c < tot && !found; c += kUnroll * kWave) {
+            uint32_t off[kUnroll], pqs[kUnroll], abv[kUnroll];
+            bool ok[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint32_t cu = c + (uint32_t)(u * kWave);
+                ok[u] = false;
+                off[u] = 0;
+                pqs[u] = 0;
+                if (cu < tot) {
+                    // the chunk's pair: the first lane whose row ends past it
+                    const uint64_t m = __ballot(end > cu);
+                    const int gl = (int)uni((uint32_t)(__ffsll((unsigned long long)m) - 1));
+                    const uint32_t gs = (uint32_t)__builtin_amdgcn_readlane((int)start, gl);
+                    const uint32_t glen = (uint32_t)__builtin_amdgcn_readlane((int)len, gl);
+                    const uint32_t gb = (uint32_t)__builtin_amdgcn_readlane((int)b0, gl);
+                    pqs[u] = (uint32_t)__builtin_amdgcn_readlane((int)pq, gl);
+                    const uint32_t pos = cu - gs + (uint32_t)l;
+                    ok[u] = pos < glen;
+                    off[u] = ok[u] ? gb + pos : 0u;  // entry 0 stands in for lanes without a candidate
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) abv[u] = T.dab[off[u]];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint32_t a = abv[u] & 0xFFFFu, b = abv[u] >> 16;
+                const bool surv = ok[u] && !found && !((occw[a >> 6] >> (a & 63)) & 1ull) &&
+                                  !((occw[b >> 6] >> (b & 63)) & 1ull);
+                const uint64_t m = __ballot(surv);
+                if (surv) {
+                    const uint32_t sq = (qh + qn + mask_below(m)) & (kQueue - 1);
+                    q64[sq] = (uint64_t)off[u] | ((uint64_t)sid << 32);
+                    qab[sq] = (uint64_t)abv[u] | ((uint64_t)pqs[u] << 32);
+                }
+                qn += (uint32_t)__popcll(m);
+                if (qn >= (uint32_t)kWave) {
+                    found = batch(kWave);
+                    wave_lds_sync();  // the batch's queue reads precede later writes
+                    qh = (qh + kWave) & (kQueue - 1);
+                    qn -= kWave;
+                }
+            }
+        }
+    };
+
+    if (PICK) {
+        segment(px, py);
+    } else {
+        int k = 0;
+        for (int yb = 0; yb < nb; ++yb)
+            for (int xb = 0; xb <= yb; ++xb, ++k) {
+                int xl = (wv - k) % nwv;
+                if (xl < 0) xl += nwv;
+                for (; xl < kPairBlock; xl += nwv) {
+                    const int x = xb * kPairBlock + xl;
+                    if (x >= ne - 1) break;
+                    segment(x, yb);
+                }
+            }
+    }
+    if (!found && qn > 0) found = batch((int)qn);
+    if (!PICK && cur_s >= 0 && l == 0) segsum[cur_s] = cur_sum;
+    wave_lds_sync();
+    if (PICK && !found && last_l >= 0) {
+        // rounding left the target past the segment's last running sum: take
+        // its last candidate with a positive rate
+        if (l == 0) {
+            double term;
+            int cp, cq, ca, cb;
+            const double2 vk = *(const double2*)(T.dvK + 2 * (size_t)last_off);
+            cand_eval<true, false, false, false, UHF>(T, V, last_off, 0u, last_ab, vk, term, cp, cq, ca, cb);
+            pick[0] = 2; pick[1] = cp; pick[2] = cq; pick[3] = ca; pick[4] = cb;
+        }
+        found = true;
+    }
+    return found;
+}
+
 // In-place inclusive prefix sum of the first n entries of a wave's log.
 __device__ __forceinline__ double log_prefix(double* a, int n) {
     const int l = lane_id();
@@ -1343,9 +1519,11 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
     double* cinv = (double*)(smem + L.cinv);
     RT *R, *Rh;
     uint16_t* Rlo = nullptr;
-    double *B, *dfac;
-    double* Fk = nullptr;  // the walker's Fock-like singles elements (state in HBM, Coulomb-exchange vectors)
-    uint32_t *dgend, *ddelta, *dvend, *dpq;
+    double* B;
+    double* Fk = nullptr;      // the walker's Fock-like singles elements (state in HBM, Coulomb-exchange vectors)
+    double* segsum = nullptr;  // rate sums of the doubles' pair segments (state in HBM)
+    uint32_t *dgend = nullptr, *ddelta = nullptr, *dvend = nullptr, *dpq = nullptr;
+    const int npb = pair_blocks(ne);
     if (SMALL) {
         R = (RT*)(smem + L.R);
         B = (double*)(smem + L.B);
@@ -1354,7 +1532,6 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
         ddelta = (uint32_t*)(smem + L.ddelta);
         dvend = (uint32_t*)(smem + L.dvend);
         dpq = (uint32_t*)(smem + L.dpq);
-        dfac = nullptr;
     } else {
         R = (RT*)S.R + (size_t)w * T.rrow * ne;
         if (SPLIT) Rlo = S.Rlo + (size_t)w * T.rrow * ne;
@@ -1362,14 +1539,9 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
         Rh = R;
         uint8_t* sc = S.scratch + (size_t)w * S.scratch_stride;
         if (T.has_sV && T.fock) Fk = (double*)(sc + scratch_fock_offset(ne));
-        const size_t st4 = al16((size_t)gd * 4);
-        dgend = (uint32_t*)sc;
-        ddelta = (uint32_t*)(sc + st4);
-        dvend = (uint32_t*)(sc + 2 * st4);
-        dpq = (uint32_t*)(sc + 3 * st4);
-        dfac = (double*)(sc + 4 * st4);
+        segsum = (double*)sc;
     }
-    const StepView<RT> V{occl, es,   SMALL ? Rh : R, sgend, sdelta, svend, spq, sfac, dgend, ddelta, dvend, dpq, dfac,
+    const StepView<RT> V{occl, es,   SMALL ? Rh : R, sgend, sdelta, svend, spq, sfac, dgend, ddelta, dvend, dpq, ies,
                          slot, cidx, cinv, Fk};
 
     // ---------------------------------------------------------------- load
@@ -1486,10 +1658,14 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
             spq[x] = (uint32_t)oslot[i];
             sfac[x] = ies[i];
         }
-        // doubles: blocks of 64 consecutive pairs, one per wave at a time;
-        // pass 1 sums each block's padded lengths, the block sums are
-        // scanned, pass 2 scans within the block and writes the descriptors
-        const int nblk = (gd + kWave - 1) / kWave;
+        // doubles, state in LDS: blocks of 64 consecutive pairs, one per wave
+        // at a time; pass 1 sums each block's padded lengths, the block sums
+        // are scanned, pass 2 scans within the block and writes the
+        // descriptors.  State in HBM: no descriptors (pair_tiles forms them
+        // per segment); the segment rate sums start at zero.
+        const int nblk = SMALL ? (gd + kWave - 1) / kWave : 0;
+        if (!SMALL && gd > 0)
+            for (int k2 = tid; k2 < ne * npb; k2 += nt) segsum[k2] = 0.0;
         auto pair_row = [&](int t, int& i, int& j, uint32_t& b0, uint32_t& len) __attribute__((always_inline)) {
             int x, y;
             pair_decode(t, ne, x, y);
@@ -1538,7 +1714,6 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
                 ddelta[t] = b0 - start;
                 dvend[t] = start + len;
                 dpq[t] = (uint32_t)oslot[i] | ((uint32_t)oslot[j] << 16);
-                if (!SMALL) dfac[t] = ies[i] * ies[j];
             }
         }
         __syncthreads();
@@ -1572,10 +1747,12 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
                 const uint32_t g0 = find_group(sgend, (uint32_t)ne, r0s);
                 stream_pass<false, false, NW1, SMALL, UHF>(T, V, occ0, occw, r0s, r1s, g0, (uint32_t)ne, r0s, q64, qab, el_lane, lsum + lb, loff + lb, lg + lb, kLogS, ns, 0.0, 0.0, false, nullptr);
             }
-            if (r0d < r1d) {
+            if (SMALL && r0d < r1d) {
                 const uint32_t g0 = find_group(dgend, (uint32_t)gd, r0d);
                 stream_pass<true, false, NW1, SMALL, UHF>(T, V, occ0, occw, r0d, r1d, g0, (uint32_t)gd, r0d, q64, qab, el_lane, lsum + lb + kLogS, loff + lb + kLogS, lg + lb + kLogS, kLogD, nd, 0.0, 0.0, false, nullptr);
             }
+            if (!SMALL && gd > 0)
+                pair_tiles<false, UHF>(T, V, occw, oslot, q64, qab, el_lane, segsum, 0, 0, 0.0, 0.0, false, nullptr);
             // per-wave inclusive prefix sums of the two logs and their totals
             const double ts = log_prefix(lsum + lb, ns), td = log_prefix(lsum + lb + kLogS, nd);
             if (l == 0) {
@@ -1596,12 +1773,27 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
         // ------------------------------------------ T and the pick location
         // T = sum of the per-wave log totals (singles then doubles, waves in
         // order); the target u*T is located first among those totals, then by
-        // binary search in that wave's prefix-summed log.
+        // binary search in that wave's prefix-summed log.  Doubles with the
+        // state in HBM: their part of T is the sum of the pair segments' rate
+        // sums in canonical order (by x, the sums of row x of the segments
+        // first), and u*T is located among the segments.
+        const bool tiled = !SMALL && gd > 0;
+        if (tiled && !singular) {
+            for (int x = tid; x < ne; x += nt) {
+                double rs = 0.0;
+                for (int yb = 0; yb < npb; ++yb) rs += segsum[x * npb + yb];
+                fcol[x] = rs;
+            }
+            __syncthreads();
+        }
         if (tid == 0) {
             double Tt = 0.0;
-            if (!singular)
+            if (!singular) {
                 for (int st = 0; st < 2; ++st)
                     for (int q = 0; q < nwv; ++q) Tt += wtot[2 * q + st];
+                if (tiled)
+                    for (int x = 0; x < ne; ++x) Tt += fcol[x];
+            }
             md[MD_T] = Tt;
             mi[MI_PTYPE] = 0;
             mi[MI_FS] = -1;
@@ -1621,7 +1813,43 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
                         else run += v;
                     }
                 bool fb = false;
-                if (fs < 0 && ls_ >= 0) { fs = ls_; fw = lw_; fbase = lbase; fb = true; }
+                if (tiled && fs < 0) {
+                    // doubles: the row x of segments, then the segment, whose
+                    // running sum first exceeds the target (or, after
+                    // rounding, the last segment with a positive sum)
+                    int fx = -1, lx = -1;
+                    double xbase = 0.0;
+                    for (int x = 0; x < ne && fx < 0; ++x) {
+                        const double v = fcol[x];
+                        if (v > 0.0) { lx = x; xbase = run; }
+                        if (v > 0.0 && run + v > target) fx = x;
+                        else run += v;
+                    }
+                    const bool xfb = fx < 0;
+                    if (xfb) fx = lx;
+                    if (fx >= 0) {
+                        double sr = xfb ? xbase : run;
+                        int fy = -1, ly = -1;
+                        double ybase = sr;
+                        for (int yb = 0; yb < npb && fy < 0; ++yb) {
+                            const double v = segsum[fx * npb + yb];
+                            if (v > 0.0) { ly = yb; ybase = sr; }
+                            if (!xfb && v > 0.0 && sr + v > target) fy = yb;
+                            else sr += v;
+                        }
+                        const bool yfb = fy < 0;
+                        if (yfb) fy = ly;
+                        mi[MI_FS] = 2;
+                        mi[MI_FW] = fx;
+                        mi[MI_FK] = fy;
+                        mi[MI_FFB] = (xfb || yfb) ? 1 : 0;
+                        md[MD_BASE] = yfb ? ybase : sr;
+                    } else if (ls_ >= 0) {
+                        fs = ls_; fw = lw_; fbase = lbase; fb = true;
+                    }
+                } else if (fs < 0 && ls_ >= 0) {
+                    fs = ls_; fw = lw_; fbase = lbase; fb = true;
+                }
                 if (fs >= 0) {
                     const int n_ent = wst[fw * 8 + (fs ? WS_ND : WS_NS)];
                     const double* pre = lsum + fw * (kLogS + kLogD) + (fs ? kLogS : 0);
@@ -1659,7 +1887,14 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
 
         // --------------------------------------------------------- pick
         if (okT && mi[MI_FS] >= 0) {
-            if (wv == 0) {
+            if (wv == 0 && mi[MI_FS] == 2) {
+                // doubles, state in HBM: re-walk the located pair segment
+                const int fx = (int)uni((uint32_t)mi[MI_FW]), fy = (int)uni((uint32_t)mi[MI_FK]);
+                const bool fb = uni((uint32_t)mi[MI_FFB]) != 0;
+                double dummy = 0.0;
+                pair_tiles<true, UHF>(T, V, occw, oslot, q64, qab, dummy, nullptr, fx, fy, md[MD_BASE], md[MD_TARGET],
+                                      fb, mi + MI_PTYPE);
+            } else if (wv == 0) {
                 const int fs = (int)uni((uint32_t)mi[MI_FS]), fw = (int)uni((uint32_t)mi[MI_FW]);
                 const int fk = (int)uni((uint32_t)mi[MI_FK]);
                 const bool fb = uni((uint32_t)mi[MI_FFB]) != 0;
