@@ -328,9 +328,7 @@ struct Mma<double> {
 // and every update carry both, so hi stays the rounding of the FP64 R instead
 // of accumulating one FP32 rounding per move.
 __device__ __forceinline__ uint16_t bf16_rn(float x) {
-    uint32_t b = __float_as_uint(x);
-    b += 0x7FFFu + ((b >> 16) & 1u);  // round to nearest, ties to even
-    return (uint16_t)(b >> 16);
+    return __builtin_bit_cast(uint16_t, (__bf16)x);  // v_cvt_pk_bf16_f32: round to nearest even
 }
 __device__ __forceinline__ float bf16_val(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 __device__ __forceinline__ void store_split(float* hi, uint16_t* lo, size_t i, double v) {
@@ -2920,7 +2918,7 @@ struct vmc_ctx {
     int block_threads = 0;  // 0 = automatic
     int64_t n_dent = 0, n_sent = 0;
     bool has_sV = true;
-    bool fock = false;  // singles elements kept per walker (see Tab::fock)
+    bool fock = true;  // singles elements kept per walker (see Tab::fock)
     uint32_t *d_row_off = nullptr, *d_dab = nullptr, *d_s_off = nullptr, *d_sa = nullptr;
     uint64_t* d_dmask = nullptr;
     double *d_dvK = nullptr, *d_sh = nullptr, *d_sV = nullptr, *d_sK = nullptr, *d_D = nullptr,
