@@ -1247,17 +1247,22 @@ __device__ __forceinline__ bool stream_pass(const Tab& T, const StepView<RT>& V,
 // Y-major by all waves of the workgroup together (segment x of tile k to wave
 // (x - X kPairBlock + k) mod nwv), so that the rows of R of the two blocks,
 // which the pairs' 2x2 minors gather, are reused from the caches across the
-// tile instead of fetched once per pair.  Per segment the lanes hold its
-// pairs' table rows, each padded to 64 positions so that a chunk lies in one
-// row; survivors queue and are evaluated 64 at a time as in stream_pass, and
-// since the queue keeps processing order each segment's survivors form one
-// run of lanes.  ELOC: E_L terms into `el`, rate sums per segment (segments
-// without survivors keep the zero written before).  PICK: segment (px, py)
-// only, running sum from `base`, pick as stream_pass.
+// tile instead of fetched once per pair.  The lanes hold the table rows of
+// four of the wave's segments at a time (pair p of segment s in lane 16 s + p,
+// then the rows with entries moved to the lowest lanes); their entries form
+// one unpadded stream, cut into 64-entry chunks whose lanes find their row by
+// walking the few rows a chunk spans with wave-uniform row data, so that the
+// table loads of several rows and segments go out together.  Survivors
+// queue and are evaluated 64 at a time as in stream_pass; the queue keeps
+// processing order, so each segment's survivors form one run of lanes.
+// ELOC: E_L terms into `el`, rate sums per segment (segments without
+// survivors keep the zero written before).  PICK: segment (px, py) only,
+// running sum from `base`, pick as stream_pass.
 template <bool PICK, bool UHF, typename RT>
 __device__ __forceinline__ bool pair_tiles(const Tab& T, const StepView<RT>& V, const uint64_t* occw, const int* oslot,
                                            uint64_t* q64, uint64_t* qab, double& el, double* segsum, int px, int py,
                                            double base, double target, bool fallback, int* pick) {
+    constexpr int kSegs = kWave / kPairBlock;  // segments held by the lanes at once
     const int l = lane_id();
     const int wv = (int)uni((uint32_t)(threadIdx.x >> 6)), nwv = blockDim.x >> 6;
     const int ne = T.ne, n_so = T.n_so, nb = pair_blocks(ne);
@@ -1320,43 +1325,102 @@ __device__ __forceinline__ bool pair_tiles(const Tab& T, const StepView<RT>& V, 
         return false;
     };
 
-    auto segment = [&](int x, int yb) __attribute__((always_inline)) {
-        const int y0 = max(x + 1, yb * kPairBlock), y1 = min(ne, (yb + 1) * kPairBlock) - 1;
-        if (y0 > y1) return;
-        const int np = y1 - y0 + 1;
-        const uint32_t sid = (uint32_t)(x * nb + yb);
-        // lane l < np: pair (x, y0 + l), its table row and its slots
-        uint32_t b0 = 0, len = 0, plen = 0, pq = 0;
-        if (l < np) {
-            const int i = V.occl[x], j = V.occl[y0 + l];
-            const int row = i * n_so + j;
-            b0 = T.row_off[row];
-            len = T.row_off[row + 1] - b0;
-            plen = (len + 63u) & ~63u;
-            pq = (uint32_t)oslot[i] | ((uint32_t)oslot[j] << 16);
+    // the wave's segments in order (wave-uniform): tiles Y-major, in tile k
+    // the local rows xl = wv - k (mod nwv), xl + nwv, ...; empty segments skipped
+    int it_yb = 0, it_xb = 0, it_k = 0, it_xl = wv % nwv;
+    bool it_done = PICK;
+    auto next_seg = [&](int& x, int& yb) __attribute__((always_inline)) -> bool {
+        while (!it_done) {
+            if (it_xl >= kPairBlock || it_xb * kPairBlock + it_xl >= ne - 1) {
+                ++it_k;
+                if (++it_xb > it_yb) {
+                    it_xb = 0;
+                    if (++it_yb >= nb) {
+                        it_done = true;
+                        break;
+                    }
+                }
+                it_xl = (wv - it_k) % nwv;
+                if (it_xl < 0) it_xl += nwv;
+                continue;
+            }
+            x = it_xb * kPairBlock + it_xl;
+            yb = it_yb;
+            it_xl += nwv;
+            if (max(x + 1, yb * kPairBlock) <= min(ne, (yb + 1) * kPairBlock) - 1) return true;
         }
-        const uint32_t end = wave_scan_u32(plen), start = end - plen;
-        const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)end, np - 1);
+        return false;
+    };
+
+    bool first = true;
+    while (!found) {
+        // the next (up to) four segments into the lanes
+        int sx[kSegs], sy[kSegs], nseg = 0;
+#pragma unroll
+        for (int k = 0; k < kSegs; ++k) {
+            sx[k] = 0;
+            sy[k] = 0;
+            if (PICK) {
+                if (k == 0 && first) { sx[0] = px; sy[0] = py; nseg = 1; }
+            } else if (nseg == k && next_seg(sx[k], sy[k])) {
+                nseg = k + 1;
+            }
+        }
+        first = false;
+        if (nseg == 0) break;
+        const int sl = l / kPairBlock, pl = l - sl * kPairBlock;
+        int x = sx[0], yb = sy[0];
+#pragma unroll
+        for (int k = 1; k < kSegs; ++k)
+            if (sl == k) { x = sx[k]; yb = sy[k]; }
+        // lane (16 s + p): the table row of pair p of segment s, its slots
+        // (10 bits each) and s
+        uint32_t b0 = 0, len = 0, pk = 0;
+        if (sl < nseg) {
+            const int y = max(x + 1, yb * kPairBlock) + pl;
+            if (y < min(ne, (yb + 1) * kPairBlock)) {
+                const int i = V.occl[x], j = V.occl[y];
+                const int row = i * n_so + j;
+                b0 = T.row_off[row];
+                len = T.row_off[row + 1] - b0;
+                pk = (uint32_t)oslot[i] | ((uint32_t)oslot[j] << 10) | ((uint32_t)sl << 20);
+            }
+        }
+        // rows with entries moved to the lowest lanes, in order (a forward
+        // permute in which every lane takes part: the empty rows go above)
+        const uint64_t nzm = __ballot(len > 0);
+        const int nrows = __popcll(nzm);
+        if (nrows == 0) continue;
+        const int dst = (len > 0) ? (int)mask_below(nzm) : nrows + (int)mask_below(~nzm);
+        b0 = (uint32_t)__builtin_amdgcn_ds_permute(dst << 2, (int)b0);
+        len = (uint32_t)__builtin_amdgcn_ds_permute(dst << 2, (int)len);
+        pk = (uint32_t)__builtin_amdgcn_ds_permute(dst << 2, (int)pk);
+        const uint32_t end = wave_scan_u32(len);
+        const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)end, nrows - 1);
         for (uint32_t c = 0; c < tot && !found; c += kUnroll * kWave) {
-            uint32_t off[kUnroll], pqs[kUnroll], abv[kUnroll];
-            bool ok[kUnroll];
+            uint32_t off[kUnroll], pkv[kUnroll], abv[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                const uint32_t cu = c + (uint32_t)(u * kWave);
-                ok[u] = false;
-                off[u] = 0;
-                pqs[u] = 0;
+                const uint32_t cu = c + (uint32_t)(u * kWave), pos = cu + (uint32_t)l;
+                off[u] = 0;  // entry 0 stands in for lanes without a candidate
+                pkv[u] = 0;
                 if (cu < tot) {
-                    // the chunk's pair: the first lane whose row ends past it
-                    const uint64_t m = __ballot(end > cu);
-                    const int gl = (int)uni((uint32_t)(__ffsll((unsigned long long)m) - 1));
-                    const uint32_t gs = (uint32_t)__builtin_amdgcn_readlane((int)start, gl);
-                    const uint32_t glen = (uint32_t)__builtin_amdgcn_readlane((int)len, gl);
-                    const uint32_t gb = (uint32_t)__builtin_amdgcn_readlane((int)b0, gl);
-                    pqs[u] = (uint32_t)__builtin_amdgcn_readlane((int)pq, gl);
-                    const uint32_t pos = cu - gs + (uint32_t)l;
-                    ok[u] = pos < glen;
-                    off[u] = ok[u] ? gb + pos : 0u;  // entry 0 stands in for lanes without a candidate
+                    // the rows this chunk spans, walked with wave-uniform row
+                    // data; bit 31 of pkv marks a lane with a candidate
+                    int k = (int)uni((uint32_t)(__ffsll((unsigned long long)__ballot(end > cu)) - 1));
+                    uint32_t sk = k > 0 ? (uint32_t)__builtin_amdgcn_readlane((int)end, k - 1) : 0u;
+                    while (true) {
+                        const uint32_t ek = (uint32_t)__builtin_amdgcn_readlane((int)end, k);
+                        const uint32_t bk = (uint32_t)__builtin_amdgcn_readlane((int)b0, k);
+                        const uint32_t qk = (uint32_t)__builtin_amdgcn_readlane((int)pk, k);
+                        if (pos >= sk && pos < ek) {
+                            off[u] = bk + (pos - sk);
+                            pkv[u] = qk | 0x80000000u;
+                        }
+                        if (ek >= cu + (uint32_t)kWave || k == nrows - 1) break;
+                        sk = ek;
+                        ++k;
+                    }
                 }
             }
 #pragma unroll
@@ -1364,13 +1428,19 @@ __device__ __forceinline__ bool pair_tiles(const Tab& T, const StepView<RT>& V, 
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
                 const uint32_t a = abv[u] & 0xFFFFu, b = abv[u] >> 16;
-                const bool surv = ok[u] && !found && !((occw[a >> 6] >> (a & 63)) & 1ull) &&
+                const bool surv = (pkv[u] >> 31) && !found && !((occw[a >> 6] >> (a & 63)) & 1ull) &&
                                   !((occw[b >> 6] >> (b & 63)) & 1ull);
                 const uint64_t m = __ballot(surv);
                 if (surv) {
                     const uint32_t sq = (qh + qn + mask_below(m)) & (kQueue - 1);
-                    q64[sq] = (uint64_t)off[u] | ((uint64_t)sid << 32);
-                    qab[sq] = (uint64_t)abv[u] | ((uint64_t)pqs[u] << 32);
+                    const int sg = (int)((pkv[u] >> 20) & 3u);
+                    int gx = sx[0], gy = sy[0];
+#pragma unroll
+                    for (int k2 = 1; k2 < kSegs; ++k2)
+                        if (sg == k2) { gx = sx[k2]; gy = sy[k2]; }
+                    const uint32_t rpq = (pkv[u] & 0x3FFu) | (((pkv[u] >> 10) & 0x3FFu) << 16);
+                    q64[sq] = (uint64_t)off[u] | ((uint64_t)(uint32_t)(gx * nb + gy) << 32);
+                    qab[sq] = (uint64_t)abv[u] | ((uint64_t)rpq << 32);
                 }
                 qn += (uint32_t)__popcll(m);
                 if (qn >= (uint32_t)kWave) {
@@ -1381,22 +1451,7 @@ __device__ __forceinline__ bool pair_tiles(const Tab& T, const StepView<RT>& V, 
                 }
             }
         }
-    };
-
-    if (PICK) {
-        segment(px, py);
-    } else {
-        int k = 0;
-        for (int yb = 0; yb < nb; ++yb)
-            for (int xb = 0; xb <= yb; ++xb, ++k) {
-                int xl = (wv - k) % nwv;
-                if (xl < 0) xl += nwv;
-                for (; xl < kPairBlock; xl += nwv) {
-                    const int x = xb * kPairBlock + xl;
-                    if (x >= ne - 1) break;
-                    segment(x, yb);
-                }
-            }
+        if (PICK) break;
     }
     if (!found && qn > 0) found = batch((int)qn);
     if (!PICK && cur_s >= 0 && l == 0) segsum[cur_s] = cur_sum;
