@@ -75,7 +75,11 @@ enum {
     VMC_ST_SINGULAR = 1u,   /* theta[N] singular at (re)inversion: psi(N) = 0 */
     VMC_ST_EMPTY = 2u,      /* no connected determinant with a positive rate: no move */
     VMC_ST_NONFINITE = 4u,  /* E_L or T not finite */
-    VMC_ST_SMALLDEN = 8u,   /* a Sherman-Morrison denominator below 1e-8 in magnitude */
+    VMC_ST_SMALLDEN = 8u,   /* a Sherman-Morrison denominator below the threshold of
+                               vmc_set_small_denominator (1e-8) in magnitude; where the sweep
+                               re-inverts in place (state in LDS, or general orbitals with more than
+                               192 electrons) the walker is re-inverted right after that move, else at
+                               its next re-inversion */
     VMC_ST_STALE = 16u      /* walkers re-inverted by the separate refresh kernel (state in HBM): B and R
                                carry updates made since their last inversion; set by a sweep that moved
                                the walker, cleared by every (re-)inversion.  Not an error. */
@@ -361,6 +365,19 @@ vmc_status vmc_uniforms(uint64_t seed, int64_t n, uint64_t step, double* out_dev
 /* Decode a packed pick: type (0 = no move, 1 single, 2 double), i, j, a, b. */
 void vmc_decode_pick(int64_t code, int32_t out5[5]);
 
+/*
+ * Threshold below which the magnitude of a Sherman-Morrison denominator (the
+ * ratio psi(M)/psi(N) of the determinants, or the 2x2 determinant of the
+ * Woodbury update of a double; the Sherman-Morrison paragraph of section
+ * "Local energy and Gradient ratios") marks the walker VMC_ST_SMALLDEN and,
+ * where the sweep re-inverts in place, makes it re-invert theta[N] from
+ * scratch right after that move: a small denominator amplifies the rounding
+ * that the update carries into B and R.  Default 1e-8; 0 never flags, +inf
+ * flags (and re-inverts after) every move.  Host-only; affects subsequent
+ * calls on h.  VMC_E_ARG for a negative or NaN threshold.
+ */
+vmc_status vmc_set_small_denominator(vmc_handle h, double threshold);
+
 /* Launch shape of the sweep kernels: threads per walker workgroup (a multiple
  * of 64 in 64..512), or 0 for the library's choice.  Host-only; affects
  * subsequent calls on h.  Results do not depend on it except for the order of
@@ -373,12 +390,22 @@ vmc_status vmc_set_launch(vmc_handle h, int32_t block_threads);
 vmc_status vmc_table_info(vmc_handle h, int64_t out[3]);
 
 /* Launch geometry of the sweep kernel for this system and the current
- * vmc_set_launch setting: out[0] = threads per walker (workgroup size),
- * out[1] = 1 when the walker state (R, B, descriptors) is held in LDS for the
- * whole sweep, 0 when it stays in the caller's HBM buffers, out[2] = LDS bytes
- * per workgroup, out[3] = 1 when re-inversion runs in the separate refresh
- * kernel (HBM-resident walkers whose B fits 160 KB of LDS). */
-vmc_status vmc_launch_info(vmc_handle h, int64_t out[4]);
+ * vmc_set_launch / vmc_set_occupancy settings: out[0] = threads per walker
+ * (workgroup size), out[1] = 1 when the walker state (R, B, descriptors) is
+ * held in LDS for the whole sweep, 0 when it stays in the caller's HBM
+ * buffers, out[2] = LDS bytes per workgroup, out[3] = 1 when re-inversion runs
+ * in the separate refresh kernel (HBM-resident walkers whose B fits 160 KB of
+ * LDS), out[4] = occupancy target of the sweep kernel in waves per SIMD (3 or
+ * 4; 0 when the state is held in LDS, whose variants fix their own). */
+vmc_status vmc_launch_info(vmc_handle h, int64_t out[5]);
+
+/* Occupancy target of the sweep kernel when the walker state stays in HBM:
+ * 3 or 4 waves per SIMD (which fixes the kernel's register budget: 168 or 128
+ * VGPRs), or 0 for the library's choice (4 when the table holds doubles, else
+ * 3).  Host-only; affects subsequent calls.  Results do not depend on it (the
+ * same arithmetic in the same order).  VMC_E_ARG for other values.
+ * vmc_batch_set_occupancy: the same for a batch's launch. */
+vmc_status vmc_set_occupancy(vmc_handle h, int32_t waves);
 
 vmc_status vmc_destroy(vmc_handle h);
 
@@ -402,6 +429,7 @@ vmc_status vmc_destroy(vmc_handle h);
 typedef struct vmc_batch_ctx* vmc_batch;
 vmc_status vmc_batch_create(const vmc_handle* systems, int32_t n, vmc_batch* out);
 vmc_status vmc_batch_set_launch(vmc_batch b, int32_t block_threads);
+vmc_status vmc_batch_set_occupancy(vmc_batch b, int32_t waves);
 vmc_status vmc_batch_local_energy(vmc_batch b, vmc_walkers* const* walkers, hipStream_t stream);
 vmc_status vmc_batch_ctmc_step(vmc_batch b, vmc_walkers* const* walkers, int32_t n_steps, hipStream_t stream);
 vmc_status vmc_batch_destroy(vmc_batch b);
@@ -409,10 +437,13 @@ vmc_status vmc_batch_destroy(vmc_batch b);
 /*
  * Launch-shape autotuner: times CTMC sweeps of n_moves moves at each
  * workgroup size in {64, 128, 256, 512} threads per walker that fits the LDS
- * budget (best of two sweeps each, HIP events on `stream`), keeps the fastest
- * (as vmc_set_launch / vmc_batch_set_launch would) and returns it in *chosen
- * (nullable).  The timed sweeps are real moves: every walker set advances by
- * 8 * n_moves moves (use it as burn-in).  Blocks until the timing is done.
+ * budget and, where the walker state stays in HBM (always in a batch), each
+ * occupancy target (3 and 4 waves per SIMD) (best of two sweeps each, HIP
+ * events on `stream`), keeps the fastest shape (as vmc_set_launch /
+ * vmc_set_occupancy or their batch forms would) and returns its workgroup
+ * size in *chosen (nullable; vmc_launch_info reports the occupancy).  The
+ * timed sweeps are real moves: every walker set advances by 2 * n_moves moves
+ * per shape tried (use it as burn-in).  Blocks until the timing is done.
  */
 vmc_status vmc_autotune(vmc_handle h, vmc_walkers* w, int32_t n_moves, int32_t* chosen, hipStream_t stream);
 vmc_status vmc_batch_autotune(vmc_batch b, vmc_walkers* const* walkers, int32_t n_moves, int32_t* chosen,

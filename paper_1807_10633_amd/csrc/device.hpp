@@ -21,6 +21,8 @@ struct Tab {
     int has_sV;               // some singles entry has a nonzero Coulomb-exchange vector
     int fock;                 // keep the walker's singles elements in its scratch (state in HBM, has_sV)
     double eps;
+    double small_den;         // Sherman-Morrison denominators below this in magnitude flag the walker (and
+                              // re-invert it after the move where the sweep re-inverts in place)
     const uint32_t* row_off;  // n_so*n_so + 1
     const uint32_t* dab;      // a | b << 16
     const uint64_t* dmask;    // (1 << a) | (1 << b) per doubles entry when n_so <= 64, else null

@@ -294,7 +294,7 @@ __host__ __device__ inline size_t scratch_layout_bytes(int ne, int64_t n_fock) {
 }
 
 // misc int slots
-enum { MI_ST = 0, MI_PIV, MI_PTYPE, MI_PP, MI_PQ, MI_PA, MI_PB, MI_FS, MI_FW, MI_FK, MI_FFB, MI_WAVE = 32 };
+enum { MI_ST = 0, MI_PIV, MI_PTYPE, MI_PP, MI_PQ, MI_PA, MI_PB, MI_FS, MI_FW, MI_FK, MI_FFB, MI_SDNOW, MI_WAVE = 32 };
 enum { MD_T = 0, MD_BASE, MD_EL, MD_HNN, MD_TARGET, MD_C00, MD_C01, MD_C10, MD_C11 };
 // per-wave state: entries of the two batch logs and the stream ranges
 enum { WS_NS = 0, WS_R1S = 3, WS_ND = 4, WS_R1D = 7 };
@@ -1850,6 +1850,7 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
             md[MD_T] = Tt;
             mi[MI_PTYPE] = 0;
             mi[MI_FS] = -1;
+            mi[MI_SDNOW] = 0;
             const bool okT0 = !singular && Tt > 0.0 && isfinite(Tt) && isfinite(el);
             if (!singular && !(isfinite(Tt) && isfinite(el))) mi[MI_ST] |= (int)VMC_ST_NONFINITE;
             else if (!singular && !(Tt > 0.0)) mi[MI_ST] |= (int)VMC_ST_EMPTY;
@@ -2047,7 +2048,10 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
             dh = block_total(dh, red);  // its barriers also publish the rows and copies above
             if (ptype == 1) {
                 const double rho = w1[p];
-                if (tid == 0 && fabs(rho) < 1e-8) mi[MI_ST] |= (int)VMC_ST_SMALLDEN;
+                if (tid == 0 && fabs(rho) < T.small_den) {
+                    mi[MI_ST] |= (int)VMC_ST_SMALLDEN;
+                    mi[MI_SDNOW] = 1;
+                }
                 __syncthreads();
                 for (int x = tid; x < ne; x += nt) w1[x] = (w1[x] - (x == p ? 1.0 : 0.0)) / rho;
                 __syncthreads();
@@ -2066,7 +2070,10 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
             } else {
                 const double c00 = w1[p], c01 = w1[q], c10 = w2[p], c11 = w2[q];
                 const double det = c00 * c11 - c10 * c01;
-                if (tid == 0 && fabs(det) < 1e-8) mi[MI_ST] |= (int)VMC_ST_SMALLDEN;
+                if (tid == 0 && fabs(det) < T.small_den) {
+                    mi[MI_ST] |= (int)VMC_ST_SMALLDEN;
+                    mi[MI_SDNOW] = 1;
+                }
                 __syncthreads();
                 for (int x = tid; x < ne; x += nt) {
                     const double ra = w1[x] - (x == p ? 1.0 : 0.0);
@@ -2148,7 +2155,9 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
             if (pick_hist) pick_hist[(size_t)k * W + w] = code_last;
         }
         // ------------------------------------------------------- refresh
-        if (refresh_period > 0 && !UHF && ((gstep + 1) % (uint64_t)refresh_period) == 0) {
+        // periodic, or right after a move whose Sherman-Morrison denominator
+        // was small (the update then amplified the rounding of B and R)
+        if (refresh_period > 0 && !UHF && (((gstep + 1) % (uint64_t)refresh_period) == 0 || mi[MI_SDNOW])) {
             refresh_state<RT, SPLIT>(T, slot, B, R, s, fcol, ipiv, mi, red, th, ths, Rlo);
             hnn_full();
         }
@@ -2228,8 +2237,8 @@ struct BatchArgs {
     int n;
 };
 
-template <typename RT>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+template <typename RT, int HW>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(HW)))
 k_sweep_batch(BatchArgs A, int mode, int n_steps) {
     const int64_t b = blockIdx.x;
     int e = 0;
@@ -2241,62 +2250,8 @@ k_sweep_batch(BatchArgs A, int mode, int n_steps) {
                                           E.ph);
 }
 
-// LDS bytes of the refresh kernel: B (Ne x Ne FP64) and its work arrays.
-__host__ __device__ inline size_t refresh_lds_bytes(int ne, int nt) {
-    const int nwv = nt / 64;
-    return al16((size_t)ne * ne * 8) + al16((size_t)ne * 8) + al16((size_t)(nwv + 2) * 8) + al16((size_t)ne * 4) * 2 +
-           al16((size_t)(32 + nwv) * 4);
-}
-
-// Periodic (and initial) re-inversion for walkers whose state lives in HBM,
-// for Ne above 128: the same Gauss-Jordan elimination with partial pivoting
-// as the sweep kernel's in-LDS refresh, with B held in LDS (up to 160 KB per
-// workgroup), then R = theta B on the matrix cores, s and H_NN.
+// Threads of the re-inversion kernel's workgroup (one walker each).
 constexpr int kRefreshThreads = 512;
-template <typename RT>
-__global__ void __launch_bounds__(kRefreshThreads) k_refresh(Tab T, Wk S, int64_t W, int lazy) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int64_t w = blockIdx.x;
-    if (w >= W) return;
-    // lazy: walkers that have not moved since their last inversion are skipped
-    if (lazy && !(S.status[w] & VMC_ST_STALE)) return;
-    const int tid = threadIdx.x, nt = blockDim.x, nwv = nt >> 6;
-    const int ne = T.ne, n_so = T.n_so;
-    size_t o = 0;
-    double* B = (double*)(smem + o);
-    o += al16((size_t)ne * ne * 8);
-    double* fcol = (double*)(smem + o);
-    o += al16((size_t)ne * 8);
-    double* red = (double*)(smem + o);
-    o += al16((size_t)(nwv + 2) * 8);
-    int* slot = (int*)(smem + o);
-    o += al16((size_t)ne * 4);
-    int* ipiv = (int*)(smem + o);
-    o += al16((size_t)ne * 4);
-    int* mi = (int*)(smem + o);
-    for (int k = tid; k < ne; k += nt) slot[k] = S.slot_orb[(size_t)w * ne + k];
-    if (tid == 0) mi[MI_ST] = (int)S.status[w];
-    __syncthreads();
-    RT* R = (RT*)S.R + (size_t)w * n_so * ne;
-    constexpr bool SPLIT = sizeof(RT) < sizeof(double);
-    uint16_t* Rlo = SPLIT ? S.Rlo + (size_t)w * n_so * ne : nullptr;
-    double* s = S.s + (size_t)w * n_so;
-    double* Bg = S.B + (size_t)w * ne * ne;
-    refresh_state<RT, SPLIT>(T, slot, B, R, s, fcol, ipiv, mi, red, T.theta, n_so, Rlo);
-    for (int k = tid; k < ne * ne; k += nt) Bg[k] = B[k];
-    double hp = 0.0;
-    for (int x = tid; x < ne; x += nt) {
-        const int i = slot[x];
-        const double* Di = T.D + (size_t)i * n_so;
-        hp += T.hdiag[i];
-        for (int y = x + 1; y < ne; ++y) hp += Di[slot[y]];
-    }
-    const double hnn = block_total(hp, red);
-    if (tid == 0) {
-        S.hnn[w] = hnn;
-        S.status[w] = (uint32_t)mi[MI_ST] & ~(uint32_t)VMC_ST_STALE;
-    }
-}
 
 // Re-inversion with the matrix held in registers: Gauss-Jordan elimination
 // with partial pivoting in exchange form (pivot rows are marked used, never
@@ -2312,10 +2267,12 @@ __global__ void __launch_bounds__(kRefreshThreads) k_refresh(Tab T, Wk S, int64_
 // row (v - (pv + 1) v / pv = -v / pv) with no per-lane case; G is scaled by a
 // power of two to max |G| in [1/2, 1) so that the pivots, and the rounding of
 // that form, stay of order one.
+template <int RB>
 __device__ __forceinline__ uint64_t pivot_key(double v, int r) {
+    constexpr uint64_t m = (1ull << RB) - 1;
     const double a = fabs(v);
     const uint64_t bits = (a >= 0.0) ? (uint64_t)__double_as_longlong(a) : 0x7FF0000000000000ull;
-    return (bits & ~127ull) | (uint64_t)(127 - r);
+    return (bits & ~m) | (uint64_t)((int)m - r);
 }
 
 __device__ __forceinline__ double readlane_d(double x, int lane) {
@@ -2327,7 +2284,8 @@ __device__ __forceinline__ double readlane_d(double x, int lane) {
 // LDS of the register Gauss-Jordan kernel: the inverse of an nm x nm matrix
 // (theta[N], or the larger spin block) and slot lists of all Ne electrons.
 __host__ __device__ inline size_t refresh_gj_lds_bytes(int nm, int ne) {
-    const size_t mat = (size_t)nm * nm * 8, bufs = (2 * 128 + 4 + 2) * 8;
+    const int cb = nm <= 128 ? 128 : 192;
+    const size_t mat = nm <= 128 ? (size_t)nm * nm * 8 : 0, bufs = (size_t)(2 * cb + 4 + 2) * 8;
     return al16(mat > bufs ? mat : bufs) + 3 * al16((size_t)ne * 4) + al16((size_t)(kRefreshThreads / 64 + 2) * 8) +
            16;
 }
@@ -2339,12 +2297,13 @@ __host__ __device__ inline size_t refresh_gj_lds_bytes(int nm, int ne) {
 // s and H_NN.  (Both spins in one launch of 2W workgroups measured slower.)
 // General orbitals: one launch, spin unused.
 template <typename RT, int H, int JC, bool UHF>
-__global__ void __launch_bounds__(kRefreshThreads) __attribute__((amdgpu_waves_per_eu(4))) k_refresh_gj(Tab T, Wk S,
-                                                                                                      int64_t W,
-                                                                                                      int spin,
-                                                                                                      int lazy) {
+__global__ void __launch_bounds__(kRefreshThreads) __attribute__((amdgpu_waves_per_eu(H == 3 ? 2 : 4)))
+k_refresh_gj(Tab T, Wk S, int64_t W, int spin, int lazy) {
     constexpr int NW = kRefreshThreads / 64;
-    static_assert(H * 64 <= 128 && NW * JC <= 128, "at most 128 rows and columns");
+    constexpr int CB = 64 * H;              // rows held by the lanes (one pivot-column buffer)
+    constexpr int RB = H == 3 ? 8 : 7;      // bits of the row index in the pivot key
+    static_assert(H * 64 <= 192 && NW * JC <= 192, "at most 192 rows and columns");
+    static_assert(H < 3 || !UHF, "spin blocks of at most 128 electrons");
     extern __shared__ __align__(16) unsigned char smem[];
     const int64_t w = blockIdx.x;
     if (w >= W) return;
@@ -2357,11 +2316,13 @@ __global__ void __launch_bounds__(kRefreshThreads) __attribute__((amdgpu_waves_p
     const int tid = threadIdx.x, ne = UHF ? (spin ? ne_all - T.na : T.na) : ne_all, n_so = T.n_so, l = lane_id();
     const int wv = (int)uni((uint32_t)(tid >> 6));
     const int nm = UHF ? max(T.na, ne_all - T.na) : ne_all;  // the largest matrix of this system
-    const size_t mat = (size_t)nm * nm * 8, bufs = (2 * 128 + 4 + 2) * 8;
+    // B is staged in LDS for up to 128 rows; above that it goes straight to
+    // the walker's buffer (160 x 160 FP64 would not fit)
+    const size_t mat = (H == 3) ? 0 : (size_t)nm * nm * 8, bufs = (2 * CB + 4 + 2) * 8;
     size_t o = 0;
     double* Bs = (double*)smem;     // B (slot layout) once the elimination is done
     double* col = Bs;               // during it: the pivot column, two buffers
-    double* pvb = Bs + 2 * 128;     // pivot and its reciprocal, two buffers
+    double* pvb = Bs + 2 * CB;      // pivot and its reciprocal, two buffers
     int* pivb = (int*)(pvb + 4);    // pivot row, two buffers
     o += al16(mat > bufs ? mat : bufs);
     int* slot = (int*)(smem + o);
@@ -2401,7 +2362,9 @@ __global__ void __launch_bounds__(kRefreshThreads) __attribute__((amdgpu_waves_p
     for (int h = 0; h < H; ++h)
 #pragma unroll
         for (int j = 0; j < JC; ++j) g[h][j] *= scale;
-    uint64_t used0 = 0, used1 = 0;  // identical in every wave
+    uint64_t used[H];  // rows already pivots, identical in every wave
+#pragma unroll
+    for (int h = 0; h < H; ++h) used[h] = 0;
     bool singular = false;
     int owned = 0;
     for (int k = 0; k < ne; ++k) {
@@ -2409,18 +2372,22 @@ __global__ void __launch_bounds__(kRefreshThreads) __attribute__((amdgpu_waves_p
         if (wv == ow) {
             // pivot: the largest |G[r][k]| over unused rows as a u64 key (the
             // bits of |G[r][k]|, whose order is that of the values, with the
-            // low 7 mantissa bits replaced by 127 - r: values within 2^-45 of
-            // each other tie and the lowest r wins; a NaN counts as the largest,
-            // so a poisoned matrix still pivots on an unused row)
+            // low RB mantissa bits replaced by 2^RB - 1 - r: values within
+            // 2^(RB-52) of each other tie and the lowest r wins; a NaN counts
+            // as the largest, so a poisoned matrix still pivots on an unused row)
             uint64_t key = 0;
-            if (l < ne && !((used0 >> l) & 1)) key = pivot_key(g[0][0], l);
-            if (H > 1 && l + 64 < ne && !((used1 >> l) & 1)) key = umax64(key, pivot_key(g[H - 1][0], l + 64));
-            const int p = 127 - (int)(wave_max_u64(key) & 127u);
-            const double pv = (H > 1 && p >= 64) ? readlane_d(g[H - 1][0], p - 64) : readlane_d(g[0][0], p);
+#pragma unroll
+            for (int h = 0; h < H; ++h)
+                if (l + 64 * h < ne && !((used[h] >> l) & 1)) key = umax64(key, pivot_key<RB>(g[h][0], l + 64 * h));
+            const int p = (int)((1u << RB) - 1) - (int)(wave_max_u64(key) & ((1u << RB) - 1));
+            double pv = 0.0;
+#pragma unroll
+            for (int h = 0; h < H; ++h)
+                if ((p >> 6) == h) pv = readlane_d(g[h][0], p & 63);
             const double ipv = (pv != 0.0) ? 1.0 / pv : 0.0;
-            double* cw = col + b * 128;
-            cw[l] = (l == p) ? pv + 1.0 : g[0][0];
-            if (H > 1) cw[l + 64] = (l + 64 == p) ? pv + 1.0 : g[H - 1][0];
+            double* cw = col + b * CB;
+#pragma unroll
+            for (int h = 0; h < H; ++h) cw[l + 64 * h] = (l + 64 * h == p) ? pv + 1.0 : g[h][0];
             if (l == 0) {
                 pvb[2 * b] = pv;
                 pvb[2 * b + 1] = ipv;
@@ -2432,23 +2399,23 @@ __global__ void __launch_bounds__(kRefreshThreads) __attribute__((amdgpu_waves_p
         __syncthreads();
         const int piv = (int)uni((uint32_t)pivb[b]);
         const double pv = pvb[2 * b], ipv = pvb[2 * b + 1];
-        if (piv < 64) used0 |= 1ull << piv;
-        else used1 |= 1ull << (piv - 64);
+#pragma unroll
+        for (int h = 0; h < H; ++h)
+            if ((piv >> 6) == h) used[h] |= 1ull << (piv & 63);
         singular |= !(fabs(pv) > 0.0) || !(fabs(pv) <= DBL_MAX);
         // every row: G[r][c] -= (G[r][k] / pv) G[p][c]; the pivot row reads
         // pv + 1 for G[p][k] and so becomes -G[p][c] / pv
         double t[H];
 #pragma unroll
-        for (int h = 0; h < H; ++h) t[h] = col[b * 128 + l + 64 * h] * ipv;
+        for (int h = 0; h < H; ++h) t[h] = col[b * CB + l + 64 * h] * ipv;
         double v[JC];
         const int pl = piv & 63;
-        if (H > 1 && piv >= 64) {
 #pragma unroll
-            for (int j = 0; j < JC; ++j) v[j] = readlane_d(g[H - 1][j], pl);
-        } else {
+        for (int h = 0; h < H; ++h)
+            if ((piv >> 6) == h) {
 #pragma unroll
-            for (int j = 0; j < JC; ++j) v[j] = readlane_d(g[0][j], pl);
-        }
+                for (int j = 0; j < JC; ++j) v[j] = readlane_d(g[h][j], pl);
+            }
 #pragma unroll
         for (int h = 0; h < H; ++h)
 #pragma unroll
@@ -2469,6 +2436,8 @@ __global__ void __launch_bounds__(kRefreshThreads) __attribute__((amdgpu_waves_p
     // B[p][x] = A^-1[x][p] = G^-1[p][x]: lane (r), register j (column c) holds
     // G^-1[q_r][p_c]; the registers have been rotated by the number of
     // columns this wave owned
+    double* Bg = S.B + (size_t)w * ne_all * ne_all;
+    double* Bo = (H == 3) ? Bg : Bs;  // general orbitals only when H == 3 (ne == ne_all)
 #pragma unroll
     for (int j = 0; j < JC; ++j) {
         const int c = wv + NW * ((j + owned) % JC);
@@ -2477,18 +2446,18 @@ __global__ void __launch_bounds__(kRefreshThreads) __attribute__((amdgpu_waves_p
 #pragma unroll
             for (int h = 0; h < H; ++h) {
                 const int r = l + 64 * h;
-                if (r < ne) Bs[(size_t)qr[r] * ne + pc] = g[h][j] * scale;
+                if (r < ne) Bo[(size_t)qr[r] * ne + pc] = g[h][j] * scale;
             }
         }
     }
     __syncthreads();
-    double* Bg = S.B + (size_t)w * ne_all * ne_all;
     RT* R = (RT*)S.R + (size_t)w * T.rrow * ne_all;
     constexpr bool SPLIT = sizeof(RT) < sizeof(double);
     uint16_t* Rlo = SPLIT ? S.Rlo + (size_t)w * T.rrow * ne_all : nullptr;
     if (!UHF) {
-        for (int k = tid; k < ne * ne; k += kRefreshThreads) Bg[k] = Bs[k];
-        r_gemm_theta_regs<RT, 16 * H, SPLIT>(T, Bs, R, T.theta, n_so, Rlo);
+        if (H < 3)
+            for (int k = tid; k < ne * ne; k += kRefreshThreads) Bg[k] = Bs[k];
+        r_gemm_theta_regs<RT, 16 * H, SPLIT>(T, Bo, R, T.theta, n_so, Rlo);
     } else {
         // this spin's rows of B, zero outside the block
         for (int k = tid; k < ne * ne_all; k += kRefreshThreads) {
@@ -2974,6 +2943,8 @@ struct vmc_ctx {
     int64_t n_dent = 0, n_sent = 0;
     bool has_sV = true;
     bool fock = true;  // singles elements kept per walker (see Tab::fock)
+    double small_den = 1e-8;  // see Tab::small_den
+    int waves = 0;            // occupancy target of the HBM-layout sweep: 3, 4 waves per SIMD, or 0 (library's choice)
     uint32_t *d_row_off = nullptr, *d_dab = nullptr, *d_s_off = nullptr, *d_sa = nullptr;
     uint64_t* d_dmask = nullptr;
     double *d_dvK = nullptr, *d_sh = nullptr, *d_sV = nullptr, *d_sK = nullptr, *d_D = nullptr,
@@ -2997,6 +2968,7 @@ struct vmc_batch_ctx {
     std::vector<vmc_ctx*> sys;
     int nt = 256;
     int precision = 0;
+    int waves = 0;  // occupancy target of the sweep kernel (waves per SIMD): 3, 4, or 0 for the library's choice
 };
 
 namespace {
@@ -3036,6 +3008,7 @@ Tab make_tab(const vmc_ctx* h) {
     T.has_doubles = h->n_dent > 0 ? 1 : 0;
     T.has_sV = h->has_sV ? 1 : 0;
     T.fock = (h->has_sV && h->fock) ? 1 : 0;
+    T.small_den = h->small_den;
     T.sK = h->d_sK;
     T.D = h->d_D;
     T.hdiag = h->d_hdiag;
@@ -3116,7 +3089,18 @@ void launch_one(dim3 grid, dim3 block, size_t lds, hipStream_t st, const Tab& T,
 }
 
 // Waves per SIMD of the HBM variant for this system: 4 with doubles, else 3.
-int hbm_waves(const vmc_ctx* h) { return h->n_dent > 0 ? 4 : 3; }
+// Occupancy target of the HBM-layout sweep (waves per SIMD, which fixes its
+// register budget): the caller's or autotuner's choice, else 4 with doubles
+// (the candidate gathers wait on the caches: more waves hide them, a few
+// spills included) and 3 without (the Hubbard update stream keeps its
+// registers).
+int hbm_waves(const vmc_ctx* h) { return h->waves ? h->waves : (h->n_dent > 0 ? 4 : 3); }
+int batch_waves(const vmc_batch_ctx* b) {
+    if (b->waves) return b->waves;
+    for (const vmc_ctx* h : b->sys)
+        if (h->n_dent > 0) return 4;
+    return 3;
+}
 
 template <bool NW1, bool UHF, typename RT>
 void launch_hbm(dim3 grid, dim3 block, size_t lds, hipStream_t st, const Tab& T, const Wk& S, const vmc_walkers* w,
@@ -3161,17 +3145,20 @@ SweepGeom sweep_geom(const vmc_ctx* h) {
     return g;
 }
 
-// Walkers whose state lives in HBM are re-inverted by the separate refresh
-// kernel when B fits its LDS budget.
+// Walkers whose state lives in HBM are re-inverted by the separate register
+// Gauss-Jordan kernel up to 192 electrons (128 per spin block); above that in
+// place in the sweep.
 constexpr size_t kMaxRefreshLds = 160 * 1024;
+// Register Gauss-Jordan shape: 1 (Ne <= 64), 2 (Ne <= 128) or, for general
+// orbitals, 3 (Ne <= 192) rows per lane; 0 where Ne is larger (re-inversion
+// in place in the sweep, or B in LDS).
+int refresh_gj_rows(int ne, bool uhf) { return ne <= 64 ? 1 : ne <= 128 ? 2 : (ne <= 192 && !uhf) ? 3 : 0; }
+
 bool use_refresh_kernel(const vmc_ctx* h) {
     if (h->uhf) return true;  // always the register kernel, one spin block at a time
-    return !sweep_geom(h).small && refresh_lds_bytes(h->ne, kRefreshThreads) <= kMaxRefreshLds;
+    return !sweep_geom(h).small && refresh_gj_rows(h->ne, false) != 0;
 }
 
-// Register Gauss-Jordan shape: 1 (Ne <= 64) or 2 (Ne <= 128) rows per lane,
-// 0 where Ne is larger (B in LDS instead).
-int refresh_gj_rows(int ne) { return ne <= 64 ? 1 : ne <= 128 ? 2 : 0; }
 
 // Size of the matrices the register Gauss-Jordan kernel inverts: theta[N], or
 // with spin-blocked orbitals the larger of its two spin blocks.
@@ -3184,37 +3171,27 @@ const void* refresh_gj_kernel(int rows, bool mixed, bool uhf) {
         if (mixed) return uhf ? (const void*)k_refresh_gj<float, 1, 8, true> : (const void*)k_refresh_gj<float, 1, 8, false>;
         return uhf ? (const void*)k_refresh_gj<double, 1, 8, true> : (const void*)k_refresh_gj<double, 1, 8, false>;
     }
+    if (rows == 3) return mixed ? (const void*)k_refresh_gj<float, 3, 24, false> : (const void*)k_refresh_gj<double, 3, 24, false>;
     if (mixed) return uhf ? (const void*)k_refresh_gj<float, 2, 16, true> : (const void*)k_refresh_gj<float, 2, 16, false>;
     return uhf ? (const void*)k_refresh_gj<double, 2, 16, true> : (const void*)k_refresh_gj<double, 2, 16, false>;
 }
 
 vmc_status launch_refresh(vmc_ctx* h, vmc_walkers* w, hipStream_t st, bool lazy = false) {
-    const size_t lds = refresh_lds_bytes(h->ne, kRefreshThreads);
-    const Tab T = make_tab(h);
-    const Wk S = make_wk(h, w);
+    const int rows = refresh_gj_rows(gj_size(h), h->uhf);
+    if (rows == 0) return fail(h, VMC_E_UNSUPPORTED, "no separate re-inversion kernel for this size");
+    Tab Ta = make_tab(h);
+    Wk Sa = make_wk(h, w);
     const dim3 grid((unsigned)w->n_walkers), block(kRefreshThreads);
-    const int rows = refresh_gj_rows(gj_size(h));
-    if (rows != 0) {
-        const bool mixed = h->precision == VMC_MIXED;
-        const size_t b = refresh_gj_lds_bytes(gj_size(h), h->ne);
-        Tab Ta = T;
-        Wk Sa = S;
-        int64_t Wa = w->n_walkers;
-        // spin-blocked: the alpha block, then the beta block (stream order)
-        int lz = lazy ? 1 : 0;
-        for (int spin = 0; spin < (h->uhf ? 2 : 1); ++spin) {
-            int sp = spin;
-            void* args[] = {&Ta, &Sa, &Wa, &sp, &lz};
-            HIP_OR_FAIL(h, hipLaunchKernel(refresh_gj_kernel(rows, mixed, h->uhf), grid, block, args, b, st));
-        }
-        return VMC_OK;
+    const bool mixed = h->precision == VMC_MIXED;
+    const size_t b = refresh_gj_lds_bytes(gj_size(h), h->ne);
+    int64_t Wa = w->n_walkers;
+    // spin-blocked: the alpha block, then the beta block (stream order)
+    int lz = lazy ? 1 : 0;
+    for (int spin = 0; spin < (h->uhf ? 2 : 1); ++spin) {
+        int sp = spin;
+        void* args[] = {&Ta, &Sa, &Wa, &sp, &lz};
+        HIP_OR_FAIL(h, hipLaunchKernel(refresh_gj_kernel(rows, mixed, h->uhf), grid, block, args, b, st));
     }
-    if (h->precision == VMC_MIXED) {
-        hipLaunchKernelGGL((k_refresh<float>), grid, block, lds, st, T, S, w->n_walkers, lazy ? 1 : 0);
-    } else {
-        hipLaunchKernelGGL((k_refresh<double>), grid, block, lds, st, T, S, w->n_walkers, lazy ? 1 : 0);
-    }
-    HIP_OR_FAIL(h, hipGetLastError());
     return VMC_OK;
 }
 
@@ -3372,7 +3349,7 @@ vmc_status vmc_init(const vmc_system_desc* desc, const double* h1, const vmc_eri
     if (desc->orbitals == VMC_UHF) {
         // the spin-blocked layout keeps one spin per slot: every kept
         // excitation must move each electron within its own spin
-        if (refresh_gj_rows(std::max(desc->n_alpha, desc->n_beta)) == 0)
+        if (refresh_gj_rows(std::max(desc->n_alpha, desc->n_beta), true) == 0)
             return fail(nullptr, VMC_E_UNSUPPORTED, "VMC_UHF supports at most 128 electrons of each spin");
         const int n = desc->n_orb, n_so = 2 * n;
         auto beta = [n](int o) { return o >= n; };
@@ -3472,7 +3449,8 @@ vmc_status vmc_init(const vmc_system_desc* desc, const double* h1, const vmc_eri
                              (const void*)k_sweep<0, 0, 0, true, false, double, true, 4>,
                              (const void*)k_sweep<0, 0, 0, false, false, float, true, 4>,
                              (const void*)k_sweep<0, 0, 0, true, false, float, true, 4>,
-                             (const void*)k_sweep_batch<double>, (const void*)k_sweep_batch<float>};
+                             (const void*)k_sweep_batch<double, 4>, (const void*)k_sweep_batch<float, 4>,
+                             (const void*)k_sweep_batch<double, 3>, (const void*)k_sweep_batch<float, 3>};
         for (const void* f : big) {
             const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLdsHbm);
             if (e != hipSuccess) {
@@ -3484,13 +3462,9 @@ vmc_status vmc_init(const vmc_system_desc* desc, const double* h1, const vmc_eri
     {
         hipError_t e = hipSuccess;
         const bool mixed = h->precision == VMC_MIXED;
-        if (refresh_lds_bytes(h->ne, kRefreshThreads) <= kMaxRefreshLds)
-            e = hipFuncSetAttribute(mixed ? (const void*)k_refresh<float> : (const void*)k_refresh<double>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)refresh_lds_bytes(h->ne, kRefreshThreads));
         const size_t gj = refresh_gj_lds_bytes(gj_size(h), h->ne);
-        if (e == hipSuccess && refresh_gj_rows(gj_size(h)) != 0 && gj <= kMaxRefreshLds)
-            e = hipFuncSetAttribute(refresh_gj_kernel(refresh_gj_rows(gj_size(h)), mixed, h->uhf),
+        if (e == hipSuccess && refresh_gj_rows(gj_size(h), h->uhf) != 0 && gj <= kMaxRefreshLds)
+            e = hipFuncSetAttribute(refresh_gj_kernel(refresh_gj_rows(gj_size(h), h->uhf), mixed, h->uhf),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)gj);
         if (e != hipSuccess) {
             free_ctx(h);
@@ -3809,6 +3783,13 @@ vmc_status vmc_amsgrad(int64_t n, double* p, double* m, double* v, double* vh, c
     return VMC_OK;
 }
 
+vmc_status vmc_set_small_denominator(vmc_handle h, double threshold) {
+    if (!h) return fail(nullptr, VMC_E_ARG, "handle is NULL");
+    if (!(threshold >= 0.0)) return fail(h, VMC_E_ARG, "threshold must be >= 0 (+inf allowed)");
+    h->small_den = threshold;
+    return VMC_OK;
+}
+
 vmc_status vmc_set_launch(vmc_handle h, int32_t block_threads) {
     if (!h) return fail(nullptr, VMC_E_ARG, "handle is NULL");
     if (block_threads != 0 && (block_threads < 64 || block_threads > 512 || (block_threads & 63) != 0))
@@ -3852,29 +3833,37 @@ vmc_status vmc_autotune(vmc_handle h, vmc_walkers* w, int32_t n_moves, int32_t* 
     vmc_status s = check_walkers(h, w);
     if (s != VMC_OK) return s;
     if (n_moves < 1) return fail(h, VMC_E_ARG, "n_moves must be >= 1");
-    const int keep = h->block_threads;
-    int best_nt = 0;
+    const int keep = h->block_threads, keep_w = h->waves;
+    int best_nt = 0, best_w = 0;
     float best = 3.0e38f;
-    for (int nt : kTuneThreads) {
-        h->block_threads = nt;
-        const SweepGeom g = sweep_geom(h);
-        if (g.lds > kMaxLdsHbm) continue;
-        float ms = 0.0f;
-        s = time_sweeps(h, w, nullptr, nullptr, n_moves, 2, st, &ms);
-        if (s != VMC_OK) {
-            h->block_threads = keep;
-            return s;
+    // workgroup size, and for walkers in HBM the occupancy target
+    for (int nt : kTuneThreads)
+        for (int wv : {3, 4}) {
+            h->block_threads = nt;
+            const SweepGeom g = sweep_geom(h);
+            if (g.lds > kMaxLdsHbm) continue;
+            if (g.small && wv == 4) continue;  // one variant: the waves target applies to the HBM layout
+            h->waves = g.small ? keep_w : wv;
+            float ms = 0.0f;
+            s = time_sweeps(h, w, nullptr, nullptr, n_moves, 2, st, &ms);
+            if (s != VMC_OK) {
+                h->block_threads = keep;
+                h->waves = keep_w;
+                return s;
+            }
+            if (ms < best) {
+                best = ms;
+                best_nt = nt;
+                best_w = h->waves;
+            }
         }
-        if (ms < best) {
-            best = ms;
-            best_nt = nt;
-        }
-    }
     if (best_nt == 0) {
         h->block_threads = keep;
+        h->waves = keep_w;
         return fail(h, VMC_E_UNSUPPORTED, "no workgroup size fits the LDS budget");
     }
     h->block_threads = best_nt;
+    h->waves = best_w;
     if (chosen) *chosen = best_nt;
     return VMC_OK;
 }
@@ -3883,31 +3872,38 @@ vmc_status vmc_batch_autotune(vmc_batch b, vmc_walkers* const* walkers, int32_t 
                               hipStream_t st) {
     if (!b) return fail(nullptr, VMC_E_ARG, "batch is NULL");
     if (n_moves < 1) return fail(nullptr, VMC_E_ARG, "n_moves must be >= 1");
-    const int keep = b->nt;
-    int best_nt = 0;
+    const int keep = b->nt, keep_w = b->waves;
+    int best_nt = 0, best_w = 0;
     float best = 3.0e38f;
-    for (int nt : kTuneThreads) {
-        size_t lds = 0;
-        for (vmc_ctx* h : b->sys)
-            lds = std::max(lds, (size_t)lds_layout(h->n_so, h->ne, h->nw, nt, false, (int)r_bytes(h), h->ncorr).total);
-        if (lds > kMaxLdsHbm) continue;
-        b->nt = nt;
-        float ms = 0.0f;
-        vmc_status s = time_sweeps(nullptr, nullptr, b, walkers, n_moves, 2, st, &ms);
-        if (s != VMC_OK) {
-            b->nt = keep;
-            return s;
+    for (int nt : kTuneThreads)
+        for (int wv : {3, 4}) {
+            size_t lds = 0;
+            for (vmc_ctx* h : b->sys)
+                lds = std::max(lds,
+                               (size_t)lds_layout(h->n_so, h->ne, h->nw, nt, false, (int)r_bytes(h), h->ncorr).total);
+            if (lds > kMaxLdsHbm) continue;
+            b->nt = nt;
+            b->waves = wv;
+            float ms = 0.0f;
+            vmc_status s = time_sweeps(nullptr, nullptr, b, walkers, n_moves, 2, st, &ms);
+            if (s != VMC_OK) {
+                b->nt = keep;
+                b->waves = keep_w;
+                return s;
+            }
+            if (ms < best) {
+                best = ms;
+                best_nt = nt;
+                best_w = wv;
+            }
         }
-        if (ms < best) {
-            best = ms;
-            best_nt = nt;
-        }
-    }
     if (best_nt == 0) {
         b->nt = keep;
+        b->waves = keep_w;
         return fail(nullptr, VMC_E_UNSUPPORTED, "no workgroup size fits the LDS budget");
     }
     b->nt = best_nt;
+    b->waves = best_w;
     if (chosen) *chosen = best_nt;
     return VMC_OK;
 }
@@ -3920,13 +3916,28 @@ vmc_status vmc_table_info(vmc_handle h, int64_t out[3]) {
     return VMC_OK;
 }
 
-vmc_status vmc_launch_info(vmc_handle h, int64_t out[4]) {
+vmc_status vmc_launch_info(vmc_handle h, int64_t out[5]) {
     if (!h || !out) return fail(h, VMC_E_ARG, "NULL argument");
     const SweepGeom g = sweep_geom(h);
     out[0] = g.nt;
     out[1] = g.small ? 1 : 0;
     out[2] = (int64_t)g.lds;
     out[3] = use_refresh_kernel(h) ? 1 : 0;
+    out[4] = g.small ? 0 : hbm_waves(h);
+    return VMC_OK;
+}
+
+vmc_status vmc_set_occupancy(vmc_handle h, int32_t waves) {
+    if (!h) return fail(nullptr, VMC_E_ARG, "handle is NULL");
+    if (waves != 0 && waves != 3 && waves != 4) return fail(h, VMC_E_ARG, "waves must be 0, 3 or 4");
+    h->waves = waves;
+    return VMC_OK;
+}
+
+vmc_status vmc_batch_set_occupancy(vmc_batch b, int32_t waves) {
+    if (!b) return fail(nullptr, VMC_E_ARG, "batch is NULL");
+    if (waves != 0 && waves != 3 && waves != 4) return fail(nullptr, VMC_E_ARG, "waves must be 0, 3 or 4");
+    b->waves = waves;
     return VMC_OK;
 }
 
@@ -3984,10 +3995,14 @@ static vmc_status launch_batch(vmc_batch b, vmc_walkers* const* ws, int mode, in
     if (lds > kMaxLdsHbm) return fail(nullptr, VMC_E_UNSUPPORTED, "a batched system exceeds the per-walker LDS budget");
     if (blocks > (int64_t)INT_MAX) return fail(nullptr, VMC_E_ARG, "too many walkers in the batch");
     const dim3 grid((unsigned)blocks), block((unsigned)b->nt);
-    if (b->precision == VMC_MIXED)
-        hipLaunchKernelGGL(k_sweep_batch<float>, grid, block, lds, st, A, mode, n_steps);
-    else
-        hipLaunchKernelGGL(k_sweep_batch<double>, grid, block, lds, st, A, mode, n_steps);
+    const int hw = batch_waves(b);
+    if (b->precision == VMC_MIXED) {
+        if (hw == 4) hipLaunchKernelGGL((k_sweep_batch<float, 4>), grid, block, lds, st, A, mode, n_steps);
+        else hipLaunchKernelGGL((k_sweep_batch<float, 3>), grid, block, lds, st, A, mode, n_steps);
+    } else {
+        if (hw == 4) hipLaunchKernelGGL((k_sweep_batch<double, 4>), grid, block, lds, st, A, mode, n_steps);
+        else hipLaunchKernelGGL((k_sweep_batch<double, 3>), grid, block, lds, st, A, mode, n_steps);
+    }
     HIP_OR_FAIL(nullptr, hipGetLastError());
     if (mode == MODE_CTMC)
         for (int e = 0; e < A.n; ++e) ws[e]->step += (uint64_t)n_steps;

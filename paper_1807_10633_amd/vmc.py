@@ -33,6 +33,7 @@ EXPORTED = (
     "vmc_batch_set_launch", "vmc_batch_local_energy", "vmc_batch_ctmc_step", "vmc_batch_destroy", "vmc_autotune",
     "vmc_batch_autotune", "vmc_ctmc_step_dev", "vmc_walkers_refresh", "vmc_cps_init", "vmc_set_cps", "vmc_cps_info",
     "vmc_ctmc_step_static",
+    "vmc_set_small_denominator", "vmc_set_occupancy", "vmc_batch_set_occupancy",
 )
 
 
@@ -78,6 +79,7 @@ def load_library() -> C.CDLL:
         "vmc_local_energy": ([P, P, P], i32),
         "vmc_ctmc_step": ([P, P, i32, P, P, P, P], i32),
         "vmc_ctmc_step_static": ([P, P, i32, P, P, P, P], i32),
+        "vmc_set_small_denominator": ([P, C.c_double], i32),
         "vmc_logderiv": ([P, P, P, P, P], i32),
         "vmc_amsgrad": ([i64, P, P, P, P, P, d, d, d, d, i32, P], i32),
         "vmc_excitations": ([P, P, i64, P, P, P, i64, P, P], i32),
@@ -88,6 +90,8 @@ def load_library() -> C.CDLL:
         "vmc_estimate": ([P, P, P, P, P], i32),
         "vmc_batch_create": ([P, i32, P], i32),
         "vmc_batch_set_launch": ([P, i32], i32),
+        "vmc_set_occupancy": ([P, i32], i32),
+        "vmc_batch_set_occupancy": ([P, i32], i32),
         "vmc_batch_local_energy": ([P, P, P], i32),
         "vmc_batch_ctmc_step": ([P, P, i32, P], i32),
         "vmc_batch_destroy": ([P], i32),
@@ -209,6 +213,11 @@ def vmc_ctmc_step_static(handle, walkers: "Walkers", n_steps: int, eloc_hist=Non
            "vmc_ctmc_step_static")
 
 
+def vmc_set_small_denominator(handle, threshold: float) -> None:
+    """Threshold of the small Sherman-Morrison denominator flag (and in-place re-inversion)."""
+    _check(load_library().vmc_set_small_denominator(handle, float(threshold)), handle, "vmc_set_small_denominator")
+
+
 def vmc_ctmc_step_dev(handle, walkers: "Walkers", n_steps: int, step_dev, stream=None) -> None:
     """CTMC moves with the step counter in device memory (graph-capturable)."""
     _check(load_library().vmc_ctmc_step_dev(handle, C.byref(walkers.cstruct), int(n_steps), _dev_ptr(step_dev),
@@ -270,10 +279,15 @@ def vmc_table_info(handle):
 
 
 def vmc_launch_info(handle):
-    out = (C.c_int64 * 4)()
+    out = (C.c_int64 * 5)()
     _check(load_library().vmc_launch_info(handle, out), handle, "vmc_launch_info")
     return {"threads": int(out[0]), "state_in_lds": bool(out[1]), "lds_bytes": int(out[2]),
-            "refresh_kernel": bool(out[3])}
+            "refresh_kernel": bool(out[3]), "waves": int(out[4])}
+
+
+def vmc_set_occupancy(handle, waves: int) -> None:
+    """Occupancy target (waves per SIMD: 3, 4, or 0 for the library's choice) of the HBM-layout sweep."""
+    _check(load_library().vmc_set_occupancy(handle, int(waves)), handle, "vmc_set_occupancy")
 
 
 def vmc_set_launch(handle, block_threads: int) -> None:
@@ -329,6 +343,10 @@ def vmc_batch_create(handles) -> int:
 
 def vmc_batch_set_launch(batch, block_threads: int) -> None:
     _check(load_library().vmc_batch_set_launch(batch, int(block_threads)), None, "vmc_batch_set_launch")
+
+
+def vmc_batch_set_occupancy(batch, waves: int) -> None:
+    _check(load_library().vmc_batch_set_occupancy(batch, int(waves)), None, "vmc_batch_set_occupancy")
 
 
 def _walker_array(walkers):

@@ -195,7 +195,7 @@ def test_batch_autotune(torch):
     torch.cuda.synchronize()
     assert nt in (64, 128, 256, 512)
     for wl, s, wk in zip(wls, systems, wks):
-        assert wk.step == 16
+        assert wk.step == 32  # 4 workgroup sizes x 2 occupancy targets x 2 timed sweeps x 2 moves
         el = field(s, wk, "eloc", torch.float64, 1)[:, 0]
         orc = OracleSystem.from_workload(wl)
         r = orc.local_energy(occ_of(s, wk)[5], ORC_LEMMA, with_candidates=False)

@@ -2,7 +2,8 @@
 one electron (no pair groups), a single walker, an empty screened set (T = 0),
 walkers at a node of the determinant and with a wrong electron count (flagged,
 never moved, no weight in the estimator), and the largest supported space
-(512 spatial orbitals)."""
+(512 spatial orbitals); the small Sherman-Morrison denominator flag and its
+in-place re-inversion."""
 import numpy as np
 import pytest
 
@@ -172,3 +173,53 @@ def test_largest_space_512_orbitals(torch):
     # are checked on the others
     live = np.isfinite(eh) & (th > 1e-9) & ~nodal[None, :]
     assert np.all(np.abs(eh[live] - e0) <= 1e-10 + 1e-13 / th[live])
+
+
+@pytest.mark.parametrize("name,W,moves", [("hchain20", 64, 7), ("hchain160", 8, 2)])
+def test_small_denominator_flags_and_reinverts(torch, name, W, moves):
+    """The small Sherman-Morrison denominator threshold (the Sherman-Morrison
+    paragraph of section "Local energy and Gradient ratios"): at the default
+    1e-8 none of these moves is flagged; at +inf every move is flagged
+    VMC_ST_SMALLDEN.  Where the sweep re-inverts in place (state in LDS: the
+    20-orbital chain) the walker is re-inverted right after the move; walkers
+    re-inverted by the separate kernel (the 160-orbital chain) wait for their
+    next re-inversion.  Either way the state left behind inverts theta[N] for
+    the walker's own slot order (against numpy) and E_L matches the oracle."""
+    from paper_1807_10633_amd.vmc import VmcError, vmc_launch_info, vmc_local_energy, vmc_set_small_denominator
+
+    ST_SMALLDEN = 8
+    wl = make_config(name, n_walkers=W)
+    sysm = gpu_system(wl)
+    info = vmc_launch_info(sysm.handle)
+    assert info["state_in_lds"] == (name == "hchain20")
+    with pytest.raises(VmcError):
+        vmc_set_small_denominator(sysm.handle, -1.0)
+    ne = wl.n_elec
+    for thr in (1e-8, float("inf")):
+        vmc_set_small_denominator(sysm.handle, thr)
+        walkers = sysm.walkers(wl.occ)
+        run_sweep(sysm, walkers, moves)
+        vmc_local_energy(sysm.handle, walkers)
+        torch.cuda.synchronize()
+        st = field(sysm, walkers, "status", torch.int32, 1)[:, 0]
+        moved = field(sysm, walkers, "pick", torch.int64, 1)[:, 0] != 0
+        assert np.all((st & 1) == 0)
+        if thr == 1e-8:
+            assert not np.any(st & ST_SMALLDEN)
+            continue
+        assert moved.any() and np.all((st[moved] & ST_SMALLDEN) != 0)
+        B = field(sysm, walkers, "ainv", torch.float64, ne * ne).reshape(W, ne, ne)
+        so = field(sysm, walkers, "slot_orb", torch.int32, ne)
+        for w in range(min(W, 4)):
+            A = wl.theta[so[w], :ne]
+            # B[p][x] = (A^-1)[x][p]: A B^T = I
+            res = np.abs(A @ B[w].T - np.eye(ne)).max()
+            assert res <= 1e-9, (w, res)
+        el = field(sysm, walkers, "eloc", torch.float64, 1)[:, 0]
+        orc = OracleSystem.from_workload(wl)
+        occ = occ_of(sysm, walkers)
+        idx = np.arange(0, W, max(1, W // 8))
+        e_o, T_o, _, sto = orc.local_energy_batch(occ[idx], ORC_LEMMA, 16)
+        assert np.all(sto == 0)
+        assert np.all(np.abs(el[idx] - e_o) <= el_tol(T_o))
+    vmc_set_small_denominator(sysm.handle, 1e-8)

@@ -270,6 +270,39 @@ def test_autotune_picks_a_valid_shape_and_keeps_walkers_valid(torch):
     _say(f"    autotuned workgroup: {nt} threads per walker")
 
 
+def test_occupancy_target_changes_no_result(torch):
+    """The occupancy target of the sweep with the walker state in HBM (3 or 4
+    waves per SIMD) changes the kernel's register budget, not its arithmetic:
+    identical walkers swept at both targets end bit for bit equal.  The
+    autotuner tries both (with every workgroup size) and reports its choice."""
+    from paper_1807_10633_amd.vmc import (VMC_MIXED, vmc_autotune, vmc_ctmc_step, vmc_launch_info, vmc_local_energy,
+                                          vmc_set_occupancy)
+
+    wl = make_config("hchain40", n_walkers=256)
+    sysm = gpu_system(wl, precision=VMC_MIXED)
+    ne, n_so = sysm.ne, sysm.n_so
+    got = []
+    for wv in (3, 4):
+        vmc_set_occupancy(sysm.handle, wv)
+        assert vmc_launch_info(sysm.handle)["waves"] == wv
+        wk = sysm.walkers(wl.occ)
+        vmc_ctmc_step(sysm.handle, wk, 20)
+        vmc_local_energy(sysm.handle, wk)
+        torch.cuda.synchronize()
+        got.append({f: field(sysm, wk, f, dt, per) for f, dt, per in (
+            ("eloc", torch.float64, 1), ("pick", torch.int64, 1), ("ainv", torch.float64, ne * ne),
+            ("r", torch.float32, ne * n_so), ("rlo", torch.int16, ne * n_so), ("status", torch.int32, 1))})
+    for f in got[0]:
+        assert np.array_equal(got[0][f], got[1][f]), f
+    vmc_set_occupancy(sysm.handle, 0)
+    wk = sysm.walkers(wl.occ)
+    nt = vmc_autotune(sysm.handle, wk, 2)
+    info = vmc_launch_info(sysm.handle)
+    assert info["threads"] == nt and info["waves"] in (3, 4) and not info["state_in_lds"]
+    assert wk.step == 32  # 4 workgroup sizes x 2 occupancy targets x 2 timed sweeps x 2 moves
+    _say(f"    autotuned: {nt} threads, {info['waves']} waves per SIMD")
+
+
 @pytest.mark.parametrize("name,scale", [("hchain40", 1e-3), ("hchain40", 1.0), ("hchain20", 1e-3)])
 def test_walkers_refresh_after_new_parameters(torch, name, scale):
     """vmc_walkers_refresh after vmc_set_params: B is the inverse of the new
@@ -355,11 +388,13 @@ def test_refresh_schedule_counts_moves_since_inversion(torch):
         assert abs(el[w] - r["eloc"]) <= el_tol(r["T"])
 
 
-def test_refresh_kernel_lds_path_above_128_electrons(torch):
+def test_refresh_kernel_above_128_electrons(torch):
     """134 electrons (ring of 136 sites, 67+67): the state lives in HBM and the
-    re-inversion runs in the LDS form of the refresh kernel (B of 140 KB), above
-    the register form's 128 rows.  Across two re-inversions and two updates, B
-    inverts A to the rounding its condition allows and E_L matches the oracle."""
+    re-inversion runs in the register Gauss-Jordan kernel with three rows per
+    lane (above 128 electrons its B goes straight to the walker's buffer and
+    the R product reads it from there).  Across two re-inversions and two
+    updates, B inverts A to the rounding its condition allows and E_L matches
+    the oracle."""
     from paper_1807_10633_amd.vmc import System, vmc_launch_info, vmc_local_energy
 
     L, na, nb, W = 136, 67, 67, 32
