@@ -167,6 +167,26 @@ def evaluate(wl, J, theta, occ, *, eps: float, rounds: int = 10, moves: int = 50
             "system": system, "walkers": walkers}
 
 
+def plateau(energies: List[float], window: int, block: int = 10) -> dict:
+    """Mean energy of the last two windows of `window` iterations, each with
+    the standard error of its means over blocks of `block` iterations (the
+    iterations' estimates are correlated through the walkers and the slowly
+    moving parameters), and their difference in units of the combined error."""
+    import numpy as np
+
+    out = {}
+    for name, seg in (("previous", energies[-2 * window:-window]), ("last", energies[-window:])):
+        seg = np.asarray(seg, dtype=np.float64)
+        nb = max(1, seg.size // block)
+        means = seg[: nb * block].reshape(nb, -1).mean(axis=1)
+        err = float(means.std(ddof=1) / np.sqrt(nb)) if nb > 1 else float("nan")
+        out[name] = {"mean": float(seg.mean()), "stderr": err}
+    d = out["last"]["mean"] - out["previous"]["mean"]
+    out["difference"] = d
+    out["difference_in_sigma"] = d / float(np.hypot(out["last"]["stderr"], out["previous"]["stderr"]))
+    return out
+
+
 def _main(argv: Optional[List[str]] = None) -> int:
     from workloads import make_config
 
@@ -185,6 +205,9 @@ def _main(argv: Optional[List[str]] = None) -> int:
                     help="after the iterations, evaluate the final parameters at this threshold")
     ap.add_argument("--eval-rounds", type=int, default=20)
     ap.add_argument("--cps", default=None, help="correlators (chainK, plus5)")
+    ap.add_argument("--window", type=int, default=0,
+                    help="after the iterations, compare the mean energy of the last two windows of this many "
+                         "iterations (blocks of 10 iterations for the error bars)")
     args = ap.parse_args(argv)
     if not torch.cuda.is_available():
         print(json.dumps({"error": "needs a GPU"}))
@@ -196,14 +219,18 @@ def _main(argv: Optional[List[str]] = None) -> int:
     walkers = system.walkers(wl.occ)
     opt = Optimizer(system, walkers, torch.as_tensor(wl.jastrow, device="cuda"),
                     torch.as_tensor(wl.theta, device="cuda"), moves=args.moves, paper_literal=args.paper_literal)
+    history = []
     for i in range(args.iters):
         t0 = time.perf_counter()
         E = float(opt.step().item())  # .item() waits for the iteration
         ea = opt.est_all.cpu().numpy()
+        history.append(float(ea[2]))
         print(json.dumps({"iteration": i, "alpha": paper_schedule(i), "energy": E,
                           "energy_all_states": float(ea[2]), "states": int(ea[3]),
                           "energy_per_electron": float(ea[2]) / wl.n_elec, "ms": (time.perf_counter() - t0) * 1e3}),
               flush=True)
+    if args.window > 0 and len(history) >= 2 * args.window:
+        print(json.dumps({"plateau": plateau(history, args.window), "n_elec": wl.n_elec}), flush=True)
     if args.eval_eps is not None:
         occ = walkers.view("occ_bits", torch.int64)[: walkers.n_walkers * system.n_words].cpu().numpy()
         ev = evaluate(wl, opt.J.clone(), opt.theta.clone(), occ.view("uint64").reshape(walkers.n_walkers, -1),
