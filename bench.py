@@ -334,11 +334,14 @@ def main():
         mixed = precision == vmc.VMC_MIXED
         sysm = vmc.System.from_workload(wl, refresh_period=S, precision=precision)
         walkers = sysm.walkers(wl.occ)
+        # burn-in of the walkers (not timed, not counted), then the launch
+        # shape: the project autotuner times sweeps of equilibrated walkers
+        # at every workgroup size and occupancy target (more burn-in)
+        vmc.vmc_ctmc_step(sysm.handle, walkers, 100, stream=stream)
         if args.threads:
             vmc.vmc_set_launch(sysm.handle, args.threads)
         else:
-            # project autotuner: launch shape from timed sweeps (they count as burn-in)
-            vmc.vmc_autotune(sysm.handle, walkers, 5)
+            vmc.vmc_autotune(sysm.handle, walkers, 10)
         npar = sysm.n_params
         params = sysm.param_vector().clone()
         m = torch.zeros_like(params)
@@ -367,8 +370,6 @@ def main():
             iteration(stream)
             return est[2]
 
-        # burn-in of the walkers (not timed, not counted)
-        vmc.vmc_ctmc_step(sysm.handle, walkers, 100, stream=stream)
         for _ in range(warmup):
             one_step(False)
         torch.cuda.synchronize()
@@ -477,7 +478,8 @@ def main():
                  "unit": "walker-steps/s", "sweep_kernel_ms": o["sweep_ms"],
                  "eloc_evals_per_s": W / (o["eloc_ms"] * 1e-3), "eloc_check": o["check"],
                  "energy": o["E"], "flagged_walkers": int(np.count_nonzero(o["status"] & 1)),
-                 "graph_replay_value": o["graph_value"], "headline_over_this": value / o["value"]}
+                 "graph_replay_value": o["graph_value"], "headline_over_this": value / o["value"],
+                 "launch": vmc.vmc_launch_info(o["sysm"].handle)}
         o["sysm"].close()
 
     # --- algorithmic work of the sweep kernel, from candidate counts of a
