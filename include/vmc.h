@@ -341,6 +341,32 @@ vmc_status vmc_logderiv(vmc_handle h, const vmc_walkers* w, const double* g_dev,
  */
 vmc_status vmc_estimate(vmc_handle h, const vmc_walkers* w, double* out, double* g, hipStream_t stream);
 
+/*
+ * The gradient estimator of Eq. eq:grad over several sets of states (one set
+ * per call, e.g. the walkers every few moves of a sweep), so that more of the
+ * sampled states than the last one per walker enter G:
+ * G_k = 2 sum_s t_s O_k(s) (E_L(s) - E) / sum_s t_s = 2 (A_k - E B_k) / sum t,
+ * A = sum t E_L O, B = sum t O, E = sum t E_L / sum t.
+ *
+ * vmc_snapshot_weights: for the walkers' current E_L and t (as left by
+ * vmc_local_energy), g_te[w] = t_w E_L,w and g_t[w] = t_w (device, W doubles
+ * each; 0 for flagged states, as in vmc_estimate), and the running sums acc
+ * (device, 4 doubles) = {sum t, sum t E_L, E, states counted}, started afresh
+ * when reset is nonzero, added to otherwise.  One workgroup, fixed order.
+ * vmc_logderiv_accumulate: out += sum_w g_w O_w (the contracted vmc_logderiv,
+ * added to out instead of overwriting it); call it with g_te into A and with
+ * g_t into B (the first set may use vmc_logderiv to overwrite).
+ * vmc_gradient_combine: out[k] = 2 (a[k] - E b[k]) / sum t from acc (0 when
+ * no state carried weight), n entries, all device.
+ * Nothing is allocated; asynchronous on stream.
+ */
+vmc_status vmc_snapshot_weights(vmc_handle h, const vmc_walkers* w, double* acc, double* g_te, double* g_t,
+                                int32_t reset, hipStream_t stream);
+vmc_status vmc_logderiv_accumulate(vmc_handle h, const vmc_walkers* w, const double* g_dev, double* out_dev,
+                                   hipStream_t stream);
+vmc_status vmc_gradient_combine(int64_t n, const double* a, const double* b, const double* acc, double* out,
+                                hipStream_t stream);
+
 /* One AMSGrad step over n parameters, all pointers device (Eqs. eq:m1, eq:m2,
  * in the Reddi form with standard betas: m = b1 m + (1-b1) g, v = b2 v +
  * (1-b2) g^2, vhat = max(vhat, v), p -= lr m / (sqrt(vhat) + delta)).

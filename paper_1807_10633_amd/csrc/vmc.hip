@@ -2677,7 +2677,7 @@ __global__ void k_logderiv_dense(Tab T, Wk S, double* out, int64_t n_p) {
 // four partial tiles are added in wave order, so the result is deterministic.
 constexpr int kSyrkWaves = 4;
 __global__ void __launch_bounds__(64 * kSyrkWaves) k_grad_J_syrk(Tab T, Wk S, int64_t W, const double* g,
-                                                                 double* out) {
+                                                                 double* out, int accumulate) {
     __shared__ double part[kSyrkWaves][16][16];
     const int n_so = T.n_so, nw = T.nw, nt16 = (n_so + 15) >> 4;
     int t = blockIdx.x, pt = 0;
@@ -2724,7 +2724,8 @@ __global__ void __launch_bounds__(64 * kSyrkWaves) k_grad_J_syrk(Tab T, Wk S, in
         if (p >= n_so || q >= n_so || q < p) continue;
         double v = 0.0;
         for (int k = 0; k < kSyrkWaves; ++k) v += part[k][r][cc];
-        out[(int64_t)p * n_so - (int64_t)p * (p - 1) / 2 + (q - p)] = v;
+        double* o = out + (int64_t)p * n_so - (int64_t)p * (p - 1) / 2 + (q - p);
+        *o = (accumulate ? *o : 0.0) + v;
     }
 }
 
@@ -2741,7 +2742,7 @@ __global__ void __launch_bounds__(64 * kSyrkWaves) k_grad_J_syrk(Tab T, Wk S, in
 constexpr int kGradWaves = 16;
 template <int NR>
 __global__ void __launch_bounds__(64 * kGradWaves) k_grad_theta_rows(Tab T, Wk S, int64_t W, const double* g,
-                                                                     double* out, int64_t nj) {
+                                                                     double* out, int64_t nj, int accumulate) {
     extern __shared__ __align__(16) unsigned char smem[];
     double* buf = (double*)smem;  // Ne doubles
     const int k = blockIdx.x, n_so = T.n_so, ne = T.ne, l = lane_id();
@@ -2807,7 +2808,7 @@ __global__ void __launch_bounds__(64 * kGradWaves) k_grad_theta_rows(Tab T, Wk S
         __syncthreads();
     }
     double* o = out + nj + (size_t)k * n_so;
-    for (int x = threadIdx.x; x < n_so; x += blockDim.x) o[x] = (x < ne) ? buf[x] : 0.0;
+    for (int x = threadIdx.x; x < n_so; x += blockDim.x) o[x] = (accumulate ? o[x] : 0.0) + ((x < ne) ? buf[x] : 0.0);
 }
 
 // Correlator part of G = sum_w g_w O_w: G[l][n] = (sum of g_w over the walkers
@@ -2819,7 +2820,7 @@ __global__ void __launch_bounds__(64 * kGradWaves) k_grad_theta_rows(Tab T, Wk S
 // add nothing.
 constexpr int kCpsWaves = 4;
 __global__ void __launch_bounds__(64 * kCpsWaves) k_grad_cps(Tab T, Wk S, int64_t W, const double* g, double* out,
-                                                             int64_t off0) {
+                                                             int64_t off0, int accumulate) {
     __shared__ double hist[kCpsWaves][1024];
     const int lam = blockIdx.x, l = lane_id(), nw = T.nw;
     const int wv = (int)uni((uint32_t)(threadIdx.x >> 6));
@@ -2857,7 +2858,8 @@ __global__ void __launch_bounds__(64 * kCpsWaves) k_grad_cps(Tab T, Wk S, int64_
     for (int e = threadIdx.x; e < ns; e += blockDim.x) {
         double v = 0.0;
         for (int q = 0; q < kCpsWaves; ++q) v += hist[q][e];
-        out[off0 + c0 + e] = v / T.cc[c0 + e];
+        double* o = out + off0 + c0 + e;
+        *o = (accumulate ? *o : 0.0) + v / T.cc[c0 + e];
     }
 }
 
@@ -2926,6 +2928,66 @@ __global__ void __launch_bounds__(1024) k_estimate(const double* eloc, const dou
             const double t = tres[k], e = eloc[k];
             g[k] = (t > 0.0 && isfinite(e) && T > 0.0) ? 2.0 * t * (e - E) / T : 0.0;
         }
+}
+
+
+// One snapshot of the covariance gradient over several sets of states: the
+// weights t_w E_L,w and t_w of the current states (0 for flagged states, as in
+// k_estimate), and the running sums acc = {sum t, sum t E_L, E, states}
+// (reset: start them here), one workgroup in a fixed summation order.  With
+// A = sum t E_L O and B = sum t O over all snapshots (the contracted backward
+// with these two weights), G = 2 (A - E B) / sum t (k_gradient_combine).
+__global__ void __launch_bounds__(1024) k_snapshot_weights(const double* eloc, const double* tres, int64_t W,
+                                                           double* acc, double* g_te, double* g_t, int reset) {
+    __shared__ double red[3][16];
+    const int tid = threadIdx.x, nt = blockDim.x, l = tid & 63, wv = tid >> 6, nwv = nt >> 6;
+    double st = 0.0, se = 0.0, sn = 0.0;
+    for (int64_t k = tid; k < W; k += nt) {
+        const double t = tres[k], e = eloc[k];
+        const bool ok = t > 0.0 && isfinite(e);
+        g_te[k] = ok ? t * e : 0.0;
+        g_t[k] = ok ? t : 0.0;
+        if (ok) {
+            st += t;
+            se += t * e;
+            sn += 1.0;
+        }
+    }
+    st = wave_total(st);
+    se = wave_total(se);
+    sn = wave_total(sn);
+    if (l == 0) {
+        red[0][wv] = st;
+        red[1][wv] = se;
+        red[2][wv] = sn;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double T = 0.0, TE = 0.0, N = 0.0;
+        for (int q = 0; q < nwv; ++q) {
+            T += red[0][q];
+            TE += red[1][q];
+            N += red[2][q];
+        }
+        if (!reset) {
+            T += acc[0];
+            TE += acc[1];
+            N += acc[3];
+        }
+        acc[0] = T;
+        acc[1] = TE;
+        acc[2] = (T > 0.0) ? TE / T : NAN;
+        acc[3] = N;
+    }
+}
+
+// G_k = 2 (A_k - E B_k) / sum t with E = acc[2], sum t = acc[0] (0 when no
+// state carried weight).
+__global__ void k_gradient_combine(int64_t n, const double* a, const double* b, const double* acc, double* out) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double T = acc[0], E = acc[2];
+    out[k] = (T > 0.0) ? 2.0 * (a[k] - E * b[k]) / T : 0.0;
 }
 
 }  // namespace
@@ -3726,41 +3788,83 @@ vmc_status vmc_uniforms(uint64_t seed, int64_t n, uint64_t step, double* out, hi
     return VMC_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// The contracted backward G = sum_w g_w O_w into out (overwritten, or added to
+// when accumulate).  Jastrow part: one SYRK tile per workgroup; orbital part:
+// one workgroup per orbital, rows of Ne/64 doubles per lane (the smallest
+// instantiation that holds them); correlator part: one workgroup per
+// correlator.  Nothing is allocated.
+vmc_status logderiv_contract(vmc_ctx* h, const vmc_walkers* w, const double* g, double* out, int accumulate,
+                             hipStream_t st) {
+    const Tab T = make_tab(h);
+    const Wk S = make_wk(h, w);
+    const int nt16 = (h->n_so + 15) / 16;
+    hipLaunchKernelGGL(k_grad_J_syrk, dim3((unsigned)(nt16 * (nt16 + 1) / 2)), dim3(64 * kSyrkWaves), 0, st, T, S,
+                       w->n_walkers, g, out, accumulate);
+    HIP_OR_FAIL(h, hipGetLastError());
+    const int nr = (h->ne + 63) / 64;
+    const int64_t nj = (int64_t)h->n_so * (h->n_so + 1) / 2;
+    const dim3 grid((unsigned)h->n_so), block(64 * kGradWaves);
+    const size_t lds = (size_t)h->ne * 8;
+    const int64_t W = w->n_walkers;
+    if (nr <= 1) hipLaunchKernelGGL(k_grad_theta_rows<1>, grid, block, lds, st, T, S, W, g, out, nj, accumulate);
+    else if (nr <= 2) hipLaunchKernelGGL(k_grad_theta_rows<2>, grid, block, lds, st, T, S, W, g, out, nj, accumulate);
+    else if (nr <= 4) hipLaunchKernelGGL(k_grad_theta_rows<4>, grid, block, lds, st, T, S, W, g, out, nj, accumulate);
+    else if (nr <= 8) hipLaunchKernelGGL(k_grad_theta_rows<8>, grid, block, lds, st, T, S, W, g, out, nj, accumulate);
+    else hipLaunchKernelGGL(k_grad_theta_rows<16>, grid, block, lds, st, T, S, W, g, out, nj, accumulate);
+    HIP_OR_FAIL(h, hipGetLastError());
+    if (h->ncorr > 0) {
+        hipLaunchKernelGGL(k_grad_cps, dim3((unsigned)h->ncorr), dim3(64 * kCpsWaves), 0, st, T, S, W, g, out,
+                           nj + (int64_t)h->n_so * h->n_so, accumulate);
+        HIP_OR_FAIL(h, hipGetLastError());
+    }
+    return VMC_OK;
+}
+}  // namespace
+
+extern "C" {
+
 vmc_status vmc_logderiv(vmc_handle h, const vmc_walkers* w, const double* g, double* out, hipStream_t st) {
     if (!h) return fail(nullptr, VMC_E_ARG, "handle is NULL");
     vmc_status s = check_walkers(h, w);
     if (s != VMC_OK) return s;
     if (!out) return fail(h, VMC_E_ARG, "out is NULL");
     const int64_t n_p = (int64_t)h->n_so * (h->n_so + 1) / 2 + (int64_t)h->n_so * h->n_so + h->n_coef;
-    const Tab T = make_tab(h);
-    const Wk S = make_wk(h, w);
     if (!g) {
-        hipLaunchKernelGGL(k_logderiv_dense, dim3((unsigned)w->n_walkers), dim3(256), 0, st, T, S, out, n_p);
+        hipLaunchKernelGGL(k_logderiv_dense, dim3((unsigned)w->n_walkers), dim3(256), 0, st, make_tab(h), make_wk(h, w),
+                           out, n_p);
         HIP_OR_FAIL(h, hipGetLastError());
         return VMC_OK;
     }
-    // Jastrow part: one SYRK tile per workgroup; orbital part: one workgroup
-    // per orbital, rows of Ne/64 doubles per lane (the smallest instantiation
-    // that holds them).  Nothing is allocated.
-    const int nt16 = (h->n_so + 15) / 16;
-    hipLaunchKernelGGL(k_grad_J_syrk, dim3((unsigned)(nt16 * (nt16 + 1) / 2)), dim3(64 * kSyrkWaves), 0, st, T, S,
-                       w->n_walkers, g, out);
+    return logderiv_contract(h, w, g, out, 0, st);
+}
+
+vmc_status vmc_logderiv_accumulate(vmc_handle h, const vmc_walkers* w, const double* g, double* out, hipStream_t st) {
+    if (!h) return fail(nullptr, VMC_E_ARG, "handle is NULL");
+    vmc_status s = check_walkers(h, w);
+    if (s != VMC_OK) return s;
+    if (!out || !g) return fail(h, VMC_E_ARG, "g and out are required");
+    return logderiv_contract(h, w, g, out, 1, st);
+}
+
+vmc_status vmc_snapshot_weights(vmc_handle h, const vmc_walkers* w, double* acc, double* g_te, double* g_t,
+                                int32_t reset, hipStream_t st) {
+    if (!h) return fail(nullptr, VMC_E_ARG, "handle is NULL");
+    if (!w || w->n_walkers <= 0 || !w->eloc || !w->tres) return fail(h, VMC_E_ARG, "bad walkers");
+    if (!acc || !g_te || !g_t) return fail(h, VMC_E_ARG, "acc, g_te and g_t are required");
+    hipLaunchKernelGGL(k_snapshot_weights, dim3(1), dim3(1024), 0, st, (const double*)w->eloc,
+                       (const double*)w->tres, w->n_walkers, acc, g_te, g_t, reset ? 1 : 0);
     HIP_OR_FAIL(h, hipGetLastError());
-    const int nr = (h->ne + 63) / 64;
-    const int64_t nj = (int64_t)h->n_so * (h->n_so + 1) / 2;
-    const dim3 grid((unsigned)h->n_so), block(64 * kGradWaves);
-    const size_t lds = (size_t)h->ne * 8;
-    if (nr <= 1) hipLaunchKernelGGL(k_grad_theta_rows<1>, grid, block, lds, st, T, S, w->n_walkers, g, out, nj);
-    else if (nr <= 2) hipLaunchKernelGGL(k_grad_theta_rows<2>, grid, block, lds, st, T, S, w->n_walkers, g, out, nj);
-    else if (nr <= 4) hipLaunchKernelGGL(k_grad_theta_rows<4>, grid, block, lds, st, T, S, w->n_walkers, g, out, nj);
-    else if (nr <= 8) hipLaunchKernelGGL(k_grad_theta_rows<8>, grid, block, lds, st, T, S, w->n_walkers, g, out, nj);
-    else hipLaunchKernelGGL(k_grad_theta_rows<16>, grid, block, lds, st, T, S, w->n_walkers, g, out, nj);
-    HIP_OR_FAIL(h, hipGetLastError());
-    if (h->ncorr > 0) {
-        hipLaunchKernelGGL(k_grad_cps, dim3((unsigned)h->ncorr), dim3(64 * kCpsWaves), 0, st, T, S, w->n_walkers, g,
-                           out, nj + (int64_t)h->n_so * h->n_so);
-        HIP_OR_FAIL(h, hipGetLastError());
-    }
+    return VMC_OK;
+}
+
+vmc_status vmc_gradient_combine(int64_t n, const double* a, const double* b, const double* acc, double* out,
+                                hipStream_t st) {
+    if (n <= 0 || !a || !b || !acc || !out) return fail(nullptr, VMC_E_ARG, "bad arguments");
+    hipLaunchKernelGGL(k_gradient_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, a, b, acc, out);
+    HIP_OR_FAIL(nullptr, hipGetLastError());
     return VMC_OK;
 }
 

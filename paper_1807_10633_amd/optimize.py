@@ -14,10 +14,14 @@ Each iteration (section "AMSGrad algorithm for optimizing the energy") is
      the schedule;
   6. the new parameters into the tables (vmc_set_params, vmc_set_cps) and the
      walkers' inverses recomputed for them (vmc_walkers_refresh).
-The gradient uses one state per walker, the last of the iteration: the O_k of
-a state need its inverse, which the sweep does not keep for the states it
-passes through, and the final states of `moves`-move walks are nearly
-independent samples; the energy uses all of them.
+The gradient needs the O_k of a state, hence its inverse, which the sweep
+does not keep for the states it passes through.  By default it uses the
+final state of each walker; with grad_every = K it uses the walkers every K
+moves (moves / K snapshots per iteration): A = sum t E_L O and B = sum t O are
+accumulated per snapshot by the contracted backward and G = 2 (A - E B) /
+sum t (vmc_snapshot_weights, vmc_logderiv_accumulate, vmc_gradient_combine).
+With many parameters the extra states matter: the gradient of one state per
+walker fits the noise of those states.  The energy uses every visited state.
 
 Every step runs in the library's kernels; this module only sequences the calls
 on one stream and holds the device buffers.  The default schedule is the
@@ -62,13 +66,19 @@ class Optimizer:
     in the order of vmc_logderiv, that the optimiser owns.
     """
 
-    def __init__(self, system, walkers, J, theta, *, cps=None, moves: int = 50,
+    def __init__(self, system, walkers, J, theta, *, cps=None, moves: int = 50, grad_every: int = 0,
                  schedule: Callable[[int], float] = paper_schedule, beta1: float = 0.9, beta2: float = 0.99,
                  delta: float = 1e-8, paper_literal: bool = False, stream=None):
         if not J.is_cuda or not theta.is_cuda:
             raise RuntimeError("the optimiser runs on the GPU only")
         self.system, self.walkers = system, walkers
         self.moves, self.schedule = int(moves), schedule
+        # gradient states: the walkers every grad_every moves (default: the
+        # final states only)
+        self.grad_every = int(grad_every) or self.moves
+        if self.grad_every < 1 or self.moves % self.grad_every:
+            raise ValueError("grad_every must divide moves")
+        self.n_snap = self.moves // self.grad_every
         self.beta1, self.beta2, self.delta, self.paper_literal = beta1, beta2, delta, paper_literal
         self.stream = stream
         dev = J.device
@@ -89,6 +99,11 @@ class Optimizer:
         self.G = torch.zeros_like(self.params)
         self.est = torch.zeros(4, dtype=torch.float64, device=dev)
         self.g = torch.zeros(walkers.n_walkers, dtype=torch.float64, device=dev)
+        if self.n_snap > 1:
+            self.A = torch.zeros_like(self.params)
+            self.B = torch.zeros_like(self.params)
+            self.acc = torch.zeros(4, dtype=torch.float64, device=dev)
+            self.g_t = torch.zeros(walkers.n_walkers, dtype=torch.float64, device=dev)
         self.iteration = 0
         self._apply()
 
@@ -110,15 +125,34 @@ class Optimizer:
         _vmc.vmc_walkers_refresh(h, self.walkers, stream=st)
 
     def step(self) -> torch.Tensor:
-        """One iteration; returns the device scalar E of the final states
-        (estimated before the parameter update).  est_all then holds {sum t,
-        sum t E_L, E, count} over every state the iteration visited."""
+        """One iteration; returns the device scalar E of the gradient's states
+        (the final states, or every grad_every-th), estimated before the
+        parameter update.  est_all then holds {sum t, sum t E_L, E, count}
+        over every state the iteration visited."""
         h, st, w = self.system.handle, self.stream, self.walkers
-        _vmc.vmc_ctmc_step(h, w, self.moves, self.eh, self.th, stream=st)
-        _vmc.vmc_estimate_arrays(h, self.eh, self.th, self.eh.numel(), self.est_all, stream=st)
-        _vmc.vmc_local_energy(h, w, stream=st)
-        _vmc.vmc_estimate(h, w, self.est, self.g, stream=st)
-        _vmc.vmc_logderiv(h, w, self.g, self.G, stream=st)
+        if self.n_snap == 1:
+            _vmc.vmc_ctmc_step(h, w, self.moves, self.eh, self.th, stream=st)
+            _vmc.vmc_estimate_arrays(h, self.eh, self.th, self.eh.numel(), self.est_all, stream=st)
+            _vmc.vmc_local_energy(h, w, stream=st)
+            _vmc.vmc_estimate(h, w, self.est, self.g, stream=st)
+            _vmc.vmc_logderiv(h, w, self.g, self.G, stream=st)
+        else:
+            # G over the states every grad_every moves: A = sum t E_L O and
+            # B = sum t O accumulated per snapshot, G = 2 (A - E B) / sum t
+            K = self.grad_every
+            for s in range(self.n_snap):
+                _vmc.vmc_ctmc_step(h, w, K, self.eh[s * K:(s + 1) * K], self.th[s * K:(s + 1) * K], stream=st)
+                _vmc.vmc_local_energy(h, w, stream=st)
+                _vmc.vmc_snapshot_weights(h, w, self.acc, self.g, self.g_t, s == 0, stream=st)
+                if s == 0:
+                    _vmc.vmc_logderiv(h, w, self.g, self.A, stream=st)
+                    _vmc.vmc_logderiv(h, w, self.g_t, self.B, stream=st)
+                else:
+                    _vmc.vmc_logderiv_accumulate(h, w, self.g, self.A, stream=st)
+                    _vmc.vmc_logderiv_accumulate(h, w, self.g_t, self.B, stream=st)
+            _vmc.vmc_estimate_arrays(h, self.eh, self.th, self.eh.numel(), self.est_all, stream=st)
+            _vmc.vmc_gradient_combine(self.A, self.B, self.acc, self.G, stream=st)
+            self.est.copy_(self.acc)
         _vmc.vmc_amsgrad(self.params, self.m, self.v, self.vhat, self.G, self.schedule(self.iteration), self.beta1,
                          self.beta2, self.delta, self.paper_literal, stream=st)
         self._apply()
@@ -195,6 +229,8 @@ def _main(argv: Optional[List[str]] = None) -> int:
     ap.add_argument("--walkers", type=int, default=0, help="0: the configuration's walker count")
     ap.add_argument("--iters", type=int, default=40)
     ap.add_argument("--moves", type=int, default=50)
+    ap.add_argument("--grad-every", type=int, default=10,
+                    help="gradient states: the walkers every this many moves (moves: the final states only)")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
     ap.add_argument("--orbitals", choices=("ghf", "uhf"), default="ghf",
                     help="general or spin-blocked (unrestricted) orbitals")
@@ -218,7 +254,8 @@ def _main(argv: Optional[List[str]] = None) -> int:
     system = _vmc.System.from_workload(wl, precision=prec, refresh_period=args.moves)
     walkers = system.walkers(wl.occ)
     opt = Optimizer(system, walkers, torch.as_tensor(wl.jastrow, device="cuda"),
-                    torch.as_tensor(wl.theta, device="cuda"), moves=args.moves, paper_literal=args.paper_literal)
+                    torch.as_tensor(wl.theta, device="cuda"), moves=args.moves, grad_every=args.grad_every,
+                    paper_literal=args.paper_literal)
     history = []
     for i in range(args.iters):
         t0 = time.perf_counter()

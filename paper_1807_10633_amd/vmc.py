@@ -33,7 +33,8 @@ EXPORTED = (
     "vmc_batch_set_launch", "vmc_batch_local_energy", "vmc_batch_ctmc_step", "vmc_batch_destroy", "vmc_autotune",
     "vmc_batch_autotune", "vmc_ctmc_step_dev", "vmc_walkers_refresh", "vmc_cps_init", "vmc_set_cps", "vmc_cps_info",
     "vmc_ctmc_step_static",
-    "vmc_set_small_denominator", "vmc_set_occupancy", "vmc_batch_set_occupancy",
+    "vmc_set_small_denominator", "vmc_set_occupancy", "vmc_batch_set_occupancy", "vmc_snapshot_weights",
+    "vmc_logderiv_accumulate", "vmc_gradient_combine",
 )
 
 
@@ -91,6 +92,9 @@ def load_library() -> C.CDLL:
         "vmc_batch_create": ([P, i32, P], i32),
         "vmc_batch_set_launch": ([P, i32], i32),
         "vmc_set_occupancy": ([P, i32], i32),
+        "vmc_snapshot_weights": ([P, P, P, P, P, i32, P], i32),
+        "vmc_logderiv_accumulate": ([P, P, P, P, P], i32),
+        "vmc_gradient_combine": ([C.c_int64, P, P, P, P, P], i32),
         "vmc_batch_set_occupancy": ([P, i32], i32),
         "vmc_batch_local_energy": ([P, P, P], i32),
         "vmc_batch_ctmc_step": ([P, P, i32, P], i32),
@@ -234,6 +238,25 @@ def vmc_estimate(handle, walkers: "Walkers", out_dev, g_dev=None, stream=None) -
     _check(load_library().vmc_estimate(handle, C.byref(walkers.cstruct), _dev_ptr(out_dev),
                                        _dev_ptr(g_dev) if g_dev is not None else None, _stream_ptr(stream)),
            handle, "vmc_estimate")
+
+
+def vmc_snapshot_weights(handle, walkers: "Walkers", acc, g_te, g_t, reset: bool, stream=None) -> None:
+    """Gradient weights t E_L and t of the walkers' current states, and running sums acc (4 doubles)."""
+    _check(load_library().vmc_snapshot_weights(handle, C.byref(walkers.cstruct), _dev_ptr(acc), _dev_ptr(g_te),
+                                               _dev_ptr(g_t), 1 if reset else 0, _stream_ptr(stream)), handle,
+           "vmc_snapshot_weights")
+
+
+def vmc_logderiv_accumulate(handle, walkers: "Walkers", g, out, stream=None) -> None:
+    """out += sum_w g_w O_w (the contracted backward, accumulated)."""
+    _check(load_library().vmc_logderiv_accumulate(handle, C.byref(walkers.cstruct), _dev_ptr(g), _dev_ptr(out),
+                                                  _stream_ptr(stream)), handle, "vmc_logderiv_accumulate")
+
+
+def vmc_gradient_combine(a, b, acc, out, stream=None) -> None:
+    """out = 2 (a - E b) / sum t with E, sum t from acc."""
+    _check(load_library().vmc_gradient_combine(int(out.numel()), _dev_ptr(a), _dev_ptr(b), _dev_ptr(acc),
+                                               _dev_ptr(out), _stream_ptr(stream)), None, "vmc_gradient_combine")
 
 
 def vmc_estimate_arrays(handle, eloc_dev, tres_dev, n: int, out_dev, g_dev=None, stream=None) -> None:

@@ -54,10 +54,12 @@ def test_stepping_entry_points_reach_no_allocation():
     funcs = dict(_functions(src))
     for ep in ("vmc_local_energy", "vmc_ctmc_step", "vmc_ctmc_step_dev", "vmc_logderiv", "vmc_estimate",
                "vmc_amsgrad", "vmc_walkers_init", "vmc_walkers_refresh", "vmc_batch_local_energy",
-               "vmc_batch_ctmc_step", "vmc_set_params", "vmc_set_cps", "vmc_ctmc_step_static"):
+               "vmc_batch_ctmc_step", "vmc_set_params", "vmc_set_cps", "vmc_ctmc_step_static", "vmc_logderiv_accumulate",
+               "vmc_snapshot_weights", "vmc_gradient_combine"):
         assert ep in funcs, ep
         assert not ALLOC.search(funcs[ep]), ep
     # the helpers they launch through
-    for helper in ("launch_sweep", "launch_refresh", "launch_batch", "launch_prec", "launch_one", "launch_hbm"):
+    for helper in ("launch_sweep", "launch_refresh", "launch_batch", "launch_prec", "launch_one", "launch_hbm",
+                   "logderiv_contract"):
         if helper in funcs:
             assert not ALLOC.search(funcs[helper]), helper

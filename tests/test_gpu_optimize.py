@@ -145,3 +145,65 @@ def test_loose_eps_optimisation_tight_eps_evaluation(torch):
     assert abs(ev["rounds"][-1] - E_ref) <= 1e-10 * max(1.0, abs(E_ref))
     _say(f"    optimised at eps 1e-4 (last sampled E {opt.est[2].item():.5f}); "
          f"at eps 1e-7: E {ev['energy']:.5f} +- {ev['stderr']:.5f}")
+
+
+def test_gradient_over_snapshots_matches_oracle(torch):
+    """The gradient estimator of Eq. eq:grad over the walkers every 5 moves of
+    a 20-move sweep (four snapshots): vmc_snapshot_weights,
+    vmc_logderiv(_accumulate) and vmc_gradient_combine give
+    G = 2 sum_s t_s O(s) (E_L(s) - E) / sum_s t_s and E over all 4 x 64 states,
+    against the oracle on the same states; Optimizer(grad_every=5) on a twin
+    walker set computes the same G bit for bit."""
+    from oracle.optim import gradient
+    from paper_1807_10633_amd.optimize import Optimizer
+    from paper_1807_10633_amd.vmc import (vmc_ctmc_step, vmc_gradient_combine, vmc_local_energy, vmc_logderiv,
+                                          vmc_logderiv_accumulate, vmc_snapshot_weights)
+
+    wl = make_config("hubbard8", n_walkers=64)
+    sysm = gpu_system(wl, refresh_period=20)
+    walkers = sysm.walkers(wl.occ)
+    n_p, W = sysm.n_params, 64
+    A = torch.zeros(n_p, dtype=torch.float64, device="cuda")
+    B = torch.zeros_like(A)
+    G = torch.zeros_like(A)
+    acc = torch.zeros(4, dtype=torch.float64, device="cuda")
+    g_te = torch.zeros(W, dtype=torch.float64, device="cuda")
+    g_t = torch.zeros_like(g_te)
+    states = []
+    for s in range(4):
+        vmc_ctmc_step(sysm.handle, walkers, 5)
+        vmc_local_energy(sysm.handle, walkers)
+        vmc_snapshot_weights(sysm.handle, walkers, acc, g_te, g_t, s == 0)
+        if s == 0:
+            vmc_logderiv(sysm.handle, walkers, g_te, A)
+            vmc_logderiv(sysm.handle, walkers, g_t, B)
+        else:
+            vmc_logderiv_accumulate(sysm.handle, walkers, g_te, A)
+            vmc_logderiv_accumulate(sysm.handle, walkers, g_t, B)
+        torch.cuda.synchronize()
+        states.append(occ_of(sysm, walkers))
+    vmc_gradient_combine(A, B, acc, G)
+    torch.cuda.synchronize()
+    orc = OracleSystem.from_workload(wl)
+    el, t, O = [], [], []
+    for occ in states:
+        for w in range(W):
+            r = orc.local_energy(occ[w], ORC_LEMMA, with_candidates=False)
+            el.append(r["eloc"])
+            t.append(1.0 / r["T"])
+            O.append(orc.logderiv(occ[w]))
+    el, t, O = np.array(el), np.array(t), np.array(O)
+    a = acc.cpu().numpy()
+    assert a[3] == 4 * W
+    assert abs(a[2] - weighted_energy(el, t)) <= 1e-10
+    G_ref = gradient(O, el, t)
+    np.testing.assert_allclose(G.cpu().numpy(), G_ref, rtol=1e-9, atol=1e-12 * np.max(np.abs(G_ref)))
+    # the optimiser's own loop on identical walkers (same seed, same moves)
+    twin = sysm.walkers(wl.occ)
+    opt = Optimizer(sysm, twin, torch.as_tensor(wl.jastrow, device="cuda"), torch.as_tensor(wl.theta, device="cuda"),
+                    moves=20, grad_every=5)
+    E = float(opt.step().item())
+    torch.cuda.synchronize()
+    assert np.array_equal(opt.G.cpu().numpy(), G.cpu().numpy())
+    assert E == a[2]
+    _say(f"    4 snapshots x {W} walkers: E {a[2]:.6f}, |G| {np.linalg.norm(G_ref):.3e}")
