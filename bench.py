@@ -123,8 +123,10 @@ def parse():
     ap.add_argument("--sweep", type=int, default=50, help="CTMC moves per step (= refresh period)")
     ap.add_argument("--config", default="hchain160",
                     help="hchain160 (default), hchain20, hubbard8, hubbard10x10, hchain40, hchain80, or batch "
-                         "(40/80/160 orbitals in one launch)")
+                         "(40/80/160 orbitals swept together)")
     ap.add_argument("--threads", type=int, default=0, help="workgroup size of the sweep kernel (0 = autotuned)")
+    ap.add_argument("--batch-mode", choices=("auto", "fused", "streams"), default="auto",
+                    help="batch: one fused launch, one stream per system, or the faster of the two (autotuned)")
     ap.add_argument("--eps", type=float, default=None, help="screening threshold (default: the workload's own)")
     ap.add_argument("--orbitals", choices=("ghf", "uhf"), default="ghf",
                     help="general or spin-blocked (unrestricted) orbitals of the same workload")
@@ -207,11 +209,13 @@ def cpu_oracle_baseline(wl, seconds, oracle_sys=None):
 
 
 def batch_bench(args):
-    """The uneven batch in one launch: H-chain-like systems of 40, 80 and 160
-    orbitals (half filled, eps = 1e-5), 2048 walkers each, swept together by
-    vmc_batch_ctmc_step.  value = walker-steps/s summed over the three systems.
-    The walker state of every system stays in HBM, so the roofline is HBM with
-    R and B read and written once per move."""
+    """The uneven batch: H-chain-like systems of 40, 80 and 160 orbitals (half
+    filled, eps = 1e-5), 2048 walkers each, swept together by
+    vmc_batch_ctmc_step, either in one fused launch (every state in HBM) or
+    with one stream per system (each system in its own variant).  value =
+    walker-steps/s summed over the three systems.  The roofline is HBM: R and B
+    read and written once per move where the state stays in HBM, once per
+    sweep where it is held in LDS."""
     import numpy as np
     import torch
 
@@ -231,10 +235,19 @@ def batch_bench(args):
     stream = torch.cuda.current_stream()
     timer = HipTimer(stream)
     try:
-        nt = args.threads or vmc.vmc_batch_autotune(b, walkers, 2)
+        # burn-in from the random initial determinants, then the launch shapes
+        # and the mode are tuned on equilibrated walkers with sweeps of 10 moves
+        vmc.vmc_batch_ctmc_step(b, walkers, 100, stream=stream)
+        if args.batch_mode != "fused" or not args.threads:
+            vmc.vmc_batch_autotune(b, walkers, 10)
+        if args.batch_mode != "auto":
+            vmc.vmc_batch_set_mode(b, vmc.VMC_BATCH_STREAMS if args.batch_mode == "streams" else vmc.VMC_BATCH_FUSED)
         if args.threads:
-            vmc.vmc_batch_set_launch(b, nt)
-        vmc.vmc_batch_ctmc_step(b, walkers, S, stream=stream)  # burn-in
+            vmc.vmc_batch_set_launch(b, args.threads)
+        info = vmc.vmc_batch_info(b)
+        streams = info["mode"] == vmc.VMC_BATCH_STREAMS
+        shapes = [vmc.vmc_launch_info(s.handle) for s in systems]
+        nt = [sh["threads"] for sh in shapes] if streams else info["threads"]
         for _ in range(args.warmup):
             vmc.vmc_batch_ctmc_step(b, walkers, S, stream=stream)
         torch.cuda.synchronize()
@@ -267,10 +280,12 @@ def batch_bench(args):
     total_w = Wb * len(names)
     # mixed form with the state in HBM: FP32 R plus its bfloat16 remainder
     rb = 6 if prec == vmc.VMC_MIXED else 8
-    bytes_per_move = sum(2.0 * (s.n_so * s.ne * rb + s.ne * s.ne * 8) * Wb for s in systems)
-    gbs = bytes_per_move * S / (ms * 1e-3) / 1e9
+    in_lds = [streams and sh["state_in_lds"] for sh in shapes]
+    bytes_per_sweep = sum(2.0 * (s.n_so * s.ne * rb + s.ne * s.ne * 8) * Wb * (1 if lds else S)
+                          for s, lds in zip(systems, in_lds))
+    gbs = bytes_per_sweep / (ms * 1e-3) / 1e9
     flagged = sum(int(np.count_nonzero(w.view("status", torch.int32)[:Wb].cpu().numpy() & 1)) for w in walkers)
-    traffic, split = counted_traffic("batch", total_w, S, nt, args.precision)
+    traffic, split = (None, None) if streams else counted_traffic("batch", total_w, S, nt, args.precision)
     cpu = None
     if not args.no_cpu_baseline:
         # the oracle on each system for a third of the time, summed as walker-steps per second of all three
@@ -283,15 +298,16 @@ def batch_bench(args):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64", "data": "synthetic",
-        "config": {"workload": "uneven batch in one launch: H-chain-like 40/80/160 orbitals, half filled, eps=1e-5",
+        "config": {"workload": "uneven batch: H-chain-like 40/80/160 orbitals, half filled, eps=1e-5",
                    "walkers": [Wb] * len(names), "ctmc_moves_per_step": S, "threads": nt,
-                   "precision": args.precision},
+                   "mode": "streams" if streams else "fused", "precision": args.precision},
         "flagged_walkers": flagged,
         ("el_max_abs_err_per_electron" if prec == vmc.VMC_MIXED else "el_max_abs_err_vs_oracle"): el_err,
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs / HBM_PEAK_GBS, "traffic": traffic, "traffic_split": split,
-                     "kernel": "k_sweep_batch (one launch)", "sweep_kernel_ms": ms,
-                     "bytes_per_move_all_walkers": bytes_per_move},
+                     "kernel": ("k_sweep per system, one stream each (time from fork to join)" if streams
+                                else "k_sweep_batch (one launch)"), "sweep_kernel_ms": ms,
+                     "bytes_per_sweep_all_walkers": bytes_per_sweep, "state_in_lds": in_lds},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

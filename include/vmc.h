@@ -437,25 +437,40 @@ vmc_status vmc_destroy(vmc_handle h);
 
 /*
  * Batches: systems of different sizes (each with its own tables, parameters
- * and walker set) swept by ONE kernel launch; workgroups are dealt to the
- * systems in order.  Every system runs the variant that keeps the walker
- * state in its HBM buffers and re-inverts in place every refresh_period
- * moves; the LDS of the launch is sized for the largest system.
+ * and walker set) swept together.  Fused mode (the default): ONE kernel
+ * launch; workgroups are dealt to the systems in order, every system runs the
+ * variant that keeps the walker state in its HBM buffers and re-inverts in
+ * place every refresh_period moves, and the LDS of the launch is sized for
+ * the largest system.  Stream mode: see vmc_batch_set_mode below.
  *
  * vmc_batch_create: 1..8 systems with the same precision whose parameters are
- * set; the batch refers to the handles (which must outlive it) and owns
- * nothing on the device.  walkers[e] is the walker set of systems[e] (already
- * initialised with vmc_walkers_init).  vmc_batch_local_energy and
- * vmc_batch_ctmc_step compute exactly what vmc_local_energy / vmc_ctmc_step
- * (without histories) compute for each system alone with the same launch
- * variant; each walker set's step counter advances by n_steps.
- * vmc_batch_set_launch: workgroup size for the whole batch (64..512).
- * Errors are reported through vmc_last_error(NULL).
+ * set; the batch refers to the handles (which must outlive it) and owns no
+ * device memory (one stream and event per system, for the stream mode).
+ * walkers[e] is the walker set of systems[e] (already initialised with
+ * vmc_walkers_init).  vmc_batch_local_energy and vmc_batch_ctmc_step compute
+ * exactly what vmc_local_energy / vmc_ctmc_step (without histories) compute
+ * for each system alone with the same launch variant; each walker set's step
+ * counter advances by n_steps.  vmc_batch_set_launch: workgroup size of the
+ * fused launch (64..512).  Errors are reported through vmc_last_error(NULL).
  */
 typedef struct vmc_batch_ctx* vmc_batch;
 vmc_status vmc_batch_create(const vmc_handle* systems, int32_t n, vmc_batch* out);
 vmc_status vmc_batch_set_launch(vmc_batch b, int32_t block_threads);
 vmc_status vmc_batch_set_occupancy(vmc_batch b, int32_t waves);
+
+/* How a batch runs (vmc_batch_set_mode; vmc_batch_info: out[0] = mode, out[1]
+ * = workgroup size and out[2] = occupancy target of the fused launch):
+ * VMC_BATCH_FUSED (default): the one launch described above; spin-blocked
+ * systems are refused (VMC_E_UNSUPPORTED) at the call.  VMC_BATCH_STREAMS:
+ * each system's own calls (vmc_ctmc_step / vmc_local_energy, with its own
+ * variant: state in LDS where it fits, its own workgroup size, occupancy and
+ * re-inversion schedule) on a stream of its own, forked from the caller's
+ * stream and joined back to it with events (created at vmc_batch_create), so
+ * the systems run concurrently; any system, spin-blocked ones included.
+ * Results are those of the separate calls, bit for bit. */
+enum { VMC_BATCH_FUSED = 0, VMC_BATCH_STREAMS = 1 };
+vmc_status vmc_batch_set_mode(vmc_batch b, int32_t mode);
+vmc_status vmc_batch_info(vmc_batch b, int64_t out[3]);
 vmc_status vmc_batch_local_energy(vmc_batch b, vmc_walkers* const* walkers, hipStream_t stream);
 vmc_status vmc_batch_ctmc_step(vmc_batch b, vmc_walkers* const* walkers, int32_t n_steps, hipStream_t stream);
 vmc_status vmc_batch_destroy(vmc_batch b);
@@ -463,13 +478,17 @@ vmc_status vmc_batch_destroy(vmc_batch b);
 /*
  * Launch-shape autotuner: times CTMC sweeps of n_moves moves at each
  * workgroup size in {64, 128, 256, 512} threads per walker that fits the LDS
- * budget and, where the walker state stays in HBM (always in a batch), each
- * occupancy target (3 and 4 waves per SIMD) (best of two sweeps each, HIP
+ * budget and, where the walker state stays in HBM (always in a fused batch),
+ * each occupancy target (3 and 4 waves per SIMD) (best of two sweeps each, HIP
  * events on `stream`), keeps the fastest shape (as vmc_set_launch /
  * vmc_set_occupancy or their batch forms would) and returns its workgroup
- * size in *chosen (nullable; vmc_launch_info reports the occupancy).  The
- * timed sweeps are real moves: every walker set advances by 2 * n_moves moves
- * per shape tried (use it as burn-in).  Blocks until the timing is done.
+ * size in *chosen (nullable; vmc_launch_info reports the occupancy).
+ * vmc_batch_autotune also tunes every system on its own (vmc_autotune), times
+ * the batch in VMC_BATCH_STREAMS mode, and keeps the faster mode (*chosen = 0
+ * for the stream mode; vmc_batch_info reports it); spin-blocked systems are
+ * tuned for the stream mode only.  The timed sweeps are real moves: every
+ * walker set advances by 2 * n_moves moves per shape tried (use it as
+ * burn-in).  Blocks until the timing is done.
  */
 vmc_status vmc_autotune(vmc_handle h, vmc_walkers* w, int32_t n_moves, int32_t* chosen, hipStream_t stream);
 vmc_status vmc_batch_autotune(vmc_batch b, vmc_walkers* const* walkers, int32_t n_moves, int32_t* chosen,

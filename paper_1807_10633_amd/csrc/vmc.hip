@@ -3031,6 +3031,12 @@ struct vmc_batch_ctx {
     int nt = 256;
     int precision = 0;
     int waves = 0;  // occupancy target of the sweep kernel (waves per SIMD): 3, 4, or 0 for the library's choice
+    int mode = 0;   // VMC_BATCH_FUSED or VMC_BATCH_STREAMS
+    // VMC_BATCH_STREAMS: one stream per system (default priority), forked from
+    // and joined back to the caller's stream through events
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> done;
+    hipEvent_t fork = nullptr;
 };
 
 namespace {
@@ -3976,11 +3982,17 @@ vmc_status vmc_batch_autotune(vmc_batch b, vmc_walkers* const* walkers, int32_t 
                               hipStream_t st) {
     if (!b) return fail(nullptr, VMC_E_ARG, "batch is NULL");
     if (n_moves < 1) return fail(nullptr, VMC_E_ARG, "n_moves must be >= 1");
-    const int keep = b->nt, keep_w = b->waves;
+    if (!walkers) return fail(nullptr, VMC_E_ARG, "walkers array is NULL");
+    const int keep = b->nt, keep_w = b->waves, keep_m = b->mode;
+    bool fusable = true;
+    for (vmc_ctx* h : b->sys) fusable = fusable && !h->uhf;
+    // the fused launch: every workgroup size and occupancy target
     int best_nt = 0, best_w = 0;
     float best = 3.0e38f;
+    b->mode = VMC_BATCH_FUSED;
     for (int nt : kTuneThreads)
         for (int wv : {3, 4}) {
+            if (!fusable) break;
             size_t lds = 0;
             for (vmc_ctx* h : b->sys)
                 lds = std::max(lds,
@@ -3993,6 +4005,7 @@ vmc_status vmc_batch_autotune(vmc_batch b, vmc_walkers* const* walkers, int32_t 
             if (s != VMC_OK) {
                 b->nt = keep;
                 b->waves = keep_w;
+                b->mode = keep_m;
                 return s;
             }
             if (ms < best) {
@@ -4001,14 +4014,42 @@ vmc_status vmc_batch_autotune(vmc_batch b, vmc_walkers* const* walkers, int32_t 
                 best_w = wv;
             }
         }
-    if (best_nt == 0) {
+    // one stream per system, each with its own autotuned shape
+    for (size_t e = 0; e < b->sys.size(); ++e) {
+        const vmc_status s = vmc_autotune(b->sys[e], walkers[e], n_moves, nullptr, st);
+        if (s != VMC_OK) {
+            b->nt = keep;
+            b->waves = keep_w;
+            b->mode = keep_m;
+            return fail(nullptr, s, "system " + std::to_string(e) + ": " + b->sys[e]->err);
+        }
+    }
+    b->mode = VMC_BATCH_STREAMS;
+    float ms_streams = 0.0f;
+    vmc_status s = time_sweeps(nullptr, nullptr, b, walkers, n_moves, 2, st, &ms_streams);
+    if (s != VMC_OK) {
         b->nt = keep;
         b->waves = keep_w;
-        return fail(nullptr, VMC_E_UNSUPPORTED, "no workgroup size fits the LDS budget");
+        b->mode = keep_m;
+        return s;
     }
-    b->nt = best_nt;
-    b->waves = best_w;
-    if (chosen) *chosen = best_nt;
+    if (best_nt != 0 && best <= ms_streams) {
+        b->mode = VMC_BATCH_FUSED;
+        b->nt = best_nt;
+        b->waves = best_w;
+    } else {
+        b->nt = keep;
+        b->waves = keep_w;
+    }
+    if (chosen) *chosen = b->mode == VMC_BATCH_FUSED ? b->nt : 0;
+    return VMC_OK;
+}
+
+vmc_status vmc_batch_info(vmc_batch b, int64_t out[3]) {
+    if (!b || !out) return fail(nullptr, VMC_E_ARG, "NULL argument");
+    out[0] = b->mode;
+    out[1] = b->nt;
+    out[2] = batch_waves(b);
     return VMC_OK;
 }
 
@@ -4056,12 +4097,32 @@ vmc_status vmc_batch_create(const vmc_handle* systems, int32_t n, vmc_batch* out
         if (systems[e]->precision != systems[0]->precision)
             return fail(nullptr, VMC_E_ARG, "all systems of a batch must have the same precision");
         if (!systems[e]->params_set) return fail(nullptr, VMC_E_ARG, "vmc_set_params has not been called");
-        if (systems[e]->uhf) return fail(nullptr, VMC_E_UNSUPPORTED, "batches hold VMC_GHF systems only");
     }
     vmc_batch_ctx* b = new vmc_batch_ctx;
     b->sys.assign(systems, systems + n);
     b->precision = systems[0]->precision;
+    bool ok = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess;
+    for (int e = 0; e < n && ok; ++e) {
+        hipStream_t s = nullptr;
+        hipEvent_t ev = nullptr;
+        ok = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
+        if (ok) b->streams.push_back(s);
+        ok = ok && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
+        if (ok) b->done.push_back(ev);
+    }
+    if (!ok) {
+        vmc_batch_destroy(b);
+        return fail(nullptr, VMC_E_HIP, "stream or event creation failed");
+    }
     *out = b;
+    return VMC_OK;
+}
+
+vmc_status vmc_batch_set_mode(vmc_batch b, int32_t mode) {
+    if (!b) return fail(nullptr, VMC_E_ARG, "batch is NULL");
+    if (mode != VMC_BATCH_FUSED && mode != VMC_BATCH_STREAMS)
+        return fail(nullptr, VMC_E_ARG, "mode must be VMC_BATCH_FUSED or VMC_BATCH_STREAMS");
+    b->mode = mode;
     return VMC_OK;
 }
 
@@ -4073,9 +4134,43 @@ vmc_status vmc_batch_set_launch(vmc_batch b, int32_t block_threads) {
     return VMC_OK;
 }
 
+// VMC_BATCH_STREAMS: each system's own calls (its own variant, occupancy,
+// workgroup size and re-inversion schedule) on its own stream, forked from st
+// and joined back to it.
+static vmc_status launch_streams(vmc_batch b, vmc_walkers* const* ws, int mode, int n_steps, hipStream_t st) {
+    const int n = (int)b->sys.size();
+    for (int e = 0; e < n; ++e) {
+        vmc_status s = check_walkers(b->sys[e], ws[e]);
+        if (s != VMC_OK) return fail(nullptr, s, "system " + std::to_string(e) + ": " + b->sys[e]->err);
+    }
+    if (hipEventRecord(b->fork, st) != hipSuccess) return fail(nullptr, VMC_E_HIP, "hipEventRecord failed");
+    vmc_status s = VMC_OK;
+    std::string msg;
+    for (int e = 0; e < n && s == VMC_OK; ++e) {
+        if (hipStreamWaitEvent(b->streams[e], b->fork, 0) != hipSuccess) {
+            s = VMC_E_HIP;
+            msg = "hipStreamWaitEvent failed";
+            break;
+        }
+        vmc_ctx* h = b->sys[e];
+        s = (mode == MODE_CTMC) ? vmc_ctmc_step(h, ws[e], n_steps, nullptr, nullptr, nullptr, b->streams[e])
+                                : vmc_local_energy(h, ws[e], b->streams[e]);
+        if (s != VMC_OK) msg = "system " + std::to_string(e) + ": " + h->err;
+        // joined even after a failure, so that st orders after whatever was launched
+        if (hipEventRecord(b->done[e], b->streams[e]) != hipSuccess || hipStreamWaitEvent(st, b->done[e], 0) != hipSuccess) {
+            if (s == VMC_OK) msg = "stream join failed";
+            s = (s == VMC_OK) ? VMC_E_HIP : s;
+        }
+    }
+    return s == VMC_OK ? VMC_OK : fail(nullptr, s, msg);
+}
+
 static vmc_status launch_batch(vmc_batch b, vmc_walkers* const* ws, int mode, int n_steps, hipStream_t st) {
     if (!b) return fail(nullptr, VMC_E_ARG, "batch is NULL");
     if (!ws) return fail(nullptr, VMC_E_ARG, "walkers array is NULL");
+    if (b->mode == VMC_BATCH_STREAMS) return launch_streams(b, ws, mode, n_steps, st);
+    for (vmc_ctx* h : b->sys)
+        if (h->uhf) return fail(nullptr, VMC_E_UNSUPPORTED, "the fused batch holds VMC_GHF systems only");
     BatchArgs A;
     std::memset(&A, 0, sizeof(A));
     A.n = (int)b->sys.size();
@@ -4125,6 +4220,9 @@ vmc_status vmc_batch_ctmc_step(vmc_batch b, vmc_walkers* const* walkers, int32_t
 
 vmc_status vmc_batch_destroy(vmc_batch b) {
     if (!b) return fail(nullptr, VMC_E_ARG, "batch is NULL");
+    for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
+    for (hipEvent_t ev : b->done) (void)hipEventDestroy(ev);
+    if (b->fork) (void)hipEventDestroy(b->fork);
     delete b;
     return VMC_OK;
 }

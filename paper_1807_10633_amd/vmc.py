@@ -34,7 +34,7 @@ EXPORTED = (
     "vmc_batch_autotune", "vmc_ctmc_step_dev", "vmc_walkers_refresh", "vmc_cps_init", "vmc_set_cps", "vmc_cps_info",
     "vmc_ctmc_step_static",
     "vmc_set_small_denominator", "vmc_set_occupancy", "vmc_batch_set_occupancy", "vmc_snapshot_weights",
-    "vmc_logderiv_accumulate", "vmc_gradient_combine",
+    "vmc_logderiv_accumulate", "vmc_gradient_combine", "vmc_batch_set_mode", "vmc_batch_info",
 )
 
 
@@ -96,6 +96,8 @@ def load_library() -> C.CDLL:
         "vmc_logderiv_accumulate": ([P, P, P, P, P], i32),
         "vmc_gradient_combine": ([C.c_int64, P, P, P, P, P], i32),
         "vmc_batch_set_occupancy": ([P, i32], i32),
+        "vmc_batch_set_mode": ([P, i32], i32),
+        "vmc_batch_info": ([P, P], i32),
         "vmc_batch_local_energy": ([P, P, P], i32),
         "vmc_batch_ctmc_step": ([P, P, i32, P], i32),
         "vmc_batch_destroy": ([P], i32),
@@ -370,6 +372,19 @@ def vmc_batch_set_launch(batch, block_threads: int) -> None:
 
 def vmc_batch_set_occupancy(batch, waves: int) -> None:
     _check(load_library().vmc_batch_set_occupancy(batch, int(waves)), None, "vmc_batch_set_occupancy")
+
+
+VMC_BATCH_FUSED, VMC_BATCH_STREAMS = 0, 1
+
+
+def vmc_batch_set_mode(batch, mode: int) -> None:
+    _check(load_library().vmc_batch_set_mode(batch, int(mode)), None, "vmc_batch_set_mode")
+
+
+def vmc_batch_info(batch) -> dict:
+    out = (C.c_int64 * 3)()
+    _check(load_library().vmc_batch_info(batch, out), None, "vmc_batch_info")
+    return {"mode": int(out[0]), "threads": int(out[1]), "waves": int(out[2])}
 
 
 def _walker_array(walkers):

@@ -60,6 +60,6 @@ def test_stepping_entry_points_reach_no_allocation():
         assert not ALLOC.search(funcs[ep]), ep
     # the helpers they launch through
     for helper in ("launch_sweep", "launch_refresh", "launch_batch", "launch_prec", "launch_one", "launch_hbm",
-                   "logderiv_contract"):
+                   "launch_streams", "logderiv_contract"):
         if helper in funcs:
             assert not ALLOC.search(funcs[helper]), helper

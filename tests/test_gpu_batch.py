@@ -3,6 +3,9 @@
 
 * The batch computes exactly what separate per-system launches of the same
   variant compute (bitwise: occupations, E_L, t, picks, B and R).
+* The stream mode (one stream per system, each system with its own variant,
+  spin-blocked systems included) computes exactly what the separate calls
+  compute; the fused mode refuses spin-blocked systems.
 * E_L of sampled walkers of every system against the oracle.
 * The hand-written O_k backward over all parameters of the three systems
   (201,880), contracted with the estimator weights, against the oracle on
@@ -44,7 +47,7 @@ def batch_setup(torch):
 
 
 def _state(torch, sysm, wk):
-    ne, n_so = sysm.ne, sysm.n_so
+    ne, n_so = sysm.ne, sysm.r_row
     return {
         "occ": occ_of(sysm, wk),
         "eloc": field(sysm, wk, "eloc", torch.float64, 1),
@@ -179,9 +182,54 @@ def test_batch_gradient_and_amsgrad_all_parameters(torch, batch_setup):
     np.testing.assert_allclose(p_d.cpu().numpy(), ref, rtol=0, atol=1e-15)
 
 
+def test_batch_stream_mode_equals_separate_calls(torch):
+    """Spin-blocked hubbard8, hchain20 (state in LDS) and hchain80 (state in
+    HBM), 256 walkers each, in VMC_BATCH_STREAMS mode: every field after 4
+    moves and E_L equals what the separate calls leave, bit for bit."""
+    from paper_1807_10633_amd.vmc import (VMC_BATCH_FUSED, VMC_BATCH_STREAMS, VmcError, vmc_batch_create,
+                                          vmc_batch_ctmc_step, vmc_batch_destroy, vmc_batch_info,
+                                          vmc_batch_local_energy, vmc_batch_set_mode, vmc_ctmc_step,
+                                          vmc_launch_info, vmc_local_energy)
+
+    wls = [make_config("hubbard8", n_walkers=256, orbitals="uhf"), make_config("hchain20", n_walkers=256),
+           make_config("hchain80", n_walkers=256)]
+    systems = [gpu_system(wl) for wl in wls]
+    lds = [vmc_launch_info(s.handle)["state_in_lds"] for s in systems]
+    assert lds[1] and not lds[2], lds
+    sep = [s.walkers(wl.occ) for s, wl in zip(systems, wls)]
+    bat = [s.walkers(wl.occ) for s, wl in zip(systems, wls)]
+    for s, wk in zip(systems, sep):
+        vmc_ctmc_step(s.handle, wk, 4)
+        vmc_local_energy(s.handle, wk)
+    b = vmc_batch_create([s.handle for s in systems])
+    try:
+        assert vmc_batch_info(b)["mode"] == VMC_BATCH_FUSED
+        with pytest.raises(VmcError):  # the fused launch holds no spin-blocked system
+            vmc_batch_ctmc_step(b, bat, 1)
+        with pytest.raises(VmcError):
+            vmc_batch_set_mode(b, 7)
+        vmc_batch_set_mode(b, VMC_BATCH_STREAMS)
+        assert vmc_batch_info(b)["mode"] == VMC_BATCH_STREAMS
+        vmc_batch_ctmc_step(b, bat, 4)
+        vmc_batch_local_energy(b, bat)
+    finally:
+        vmc_batch_destroy(b)
+    torch.cuda.synchronize()
+    for wl, s, a, c in zip(wls, systems, sep, bat):
+        assert a.step == c.step == 4
+        sa, sc = _state(torch, s, a), _state(torch, s, c)
+        for k in sa:
+            assert np.array_equal(sa[k], sc[k]), f"{wl.name}: field {k} differs between stream mode and separate calls"
+        el = sc["eloc"][:, 0]
+        orc = OracleSystem.from_workload(wl)
+        r = orc.local_energy(occ_of(s, c)[7], ORC_LEMMA, with_candidates=False)
+        assert abs(el[7] - r["eloc"]) <= el_tol(r["T"]), (wl.name, el[7], r["eloc"])
+        _say(f"    {wl.name}: stream mode == separate calls (4 moves + E_L), mean E_L {np.mean(el):.6f}")
+
+
 def test_batch_autotune(torch):
-    from paper_1807_10633_amd.vmc import (vmc_batch_autotune, vmc_batch_create, vmc_batch_destroy,
-                                          vmc_batch_local_energy)
+    from paper_1807_10633_amd.vmc import (VMC_BATCH_FUSED, VMC_BATCH_STREAMS, vmc_batch_autotune, vmc_batch_create,
+                                          vmc_batch_destroy, vmc_batch_info, vmc_batch_local_energy, vmc_launch_info)
 
     wls = [make_config(n, n_walkers=128) for n in ("hchain40", "hchain80")]
     systems = [gpu_system(wl) for wl in wls]
@@ -189,15 +237,23 @@ def test_batch_autotune(torch):
     b = vmc_batch_create([s.handle for s in systems])
     try:
         nt = vmc_batch_autotune(b, wks, 2)
+        info = vmc_batch_info(b)
         vmc_batch_local_energy(b, wks)
     finally:
         vmc_batch_destroy(b)
     torch.cuda.synchronize()
-    assert nt in (64, 128, 256, 512)
+    if nt == 0:
+        assert info["mode"] == VMC_BATCH_STREAMS
+    else:
+        assert info["mode"] == VMC_BATCH_FUSED and info["threads"] == nt and nt in (64, 128, 256, 512)
     for wl, s, wk in zip(wls, systems, wks):
-        assert wk.step == 32  # 4 workgroup sizes x 2 occupancy targets x 2 timed sweeps x 2 moves
+        # 2 timed sweeps of 2 moves per shape: 8 fused shapes, then the
+        # system's own shapes (4, or 8 with the occupancy targets where the
+        # state stays in HBM), then the stream mode once
+        own = 4 if vmc_launch_info(s.handle)["state_in_lds"] else 8
+        assert wk.step == 4 * (8 + own + 1), (wl.name, wk.step)
         el = field(s, wk, "eloc", torch.float64, 1)[:, 0]
         orc = OracleSystem.from_workload(wl)
         r = orc.local_energy(occ_of(s, wk)[5], ORC_LEMMA, with_candidates=False)
         assert abs(el[5] - r["eloc"]) <= el_tol(r["T"])
-    _say(f"    batch autotuned workgroup: {nt}")
+    _say(f"    batch autotune: mode {info['mode']}, workgroup {info['threads']}, waves {info['waves']}")

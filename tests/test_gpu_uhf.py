@@ -327,10 +327,21 @@ def test_uhf_excitation_lists(torch, name, nw):
         assert np.allclose(np.abs(r), np.abs(ref["ratio"]), rtol=1e-10, atol=1e-13 * scale)
 
 
-def test_uhf_systems_are_not_batched(torch):
-    from paper_1807_10633_amd.vmc import VmcError, vmc_batch_create
+def test_uhf_systems_batch_in_stream_mode_only(torch):
+    from paper_1807_10633_amd.vmc import (VMC_BATCH_STREAMS, VmcError, vmc_batch_create, vmc_batch_ctmc_step,
+                                          vmc_batch_destroy, vmc_batch_set_mode)
 
     wl = _uhf("hubbard8", 8)
     sysm = gpu_system(wl)
-    with pytest.raises(VmcError):
-        vmc_batch_create([sysm.handle])
+    wk = sysm.walkers(wl.occ)
+    b = vmc_batch_create([sysm.handle])
+    try:
+        with pytest.raises(VmcError):  # the fused launch is for the general form only
+            vmc_batch_ctmc_step(b, [wk], 1)
+        assert wk.step == 0
+        vmc_batch_set_mode(b, VMC_BATCH_STREAMS)
+        vmc_batch_ctmc_step(b, [wk], 2)
+    finally:
+        vmc_batch_destroy(b)
+    torch.cuda.synchronize()
+    assert wk.step == 2
