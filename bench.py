@@ -236,10 +236,11 @@ def batch_bench(args):
     timer = HipTimer(stream)
     try:
         # burn-in from the random initial determinants, then the launch shapes
-        # and the mode are tuned on equilibrated walkers with sweeps of 10 moves
+        # and the mode are tuned on equilibrated walkers with sweeps as long
+        # as the timed ones
         vmc.vmc_batch_ctmc_step(b, walkers, 100, stream=stream)
         if args.batch_mode != "fused" or not args.threads:
-            vmc.vmc_batch_autotune(b, walkers, 10)
+            vmc.vmc_batch_autotune(b, walkers, S)
         if args.batch_mode != "auto":
             vmc.vmc_batch_set_mode(b, vmc.VMC_BATCH_STREAMS if args.batch_mode == "streams" else vmc.VMC_BATCH_FUSED)
         if args.threads:
@@ -352,12 +353,14 @@ def main():
         walkers = sysm.walkers(wl.occ)
         # burn-in of the walkers (not timed, not counted), then the launch
         # shape: the project autotuner times sweeps of equilibrated walkers
-        # at every workgroup size and occupancy target (more burn-in)
+        # at every workgroup size and occupancy target (more burn-in), each
+        # as long as the timed ones, since a launch also carries a fixed
+        # set-up cost that depends on the shape
         vmc.vmc_ctmc_step(sysm.handle, walkers, 100, stream=stream)
         if args.threads:
             vmc.vmc_set_launch(sysm.handle, args.threads)
         else:
-            vmc.vmc_autotune(sysm.handle, walkers, 10)
+            vmc.vmc_autotune(sysm.handle, walkers, S)
         npar = sysm.n_params
         params = sysm.param_vector().clone()
         m = torch.zeros_like(params)

@@ -488,7 +488,10 @@ vmc_status vmc_batch_destroy(vmc_batch b);
  * for the stream mode; vmc_batch_info reports it); spin-blocked systems are
  * tuned for the stream mode only.  The timed sweeps are real moves: every
  * walker set advances by 2 * n_moves moves per shape tried (use it as
- * burn-in).  Blocks until the timing is done.
+ * burn-in).  Pass the number of moves per call that will be run: a launch
+ * carries a fixed set-up cost (the first evaluation of every candidate) that
+ * depends on the shape, so short timed sweeps can favour another shape than
+ * long ones.  Blocks until the timing is done.
  */
 vmc_status vmc_autotune(vmc_handle h, vmc_walkers* w, int32_t n_moves, int32_t* chosen, hipStream_t stream);
 vmc_status vmc_batch_autotune(vmc_batch b, vmc_walkers* const* walkers, int32_t n_moves, int32_t* chosen,

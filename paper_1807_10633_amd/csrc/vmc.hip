@@ -217,8 +217,8 @@ constexpr int kUnroll = 6;  // 64-entry chunks whose table loads are issued toge
 
 struct Lds {
     uint32_t occw, occl, slot, oslot, s, es, ies, red, stmp, mi, md, wst, wtot, q64, qab, lsum, loff, lg, sgend, sdelta,
-        svend, spq, sfac, dgend, ddelta, dvend, dpq, dfac, w1, w2, cRp, cRq, cBp, cBq, ipiv, dblk, fcol, cidx, cinv, R, B, Rh,
-        thl, total;
+        svend, spq, sfac, dgend, ddelta, dvend, dpq, dfac, w1, w2, cRp, cRq, cBp, cBq, ipiv, dblk, fcol, cidx, cinv, mark, R,
+        B, Rh, thl, total;
 };
 __host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~(size_t)15; }
 // Doubles of the layout with the walker state in HBM run over tiles of
@@ -267,6 +267,8 @@ __host__ __device__ __forceinline__ Lds lds_layout(int n_so, int ne, int nw, int
     L.fcol = take((size_t)ne * 8);
     L.cidx = take((size_t)ncorr * 4);
     L.cinv = take((size_t)ncorr * 8);
+    // state in HBM: per wave, the marker bytes of pair_tiles' row lookup
+    L.mark = small ? 0u : take((size_t)nwv * kUnroll * 64);
     if (small) {
         L.dgend = take(gd * 4);
         L.ddelta = take(gd * 4);
@@ -1250,16 +1252,19 @@ __device__ __forceinline__ bool stream_pass(const Tab& T, const StepView<RT>& V,
 // tile instead of fetched once per pair.  The lanes hold the table rows of
 // four of the wave's segments at a time (pair p of segment s in lane 16 s + p,
 // then the rows with entries moved to the lowest lanes); their entries form
-// one unpadded stream, cut into 64-entry chunks whose lanes find their row by
-// walking the few rows a chunk spans with wave-uniform row data, so that the
-// table loads of several rows and segments go out together.  Survivors
-// queue and are evaluated 64 at a time as in stream_pass; the queue keeps
-// processing order, so each segment's survivors form one run of lanes.
+// one unpadded stream, cut into 64-entry chunks, so that the table loads of
+// several rows and segments go out together.  A lane finds its row in
+// constant time: the rows starting inside the chunk set one marker byte each
+// in LDS, and the lane counts the markers below it (one ballot, one mbcnt).
+// An entry survives when both its target orbitals are empty (their slots are
+// -1).  Survivors queue and are evaluated 64 at a time as in stream_pass; the
+// queue keeps processing order, so each segment's survivors form one run of
+// lanes.
 // ELOC: E_L terms into `el`, rate sums per segment (segments without
 // survivors keep the zero written before).  PICK: segment (px, py) only,
 // running sum from `base`, pick as stream_pass.
 template <bool PICK, bool UHF, typename RT>
-__device__ __forceinline__ bool pair_tiles(const Tab& T, const StepView<RT>& V, const uint64_t* occw, const int* oslot,
+__device__ __forceinline__ bool pair_tiles(const Tab& T, const StepView<RT>& V, const int* oslot, uint8_t* mark,
                                            uint64_t* q64, uint64_t* qab, double& el, double* segsum, int px, int py,
                                            double base, double target, bool fallback, int* pick) {
     constexpr int kSegs = kWave / kPairBlock;  // segments held by the lanes at once
@@ -1274,6 +1279,9 @@ __device__ __forceinline__ bool pair_tiles(const Tab& T, const StepView<RT>& V, 
     uint64_t last_ab = 0;
     int cur_s = -1;  // ELOC: the open segment and its rate sum so far (wave-uniform)
     double cur_sum = 0.0;
+    // the wave's marker bytes (kUnroll x 64) are zero between uses
+    for (int k = l; k < kUnroll * kWave / 4; k += kWave) ((uint32_t*)mark)[k] = 0u;
+    wave_lds_sync();
 
     auto batch = [&](int k) __attribute__((always_inline)) -> bool {
         wave_lds_sync();
@@ -1374,8 +1382,8 @@ __device__ __forceinline__ bool pair_tiles(const Tab& T, const StepView<RT>& V, 
         for (int k = 1; k < kSegs; ++k)
             if (sl == k) { x = sx[k]; yb = sy[k]; }
         // lane (16 s + p): the table row of pair p of segment s, its slots
-        // (10 bits each) and s
-        uint32_t b0 = 0, len = 0, pk = 0;
+        // (16 bits each) and the segment's index
+        uint32_t b0 = 0, len = 0, pk = 0, sg = 0;
         if (sl < nseg) {
             const int y = max(x + 1, yb * kPairBlock) + pl;
             if (y < min(ne, (yb + 1) * kPairBlock)) {
@@ -1383,7 +1391,8 @@ __device__ __forceinline__ bool pair_tiles(const Tab& T, const StepView<RT>& V, 
                 const int row = i * n_so + j;
                 b0 = T.row_off[row];
                 len = T.row_off[row + 1] - b0;
-                pk = (uint32_t)oslot[i] | ((uint32_t)oslot[j] << 10) | ((uint32_t)sl << 20);
+                pk = (uint32_t)oslot[i] | ((uint32_t)oslot[j] << 16);
+                sg = (uint32_t)(x * nb + yb);
             }
         }
         // rows with entries moved to the lowest lanes, in order (a forward
@@ -1395,31 +1404,41 @@ __device__ __forceinline__ bool pair_tiles(const Tab& T, const StepView<RT>& V, 
         b0 = (uint32_t)__builtin_amdgcn_ds_permute(dst << 2, (int)b0);
         len = (uint32_t)__builtin_amdgcn_ds_permute(dst << 2, (int)len);
         pk = (uint32_t)__builtin_amdgcn_ds_permute(dst << 2, (int)pk);
+        sg = (uint32_t)__builtin_amdgcn_ds_permute(dst << 2, (int)sg);
         const uint32_t end = wave_scan_u32(len);
         const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)end, nrows - 1);
+        const uint32_t start = end - len;  // = tot in the lanes past the last row
         for (uint32_t c = 0; c < tot && !found; c += kUnroll * kWave) {
-            uint32_t off[kUnroll], pkv[kUnroll], abv[kUnroll];
+            uint32_t off[kUnroll], pkv[kUnroll], sgv[kUnroll], abv[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
                 const uint32_t cu = c + (uint32_t)(u * kWave), pos = cu + (uint32_t)l;
                 off[u] = 0;  // entry 0 stands in for lanes without a candidate
                 pkv[u] = 0;
+                sgv[u] = 0;
                 if (cu < tot) {
-                    // the rows this chunk spans, walked with wave-uniform row
-                    // data; bit 31 of pkv marks a lane with a candidate
-                    int k = (int)uni((uint32_t)(__ffsll((unsigned long long)__ballot(end > cu)) - 1));
-                    uint32_t sk = k > 0 ? (uint32_t)__builtin_amdgcn_readlane((int)end, k - 1) : 0u;
-                    while (true) {
-                        const uint32_t ek = (uint32_t)__builtin_amdgcn_readlane((int)end, k);
-                        const uint32_t bk = (uint32_t)__builtin_amdgcn_readlane((int)b0, k);
-                        const uint32_t qk = (uint32_t)__builtin_amdgcn_readlane((int)pk, k);
-                        if (pos >= sk && pos < ek) {
-                            off[u] = bk + (pos - sk);
-                            pkv[u] = qk | 0x80000000u;
-                        }
-                        if (ek >= cu + (uint32_t)kWave || k == nrows - 1) break;
-                        sk = ek;
-                        ++k;
+                    // the row of each lane's position: the row holding cu
+                    // (the rows starting at or before it, less one) plus the
+                    // rows starting in cu+1 .. pos, found from one marker
+                    // byte per row start in this chunk; its data comes from
+                    // the row's lane.  Bit 31 of pkv marks a candidate.
+                    const int k0 = __popcll(__ballot(start <= cu)) - 1;
+                    uint8_t* mk = mark + u * kWave;
+                    const uint32_t rel = start - cu;
+                    if (l < nrows && rel - 1u < (uint32_t)(kWave - 1)) mk[rel] = 1;
+                    wave_lds_sync();
+                    const uint64_t sm = __ballot(mk[l] != 0);
+                    mk[l] = 0;
+                    wave_lds_sync();
+                    const int src = (k0 + (int)mask_below(sm >> 1)) << 2;
+                    const uint32_t rb0 = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)b0);
+                    const uint32_t rst = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)start);
+                    const uint32_t rpk = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)pk);
+                    const uint32_t rsg = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)sg);
+                    if (pos < tot) {
+                        off[u] = rb0 + (pos - rst);
+                        pkv[u] = rpk | 0x80000000u;
+                        sgv[u] = rsg;
                     }
                 }
             }
@@ -1427,20 +1446,15 @@ __device__ __forceinline__ bool pair_tiles(const Tab& T, const StepView<RT>& V, 
             for (int u = 0; u < kUnroll; ++u) abv[u] = T.dab[off[u]];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
+                // both target orbitals empty: both their slots are -1, so the
+                // sign bit of their AND, and with it the candidate bit, stays
                 const uint32_t a = abv[u] & 0xFFFFu, b = abv[u] >> 16;
-                const bool surv = (pkv[u] >> 31) && !found && !((occw[a >> 6] >> (a & 63)) & 1ull) &&
-                                  !((occw[b >> 6] >> (b & 63)) & 1ull);
+                const bool surv = ((int)(pkv[u] & (uint32_t)(oslot[a] & oslot[b])) < 0) && !found;
                 const uint64_t m = __ballot(surv);
                 if (surv) {
                     const uint32_t sq = (qh + qn + mask_below(m)) & (kQueue - 1);
-                    const int sg = (int)((pkv[u] >> 20) & 3u);
-                    int gx = sx[0], gy = sy[0];
-#pragma unroll
-                    for (int k2 = 1; k2 < kSegs; ++k2)
-                        if (sg == k2) { gx = sx[k2]; gy = sy[k2]; }
-                    const uint32_t rpq = (pkv[u] & 0x3FFu) | (((pkv[u] >> 10) & 0x3FFu) << 16);
-                    q64[sq] = (uint64_t)off[u] | ((uint64_t)(uint32_t)(gx * nb + gy) << 32);
-                    qab[sq] = (uint64_t)abv[u] | ((uint64_t)rpq << 32);
+                    q64[sq] = (uint64_t)off[u] | ((uint64_t)sgv[u] << 32);
+                    qab[sq] = (uint64_t)abv[u] | ((uint64_t)(pkv[u] & 0x7FFFFFFFu) << 32);
                 }
                 qn += (uint32_t)__popcll(m);
                 if (qn >= (uint32_t)kWave) {
@@ -1545,6 +1559,7 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
     int* wst = (int*)(smem + L.wst);
     uint64_t* q64 = (uint64_t*)(smem + L.q64) + wv * kQueue;
     uint64_t* qab = (uint64_t*)(smem + L.qab) + wv * kQueue;
+    uint8_t* mark = smem + L.mark + (size_t)wv * kUnroll * kWave;
     double* wtot = (double*)(smem + L.wtot);
     double* lsum = (double*)(smem + L.lsum);
     uint32_t* loff = (uint32_t*)(smem + L.loff);
@@ -1805,7 +1820,7 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
                 stream_pass<true, false, NW1, SMALL, UHF>(T, V, occ0, occw, r0d, r1d, g0, (uint32_t)gd, r0d, q64, qab, el_lane, lsum + lb + kLogS, loff + lb + kLogS, lg + lb + kLogS, kLogD, nd, 0.0, 0.0, false, nullptr);
             }
             if (!SMALL && gd > 0)
-                pair_tiles<false, UHF>(T, V, occw, oslot, q64, qab, el_lane, segsum, 0, 0, 0.0, 0.0, false, nullptr);
+                pair_tiles<false, UHF>(T, V, oslot, mark, q64, qab, el_lane, segsum, 0, 0, 0.0, 0.0, false, nullptr);
             // per-wave inclusive prefix sums of the two logs and their totals
             const double ts = log_prefix(lsum + lb, ns), td = log_prefix(lsum + lb + kLogS, nd);
             if (l == 0) {
@@ -1946,7 +1961,7 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
                 const int fx = (int)uni((uint32_t)mi[MI_FW]), fy = (int)uni((uint32_t)mi[MI_FK]);
                 const bool fb = uni((uint32_t)mi[MI_FFB]) != 0;
                 double dummy = 0.0;
-                pair_tiles<true, UHF>(T, V, occw, oslot, q64, qab, dummy, nullptr, fx, fy, md[MD_BASE], md[MD_TARGET],
+                pair_tiles<true, UHF>(T, V, oslot, mark, q64, qab, dummy, nullptr, fx, fy, md[MD_BASE], md[MD_TARGET],
                                       fb, mi + MI_PTYPE);
             } else if (wv == 0) {
                 const int fs = (int)uni((uint32_t)mi[MI_FS]), fw = (int)uni((uint32_t)mi[MI_FW]);
