@@ -125,6 +125,9 @@ def parse():
                     help="hchain160 (default), hchain20, hubbard8, hubbard10x10, hchain40, hchain80, or batch "
                          "(40/80/160 orbitals swept together)")
     ap.add_argument("--threads", type=int, default=0, help="workgroup size of the sweep kernel (0 = autotuned)")
+    ap.add_argument("--waves", type=int, default=0,
+                    help="with --threads: occupancy target of the HBM-layout sweep, 3 or 4 waves per SIMD "
+                         "(0 = the library's choice)")
     ap.add_argument("--batch-mode", choices=("auto", "fused", "streams"), default="auto",
                     help="batch: one fused launch, one stream per system, or the faster of the two (autotuned)")
     ap.add_argument("--eps", type=float, default=None, help="screening threshold (default: the workload's own)")
@@ -245,6 +248,7 @@ def batch_bench(args):
             vmc.vmc_batch_set_mode(b, vmc.VMC_BATCH_STREAMS if args.batch_mode == "streams" else vmc.VMC_BATCH_FUSED)
         if args.threads:
             vmc.vmc_batch_set_launch(b, args.threads)
+            vmc.vmc_batch_set_occupancy(b, args.waves)
         info = vmc.vmc_batch_info(b)
         streams = info["mode"] == vmc.VMC_BATCH_STREAMS
         shapes = [vmc.vmc_launch_info(s.handle) for s in systems]
@@ -359,6 +363,7 @@ def main():
         vmc.vmc_ctmc_step(sysm.handle, walkers, 100, stream=stream)
         if args.threads:
             vmc.vmc_set_launch(sysm.handle, args.threads)
+            vmc.vmc_set_occupancy(sysm.handle, args.waves)
         else:
             vmc.vmc_autotune(sysm.handle, walkers, S)
         npar = sysm.n_params

@@ -137,7 +137,14 @@ enum {
     VMC_F_TRES,      /* double [W]         last residence time t = 1/T (0 when T = 0) */
     VMC_F_PICK,      /* int64  [W]         last move, packed (see vmc_decode_pick) */
     VMC_F_STATUS,    /* uint32 [W]         VMC_ST_* bits, cleared by vmc_walkers_init */
-    VMC_F_SCRATCH,   /* bytes  [W][...]    kernel scratch; contents undefined between calls */
+    VMC_F_SCRATCH,   /* bytes  [W][...]    kernel scratch, the library's between calls: with the
+                        walker state in HBM it keeps each walker's singles elements
+                        H_ia = h_ia + sum_j V_ia[j] with a tag naming the occupation and
+                        the system they were built for, and a launch whose walker matches
+                        the tag reuses them instead of rebuilding them (rebuilt at least
+                        every 4096 moves, which bounds the rounding of the per-move
+                        updates).  Callers do not
+                        write it, except to fill it with zeros (which clears every tag) */
     VMC_NFIELDS
 };
 

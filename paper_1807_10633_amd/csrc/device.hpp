@@ -23,6 +23,8 @@ struct Tab {
     double eps;
     double small_den;         // Sherman-Morrison denominators below this in magnitude flag the walker (and
                               // re-invert it after the move where the sweep re-inverts in place)
+    uint64_t ham_id;          // identifies this system's Hamiltonian tables (never 0) in the scratch's
+                              // singles-element tag
     const uint32_t* row_off;  // n_so*n_so + 1
     const uint32_t* dab;      // a | b << 16
     const uint64_t* dmask;    // (1 << a) | (1 << b) per doubles entry when n_so <= 64, else null

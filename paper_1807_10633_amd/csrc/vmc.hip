@@ -28,6 +28,7 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <random>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -287,16 +288,25 @@ __host__ __device__ __forceinline__ Lds lds_layout(int n_so, int ne, int nw, int
     return L;
 }
 // per-walker global scratch (walker state in HBM): the rate sums of the
-// doubles' pair segments (Ne x pair_blocks(Ne)), followed, when the singles
-// carry Coulomb-exchange vectors, by the walker's Fock-like singles elements
-// (one double per singles-table entry)
-__host__ __device__ inline size_t scratch_fock_offset(int ne) { return al16((size_t)ne * pair_blocks(ne) * 8 + 16); }
-__host__ __device__ inline size_t scratch_layout_bytes(int ne, int64_t n_fock) {
-    return scratch_fock_offset(ne) + (size_t)n_fock * 8;
+// doubles' pair segments (Ne x pair_blocks(Ne)), then the tag of the singles
+// elements (the nw occupation words they hold, the Hamiltonian's id (0: none)
+// and the moves applied to them since they were last built), followed, when
+// the singles carry Coulomb-exchange vectors, by the walker's Fock-like
+// singles elements (one double per singles-table entry).  The elements depend
+// on the occupation and the Hamiltonian only, so a launch whose walker matches
+// the tag reuses them; they are rebuilt after kFockRebuild moves so that the
+// rounding of the per-move updates stays bounded.
+constexpr uint64_t kFockRebuild = 4096;
+__host__ __device__ inline size_t scratch_tag_offset(int ne) { return al16((size_t)ne * pair_blocks(ne) * 8 + 16); }
+__host__ __device__ inline size_t scratch_fock_offset(int ne, int nw) {
+    return scratch_tag_offset(ne) + al16((size_t)(nw + 2) * 8);
+}
+__host__ __device__ inline size_t scratch_layout_bytes(int ne, int nw, int64_t n_fock) {
+    return scratch_fock_offset(ne, nw) + (size_t)n_fock * 8;
 }
 
 // misc int slots
-enum { MI_ST = 0, MI_PIV, MI_PTYPE, MI_PP, MI_PQ, MI_PA, MI_PB, MI_FS, MI_FW, MI_FK, MI_FFB, MI_SDNOW, MI_WAVE = 32 };
+enum { MI_ST = 0, MI_PIV, MI_PTYPE, MI_PP, MI_PQ, MI_PA, MI_PB, MI_FS, MI_FW, MI_FK, MI_FFB, MI_SDNOW, MI_FTAG, MI_WAVE = 32 };
 enum { MD_T = 0, MD_BASE, MD_EL, MD_HNN, MD_TARGET, MD_C00, MD_C01, MD_C10, MD_C11 };
 // per-wave state: entries of the two batch logs and the stream ranges
 enum { WS_NS = 0, WS_R1S = 3, WS_ND = 4, WS_R1D = 7 };
@@ -416,6 +426,26 @@ __device__ __forceinline__ void r_gemm_theta_regs(const Tab& T, const double* B,
     }
 }
 
+// Row and column of the vector index vi = r * cv + c, stepped by a fixed
+// stride with one division at set-up instead of one per step.
+struct VecCursor {
+    int r, c, dr, dc, cv;
+    __device__ __forceinline__ VecCursor(int vi, int stride, int cv_) : cv(cv_) {
+        r = vi / cv_;
+        c = vi - r * cv_;
+        dr = stride / cv_;
+        dc = stride - dr * cv_;
+    }
+    __device__ __forceinline__ void advance() {
+        r += dr;
+        c += dc;
+        if (c >= cv) {
+            c -= cv;
+            ++r;
+        }
+    }
+};
+
 // M[r][c] -= c1[c] r1[r] (+ c2[c] r2[r]) over rows x cols, by the whole block,
 // arithmetic in FP64.  Rows are contiguous; when they split into 16-byte
 // vectors each thread keeps four vector loads in flight (the update is a
@@ -432,18 +462,23 @@ __device__ __forceinline__ void rank_update(E* M, int rows, int cols, const doub
     if ((cols % V) == 0 && (((uintptr_t)M) & 15) == 0) {
         const int cv = cols / V, nv = rows * cv;
         Vec* Mv = (Vec*)M;
+        VecCursor cur(tid, nt, cv);
         for (int v0 = tid; v0 < nv; v0 += nt * U) {
             Vec val[U];
+            int rr[U], cc[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int vi = v0 + u * nt;
+                rr[u] = cur.r;
+                cc[u] = cur.c * V;
+                cur.advance();
                 if (vi < nv) val[u] = Mv[vi];
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int vi = v0 + u * nt;
                 if (vi < nv) {
-                    const int r = vi / cv, c = (vi - r * cv) * V;
+                    const int r = rr[u], c = cc[u];
                     const double a1 = r1[r], a2 = TWO ? r2[r] : 0.0;
 #pragma unroll
                     for (int j = 0; j < V; ++j) {
@@ -542,21 +577,23 @@ __device__ __forceinline__ void rank_update_ld(double* M, int rows, int cols, in
     if ((cols & 1) == 0 && (ld & 1) == 0 && (((uintptr_t)M) & 15) == 0) {
         // 16-byte vectors, four loads in flight per thread as in rank_update
         const int cv = cols >> 1, nv = rows * cv;
+        VecCursor cur(tid, nt, cv);
         for (int v0 = tid; v0 < nv; v0 += nt * U) {
             double2 val[U];
+            int rr[U], cc[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int vi = v0 + u * nt;
-                if (vi < nv) {
-                    const int r = vi / cv, c = (vi - r * cv) * 2;
-                    val[u] = *(const double2*)(M + (size_t)r * ld + c);
-                }
+                rr[u] = cur.r;
+                cc[u] = cur.c * 2;
+                cur.advance();
+                if (vi < nv) val[u] = *(const double2*)(M + (size_t)rr[u] * ld + cc[u]);
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int vi = v0 + u * nt;
                 if (vi < nv) {
-                    const int r = vi / cv, c = (vi - r * cv) * 2;
+                    const int r = rr[u], c = cc[u];
                     const double a1 = r1[r], a2 = TWO ? r2[r] : 0.0;
                     double d0 = c1[c] * a1, d1 = c1[c + 1] * a1;
                     if (TWO) {
@@ -729,11 +766,18 @@ __device__ __forceinline__ uint32_t wave_scan_u32(uint32_t x) {
 }
 
 // Data-parallel-primitive move of a double (both halves), reading 0 where the
-// row mask disables the destination.
+// row mask disables the destination.  With every row enabled each lane is
+// written, so no zero needs to be placed in the destination first.
 template <int CTRL, int ROW_MASK = 0xF>
 __device__ __forceinline__ double dpp_d(double x) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROW_MASK, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROW_MASK, 0xF, false);
+    int lo, hi;
+    if constexpr (ROW_MASK == 0xF) {
+        lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, false);
+        hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, false);
+    } else {
+        lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROW_MASK, 0xF, false);
+        hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROW_MASK, 0xF, false);
+    }
     return __hiloint2double(hi, lo);
 }
 // Sum over the 64 lanes in a fixed order (quads, rows of 16, then row
@@ -1300,10 +1344,12 @@ __device__ __forceinline__ bool pair_tiles(const Tab& T, const StepView<RT>& V, 
             el += term;
             uint64_t rem = __ballot(act);
             while (rem) {
+                // lanes without a candidate hold r = 0 and never enter rem
                 const int fl = __ffsll((unsigned long long)rem) - 1;
                 const int s0 = __builtin_amdgcn_readlane((int)sg, fl);
-                const uint64_t m = __ballot(act && (int)sg == s0);
-                const double part = wave_total(((m >> l) & 1ull) ? r : 0.0);
+                const bool in = (int)sg == s0;
+                const uint64_t m = __ballot(in);
+                const double part = wave_total(in ? r : 0.0);
                 if (s0 != cur_s) {
                     if (cur_s >= 0 && l == 0) segsum[cur_s] = cur_sum;
                     cur_s = s0;
@@ -1589,6 +1635,7 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
     uint16_t* Rlo = nullptr;
     double* B;
     double* Fk = nullptr;      // the walker's Fock-like singles elements (state in HBM, Coulomb-exchange vectors)
+    uint64_t* ftag = nullptr;  // their tag: the occupation words they hold, the Hamiltonian's id, moves since built
     double* segsum = nullptr;  // rate sums of the doubles' pair segments (state in HBM)
     uint32_t *dgend = nullptr, *ddelta = nullptr, *dvend = nullptr, *dpq = nullptr;
     const int npb = pair_blocks(ne);
@@ -1606,7 +1653,10 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
         B = S.B + (size_t)w * ne * ne;
         Rh = R;
         uint8_t* sc = S.scratch + (size_t)w * S.scratch_stride;
-        if (T.has_sV && T.fock) Fk = (double*)(sc + scratch_fock_offset(ne));
+        if (T.has_sV && T.fock) {
+            Fk = (double*)(sc + scratch_fock_offset(ne, nw));
+            ftag = (uint64_t*)(sc + scratch_tag_offset(ne));
+        }
         segsum = (double*)sc;
     }
     const StepView<RT> V{occl, es,   SMALL ? Rh : R, sgend, sdelta, svend, spq, sfac, dgend, ddelta, dvend, dpq, ies,
@@ -1689,7 +1739,9 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
     const int steps = (mode == MODE_CTMC) ? n_steps : 1;
     double el_last = 0.0, t_last = 0.0;
     int64_t code_last = 0;
-    bool moved = false;  // block-uniform: some move changed the state
+    bool moved = false;     // block-uniform: some move changed the state
+    bool fock_ok = false;   // block-uniform: Fk holds the elements of the current occupation
+    uint64_t fock_moves = 0;  // thread 0: moves applied to Fk since it was built
     for (int k = 0; k < steps && mode != MODE_INIT; ++k) {
         const uint64_t gstep = step0 + (uint64_t)k;
         const bool singular = (mi[MI_ST] & (int)VMC_ST_SINGULAR) != 0;
@@ -1794,11 +1846,25 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
         }
         __syncthreads();
 
-        // Fock-like singles elements of the occupied rows, from scratch at the
-        // first move of the launch, updated after every move below
-        if (Fk && k == 0 && !singular) {
-            fock_rows(T, Fk, occl, ne, occl, ne);
+        // Fock-like singles elements of the occupied rows: kept from the
+        // previous launch when its tag names this occupation and Hamiltonian,
+        // else built here; updated after every move below.  The tag is
+        // cleared first and written back at the end only if the elements are
+        // then current.
+        if (Fk && k == 0) {
+            if (tid == 0) {
+                bool same = ftag[nw] == T.ham_id && ftag[nw + 1] < kFockRebuild;
+                for (int q = 0; q < nw; ++q) same = same && ftag[q] == occw[q];
+                mi[MI_FTAG] = same ? 1 : 0;
+                fock_moves = same ? ftag[nw + 1] : 0ull;
+                ftag[nw] = 0ull;
+            }
             __syncthreads();
+            if (!singular) {
+                if (!mi[MI_FTAG]) fock_rows(T, Fk, occl, ne, occl, ne);
+                fock_ok = true;
+                __syncthreads();
+            }
         }
         // ------------------------------------------------- local energy
         double el_lane = 0.0;
@@ -2163,6 +2229,7 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
             moved = true;
             __syncthreads();
             if (Fk) fock_move(T, Fk, slot, ne, i, ptype == 2 ? j : -1, a, ptype == 2 ? b : -1);
+            ++fock_moves;
         }
         if (tid == 0) {
             if (eloc_hist) eloc_hist[(size_t)k * W + w] = el;
@@ -2201,6 +2268,11 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
         }
     }
     if (tid == 0) {
+        if (fock_ok) {
+            for (int q = 0; q < nw; ++q) ftag[q] = occw[q];
+            ftag[nw] = T.ham_id;
+            ftag[nw + 1] = fock_moves;
+        }
         S.hnn[w] = md[MD_HNN];
         // walkers re-inverted by the separate refresh kernel carry updates
         // since their last inversion once they have moved
@@ -3021,6 +3093,7 @@ struct vmc_ctx {
     bool has_sV = true;
     bool fock = true;  // singles elements kept per walker (see Tab::fock)
     double small_den = 1e-8;  // see Tab::small_den
+    uint64_t ham_id = 0;      // see Tab::ham_id
     int waves = 0;            // occupancy target of the HBM-layout sweep: 3, 4 waves per SIMD, or 0 (library's choice)
     uint32_t *d_row_off = nullptr, *d_dab = nullptr, *d_s_off = nullptr, *d_sa = nullptr;
     uint64_t* d_dmask = nullptr;
@@ -3092,6 +3165,7 @@ Tab make_tab(const vmc_ctx* h) {
     T.has_sV = h->has_sV ? 1 : 0;
     T.fock = (h->has_sV && h->fock) ? 1 : 0;
     T.small_den = h->small_den;
+    T.ham_id = h->ham_id;
     T.sK = h->d_sK;
     T.D = h->d_D;
     T.hdiag = h->d_hdiag;
@@ -3108,7 +3182,7 @@ Tab make_tab(const vmc_ctx* h) {
 
 // the Fock-like elements are sized whatever the launch shape, so that a later
 // vmc_set_launch cannot outgrow walkers allocated before it
-int64_t scratch_bytes(const vmc_ctx* h) { return (int64_t)scratch_layout_bytes(h->ne, h->has_sV ? h->n_sent : 0); }
+int64_t scratch_bytes(const vmc_ctx* h) { return (int64_t)scratch_layout_bytes(h->ne, h->nw, h->has_sV ? h->n_sent : 0); }
 
 // bytes per element of R: FP64 form 8, mixed form 4
 size_t r_bytes(const vmc_ctx* h) { return h->precision == VMC_MIXED ? 4 : 8; }
@@ -3416,6 +3490,20 @@ vmc_status vmc_host_tables_get(const vmc_host_tables* t, int64_t* row_off, int32
 
 void vmc_host_tables_free(vmc_host_tables* t) { delete t; }
 
+// Id of a new system's Hamiltonian (never 0): a random 32-bit prefix drawn
+// once per process, then a counter, so no two systems of the process share
+// one, and a walker scratch left by another process almost surely matches none.
+static uint64_t next_ham_id() {
+    static std::mutex mu;
+    static uint64_t prefix = 0, count = 0;
+    std::lock_guard<std::mutex> lock(mu);
+    if (prefix == 0) {
+        std::random_device rd;
+        prefix = (uint64_t)(rd() | 1u) << 32;
+    }
+    return prefix | (++count & 0xFFFFFFFFull);
+}
+
 vmc_status vmc_init(const vmc_system_desc* desc, const double* h1, const vmc_eri_list* eri, double eps,
                     hipStream_t stream, vmc_handle* out) {
     if (!out) return fail(nullptr, VMC_E_ARG, "out is NULL");
@@ -3447,6 +3535,7 @@ vmc_status vmc_init(const vmc_system_desc* desc, const double* h1, const vmc_eri
                         return fail(nullptr, VMC_E_ARG, "VMC_UHF needs spin-conserving doubles");
     }
     vmc_ctx* h = new vmc_ctx;
+    h->ham_id = next_ham_id();
     h->n = desc->n_orb;
     h->n_so = 2 * h->n;
     h->na = desc->n_alpha;
