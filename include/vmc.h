@@ -435,8 +435,10 @@ vmc_status vmc_launch_info(vmc_handle h, int64_t out[5]);
 /* Occupancy target of the sweep kernel when the walker state stays in HBM:
  * 3 or 4 waves per SIMD (which fixes the kernel's register budget: 168 or 128
  * VGPRs), or 0 for the library's choice (4 when the table holds doubles, else
- * 3).  Host-only; affects subsequent calls.  Results do not depend on it (the
- * same arithmetic in the same order).  VMC_E_ARG for other values.
+ * 3; a system with correlators always runs at 3: its sweep variants are
+ * compiled for that target only).  Host-only; affects subsequent calls.
+ * Results do not depend on it (the same arithmetic in the same order).
+ * VMC_E_ARG for other values.
  * vmc_batch_set_occupancy: the same for a batch's launch. */
 vmc_status vmc_set_occupancy(vmc_handle h, int32_t waves);
 
@@ -468,7 +470,8 @@ vmc_status vmc_batch_set_occupancy(vmc_batch b, int32_t waves);
 /* How a batch runs (vmc_batch_set_mode; vmc_batch_info: out[0] = mode, out[1]
  * = workgroup size and out[2] = occupancy target of the fused launch):
  * VMC_BATCH_FUSED (default): the one launch described above; spin-blocked
- * systems are refused (VMC_E_UNSUPPORTED) at the call.  VMC_BATCH_STREAMS:
+ * systems and systems with correlators are refused (VMC_E_UNSUPPORTED) at
+ * the call.  VMC_BATCH_STREAMS:
  * each system's own calls (vmc_ctmc_step / vmc_local_energy, with its own
  * variant: state in LDS where it fits, its own workgroup size, occupancy and
  * re-inversion schedule) on a stream of its own, forked from the caller's
@@ -492,10 +495,10 @@ vmc_status vmc_batch_destroy(vmc_batch b);
  * size in *chosen (nullable; vmc_launch_info reports the occupancy).
  * vmc_batch_autotune also tunes every system on its own (vmc_autotune), times
  * the batch in VMC_BATCH_STREAMS mode, and keeps the faster mode (*chosen = 0
- * for the stream mode; vmc_batch_info reports it); spin-blocked systems are
- * tuned for the stream mode only.  The timed sweeps are real moves: every
- * walker set advances by 2 * n_moves moves per shape tried (use it as
- * burn-in).  Pass the number of moves per call that will be run: a launch
+ * for the stream mode; vmc_batch_info reports it); a batch holding a
+ * spin-blocked system or one with correlators is tuned for the stream mode
+ * only.  The timed sweeps are real moves: every walker set advances by
+ * 2 * n_moves moves per shape tried (use it as burn-in).  Pass the number of moves per call that will be run: a launch
  * carries a fixed set-up cost (the first evaluation of every candidate) that
  * depends on the shape, so short timed sweeps can favour another shape than
  * long ones.  Blocks until the timing is done.

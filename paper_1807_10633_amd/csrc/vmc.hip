@@ -1567,13 +1567,16 @@ constexpr int sweep_waves_target(int nso_t, bool small, int hw) {
 // update denominators and every accumulation stay FP64).
 // sweep_body runs walker w of the walker set S (W walkers) on the calling
 // workgroup.
-template <int NSO_T, int NE_T, int NT_T, bool NW1, bool SMALL, typename RT, bool UHF = false>
+template <int NSO_T, int NE_T, int NT_T, bool NW1, bool SMALL, typename RT, bool UHF = false, bool CPS = false>
 __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t W, int64_t w, int mode, int n_steps,
                                            uint64_t step0, uint64_t seed, int refresh_period, double* eloc_hist,
                                            double* t_hist, int64_t* pick_hist) {
     static_assert(!(UHF && SMALL), "spin-blocked orbitals keep the walker state in HBM");
     extern __shared__ __align__(16) unsigned char smem[];
     Tab T = Targ;
+    // compiled without correlators: every correlator branch folds away (a
+    // system with correlators runs the variants compiled with them)
+    if constexpr (!CPS) T.ncorr = 0;
     if (NSO_T) {
         T.n_so = NSO_T;
         T.ne = NE_T;
@@ -2288,7 +2291,8 @@ __device__ __forceinline__ void sweep_body(const Tab& Targ, const Wk& S, int64_t
 }
 
 // One workgroup per walker of one system.
-template <int NSO_T, int NE_T, int NT_T, bool NW1, bool SMALL, typename RT, bool UHF = false, int HW = 3>
+template <int NSO_T, int NE_T, int NT_T, bool NW1, bool SMALL, typename RT, bool UHF = false, int HW = 3,
+          bool CPS = false>
 __global__ void __launch_bounds__(NT_T ? NT_T : 512) __attribute__((amdgpu_waves_per_eu(sweep_waves_target(NSO_T, SMALL, HW))))
 k_sweep(Tab T, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, const uint64_t* step_dev, uint64_t seed,
         int refresh_period, double* eloc_hist, double* t_hist, int64_t* pick_hist) {
@@ -2297,8 +2301,8 @@ k_sweep(Tab T, Wk S, int64_t W, int mode, int n_steps, uint64_t step0, const uin
     // global step of the first move: step0, plus a device-resident counter
     // when the caller keeps one (graph replays advance it)
     const uint64_t s0 = step_dev ? step0 + *step_dev : step0;
-    sweep_body<NSO_T, NE_T, NT_T, NW1, SMALL, RT, UHF>(T, S, W, w, mode, n_steps, s0, seed, refresh_period, eloc_hist,
-                                                  t_hist, pick_hist);
+    sweep_body<NSO_T, NE_T, NT_T, NW1, SMALL, RT, UHF, CPS>(T, S, W, w, mode, n_steps, s0, seed, refresh_period,
+                                                       eloc_hist, t_hist, pick_hist);
 }
 
 __global__ void k_step_advance(uint64_t* step_dev, uint64_t n) {
@@ -2308,7 +2312,7 @@ __global__ void k_step_advance(uint64_t* step_dev, uint64_t n) {
 // Several systems of different sizes in one launch: workgroups [block0,
 // block0 + W) of the grid belong to entry e.  Every system runs the variant
 // with the walker state in HBM (any size, one layout per system, LDS sized
-// for the largest) and refreshes in place.
+// for the largest) and refreshes in place; none carries correlators.
 constexpr int kMaxBatch = 8;
 struct BatchEntry {
     Tab T;
@@ -3238,10 +3242,10 @@ struct SweepArgs {
     const uint64_t* step_dev;
 };
 
-template <int NSO, int NE, int NT, bool NW1, bool SM, typename RT, bool UHF = false, int HW = 3>
+template <int NSO, int NE, int NT, bool NW1, bool SM, typename RT, bool UHF = false, int HW = 3, bool CPS = false>
 void launch_one(dim3 grid, dim3 block, size_t lds, hipStream_t st, const Tab& T, const Wk& S, const vmc_walkers* w,
                 const SweepArgs& a, const vmc_ctx* h) {
-    hipLaunchKernelGGL((k_sweep<NSO, NE, NT, NW1, SM, RT, UHF, HW>), grid, block, lds, st, T, S, w->n_walkers, a.mode,
+    hipLaunchKernelGGL((k_sweep<NSO, NE, NT, NW1, SM, RT, UHF, HW, CPS>), grid, block, lds, st, T, S, w->n_walkers, a.mode,
                        a.n_steps, a.step0, a.step_dev, h->seed, a.refresh, a.eh, a.th, a.ph);
 }
 
@@ -3251,7 +3255,10 @@ void launch_one(dim3 grid, dim3 block, size_t lds, hipStream_t st, const Tab& T,
 // (the candidate gathers wait on the caches: more waves hide them, a few
 // spills included) and 3 without (the Hubbard update stream keeps its
 // registers).
-int hbm_waves(const vmc_ctx* h) { return h->waves ? h->waves : (h->n_dent > 0 ? 4 : 3); }
+int hbm_waves(const vmc_ctx* h) {
+    if (h->ncorr > 0) return 3;  // the variants with correlators are compiled for 3 only
+    return h->waves ? h->waves : (h->n_dent > 0 ? 4 : 3);
+}
 int batch_waves(const vmc_batch_ctx* b) {
     if (b->waves) return b->waves;
     for (const vmc_ctx* h : b->sys)
@@ -3270,6 +3277,16 @@ template <typename RT>
 void launch_prec(bool small, bool nw1, int nt, dim3 grid, dim3 block, size_t lds, hipStream_t st, const Tab& T,
                  const Wk& S, const vmc_walkers* w, const SweepArgs& a, const vmc_ctx* h) {
     auto spec = [&](int n_so, int ne, int c) { return small && h->n_so == n_so && h->ne == ne && nt == c; };
+    // with correlators: the variants of any size compiled with them
+    if (h->ncorr > 0) {
+        if (small && nw1) launch_one<0, 0, 0, true, true, RT, false, 3, true>(grid, block, lds, st, T, S, w, a, h);
+        else if (small) launch_one<0, 0, 0, false, true, RT, false, 3, true>(grid, block, lds, st, T, S, w, a, h);
+        else if (h->uhf && nw1) launch_one<0, 0, 0, true, false, RT, true, 3, true>(grid, block, lds, st, T, S, w, a, h);
+        else if (h->uhf) launch_one<0, 0, 0, false, false, RT, true, 3, true>(grid, block, lds, st, T, S, w, a, h);
+        else if (nw1) launch_one<0, 0, 0, true, false, RT, false, 3, true>(grid, block, lds, st, T, S, w, a, h);
+        else launch_one<0, 0, 0, false, false, RT, false, 3, true>(grid, block, lds, st, T, S, w, a, h);
+        return;
+    }
     // walker state in HBM (always, with spin-blocked orbitals)
     if (!small) {
         if (h->uhf && nw1) launch_hbm<true, true, RT>(grid, block, lds, st, T, S, w, a, h);
@@ -3621,6 +3638,14 @@ vmc_status vmc_init(const vmc_system_desc* desc, const double* h1, const vmc_eri
                              (const void*)k_sweep<0, 0, 0, true, false, double, true, 4>,
                              (const void*)k_sweep<0, 0, 0, false, false, float, true, 4>,
                              (const void*)k_sweep<0, 0, 0, true, false, float, true, 4>,
+                             (const void*)k_sweep<0, 0, 0, false, false, double, false, 3, true>,
+                             (const void*)k_sweep<0, 0, 0, true, false, double, false, 3, true>,
+                             (const void*)k_sweep<0, 0, 0, false, false, float, false, 3, true>,
+                             (const void*)k_sweep<0, 0, 0, true, false, float, false, 3, true>,
+                             (const void*)k_sweep<0, 0, 0, false, false, double, true, 3, true>,
+                             (const void*)k_sweep<0, 0, 0, true, false, double, true, 3, true>,
+                             (const void*)k_sweep<0, 0, 0, false, false, float, true, 3, true>,
+                             (const void*)k_sweep<0, 0, 0, true, false, float, true, 3, true>,
                              (const void*)k_sweep_batch<double, 4>, (const void*)k_sweep_batch<float, 4>,
                              (const void*)k_sweep_batch<double, 3>, (const void*)k_sweep_batch<float, 3>};
         for (const void* f : big) {
@@ -4089,7 +4114,7 @@ vmc_status vmc_batch_autotune(vmc_batch b, vmc_walkers* const* walkers, int32_t 
     if (!walkers) return fail(nullptr, VMC_E_ARG, "walkers array is NULL");
     const int keep = b->nt, keep_w = b->waves, keep_m = b->mode;
     bool fusable = true;
-    for (vmc_ctx* h : b->sys) fusable = fusable && !h->uhf;
+    for (vmc_ctx* h : b->sys) fusable = fusable && !h->uhf && h->ncorr == 0;
     // the fused launch: every workgroup size and occupancy target
     int best_nt = 0, best_w = 0;
     float best = 3.0e38f;
@@ -4273,8 +4298,11 @@ static vmc_status launch_batch(vmc_batch b, vmc_walkers* const* ws, int mode, in
     if (!b) return fail(nullptr, VMC_E_ARG, "batch is NULL");
     if (!ws) return fail(nullptr, VMC_E_ARG, "walkers array is NULL");
     if (b->mode == VMC_BATCH_STREAMS) return launch_streams(b, ws, mode, n_steps, st);
-    for (vmc_ctx* h : b->sys)
+    for (vmc_ctx* h : b->sys) {
         if (h->uhf) return fail(nullptr, VMC_E_UNSUPPORTED, "the fused batch holds VMC_GHF systems only");
+        if (h->ncorr > 0)
+            return fail(nullptr, VMC_E_UNSUPPORTED, "the fused batch holds systems without correlators only");
+    }
     BatchArgs A;
     std::memset(&A, 0, sizeof(A));
     A.n = (int)b->sys.size();
