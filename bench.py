@@ -42,49 +42,38 @@ METRIC = "walker-steps/s (E_L+CTMC) at stated E_L error vs FP64 oracle; % HBM/MF
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per sweep launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of
-# `bench.py [--config hubbard10x10 --walkers 16384] --steps 2 --warmup 1
+# HBM bytes per sweep launch (the timed 50-move sweeps, mean of two) from
+# rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of `bench.py --steps 2 --warmup 1
 # --no-cpu-baseline --no-check --no-other-form --no-graph`, scaled by the
 # readings of a plain 1 GiB device copy (FETCH_SIZE reads 0.5 KiB per KiB
 # moved, WRITE_SIZE 1 KiB per KiB).  Keyed by the SHA-256 of the kernel sources
-# and the workload: any other kernel source or workload reports null.
+# and the workload (config, walkers, moves per sweep, threads per walker,
+# form): any other kernel source or workload reports null.
 KERNEL_SOURCES = ("paper_1807_10633_amd/csrc/vmc.hip", "paper_1807_10633_amd/csrc/device.hpp",
                   "paper_1807_10633_amd/csrc/tables.cpp")
+_SRC = ("8293154c24cfdab669f019f92db825f19b99ea499bb9d4bc4de93b879f6d87c3",
+        "34612a5fdacc07521f2c4a2be434138557890b663234c3daf1567a7241d1ca55",
+        "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d")
 COUNTED_TRAFFIC = {
-    ("5af7e828dc7bc47fb823d8a564888dedd12b92e4d5c47e6577002d4f097a2631",
-     "e42321a173f348e60cbd4a8c9a6c2ece6e89405d4e145e8681061726bb564736",
-     "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d", "hchain20", 4096, 50, 256, "fp64"):
-        {"fetch_kib": 59086.56, "fetch_factor": 2.0, "write_kib": 62350.08, "write_factor": 1.0},
-    ("5af7e828dc7bc47fb823d8a564888dedd12b92e4d5c47e6577002d4f097a2631",
-     "e42321a173f348e60cbd4a8c9a6c2ece6e89405d4e145e8681061726bb564736",
-     "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d", "hubbard10x10", 16384, 50, 256, "fp64"):
-        {"fetch_kib": 112855937.47, "fetch_factor": 2.0, "write_kib": 191992325.92, "write_factor": 1.0},
-    ("5af7e828dc7bc47fb823d8a564888dedd12b92e4d5c47e6577002d4f097a2631",
-     "e42321a173f348e60cbd4a8c9a6c2ece6e89405d4e145e8681061726bb564736",
-     "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d", "hubbard10x10", 16384, 50, 128, "mixed"):
-        {"fetch_kib": 80298374.16, "fetch_factor": 2.0, "write_kib": 127996267.33, "write_factor": 1.0},
-    ("5af7e828dc7bc47fb823d8a564888dedd12b92e4d5c47e6577002d4f097a2631",
-     "e42321a173f348e60cbd4a8c9a6c2ece6e89405d4e145e8681061726bb564736",
-     "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d", "hubbard10x10:uhf", 16384, 50, 128, "fp64"):
-        {"fetch_kib": 39086717.72, "fetch_factor": 2.0, "write_kib": 48678339.64, "write_factor": 1.0},
-    ("5af7e828dc7bc47fb823d8a564888dedd12b92e4d5c47e6577002d4f097a2631",
-     "e42321a173f348e60cbd4a8c9a6c2ece6e89405d4e145e8681061726bb564736",
-     "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d", "hubbard10x10:uhf", 16384, 50, 128, "mixed"):
-        {"fetch_kib": 26732429.3, "fetch_factor": 2.0, "write_kib": 32659113.0, "write_factor": 1.0},
+    _SRC + ("hchain160", 8192, 50, 512, "mixed"):
+        {"fetch_kib": 1632436415.28, "fetch_factor": 2.0, "write_kib": 238008667.39, "write_factor": 1.0},
 }
 
 
-# Instruction counts per sweep launch (rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_SALU
-# SQ_INSTS_LDS SQ_INSTS_VMEM_RD, and VALUBusy in a run of its own, on the same bench command as the HBM
-# counters), keyed like COUNTED_TRAFFIC.  The issue peak is one wave64 VALU
-# instruction per SIMD every 4 cycles (16 lanes): 256 CUs x 4 SIMDs x 2.4 GHz / 4.
+# Instruction counts per sweep launch (rocprofv3 --pmc SQ_WAVES SQ_BUSY_CYCLES
+# SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_INSTS_VMEM_RD SQ_WAIT_INST_ANY and
+# one more SQ counter, on the same bench command as the HBM counters; hchain20
+# with --config hchain20 --precision fp64), keyed like COUNTED_TRAFFIC.  The
+# issue peak is one wave64 VALU instruction per SIMD every 4 cycles (16 lanes):
+# 256 CUs x 4 SIMDs x 2.4 GHz / 4.
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 COUNTED_ISSUE = {
-    ("5af7e828dc7bc47fb823d8a564888dedd12b92e4d5c47e6577002d4f097a2631",
-     "e42321a173f348e60cbd4a8c9a6c2ece6e89405d4e145e8681061726bb564736",
-     "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d", "hchain20", 4096, 50, 256, "fp64"):
-        {"valu_insts": 4890615390.0, "salu_insts": 2665940988.0, "lds_insts": 548790633.5,
-         "vmem_rd_insts": 168605103.5, "valu_busy_pct": 64.72},
+    _SRC + ("hchain160", 8192, 50, 512, "mixed"):
+        {"valu_insts": 197086000000.0, "salu_insts": 80502350000.0, "lds_insts": 36842300000.0,
+         "vmem_rd_insts": 7490110000.0},
+    _SRC + ("hchain20", 4096, 50, 256, "fp64"):
+        {"valu_insts": 4805510000.0, "salu_insts": 2691640000.0, "lds_insts": 549758000.0,
+         "vmem_rd_insts": 171025000.0},
 }
 
 
@@ -101,7 +90,7 @@ def counted_issue(config, walkers, sweep, threads, precision, sweep_s):
     rate = rec["valu_insts"] / sweep_s
     return {"valu_insts_per_launch": rec["valu_insts"], "salu_insts_per_launch": rec["salu_insts"],
             "lds_insts_per_launch": rec["lds_insts"], "vmem_rd_insts_per_launch": rec["vmem_rd_insts"],
-            "valu_busy_pct": rec["valu_busy_pct"], "valu_issue_per_s": rate, "valu_issue_peak_per_s": VALU_ISSUE_PEAK,
+            "valu_issue_per_s": rate, "valu_issue_peak_per_s": VALU_ISSUE_PEAK,
             "valu_issue_frac": rate / VALU_ISSUE_PEAK}
 
 
