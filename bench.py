@@ -51,12 +51,12 @@ HBM_PEAK_GBS = 8000.0
 # form): any other kernel source or workload reports null.
 KERNEL_SOURCES = ("paper_1807_10633_amd/csrc/vmc.hip", "paper_1807_10633_amd/csrc/device.hpp",
                   "paper_1807_10633_amd/csrc/tables.cpp")
-_SRC = ("8293154c24cfdab669f019f92db825f19b99ea499bb9d4bc4de93b879f6d87c3",
+_SRC = ("fdc4aefeda0d591ec28373233eae9371ceca4662b2017e8c40409f6fa868dc8c",
         "34612a5fdacc07521f2c4a2be434138557890b663234c3daf1567a7241d1ca55",
         "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d")
 COUNTED_TRAFFIC = {
     _SRC + ("hchain160", 8192, 50, 512, "mixed"):
-        {"fetch_kib": 1632436415.28, "fetch_factor": 2.0, "write_kib": 238008667.39, "write_factor": 1.0},
+        {"fetch_kib": 1639454750.56, "fetch_factor": 2.0, "write_kib": 238543762.73, "write_factor": 1.0},
 }
 
 
@@ -69,11 +69,11 @@ COUNTED_TRAFFIC = {
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 COUNTED_ISSUE = {
     _SRC + ("hchain160", 8192, 50, 512, "mixed"):
-        {"valu_insts": 197086000000.0, "salu_insts": 80502350000.0, "lds_insts": 36842300000.0,
-         "vmem_rd_insts": 7490110000.0},
+        {"valu_insts": 196698000000.0, "salu_insts": 81344600000.0, "lds_insts": 35539750000.0,
+         "vmem_rd_insts": 7590985000.0},
     _SRC + ("hchain20", 4096, 50, 256, "fp64"):
-        {"valu_insts": 4805510000.0, "salu_insts": 2691640000.0, "lds_insts": 549758000.0,
-         "vmem_rd_insts": 171025000.0},
+        {"valu_insts": 4802290000.0, "salu_insts": 2703860000.0, "lds_insts": 550168000.0,
+         "vmem_rd_insts": 177995000.0},
 }
 
 
