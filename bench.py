@@ -57,6 +57,14 @@ _SRC = ("fdc4aefeda0d591ec28373233eae9371ceca4662b2017e8c40409f6fa868dc8c",
 COUNTED_TRAFFIC = {
     _SRC + ("hchain160", 8192, 50, 512, "mixed"):
         {"fetch_kib": 1639454750.56, "fetch_factor": 2.0, "write_kib": 238543762.73, "write_factor": 1.0},
+    _SRC + ("hubbard10x10", 16384, 50, 256, "mixed"):
+        {"fetch_kib": 100581070.34, "fetch_factor": 2.0, "write_kib": 160293294.11, "write_factor": 1.0},
+    _SRC + ("hubbard10x10", 16384, 50, 256, "fp64"):
+        {"fetch_kib": 113775108.91, "fetch_factor": 2.0, "write_kib": 192138756.77, "write_factor": 1.0},
+    _SRC + ("hubbard10x10:uhf", 16384, 50, 128, "mixed"):
+        {"fetch_kib": 33670670.44, "fetch_factor": 2.0, "write_kib": 40722860.16, "write_factor": 1.0},
+    _SRC + ("hubbard10x10:uhf", 16384, 50, 128, "fp64"):
+        {"fetch_kib": 39134683.5, "fetch_factor": 2.0, "write_kib": 48710968.17, "write_factor": 1.0},
 }
 
 
