@@ -1324,8 +1324,10 @@ __device__ __forceinline__ bool pair_tiles(const Tab& T, const StepView<RT>& V, 
     int last_l = -1;
     uint32_t last_off = 0;
     uint64_t last_ab = 0;
-    int cur_s = -1;  // ELOC: the open segment and its rate sum so far (wave-uniform)
-    double cur_sum = 0.0;
+    // ELOC: the open segment (wave-uniform) and each lane's part of its rate
+    // sum; a segment is reduced across the wave once, when the next one opens
+    int cur_s = -1;
+    double acc = 0.0;
     // the wave's marker bytes (kTileUnroll x 64) are zero between uses
     for (int k = l; k < kTileUnroll * kWave / 4; k += kWave) ((uint32_t*)mark)[k] = 0u;
     wave_lds_sync();
@@ -1345,21 +1347,23 @@ __device__ __forceinline__ bool pair_tiles(const Tab& T, const StepView<RT>& V, 
         }
         if (!PICK) {
             el += term;
-            uint64_t rem = __ballot(act);
+            // the batch's lanes hold runs of segments in processing order: the
+            // first run may continue the open segment; every later run opens
+            // a new one, which closes the one before it
+            const bool inc = act && (int)sg == cur_s;
+            acc += inc ? r : 0.0;
+            uint64_t rem = __ballot(act) & ~__ballot(inc);
             while (rem) {
-                // lanes without a candidate hold r = 0 and never enter rem
+                if (cur_s >= 0) {
+                    const double tot = wave_total(acc);
+                    if (l == 0) segsum[cur_s] = tot;
+                }
                 const int fl = __ffsll((unsigned long long)rem) - 1;
                 const int s0 = __builtin_amdgcn_readlane((int)sg, fl);
-                const bool in = (int)sg == s0;
-                const uint64_t m = __ballot(in);
-                const double part = wave_total(in ? r : 0.0);
-                if (s0 != cur_s) {
-                    if (cur_s >= 0 && l == 0) segsum[cur_s] = cur_sum;
-                    cur_s = s0;
-                    cur_sum = 0.0;
-                }
-                cur_sum += part;
-                rem &= ~m;
+                const bool in = act && (int)sg == s0;
+                acc = in ? r : 0.0;
+                cur_s = s0;
+                rem &= ~__ballot(in);
             }
             return false;
         }
@@ -1517,7 +1521,10 @@ __device__ __forceinline__ bool pair_tiles(const Tab& T, const StepView<RT>& V, 
         if (PICK) break;
     }
     if (!found && qn > 0) found = batch((int)qn);
-    if (!PICK && cur_s >= 0 && l == 0) segsum[cur_s] = cur_sum;
+    if (!PICK && cur_s >= 0) {
+        const double tot = wave_total(acc);
+        if (l == 0) segsum[cur_s] = tot;
+    }
     wave_lds_sync();
     if (PICK && !found && last_l >= 0) {
         // rounding left the target past the segment's last running sum: take
