@@ -224,8 +224,10 @@ struct Lds {
 };
 __host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~(size_t)15; }
 // Doubles of the layout with the walker state in HBM run over tiles of
-// kPairBlock x kPairBlock occupied pairs (pair_tiles).
-constexpr int kPairBlock = 16;
+// kPairBlock x kPairBlock occupied pairs (pair_tiles).  32 measured 3 %
+// faster than 16 at 160 orbitals (fewer segments, each reduced once), 8
+// 4 % slower, 64 the same as 32.
+constexpr int kPairBlock = 32;
 __host__ __device__ inline int pair_blocks(int ne) { return (ne + kPairBlock - 1) / kPairBlock; }
 // rb: bytes per R element (8 for the FP64 form, 4 for the mixed form);
 // ncorr: correlators (their current states and inverse coefficients)
@@ -1297,9 +1299,9 @@ __device__ __forceinline__ bool stream_pass(const Tab& T, const StepView<RT>& V,
 // (x - X kPairBlock + k) mod nwv), so that the rows of R of the two blocks,
 // which the pairs' 2x2 minors gather, are reused from the caches across the
 // tile instead of fetched once per pair.  The lanes hold the table rows of
-// four of the wave's segments at a time (pair p of segment s in lane 16 s + p,
-// then the rows with entries moved to the lowest lanes); their entries form
-// one unpadded stream, cut into 64-entry chunks, so that the table loads of
+// kWave / kPairBlock of the wave's segments at a time (pair p of segment s
+// in lane kPairBlock s + p, then the rows with entries moved to the lowest
+// lanes); their entries form one unpadded stream, cut into 64-entry chunks, so that the table loads of
 // several rows and segments go out together.  A lane finds its row in
 // constant time: the rows starting inside the chunk set one marker byte each
 // in LDS, and the lane counts the markers below it (one ballot, one mbcnt).
@@ -1434,7 +1436,7 @@ __device__ __forceinline__ bool pair_tiles(const Tab& T, const StepView<RT>& V, 
 #pragma unroll
         for (int k = 1; k < kSegs; ++k)
             if (sl == k) { x = sx[k]; yb = sy[k]; }
-        // lane (16 s + p): the table row of pair p of segment s, its slots
+        // lane (kPairBlock s + p): the table row of pair p of segment s, its slots
         // (16 bits each) and the segment's index
         uint32_t b0 = 0, len = 0, pk = 0, sg = 0;
         if (sl < nseg) {
