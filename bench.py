@@ -51,20 +51,20 @@ HBM_PEAK_GBS = 8000.0
 # form): any other kernel source or workload reports null.
 KERNEL_SOURCES = ("paper_1807_10633_amd/csrc/vmc.hip", "paper_1807_10633_amd/csrc/device.hpp",
                   "paper_1807_10633_amd/csrc/tables.cpp")
-_SRC = ("3e1a13fa09e72a35af9975cb6de36f5d1fb728accce4f873927ef4117a71efa7",
+_SRC = ("7885e6cf14e839e58c22eb66ed851862fc477c2f5f76f0520383a0f20a7dc6dc",
         "34612a5fdacc07521f2c4a2be434138557890b663234c3daf1567a7241d1ca55",
         "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d")
 COUNTED_TRAFFIC = {
     _SRC + ("hchain160", 8192, 50, 512, "mixed"):
-        {"fetch_kib": 1639044829.19, "fetch_factor": 2.0, "write_kib": 238561090.41, "write_factor": 1.0},
+        {"fetch_kib": 1638286638.34, "fetch_factor": 2.0, "write_kib": 235106818.19, "write_factor": 1.0},
     _SRC + ("hubbard10x10", 16384, 50, 256, "mixed"):
-        {"fetch_kib": 100584994.0, "fetch_factor": 2.0, "write_kib": 160300082.17, "write_factor": 1.0},
+        {"fetch_kib": 100573459.81, "fetch_factor": 2.0, "write_kib": 160296536.84, "write_factor": 1.0},
     _SRC + ("hubbard10x10", 16384, 50, 256, "fp64"):
-        {"fetch_kib": 113772285.13, "fetch_factor": 2.0, "write_kib": 192135040.16, "write_factor": 1.0},
+        {"fetch_kib": 113773672.0, "fetch_factor": 2.0, "write_kib": 192127750.48, "write_factor": 1.0},
     _SRC + ("hubbard10x10:uhf", 16384, 50, 128, "mixed"):
-        {"fetch_kib": 33687790.5, "fetch_factor": 2.0, "write_kib": 40747855.81, "write_factor": 1.0},
+        {"fetch_kib": 33757116.31, "fetch_factor": 2.0, "write_kib": 40724744.66, "write_factor": 1.0},
     _SRC + ("hubbard10x10:uhf", 16384, 50, 128, "fp64"):
-        {"fetch_kib": 39197536.81, "fetch_factor": 2.0, "write_kib": 48712995.8, "write_factor": 1.0},
+        {"fetch_kib": 39134011.94, "fetch_factor": 2.0, "write_kib": 48711488.89, "write_factor": 1.0},
 }
 
 
@@ -77,11 +77,11 @@ COUNTED_TRAFFIC = {
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 COUNTED_ISSUE = {
     _SRC + ("hchain160", 8192, 50, 512, "mixed"):
-        {"valu_insts": 177160000000.0, "salu_insts": 76548900000.0, "lds_insts": 35540050000.0,
-         "vmem_rd_insts": 7590850000.0},
+        {"valu_insts": 161554000000.0, "salu_insts": 65892950000.0, "lds_insts": 35689000000.0,
+         "vmem_rd_insts": 7602250000.0},
     _SRC + ("hchain20", 4096, 50, 256, "fp64"):
-        {"valu_insts": 4802290000.0, "salu_insts": 2703860000.0, "lds_insts": 550168000.0,
-         "vmem_rd_insts": 177995000.0},
+        {"valu_insts": 4833230000.0, "salu_insts": 2676670000.0, "lds_insts": 550168000.0,
+         "vmem_rd_insts": 174520000.0},
 }
 
 
