@@ -1463,6 +1463,7 @@ __device__ __forceinline__ bool pair_tiles(const Tab& T, const StepView<RT>& V, 
         const uint32_t end = wave_scan_u32(len);
         const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)end, nrows - 1);
         const uint32_t start = end - len;  // = tot in the lanes past the last row
+        const uint32_t delta = b0 - start;  // table offset of stream position pos in the row: pos + delta
         for (uint32_t c = 0; c < tot && !found; c += kTileUnroll * kWave) {
             uint32_t off[kTileUnroll], pkv[kTileUnroll], sgv[kTileUnroll], abv[kTileUnroll];
 #pragma unroll
@@ -1486,12 +1487,11 @@ __device__ __forceinline__ bool pair_tiles(const Tab& T, const StepView<RT>& V, 
                     mk[l] = 0;
                     wave_lds_sync();
                     const int src = (k0 + (int)mask_below(sm >> 1)) << 2;
-                    const uint32_t rb0 = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)b0);
-                    const uint32_t rst = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)start);
+                    const uint32_t rdl = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)delta);
                     const uint32_t rpk = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)pk);
                     const uint32_t rsg = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)sg);
                     if (pos < tot) {
-                        off[u] = rb0 + (pos - rst);
+                        off[u] = pos + rdl;
                         pkv[u] = rpk | 0x80000000u;
                         sgv[u] = rsg;
                     }
