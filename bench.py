@@ -51,20 +51,20 @@ HBM_PEAK_GBS = 8000.0
 # form): any other kernel source or workload reports null.
 KERNEL_SOURCES = ("paper_1807_10633_amd/csrc/vmc.hip", "paper_1807_10633_amd/csrc/device.hpp",
                   "paper_1807_10633_amd/csrc/tables.cpp")
-_SRC = ("7885e6cf14e839e58c22eb66ed851862fc477c2f5f76f0520383a0f20a7dc6dc",
+_SRC = ("bb578bb639b811048fb7d47dbf50f54cd3252dae6ed26ced2326b7282bd44fda",
         "34612a5fdacc07521f2c4a2be434138557890b663234c3daf1567a7241d1ca55",
         "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d")
 COUNTED_TRAFFIC = {
     _SRC + ("hchain160", 8192, 50, 512, "mixed"):
-        {"fetch_kib": 1638286638.34, "fetch_factor": 2.0, "write_kib": 235106818.19, "write_factor": 1.0},
+        {"fetch_kib": 1636266541.66, "fetch_factor": 2.0, "write_kib": 235135008.77, "write_factor": 1.0},
     _SRC + ("hubbard10x10", 16384, 50, 256, "mixed"):
-        {"fetch_kib": 100573459.81, "fetch_factor": 2.0, "write_kib": 160296536.84, "write_factor": 1.0},
+        {"fetch_kib": 100595460.31, "fetch_factor": 2.0, "write_kib": 160300181.20, "write_factor": 1.0},
     _SRC + ("hubbard10x10", 16384, 50, 256, "fp64"):
-        {"fetch_kib": 113773672.0, "fetch_factor": 2.0, "write_kib": 192127750.48, "write_factor": 1.0},
+        {"fetch_kib": 113842600.34, "fetch_factor": 2.0, "write_kib": 192136607.17, "write_factor": 1.0},
     _SRC + ("hubbard10x10:uhf", 16384, 50, 128, "mixed"):
-        {"fetch_kib": 33757116.31, "fetch_factor": 2.0, "write_kib": 40724744.66, "write_factor": 1.0},
+        {"fetch_kib": 33712208.12, "fetch_factor": 2.0, "write_kib": 40723642.73, "write_factor": 1.0},
     _SRC + ("hubbard10x10:uhf", 16384, 50, 128, "fp64"):
-        {"fetch_kib": 39134011.94, "fetch_factor": 2.0, "write_kib": 48711488.89, "write_factor": 1.0},
+        {"fetch_kib": 39138386.47, "fetch_factor": 2.0, "write_kib": 48713115.11, "write_factor": 1.0},
 }
 
 
@@ -77,11 +77,11 @@ COUNTED_TRAFFIC = {
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 COUNTED_ISSUE = {
     _SRC + ("hchain160", 8192, 50, 512, "mixed"):
-        {"valu_insts": 161554000000.0, "salu_insts": 65892950000.0, "lds_insts": 35689000000.0,
-         "vmem_rd_insts": 7602250000.0},
+        {"valu_insts": 159128644210.0, "salu_insts": 65886576204.5, "lds_insts": 33176019209.5,
+         "vmem_rd_insts": 7602248022.0},
     _SRC + ("hchain20", 4096, 50, 256, "fp64"):
-        {"valu_insts": 4833230000.0, "salu_insts": 2676670000.0, "lds_insts": 550168000.0,
-         "vmem_rd_insts": 174520000.0},
+        {"valu_insts": 4833229787.0, "salu_insts": 2676674381.0, "lds_insts": 550167940.0,
+         "vmem_rd_insts": 174519680.0},
 }
 
 
