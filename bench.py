@@ -51,20 +51,20 @@ HBM_PEAK_GBS = 8000.0
 # form): any other kernel source or workload reports null.
 KERNEL_SOURCES = ("paper_1807_10633_amd/csrc/vmc.hip", "paper_1807_10633_amd/csrc/device.hpp",
                   "paper_1807_10633_amd/csrc/tables.cpp")
-_SRC = ("3602b84893cb17f20a38fd840a34ec6b78f34bfc0b9c37098600ca963b48b577",
+_SRC = ("ecebd9598f8ddc59f3a4a99104d30bebc01774b07f12dee8c1c08c31765475ff",
         "34612a5fdacc07521f2c4a2be434138557890b663234c3daf1567a7241d1ca55",
         "b71e869fe74a959896df20f208b4336cf4a33be250449d90fe9120f44388047d")
 COUNTED_TRAFFIC = {
     _SRC + ("hchain160", 8192, 50, 512, "mixed"):
-        {"fetch_kib": 1635360753.09, "fetch_factor": 2.0, "write_kib": 235132337.38, "write_factor": 1.0},
+        {"fetch_kib": 1636928178.12, "fetch_factor": 2.0, "write_kib": 235131567.73, "write_factor": 1.0},
     _SRC + ("hubbard10x10", 16384, 50, 256, "mixed"):
-        {"fetch_kib": 100629253.06, "fetch_factor": 2.0, "write_kib": 160300038.03, "write_factor": 1.0},
+        {"fetch_kib": 100650311.31, "fetch_factor": 2.0, "write_kib": 160297958.50, "write_factor": 1.0},
     _SRC + ("hubbard10x10", 16384, 50, 256, "fp64"):
-        {"fetch_kib": 113867491.41, "fetch_factor": 2.0, "write_kib": 192139292.78, "write_factor": 1.0},
+        {"fetch_kib": 113866261.94, "fetch_factor": 2.0, "write_kib": 192131068.98, "write_factor": 1.0},
     _SRC + ("hubbard10x10:uhf", 16384, 50, 128, "mixed"):
-        {"fetch_kib": 33739285.91, "fetch_factor": 2.0, "write_kib": 40723993.16, "write_factor": 1.0},
+        {"fetch_kib": 33707762.03, "fetch_factor": 2.0, "write_kib": 40722610.92, "write_factor": 1.0},
     _SRC + ("hubbard10x10:uhf", 16384, 50, 128, "fp64"):
-        {"fetch_kib": 39162156.06, "fetch_factor": 2.0, "write_kib": 48711762.12, "write_factor": 1.0},
+        {"fetch_kib": 39151712.72, "fetch_factor": 2.0, "write_kib": 48711148.83, "write_factor": 1.0},
 }
 
 

@@ -158,6 +158,13 @@ __device__ __forceinline__ int r_index_uhf(const Tab& T, int p, int a) {
 __device__ __forceinline__ int r_index(const Tab& T, int p, int a) {
     return T.uhf ? r_index_uhf(T, p, a) : p * T.n_so + a;
 }
+// 2x2 minor from its four gathered FP64 entries of R, with the first product
+// fused in one fixed form, so that every evaluation of a candidate rounds
+// alike.  (FP32 entries need no such care: their products are exact in FP64,
+// and the difference is rounded once however it is contracted.)
+__device__ __forceinline__ double minor_of(double rpa, double rqb, double rpb, double rqa) {
+    return fma(rpa, rqb, -(rpb * rqa));
+}
 // 2x2 minor R[a][p] R[b][q] - R[b][p] R[a][q] of a double (section "Local
 // energy and Gradient ratios", Eq. eq:R).  Spin-blocked orbitals: a pair of
 // the same spin is the full minor within that spin's rows; a pair of opposite
@@ -170,6 +177,7 @@ __device__ __forceinline__ double pair_minor_uhf(const Tab& T, const RT* R, int 
     const int op = (p >= T.na) ? T.n : 0, oq = (q >= T.na) ? T.n : 0;
     const int rp = p * T.n - op, rq = q * T.n - oq;
     if (op != oq) return (double)R[rp + a] * (double)R[rq + b];
+    if constexpr (sizeof(RT) == 8) return minor_of(R[rp + a], R[rq + b], R[rp + b], R[rq + a]);
     return (double)R[rp + a] * (double)R[rq + b] - (double)R[rp + b] * (double)R[rq + a];
 }
 template <typename RT>
@@ -970,14 +978,6 @@ __device__ __forceinline__ void cps_states(const Tab& T, const uint64_t* occw, u
     }
 }
 
-// 2x2 minor from its four gathered FP64 entries of R, with the first product
-// fused in one fixed form, so that every evaluation of a candidate rounds
-// alike.  (FP32 entries need no such care: their products are exact in FP64,
-// and the difference is rounded once however it is contracted.)
-__device__ __forceinline__ double minor_of(double rpa, double rqb, double rpb, double rqa) {
-    return fma(rpa, rqb, -(rpb * rqa));
-}
-
 // Ratio psi(M)/psi(N) (and, when WANT_H, the local-energy term H_NM * ratio)
 // of a queued candidate: table offset `off`, group g, targets in `ab` (a
 // 64-bit occupancy mask when MASK, else a | b << 16 / a in the low word).
@@ -1397,13 +1397,14 @@ __device__ __forceinline__ bool pair_tiles(const Tab& T, const StepView<RT>& V, 
         return false;
     };
 
-    // ELOC with unblocked orbitals and FP64 R: a full batch's table and R
-    // loads are issued when it fills and its terms formed when the next one
-    // fills (or at the end), so that its gathers are in flight during the scan
-    // of the chunks that follow.  Lanes without a candidate load entry 0 of
-    // both.  (Measured: the FP64 sweep 5.5 % faster at 160 orbitals and 6 %
-    // at 40; with FP32 R, whose gathers take half the bytes, 1.4 % slower.)
-    constexpr bool DEFER = !PICK && !UHF && sizeof(RT) == 8;
+    // ELOC with FP64 R: a full batch's table and R loads are issued when it
+    // fills and its terms formed when the next one fills (or at the end), so
+    // that its gathers are in flight during the scan of the chunks that
+    // follow.  Lanes without a candidate load entry 0 of both (spin-blocked:
+    // a pair of opposite spins loads two entries).  (Measured: the FP64 sweep
+    // 5.5 % faster at 160 orbitals and 6 % at 40; with FP32 R, whose gathers
+    // take half the bytes, 1.4 % slower.)
+    constexpr bool DEFER = !PICK && sizeof(RT) == 8;
     bool pend = false, p_act = false;
     uint32_t p_sg = 0;
     uint64_t p_ab = 0;
@@ -1418,10 +1419,21 @@ __device__ __forceinline__ bool pair_tiles(const Tab& T, const StepView<RT>& V, 
         p_sg = (uint32_t)(og >> 32);
         const uint32_t a = (uint32_t)p_ab & 0xFFFFu, b = (uint32_t)(p_ab >> 16) & 0xFFFFu;
         const uint32_t pp = (uint32_t)(p_ab >> 32) & 0xFFFFu, qq = (uint32_t)(p_ab >> 48);
-        const RT* Rp = V.R + __umul24(pp, (uint32_t)n_so);
-        const RT* Rq = V.R + __umul24(qq, (uint32_t)n_so);
         p_vk = *(const double2*)(T.dvK + 2 * (size_t)(uint32_t)og);
-        p_x0 = Rp[a]; p_x1 = Rq[b]; p_x2 = Rp[b]; p_x3 = Rq[a];
+        if (UHF) {
+            // (slot 0 of a lane without a candidate counts as alpha: row 0)
+            const int op = (p_act && (int)pp >= T.na) ? T.n : 0, oq = (p_act && (int)qq >= T.na) ? T.n : 0;
+            const RT* Rp = V.R + ((int)pp * T.n - op);
+            const RT* Rq = V.R + ((int)qq * T.n - oq);
+            p_x0 = Rp[a];
+            p_x1 = Rq[b];
+            p_x2 = (op == oq) ? Rp[b] : (RT)0;
+            p_x3 = (op == oq) ? Rq[a] : (RT)0;
+        } else {
+            const RT* Rp = V.R + __umul24(pp, (uint32_t)n_so);
+            const RT* Rq = V.R + __umul24(qq, (uint32_t)n_so);
+            p_x0 = Rp[a]; p_x1 = Rq[b]; p_x2 = Rp[b]; p_x3 = Rq[a];
+        }
         pend = true;
     };
     auto finish = [&]() __attribute__((always_inline)) {
@@ -1431,7 +1443,8 @@ __device__ __forceinline__ bool pair_tiles(const Tab& T, const StepView<RT>& V, 
         if (p_act) {
             const int a = (int)(p_ab & 0xFFFFu), b = (int)((p_ab >> 16) & 0xFFFFu);
             const int p = (int)((p_ab >> 32) & 0xFFFFu), q = (int)(p_ab >> 48);
-            const double det = minor_of(p_x0, p_x1, p_x2, p_x3);
+            const bool opp = UHF && ((p >= T.na) != (q >= T.na));
+            const double det = opp ? (double)p_x0 * (double)p_x1 : minor_of(p_x0, p_x1, p_x2, p_x3);
             double ratio = det * V.es[a] * V.es[b] * p_vk.y * (V.sies[p] * V.sies[q]);
             if (T.ncorr) ratio *= cps_ratio(T, V.cidx, V.cinv, 4, V.slot[p], V.slot[q], a, b);
             term = p_vk.x * ratio;
